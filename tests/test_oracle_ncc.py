@@ -1,0 +1,77 @@
+"""Pins for the oracle's similarity and per-patch registration.
+
+The similarity is the cross-correlation of paper Sec. IV-A (eq. CC), also used
+as the 2D-3D registration cost (Sec. II); registration is per-patch gradient
+ascent (Sec. III, level I).  Pinned by: numpy's corrcoef on the valid samples,
+NCC(y, y) = 1, invariance to a y + b, the truth being a fixed point, the
+monotone objective, and recovery of known motion on a textured phantom.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.ndimage import gaussian_filter
+
+import oracle
+from paper_1611_07289_amd import synth
+from tests._problems import tiny
+
+
+@pytest.fixture(scope="module")
+def tex():
+    P = synth.tiny_problem()
+    X = gaussian_filter(np.random.default_rng(5).uniform(0, 1000, (32, 32, 32)), 1.5)
+    X = (X - X.min()) / (X.max() - X.min()) * 1000.0
+    ctx = oracle.Ctx(P.grid, P.stacks, P.patches)
+    y, _, val = ctx.simulate(X, P.theta_true)
+    return P, ctx, X, y, val
+
+
+def test_ncc_matches_corrcoef_and_invariances(tex):
+    P, ctx, X, y, val = tex
+    th = P.theta_true + synth.random_motion(P.M, 3.0, 1.0, 42)
+    yobs = y + np.random.default_rng(1).normal(0, 30, y.shape)
+    ncc = ctx.ncc(X, yobs, th)
+    yh, _, v = ctx.simulate(X, th)
+    off = P.patches.sample_off
+    for s in range(0, P.M, 7):
+        sl = slice(off[s], off[s + 1])
+        vv = v[sl]
+        ref = np.corrcoef(yobs[sl][vv], yh[sl][vv])[0, 1]
+        assert ncc[s] == pytest.approx(ref, abs=1e-12)
+    assert np.allclose(ctx.ncc(X, 3.0 * yobs + 17.0, th), ncc, atol=1e-12)
+    assert np.allclose(ctx.ncc(X, y, P.theta_true)[val.reshape(-1)[off[:-1]]], 1.0)
+
+
+def test_truth_is_a_fixed_point(tex):
+    P, ctx, X, y, val = tex
+    th, ncc = ctx.register(X, y, P.theta_true)
+    # NCC is 1 at the truth, so only rounding-level "improvements" can move it
+    assert np.allclose(th, P.theta_true, atol=1e-6)
+    assert np.allclose(ncc, 1.0)
+
+
+def test_register_recovers_known_motion(tex):
+    P, ctx, X, y, val = tex
+    th0 = P.theta_true + synth.random_motion(P.M, 3.0, 1.0, 99)
+    n0 = ctx.ncc(X, y, th0)
+    th, ncc = ctx.register(X, y, th0)
+    assert np.all(ncc >= n0 - 1e-15)
+    assert np.allclose(ncc, ctx.ncc(X, y, th), atol=1e-14)
+    drot = np.degrees(np.abs(th[:, :3] - P.theta_true[:, :3])).max(1)
+    dtr = np.abs(th[:, 3:] - P.theta_true[:, 3:]).max(1)
+    drot0 = np.degrees(np.abs(th0[:, :3] - P.theta_true[:, :3])).max(1)
+    dtr0 = np.abs(th0[:, 3:] - P.theta_true[:, 3:]).max(1)
+    assert np.median(dtr) < 0.03 and np.median(dtr) < 0.1 * np.median(dtr0)
+    assert np.median(drot) < 0.35 and np.median(drot) < 0.3 * np.median(drot0)
+    assert np.mean(ncc > 0.999) > 0.8
+
+
+def test_flat_patches_keep_parameters():
+    P = tiny()
+    ctx = oracle.Ctx(P.grid, P.stacks, P.patches)
+    X = np.asarray(P.x_true, np.float64)
+    y = np.full(P.N, 100.0)  # observed patches without structure
+    th0 = P.theta_true + 0.01
+    th, _ = ctx.register(X, y, th0, min_std=1.0)
+    assert np.array_equal(th, th0)
