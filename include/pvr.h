@@ -1,0 +1,268 @@
+/*
+ * pvr.h -- C ABI of the MI355X (gfx950) patch-to-volume reconstruction
+ * hot path.  Method: Alansary, Kainz et al., "PVR: Patch-to-Volume
+ * Reconstruction for Large Area Motion Correction of Fetal MRI",
+ * arXiv 1611.07289.
+ *
+ * The library reconstructs one or more independent volumes X from many
+ * overlapping 2D patches cut out of stacks of slices, each patch moved by its
+ * own rigid transform (Sec. II, eq. for Y = {y_s}).  It exposes the steps of
+ * one super-resolution (SR) iteration and the per-patch registration:
+ *
+ *   pvr_plan_build        per-patch motion geometry, PSF normalisers and the
+ *                         brick -> patch index used by the adjoint
+ *   pvr_simulate          y_hat = A X, residual e = y - y_hat
+ *                         (observation model x_i = W_i y + n_i,
+ *                         W_i = D B T_i, Sec. I eq. (1))
+ *   pvr_backproject       num = A^T(W p e), den = A^T(W p), a gather
+ *                         (every voxel sums over the samples whose PSF
+ *                         covers it; no atomics, fixed summation order)
+ *   pvr_robust_weights    EM outlier model: m = 1/(max e - min e), inlier
+ *                         posterior p, patch potential p_bar, patch
+ *                         classification W, M-step for sigma^2 and c
+ *                         (Sec. II "EM-Based Outlier Removal")
+ *   pvr_sr_update         X' = max(clamp, X + a num/den + a l R(X)) with an
+ *                         edge-preserving 26-neighbour regulariser
+ *                         (Sec. II gradient-descent SR; anisotropic
+ *                         diffusion of the cited method, Sec. I-A)
+ *   pvr_register_patches  per-patch rigid 2D-3D registration maximising the
+ *                         cross-correlation of Sec. IV-A eq. CC
+ *                         (Sec. II "Patch to Volume Registration",
+ *                         Sec. III parallelisation level I)
+ *
+ * Conventions
+ *  - Pointers are DEVICE pointers unless marked (host).  The caller owns every
+ *    buffer passed in; the plan owns its own device buffers (allocated by
+ *    pvr_plan_create / pvr_plan_build, freed by pvr_plan_destroy).
+ *  - Calls are asynchronous on `stream` except where noted.  A plan is used on
+ *    one stream at a time (thread-compatible, not thread-safe).
+ *  - Every function returns a pvr_status; no exception crosses the ABI.  On
+ *    error pvr_last_error() returns a message (thread-local, valid until the
+ *    next call on the same thread).  Invalid arguments are rejected before any
+ *    launch.
+ *  - Volume layout: problem b occupies X[vol_off[b] .. vol_off[b+1]) with voxel
+ *    (i, j, k) at vol_off[b] + (k*ny + j)*nx + i.  Sample layout: patch s
+ *    occupies samples [sample_off[s], sample_off[s+1]) row-major inside the
+ *    patch.  Both offset tables come from pvr_plan_offsets.
+ *  - Motion theta: [M][6] = (rx, ry, rz [rad], tx, ty, tz [mm]);
+ *    R = Rz Ry Rx; a patch rotates about its centre c_s:
+ *    x = R (P - c_s) + c_s + t.
+ *  - PSF: Gaussian along the moved stack axes with the stack's FWHMs,
+ *    support sum (d_a/sigma_a)^2 <= k^2, weight exp(-Q/2) - exp(-k^2/2)
+ *    (continuous at the cut-off), normalised over in-volume voxels.  A sample
+ *    is valid iff its moved centre lies in [-1/2, n-1/2)^3, its normaliser is
+ *    positive, its mask byte is non-zero and its patch is active; invalid
+ *    samples simulate to 0 and contribute nothing.
+ */
+#ifndef PVR_H
+#define PVR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PVR_OK = 0,
+  PVR_EINVAL = 1,       /* null / inconsistent argument */
+  PVR_ESHAPE = 2,       /* sizes or layouts do not fit */
+  PVR_ENOMEM = 3,       /* device allocation failed */
+  PVR_EHIP = 4,         /* a HIP runtime call failed (message attached) */
+  PVR_ENUMERIC = 5,     /* non-finite input detected */
+  PVR_EUNSUPPORTED = 6  /* valid request the library does not implement */
+} pvr_status;
+
+/* Volume grid of one reconstruction: voxel index -> world mm affine, row-major
+ * 3x4.  The three linear columns must be linearly independent. */
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t pad_;
+  double vox2world[12];
+} pvr_grid;
+
+/* A stack of 2D slices (Sec. I: LR images; Sec. II: input stacks).
+ * pix2world maps (u, v, slice) to world mm, row-major 3x4; its three linear
+ * columns must be mutually orthogonal (in-plane axes x spacing, slice normal x
+ * slice spacing).  fwhm_mm: PSF full widths at half maximum along the
+ * in-plane x, in-plane y and normal axes. */
+typedef struct {
+  int32_t problem;          /* reconstruction this stack belongs to */
+  int32_t nx, ny, nslices;
+  double pix2world[12];
+  double fwhm_mm[3];
+} pvr_stack;
+
+/* A rectangular patch y_s (Sec. II "Patch Extraction": square patches of size
+ * a, stride omega) on one slice: pixels (x0+u, y0+v, slice), u < w, v < h. */
+typedef struct {
+  int32_t stack, slice, x0, y0, w, h;
+} pvr_patch;
+
+typedef struct {
+  int64_t n_samples;        /* N = sum over patches of w*h */
+  int64_t n_voxels;         /* total over problems */
+  int32_t n_patches;        /* M */
+  int32_t n_problems;
+  int32_t n_stacks;
+  int32_t n_bricks;         /* 8x8x8 voxel bricks over all problems */
+  int64_t n_bin_pairs;      /* brick/patch pairs after the last build */
+  int64_t device_bytes;     /* device memory owned by the plan */
+} pvr_plan_sizes;
+
+/* EM state of one reconstruction, kept on the device so that an SR iteration
+ * needs no host round trip (one entry per problem, caller-allocated). */
+typedef struct {
+  double sigma2;            /* inlier variance sigma^2 */
+  double c;                 /* inlier proportion c */
+  double m;                 /* outlier density of the last E-step */
+  double y_abs_max;         /* max |y| over valid samples */
+  double sum_wp, sum_wpe2, sum_w;  /* M-step sums of the last iteration */
+  int32_t n_used;           /* patches entering the patch classification */
+  int32_t n_excluded;       /* patches with W = 0 among them */
+  int32_t started;          /* sigma2 / c hold a value */
+  int32_t pad_;
+} pvr_em_state;
+
+/* pvr_robust_weights flags */
+#define PVR_EM_INIT  1      /* start of a cycle: sigma^2 = mean(e^2), c = 0.9 */
+#define PVR_EM_FIX_W 2      /* use patch_w as given instead of classifying */
+
+typedef struct {
+  float alpha;              /* step length (default 1) */
+  float lambda;             /* regularisation weight (default 0.02) */
+  float delta;              /* edge threshold of the diffusion (default 150) */
+  float clamp_min;          /* lower bound of X' (default 0) */
+  float den_eps;            /* voxels with den <= den_eps get no data step */
+  int32_t use_clamp;        /* 1: apply clamp_min */
+} pvr_sr_params;
+
+typedef struct {
+  double step0;             /* initial / largest step (default 1.0) */
+  double step_min;          /* stop when the step falls below (0.01) */
+  double fd_h;              /* central-difference step (0.05) */
+  double min_std;           /* patches with std(y) below keep theta */
+  int32_t max_iter;         /* trial steps (40) */
+  int32_t pad_;
+} pvr_reg_params;
+
+typedef struct pvr_plan pvr_plan;
+
+/* Thread-local text of the last error. */
+const char *pvr_last_error(void);
+
+/* Library version string. */
+const char *pvr_version(void);
+
+/* Create a plan.  All arrays are (host) and copied.  Patches must reference
+ * valid stacks and lie inside their slice; every stack names a valid problem.
+ * cutoff_k: PSF support radius in standard deviations (> 0, default 3).
+ * Errors: PVR_EINVAL for null pointers or out-of-range indices, PVR_ESHAPE
+ * for non-orthogonal stack axes or empty sizes, PVR_ENOMEM, PVR_EHIP. */
+pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
+                           const pvr_stack *stacks, int32_t n_stacks,
+                           const pvr_patch *patches, int32_t n_patches,
+                           double cutoff_k, pvr_plan **out);
+
+/* Free a plan and its device buffers (NULL is a no-op).  Synchronises the
+ * device first. */
+void pvr_plan_destroy(pvr_plan *plan);
+
+/* (host) sizes. */
+pvr_status pvr_plan_info(const pvr_plan *plan, pvr_plan_sizes *out);
+
+/* (host) sample_off[M+1] and vol_off[n_problems+1]; either may be NULL. */
+pvr_status pvr_plan_offsets(const pvr_plan *plan, int64_t *sample_off,
+                            int64_t *vol_off);
+
+/* Build the motion-dependent state for theta (float [M][6] or double
+ * [M][6]): per-patch geometry, per-sample inverse PSF normalisers (0 marks an
+ * invalid sample) and the brick -> patch index of the adjoint.  active
+ * ([M], nullable = all) and sample_mask ([N], nullable = all) are read here.
+ * Synchronises `stream` once (to size the index). */
+pvr_status pvr_plan_build(pvr_plan *plan, const float *theta,
+                          const uint8_t *active, const uint8_t *sample_mask,
+                          hipStream_t stream);
+pvr_status pvr_plan_build_f64(pvr_plan *plan, const double *theta,
+                              const uint8_t *active, const uint8_t *sample_mask,
+                              hipStream_t stream);
+
+/* (device) inverse normalisers 1/Z_j of the last build, [N] float
+ * (0 for invalid samples).  The pointer stays valid until the next build. */
+const float *pvr_plan_inv_z(const pvr_plan *plan);
+
+/* Forward simulation ("volume-pixel"): y_sim = A X over valid samples.
+ * X [V], y_obs [N] (nullable), y_sim [N] (nullable), resid [N] (nullable;
+ * requires y_obs) = y_obs - y_sim for valid samples, 0 otherwise. */
+pvr_status pvr_simulate(const pvr_plan *plan, const float *X,
+                        const float *y_obs, float *y_sim, float *resid,
+                        hipStream_t stream);
+pvr_status pvr_simulate_f64(const pvr_plan *plan, const double *X,
+                            const double *y_obs, double *y_sim, double *resid,
+                            hipStream_t stream);
+
+/* Adjoint ("pixel-volume"), gather form: for every voxel i
+ *   num_i = sum_j psi_ji W_s(j) p_j e_j,   den_i = sum_j psi_ji W_s(j) p_j
+ * e [N] (required), p [N] (nullable = 1), patch_w [M] (nullable = 1),
+ * num [V] (required), den [V] (nullable).  Deterministic: the summation order
+ * is fixed (patch order, then pixel order). */
+pvr_status pvr_backproject(const pvr_plan *plan, const float *e,
+                           const float *p, const float *patch_w, float *num,
+                           float *den, hipStream_t stream);
+pvr_status pvr_backproject_f64(const pvr_plan *plan, const double *e,
+                               const double *p, const double *patch_w,
+                               double *num, double *den, hipStream_t stream);
+
+/* EM robust weights of one SR iteration (per problem):
+ *   m = 1/max(max e - min e, 1e-6 max|y|) over valid samples,
+ *   p_j = c G(e_j) / (c G(e_j) + m (1 - c)),  G zero-mean Gaussian (sigma^2),
+ *   p_bar_s = sqrt(sum_{j in s} p_j^2 / N_s),
+ *   W_s from a two-component Gaussian mixture fitted to {p_bar_s} (20 EM
+ *   iterations from a median split; W = inlier posterior if >= 0.5 else 0),
+ *   then sigma^2 = sum W p e^2 / sum W p (floored at (1e-4 max|y|)^2) and
+ *   c = sum W p / sum_s W_s N_s for the next call.
+ * resid, y_obs [N]; em [n_problems] (device, in/out); p [N], pbar [M] and
+ * patch_w [M] out (patch_w in with PVR_EM_FIX_W). */
+pvr_status pvr_robust_weights(pvr_plan *plan, const float *resid,
+                              const float *y_obs, pvr_em_state *em, float *p,
+                              float *pbar, float *patch_w, int32_t flags,
+                              hipStream_t stream);
+
+/* SR update of every volume (Jacobi: reads X only, writes X_out; X_out must
+ * not alias X):
+ *   X'_i = max(clamp, X_i + alpha num_i/den_i [den_i > den_eps]
+ *                        + alpha lambda R_i(X))
+ *   R_i = sum over the 26 neighbours d inside the grid of
+ *         b_d D_d / sqrt(1 + (D_d/delta)^2),  D_d = X_{i+d} - X_i,
+ *         b_d = 1/|d| (voxel units).
+ * params (host). */
+pvr_status pvr_sr_update(const pvr_plan *plan, const float *X,
+                         const float *num, const float *den,
+                         const pvr_sr_params *params, float *X_out,
+                         hipStream_t stream);
+
+/* Per-patch rigid registration (one workgroup per patch): maximise
+ * NCC(y_s, A_s(theta) X) over the six parameters, where the simulated patch
+ * uses the full PSF forward model and NCC runs over samples valid at theta.
+ * Optimiser: variables (rho * angles, translations) with rho the patch
+ * half-diagonal in mm; central differences with step fd_h; a normalised
+ * step of length delta is accepted on strict improvement (delta doubles,
+ * capped at step0) or delta halves; stop below step_min or after max_iter
+ * trial steps.  Patches with std(y_s) < min_std keep theta.
+ * theta [M][6] in/out; ncc [M] out (nullable); reg [M] (nullable = all):
+ * only patches with reg != 0 move; params (host); sample_mask of the last
+ * build applies.  With max_iter = 0 it only evaluates NCC at theta. */
+pvr_status pvr_register_patches(const pvr_plan *plan, const float *X,
+                                const float *y_obs, float *theta, float *ncc,
+                                const uint8_t *reg,
+                                const pvr_reg_params *params,
+                                hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PVR_H */

@@ -1,0 +1,256 @@
+// Forward direction ("volume-pixel"): PSF-weighted simulation of moved patch
+// samples, and the per-patch NCC registration built on the same PSF walk.
+//
+// One workgroup (256 lanes = 4 waves) covers a chunk of up to 1024 samples of
+// one patch, so the patch's geometry is uniform across the workgroup; lanes
+// take consecutive pixels of a patch row, whose supports are near-identical
+// shapes shifted by one pixel, so the volume reads of a wave coalesce along
+// the row direction.
+#include <math.h>
+
+#include "pvr_geometry.h"
+#include "pvr_internal.h"
+#include "pvr_util.h"
+
+using namespace pvr;
+
+template <typename T>
+__global__ void __launch_bounds__(SIM_THREADS)
+k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patches,
+           const BlockWork *__restrict__ work, const typename GeoOf<T>::type *__restrict__ geo,
+           const T *__restrict__ invz, const T *__restrict__ X, const T *__restrict__ y_obs,
+           T *__restrict__ y_sim, T *__restrict__ resid) {
+  const BlockWork wk = work[blockIdx.x];
+  const PatchDev pt = patches[wk.patch];
+  const ProbDev pr = probs[pt.problem];
+  const typename GeoOf<T>::type &g = geo[wk.patch];
+  const T *Xp = X + pr.vol_off;
+  const int n = pt.w * pt.h;
+  const int l1 = min(n, wk.l0 + SIM_CHUNK);
+  for (int l = wk.l0 + threadIdx.x; l < l1; l += SIM_THREADS) {
+    const long long j = pt.off + l;
+    const T iz = invz[j];
+    T yh = (T)0;
+    if (iz > (T)0) {
+      const int u = pt.x0 + l % pt.w, v = pt.y0 + l / pt.w;
+      int b[3];
+      T f[3];
+      sample_centre(g, pr, u, v, pt.slice, b, f);
+      T z = 0, acc = 0;
+      psf_walk<T, typename GeoOf<T>::type, true>(g, pr, b, f, Xp, z, acc);
+      yh = acc * iz;
+    }
+    if (y_sim) y_sim[j] = yh;
+    if (resid) resid[j] = iz > (T)0 ? y_obs[j] - yh : (T)0;
+  }
+}
+
+template <typename T>
+static pvr_status simulate_impl(const pvr_plan *p, const T *X, const T *y_obs, T *y_sim, T *resid,
+                                const T *invz, hipStream_t stream) {
+  if (!X) return fail(PVR_EINVAL, "pvr_simulate: X is NULL");
+  if (resid && !y_obs) return fail(PVR_EINVAL, "pvr_simulate: resid requires y_obs");
+  if (!y_sim && !resid) return PVR_OK;
+  hipLaunchKernelGGL(k_simulate<T>, dim3(p->n_sim_blocks), dim3(SIM_THREADS), 0, stream, p->d_prob,
+                     p->d_patch, p->d_sim_blocks,
+                     (const typename GeoOf<T>::type *)(sizeof(T) == 4 ? (const void *)p->d_geof
+                                                                      : (const void *)p->d_geod),
+                     invz, X, y_obs, y_sim, resid);
+  HIP_TRY(hipGetLastError());
+  return PVR_OK;
+}
+
+extern "C" pvr_status pvr_simulate(const pvr_plan *p, const float *X, const float *y_obs,
+                                   float *y_sim, float *resid, hipStream_t stream) {
+  PVR_API_BEGIN();
+  if (!p) return fail(PVR_EINVAL, "pvr_simulate: plan is NULL");
+  if (!p->built) return fail(PVR_EINVAL, "pvr_simulate: plan has not been built");
+  return simulate_impl<float>(p, X, y_obs, y_sim, resid, p->d_invz, stream);
+  PVR_API_END();
+}
+
+extern "C" pvr_status pvr_simulate_f64(const pvr_plan *p, const double *X, const double *y_obs,
+                                       double *y_sim, double *resid, hipStream_t stream) {
+  PVR_API_BEGIN();
+  if (!p) return fail(PVR_EINVAL, "pvr_simulate_f64: plan is NULL");
+  if (!p->built || !p->built64) return fail(PVR_EINVAL, "pvr_simulate_f64: plan needs pvr_plan_build_f64");
+  return simulate_impl<double>(p, X, y_obs, y_sim, resid, p->d_invz64, stream);
+  PVR_API_END();
+}
+
+// ---------------------------------------------------------------------------
+// registration
+// ---------------------------------------------------------------------------
+constexpr int REG_THREADS = 256;
+
+// Sum of 6 doubles over the workgroup (fixed order: wave butterflies, then
+// the 4 wave results in order).
+__device__ __forceinline__ void block_sum6(double v[6], double (*lds)[REG_THREADS / 64]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    double x = v[q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) lds[q][wave] = x;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    double x = 0;
+#pragma unroll
+    for (int w = 0; w < REG_THREADS / 64; ++w) x += lds[q][w];
+    v[q] = x;
+  }
+  __syncthreads();
+}
+
+struct RegShared {
+  GeoF g;
+  double red[6][REG_THREADS / 64];
+};
+
+// NCC of the patch against its simulation at theta (valid samples only).
+__device__ double reg_eval(RegShared &sh, const ProbDev &pr, const StackDev &st, const PatchDev &pt,
+                           const double th[6], double k, const float *__restrict__ Xp,
+                           const float *__restrict__ y, const uint8_t *__restrict__ mask) {
+  if (threadIdx.x == 0) {
+    GeoD gd;
+    int bb[6];
+    make_geometry(pr, st, pt, th, k, gd, sh.g, bb);
+  }
+  __syncthreads();
+  const GeoF &g = sh.g;
+  double acc6[6] = {0, 0, 0, 0, 0, 0};
+  const int n = pt.w * pt.h;
+  for (int l = threadIdx.x; l < n; l += REG_THREADS) {
+    const long long j = pt.off + l;
+    if (mask && !mask[j]) continue;
+    const int u = pt.x0 + l % pt.w, v = pt.y0 + l / pt.w;
+    int b[3];
+    float f[3];
+    if (!sample_centre(g, pr, u, v, pt.slice, b, f)) continue;
+    float z = 0.f, a = 0.f;
+    psf_walk<float, GeoF, true>(g, pr, b, f, Xp, z, a);
+    if (!(z > 0.f)) continue;
+    const double yh = (double)(a / z), yo = (double)y[j];
+    acc6[0] += 1.0;
+    acc6[1] += yo;
+    acc6[2] += yo * yo;
+    acc6[3] += yh;
+    acc6[4] += yh * yh;
+    acc6[5] += yo * yh;
+  }
+  block_sum6(acc6, sh.red);
+  const double cnt = acc6[0];
+  if (!(cnt > 0)) return 0.0;
+  const double my = acc6[1] / cnt, mh = acc6[3] / cnt;
+  const double vy = acc6[2] / cnt - my * my, vh = acc6[4] / cnt - mh * mh;
+  const double cv = acc6[5] / cnt - my * mh;
+  if (!(vy > 1e-12 * my * my) || !(vh > 1e-12 * mh * mh) || !(vy > 0) || !(vh > 0)) return 0.0;
+  return cv / sqrt(vy * vh);
+}
+
+__global__ void __launch_bounds__(REG_THREADS)
+k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stacks,
+           const PatchDev *__restrict__ patches, const float *__restrict__ X,
+           const float *__restrict__ y, const uint8_t *__restrict__ mask, float *__restrict__ theta,
+           float *__restrict__ ncc_out, const uint8_t *__restrict__ reg, pvr_reg_params prm,
+           double k) {
+  __shared__ RegShared sh;
+  const int s = blockIdx.x;
+  const PatchDev pt = patches[s];
+  const StackDev st = stacks[pt.stack];
+  const ProbDev pr = probs[pt.problem];
+  const float *Xp = X + pr.vol_off;
+  double th[6];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) th[a] = (double)theta[6 * s + a];
+  // observed standard deviation over unmasked samples
+  double sy[6] = {0, 0, 0, 0, 0, 0};
+  const int n = pt.w * pt.h;
+  for (int l = threadIdx.x; l < n; l += REG_THREADS) {
+    const long long j = pt.off + l;
+    if (mask && !mask[j]) continue;
+    const double yo = y[j];
+    sy[0] += 1.0;
+    sy[1] += yo;
+    sy[2] += yo * yo;
+  }
+  block_sum6(sy, sh.red);
+  double sd = 0;
+  if (sy[0] > 0) {
+    const double m = sy[1] / sy[0];
+    sd = sqrt(fmax(sy[2] / sy[0] - m * m, 0.0));
+  }
+  double f0 = reg_eval(sh, pr, st, pt, th, k, Xp, y, mask);
+  const bool do_reg = (reg ? reg[s] != 0 : true) && sd >= prm.min_std && prm.max_iter > 0;
+  if (do_reg) {
+    const double su = st.spacing[0], sv = st.spacing[1];
+    double rho = 0.5 * sqrt((pt.w - 1) * (pt.w - 1) * su * su + (pt.h - 1) * (pt.h - 1) * sv * sv);
+    rho = rho < 1.0 ? 1.0 : rho;
+    const double sc[6] = {rho, rho, rho, 1.0, 1.0, 1.0};
+    double q[6], grad[6], tt[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) q[a] = th[a] * sc[a];
+    double delta = prm.step0;
+    bool have_grad = false, moved = false;
+    for (int it = 0; it < prm.max_iter; ++it) {
+      if (delta < prm.step_min) break;
+      if (!have_grad) {
+        for (int a = 0; a < 6; ++a) {
+#pragma unroll
+          for (int b = 0; b < 6; ++b) tt[b] = q[b] / sc[b];
+          tt[a] = (q[a] + prm.fd_h) / sc[a];
+          const double fp = reg_eval(sh, pr, st, pt, tt, k, Xp, y, mask);
+          tt[a] = (q[a] - prm.fd_h) / sc[a];
+          const double fm = reg_eval(sh, pr, st, pt, tt, k, Xp, y, mask);
+          grad[a] = (fp - fm) / (2.0 * prm.fd_h);
+        }
+        have_grad = true;
+      }
+      double gn = 0;
+#pragma unroll
+      for (int a = 0; a < 6; ++a) gn += grad[a] * grad[a];
+      gn = sqrt(gn);
+      if (!(gn > 0)) break;
+      double trial[6];
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        trial[a] = q[a] + delta * grad[a] / gn;
+        tt[a] = trial[a] / sc[a];
+      }
+      const double ft = reg_eval(sh, pr, st, pt, tt, k, Xp, y, mask);
+      if (ft > f0) {
+#pragma unroll
+        for (int a = 0; a < 6; ++a) q[a] = trial[a];
+        f0 = ft;
+        have_grad = false;
+        moved = true;
+        delta = fmin(2.0 * delta, prm.step0);
+      } else {
+        delta *= 0.5;
+      }
+    }
+    if (moved && threadIdx.x == 0) {
+#pragma unroll
+      for (int a = 0; a < 6; ++a) theta[6 * s + a] = (float)(q[a] / sc[a]);
+    }
+  }
+  if (ncc_out && threadIdx.x == 0) ncc_out[s] = (float)f0;
+}
+
+extern "C" pvr_status pvr_register_patches(const pvr_plan *p, const float *X, const float *y_obs,
+                                           float *theta, float *ncc, const uint8_t *reg,
+                                           const pvr_reg_params *prm, hipStream_t stream) {
+  PVR_API_BEGIN();
+  if (!p || !X || !y_obs || !theta || !prm) return fail(PVR_EINVAL, "pvr_register_patches: NULL argument");
+  if (!p->built) return fail(PVR_EINVAL, "pvr_register_patches: plan has not been built");
+  if (prm->max_iter < 0 || !(prm->step0 > 0) || !(prm->step_min > 0) || !(prm->fd_h > 0))
+    return fail(PVR_EINVAL, "pvr_register_patches: invalid optimiser parameters");
+  hipLaunchKernelGGL(k_register, dim3(p->M), dim3(REG_THREADS), 0, stream, p->d_prob, p->d_stack,
+                     p->d_patch, X, y_obs, p->d_mask, theta, ncc, reg, *prm, p->k);
+  HIP_TRY(hipGetLastError());
+  return PVR_OK;
+  PVR_API_END();
+}

@@ -1,0 +1,264 @@
+// Internal declarations of the PVR HIP library (gfx950, wave64).
+//
+// Data held by a plan:
+//   ProbDev   one per reconstruction: grid, volume / brick / patch ranges
+//   StackDev  one per stack: pixel -> world affine, unit axes, PSF sigmas
+//   PatchDev  one per patch: stack, slice, rectangle, sample offset
+//   GeoD/GeoF one per patch, rebuilt from theta: the moved sample-centre map
+//             H (pixel -> voxel coordinates), its inverse G, the constants of
+//             the PSF quadratic form in voxel offsets (forward direction) and
+//             in pixel offsets (adjoint direction), and the brick range the
+//             patch can touch.
+//
+// The PSF weight of voxel v for a sample centred at x is
+//   g_hat = 2^(-Q') - 2^(-K2)   if Q' <= K2, else 0,
+// with Q' = kappa * sum_a (d_a / sigma_a)^2, d = F^T (v - x), kappa =
+// log2(e)/2 and K2 = kappa k^2, i.e. exp(-Q/2) - exp(-k^2/2) on the support
+// sum (d_a/sigma_a)^2 <= k^2 (Gaussian PSF along the moved stack axes,
+// continuous at the cut-off).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pvr.h"
+
+namespace pvr {
+
+constexpr int BRICK = 8;            // adjoint brick edge (voxels)
+constexpr int SIM_CHUNK = 1024;     // samples per forward workgroup
+constexpr int SIM_THREADS = 256;
+constexpr double KAPPA = 0.72134752044448170368;  // log2(e) / 2
+
+struct ProbDev {
+  int nx, ny, nz;
+  int nbx, nby, nbz;
+  int brick_base, n_bricks;
+  int patch_begin, patch_end;
+  long long vol_off;
+  long long sample_begin, sample_end;
+  double v2w[12];
+  double w2v[12];
+};
+
+struct StackDev {
+  int problem, nx, ny, ns;
+  double p2w[12];
+  double E[9];        // unit axes as columns (row-major 3x3)
+  double spacing[3];  // column norms of the linear part
+  double sigma[3];    // PSF standard deviations (mm)
+};
+
+struct PatchDev {
+  int stack, slice, x0, y0, w, h, problem, pad;
+  long long off;
+};
+
+// Motion-dependent per-patch constants, double precision.
+struct GeoD {
+  double H[12];   // (u, v, slice, 1) -> voxel coords of the moved centre
+  double G[12];   // voxel (i, j, k, 1) -> unmoved pixel coords (u, v, s)
+  // forward quadratic form Q'(w) = w^T A w in voxel offsets w, permuted so
+  // that axis c (inner loop) has the longest extent; a outer, b middle.
+  double Acc, Aca, Acb, Saa, Sab, Sbb, iAinv_aa, ha;
+  double inv_Acc, inv_Sbb, nSab_Sbb;
+  double K2, cut;           // kappa k^2 and 2^-K2
+  double cu, cv, ck;        // adjoint: sqrt(kappa) * spacing / sigma
+  double inv_cu, inv_cv;
+  int perm[3];
+  int bb_lo[3], bb_hi[3];   // brick range (inclusive); empty if lo > hi
+  int pad_;
+};
+
+// The same constants in single precision for the float kernels (G stays in
+// double: it maps voxel indices of up to a few hundred to pixel coordinates
+// whose fractional part sets the weights).
+struct GeoF {
+  double H[12];
+  double G[12];
+  float Acc, Aca, Acb, Saa, Sab, Sbb, iAinv_aa, ha;
+  float inv_Acc, inv_Sbb, nSab_Sbb;
+  float K2, cut;
+  float cu, cv, ck, inv_cu, inv_cv;
+  int perm[3];
+  int pad_;
+};
+
+template <typename T> struct GeoOf;
+template <> struct GeoOf<float> { using type = GeoF; };
+template <> struct GeoOf<double> { using type = GeoD; };
+
+struct BlockWork {   // one forward workgroup: a chunk of one patch
+  int patch;
+  int l0;            // first local sample
+};
+
+template <typename T> __device__ __forceinline__ T fast_exp2(T x);
+template <> __device__ __forceinline__ float fast_exp2<float>(float x) {
+  return __builtin_amdgcn_exp2f(x);
+}
+template <> __device__ __forceinline__ double fast_exp2<double>(double x) {
+  return exp2(x);
+}
+
+__device__ __forceinline__ int sel3(int i, int a0, int a1, int a2) {
+  return i == 0 ? a0 : (i == 1 ? a1 : a2);
+}
+template <typename T>
+__device__ __forceinline__ T sel3f(int i, T a0, T a1, T a2) {
+  return i == 0 ? a0 : (i == 1 ? a1 : a2);
+}
+
+// Moved centre of pixel (u, v) of patch geometry g in voxel coordinates,
+// split into the nearest voxel b and the offset f = x - b (|f| <= 1/2).
+// Returns whether the centre lies in the half-open box [-1/2, n - 1/2)^3.
+template <typename GEO, typename T>
+__device__ __forceinline__ bool sample_centre(const GEO &g, const ProbDev &p,
+                                              int u, int v, int slice,
+                                              int b[3], T f[3]) {
+  double x[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    x[r] = fma(g.H[4 * r], (double)u,
+               fma(g.H[4 * r + 1], (double)v,
+                   fma(g.H[4 * r + 2], (double)slice, g.H[4 * r + 3])));
+  bool in = x[0] >= -0.5 && x[0] < p.nx - 0.5 && x[1] >= -0.5 &&
+            x[1] < p.ny - 0.5 && x[2] >= -0.5 && x[2] < p.nz - 0.5;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    double bb = rint(x[r]);
+    b[r] = (int)bb;
+    f[r] = (T)(x[r] - bb);
+  }
+  return in;
+}
+
+// Walk the PSF support of one sample (nearest voxel b, offset f) over the
+// voxels inside the grid and return sum g_hat and sum g_hat * X.  Rows along
+// the inner axis c are enumerated exactly from the quadratic form: for the
+// outer offset w_a the middle range comes from the Schur complement, for each
+// (w_a, w_b) the inner range from the 1D quadratic in w_c.
+template <typename T, typename GEO, bool HAS_X>
+__device__ __forceinline__ void psf_walk(const GEO &g, const ProbDev &p,
+                                         const int b[3], const T f[3],
+                                         const T *__restrict__ X, T &z,
+                                         T &acc) {
+  const int ia = g.perm[0], ib = g.perm[1], ic = g.perm[2];
+  const int n_a = sel3(ia, p.nx, p.ny, p.nz), n_b = sel3(ib, p.nx, p.ny, p.nz),
+            n_c = sel3(ic, p.nx, p.ny, p.nz);
+  const long long sx = 1, sy = p.nx, sz = (long long)p.nx * p.ny;
+  const long long st_a = ia == 0 ? sx : (ia == 1 ? sy : sz);
+  const long long st_b = ib == 0 ? sx : (ib == 1 ? sy : sz);
+  const long long st_c = ic == 0 ? sx : (ic == 1 ? sy : sz);
+  const int b_a = sel3(ia, b[0], b[1], b[2]), b_b = sel3(ib, b[0], b[1], b[2]),
+            b_c = sel3(ic, b[0], b[1], b[2]);
+  const T f_a = sel3f<T>(ia, f[0], f[1], f[2]), f_b = sel3f<T>(ib, f[0], f[1], f[2]),
+          f_c = sel3f<T>(ic, f[0], f[1], f[2]);
+  const T K2 = (T)g.K2, cut = (T)g.cut, Acc = (T)g.Acc, Aca = (T)g.Aca,
+          Acb = (T)g.Acb, Saa = (T)g.Saa, Sab = (T)g.Sab, Sbb = (T)g.Sbb,
+          iAaa = (T)g.iAinv_aa, ha = (T)g.ha, iAcc = (T)g.inv_Acc,
+          iSbb = (T)g.inv_Sbb, nSab = (T)g.nSab_Sbb;
+  const long long base = (long long)b[0] + sy * b[1] + sz * b[2];
+  int lo_a = max((int)ceil(f_a - ha), -b_a);
+  int hi_a = min((int)floor(f_a + ha), n_a - 1 - b_a);
+  for (int oa = lo_a; oa <= hi_a; ++oa) {
+    const T wa = (T)oa - f_a;
+    const T rem = K2 - wa * wa * iAaa;
+    if (rem < (T)0) continue;
+    const T wbc = nSab * wa;
+    const T rb = sqrt(rem * iSbb);
+    const int lo_b = max((int)ceil(f_b + wbc - rb), -b_b);
+    const int hi_b = min((int)floor(f_b + wbc + rb), n_b - 1 - b_b);
+    const T qa = Saa * wa * wa;
+    const T sa2 = (T)2 * Sab * wa;
+    for (int ob = lo_b; ob <= hi_b; ++ob) {
+      const T wb = (T)ob - f_b;
+      const T q1 = qa + wb * (sa2 + Sbb * wb);
+      const T rem2 = K2 - q1;
+      if (rem2 < (T)0) continue;
+      const T wcc = -(Aca * wa + Acb * wb) * iAcc;
+      const T rc = sqrt(rem2 * iAcc);
+      const int lo_c = max((int)ceil(f_c + wcc - rc), -b_c);
+      const int hi_c = min((int)floor(f_c + wcc + rc), n_c - 1 - b_c);
+      T d = ((T)lo_c - f_c) - wcc;
+      const T *ptr = HAS_X ? X + base + oa * st_a + ob * st_b + lo_c * st_c : nullptr;
+      for (int oc = lo_c; oc <= hi_c; ++oc) {
+        const T Q = fma(Acc * d, d, q1);
+        T gh = fast_exp2<T>(-Q) - cut;
+        gh = gh > (T)0 ? gh : (T)0;
+        z += gh;
+        if (HAS_X) {
+          acc = fma(gh, *ptr, acc);
+          ptr += st_c;
+        }
+        d += (T)1;
+      }
+    }
+  }
+}
+
+// Per-thread-slot helpers for deterministic block reductions.
+template <typename T, int NT>
+__device__ __forceinline__ T block_sum(T v, T *lds) {
+  const int tid = threadIdx.x;
+  lds[tid] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (tid < s) lds[tid] = lds[tid] + lds[tid + s];
+    __syncthreads();
+  }
+  T r = lds[0];
+  __syncthreads();
+  return r;
+}
+
+}  // namespace pvr
+
+// ---------------------------------------------------------------------------
+// host-side plan object
+// ---------------------------------------------------------------------------
+struct pvr_plan {
+  int device;
+  int P, S, M;
+  long long N, V;
+  int n_bricks;
+  double k;
+  // host copies
+  pvr::ProbDev *h_prob;
+  pvr::StackDev *h_stack;
+  pvr::PatchDev *h_patch;
+  long long *h_sample_off;   // [M+1]
+  long long *h_vol_off;      // [P+1]
+  int n_sim_blocks;
+  // device, static
+  pvr::ProbDev *d_prob;
+  pvr::StackDev *d_stack;
+  pvr::PatchDev *d_patch;
+  pvr::BlockWork *d_sim_blocks;
+  int *d_brick_prob;         // [n_bricks]
+  // device, per build
+  double *d_theta;           // [M][6]
+  pvr::GeoD *d_geod;
+  pvr::GeoF *d_geof;
+  float *d_invz;             // [N]
+  double *d_invz64;          // [N] (f64 builds)
+  uint8_t *d_mask;           // [N]
+  uint8_t *d_active;         // [M]
+  int *d_bb;                 // [M][6] brick range per patch
+  int *d_bin_count;          // [n_bricks]
+  int *d_bin_off;            // [n_bricks + 1]
+  int *d_bin_patch;          // [capacity]
+  long long bin_cap;
+  long long n_pairs;
+  bool built, built64;
+  // scratch
+  float2 *d_rq;              // [N]
+  double2 *d_rq64;           // [N] (lazy)
+  double *d_pstat;           // [M][10] per-patch EM partials
+  double *d_resp;            // [M] mixture responsibilities
+  float *d_pbar;             // [M] potentials when the caller passes none
+  int *d_total;              // [1] pinned readback target (device side)
+  int *h_total;              // pinned host
+  long long device_bytes;
+};

@@ -1,0 +1,61 @@
+// Host-side error handling and allocation helpers of the PVR library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <exception>
+
+#include "pvr_internal.h"
+
+namespace pvr {
+
+pvr_status fail(pvr_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+void plan_free(pvr_plan *p);
+void launch_fill_u8(uint8_t *dst, uint8_t v, long long n, hipStream_t stream);
+void launch_fill_f32(float *dst, float v, long long n, hipStream_t stream);
+void launch_fill_f64(double *dst, double v, long long n, hipStream_t stream);
+
+struct PlanGuard {
+  pvr_plan *p;
+  explicit PlanGuard(pvr_plan *q) : p(q) {}
+  ~PlanGuard() { if (p) plan_free(p); }
+  void release() { p = nullptr; }
+};
+
+}  // namespace pvr
+
+#define PVR_API_BEGIN() \
+  pvr::clear_error();   \
+  try {
+#define PVR_API_END()                                                          \
+  }                                                                            \
+  catch (const std::exception &e) {                                            \
+    return pvr::fail(PVR_EINVAL, "internal error: %s", e.what());              \
+  }                                                                            \
+  catch (...) {                                                                \
+    return pvr::fail(PVR_EINVAL, "internal error");                            \
+  }
+
+#define HIP_TRY(expr)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (expr);                                                    \
+    if (e_ != hipSuccess)                                                      \
+      return pvr::fail(PVR_EHIP, "%s failed: %s (%s:%d)", #expr,               \
+                       hipGetErrorString(e_), __FILE__, __LINE__);             \
+  } while (0)
+
+#define DEV_ALLOC(plan, ptr, count)                                            \
+  do {                                                                         \
+    size_t n_ = (size_t)(count) * sizeof(*(ptr));                              \
+    if (n_ == 0) n_ = 16;                                                      \
+    hipError_t e_ = hipMalloc((void **)&(ptr), n_);                            \
+    if (e_ != hipSuccess) {                                                    \
+      (ptr) = nullptr;                                                         \
+      return pvr::fail(PVR_ENOMEM, "hipMalloc of %zu bytes failed: %s", n_,    \
+                       hipGetErrorString(e_));                                 \
+    }                                                                          \
+    (plan)->device_bytes += (long long)n_;                                     \
+  } while (0)
