@@ -1,0 +1,308 @@
+#!/usr/bin/env python3
+"""Benchmark of the PVR super-resolution hot path on one MI355X.
+
+Workload (default): the 256^3 whole-uterus case -- 1 mm grid, 4 stacks of
+256x256x60 slices at 1x1x4 mm (3 orthogonal + 1 oblique at 30 deg), PSF FWHM
+(1, 1, 4) mm, 64x64 patches with stride 32 (11 760 patches, 48.2 M samples),
+per-patch motion <= 10 deg / <= 5 mm, 1 % noise, 10 % outlier patches.  All
+inputs are seeded synthetic stand-ins for the paper's fetal data.
+
+A step is one SR iteration over the whole batch: simulate (residuals), EM
+robust weights, gather back-projection, volume update, all through the C ABI
+of libpvr.so with inputs resident in HBM.  Reported value: valid patch
+samples processed per second (whole job).
+
+Extra objects on the JSON line:
+  roofline      dominant kernel: algorithmic work per launch / its average
+                event-timed duration, against the chip's peak;
+  kernels_ms    average duration of every call of the step (HIP events on
+                the library's stream);
+  cpu_baseline  the FP64 oracle timed on the host on a bounded sample;
+  full_pvr      (with --full-pvr) seconds of a whole reconstruction:
+                initial volume, then 3 cycles of [registration, 10 SR
+                iterations].
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# FP32 peak without packed-FP32 instructions (the library is built with them
+# disabled): 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz.
+FP32_VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+# Algorithmic FP32 work of one PSF nonzero (one sample-voxel pair): offset
+# along the 3 stack axes (3), scaling by 1/sigma (3), squared norm (5), the
+# exponential (1), cut-off shift (1), and the accumulation (forward: weight sum
+# 1 + weighted value 2; adjoint: two weighted sums 4).
+FLOP_PER_NNZ_FWD = 16
+FLOP_PER_NNZ_ADJ = 17
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_workload(name: str):
+    from paper_1611_07289_amd import synth
+    if name == "uterus256":
+        return [synth.full_problem()]
+    if name == "tiny32":
+        return [synth.tiny_problem()]
+    if name == "batched":
+        return synth.batched_problems()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def nnz_estimate(probs, n_valid):
+    """Expected PSF support size times the valid samples: a support is the
+    lattice points inside the ellipsoid of semi-axes k sigma, on average its
+    volume 4/3 pi k^3 prod(sigma) over the voxel volume (k = 3)."""
+    P = probs[0]
+    vox = abs(np.linalg.det(P.grid.vox2world[:, :3]))
+    sig = np.asarray(P.stacks[0].fwhm_mm) / (2 * math.sqrt(2 * math.log(2)))
+    return 4.0 / 3.0 * math.pi * 27.0 * float(np.prod(sig)) / vox * n_valid
+
+
+def cpu_baseline(P, n_patch_sample: int = 192):
+    """FP64 oracle on a bounded sample of the same workload: one SR
+    iteration restricted to n_patch_sample patches (simulate, EM, two
+    back-projections) plus the update of the full volume, extrapolated to all
+    patches.  Value in patch-samples/s."""
+    import oracle
+    from oracle import em as oem
+    from oracle import recon
+    from oracle.update import sr_update
+    from paper_1611_07289_amd import synth
+    rng = np.random.default_rng(7)
+    sel = np.sort(rng.choice(P.M, size=min(n_patch_sample, P.M), replace=False))
+    tab = P.patches.table()[sel]
+    sub = synth.Patches(*[tab[:, i].copy() for i in range(6)])
+    ctx = oracle.Ctx(P.grid, P.stacks, sub)
+    th = P.theta_true[sel]
+    X = np.asarray(P.x_true, np.float64)
+    t0 = time.perf_counter()
+    yh, _, val = ctx.simulate(X, th)
+    y = yh * 1.01
+    e = np.where(val, y - yh, 0.0)
+    p, pbar, W, pi, st, _ = recon.robust_weights(e, y, val, recon.EMState(),
+                                                 ctx.patch_of_sample, ctx.M)
+    Ws = W[ctx.patch_of_sample]
+    num = ctx.backproject(th, Ws * p * e)
+    den = ctx.backproject(th, Ws * p)
+    t_samples = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    sr_update(X, num, den)
+    t_volume = time.perf_counter() - t1
+    n_sub = int(val.sum())
+    frac = P.M / len(sel)
+    t_full = t_samples * frac + t_volume
+    n_valid_full = n_sub * frac
+    return {
+        "value": n_valid_full / t_full,
+        "unit": "patch-samples/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"one FP64 SR iteration over {len(sel)} of {P.M} patches "
+                   f"({n_sub} valid samples; simulate, EM, 2 back-projections: "
+                   f"{t_samples:.1f} s) plus the full-volume update ({t_volume:.1f} s), "
+                   f"sample part extrapolated x{frac:.1f}"),
+        "seconds_measured": t_samples + t_volume,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="uterus256")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--full-pvr", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one 1 GiB device copy (for counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design, see the documentation)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1611_07289_amd import pvr, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    probs = make_workload(args.workload)
+    log(f"[bench] workload {args.workload}: generated in {time.time() - t0:.1f} s")
+    plan = pvr.Plan.from_problems(probs)
+    log(f"[bench] plan: N={plan.N} M={plan.M} V={plan.V} problems={plan.P}")
+
+    theta = torch.from_numpy(np.concatenate([P.theta_true for P in probs]).astype(np.float32)).to(dev)
+    Xtrue = torch.from_numpy(np.concatenate([P.x_true.reshape(-1) for P in probs])).to(dev)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    plan.build(theta)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - tb
+    info = plan.info()
+    log(f"[bench] build {t_build * 1e3:.1f} ms, brick/patch pairs {info.n_bin_pairs}")
+
+    # observations: the forward model at the true motion, then noise and
+    # outlier patches drawn by the generator
+    yc = torch.empty(plan.N, dtype=torch.float32, device=dev)
+    plan.simulate(Xtrue, y_sim=yc)
+    ych = yc.cpu().numpy()
+    y_parts = []
+    for b, P in enumerate(probs):
+        a, z = plan.sample_off[plan_patch_begin(plan, probs, b)], plan.sample_off[plan_patch_begin(plan, probs, b + 1)]
+        y_parts.append(synth.corrupt(ych[a:z], P.patches, P.outlier_patch, P.noise_frac,
+                                     P.seed_base + 3, P.seed_base + 5))
+    y = torch.from_numpy(np.concatenate(y_parts)).to(dev)
+    del yc, ych
+    # valid samples (inverse normaliser > 0)
+    ones = torch.ones(plan.V, dtype=torch.float32, device=dev)
+    ysim1 = torch.empty(plan.N, dtype=torch.float32, device=dev)
+    plan.simulate(ones, y_sim=ysim1)
+    n_valid = int((ysim1 > 0.5).sum().item())
+    del ysim1, ones
+
+    e = torch.empty(plan.N, dtype=torch.float32, device=dev)
+    p = torch.empty_like(e)
+    pbar = torch.empty(plan.M, dtype=torch.float32, device=dev)
+    W = torch.empty_like(pbar)
+    num = torch.empty(plan.V, dtype=torch.float32, device=dev)
+    den = torch.empty_like(num)
+    em = plan.em_state()
+    # initial volume X0 = A^T y / A^T 1 (the update with X = 0, lambda = 0)
+    X = torch.zeros(plan.V, dtype=torch.float32, device=dev)
+    Xn = torch.empty_like(X)
+    plan.backproject(y, None, None, num, den)
+    plan.sr_update(X, num, den, Xn, pvr.SRParams.make(lam=0.0))
+    X, Xn = Xn, X
+    prm = pvr.SRParams.make()
+
+    def step(first=False, ev=None):
+        if ev is not None:
+            ev[0].record()
+        plan.simulate(X_ref[0], y_obs=y, resid=e)
+        if ev is not None:
+            ev[1].record()
+        plan.robust_weights(e, y, em, p, pbar, W, pvr.PVR_EM_INIT if first else 0)
+        if ev is not None:
+            ev[2].record()
+        plan.backproject(e, p, W, num, den)
+        if ev is not None:
+            ev[3].record()
+        plan.sr_update(X_ref[0], num, den, X_ref[1], prm)
+        if ev is not None:
+            ev[4].record()
+        X_ref.reverse()
+
+    X_ref = [X, Xn]
+    for i in range(args.warmup):
+        step(first=(i == 0))
+    torch.cuda.synchronize()
+    log(f"[bench] warmup {args.warmup} steps done")
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        step(first=(args.warmup == 0 and i == 0), ev=evs[i])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    names = ["simulate", "robust_weights", "backproject", "sr_update"]
+    per = {n: 0.0 for n in names}
+    for ev in evs:
+        for k, n in enumerate(names):
+            per[n] += ev[k].elapsed_time(ev[k + 1])
+    per = {n: v / args.steps for n, v in per.items()}
+    ms_step = elapsed * 1e3 / args.steps
+    value = n_valid * args.steps / elapsed
+    log(f"[bench] {ms_step:.3f} ms/step, {value / 1e9:.3f} G samples/s; "
+        + ", ".join(f"{n} {v:.3f} ms" for n, v in per.items()))
+
+    nnz = nnz_estimate(probs, n_valid)
+    dom = max(["simulate", "backproject"], key=lambda n: per[n])
+    fl = nnz * (FLOP_PER_NNZ_FWD if dom == "simulate" else FLOP_PER_NNZ_ADJ)
+    achieved = fl / (per[dom] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved,
+                "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": None,
+                "nnz_per_launch": nnz,
+                "flop_per_nnz": FLOP_PER_NNZ_FWD if dom == "simulate" else FLOP_PER_NNZ_ADJ}
+
+    st = pvr.Plan.read_em(em)
+    out = {
+        "metric": "SR-iteration patch-samples/s",
+        "value": value,
+        "unit": "patch-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "problems": plan.P, "patches": plan.M,
+                   "samples": plan.N, "valid_samples": n_valid, "voxels": plan.V,
+                   "patch": "64x64 stride 32" if args.workload == "uterus256" else "mixed",
+                   "psf_fwhm_mm": [1, 1, 4], "parallelism": "single GPU"},
+        "kernels_ms": per,
+        "build_ms": t_build * 1e3,
+        "roofline": roofline,
+        "em": {"sigma2": st[0].sigma2, "c": st[0].c, "excluded": st[0].n_excluded},
+    }
+
+    if args.full_pvr:
+        out["full_pvr"] = full_pvr(plan, probs, y, Xtrue, dev)
+
+    if args.copy_calibration:
+        a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = a.numel() * 4
+        del a, b
+
+    if not args.no_cpu_baseline and args.workload != "batched":
+        log("[bench] timing the FP64 oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(probs[0])
+    print(json.dumps(out), flush=True)
+
+
+def plan_patch_begin(plan, probs, b):
+    return int(sum(P.M for P in probs[:b]))
+
+
+def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10):
+    """Seconds of a whole reconstruction from the motion-corrupted start."""
+    import torch
+    from paper_1611_07289_amd import driver
+    th0 = torch.zeros(plan.M, 6, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, th, hist = driver.reconstruct(plan, y, th0, cycles=cycles, n_sr=n_sr)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    psnr = driver.psnr(X, Xtrue, plan)
+    return {"seconds": secs, "cycles": cycles, "sr_iterations": n_sr, "psnr_db": psnr,
+            "init": "plain", "timings": hist.get("timings")}
+
+
+if __name__ == "__main__":
+    main()

@@ -2,8 +2,7 @@
 // order, the contributions of the samples whose PSF support covers it, so no
 // two lanes ever write the same address and the result is bitwise repeatable.
 //
-// One workgroup = one 8x8x8 brick (512 lanes, one voxel each).  The brick's
-// list holds the patches whose support box can reach it, in patch order.  For
+// Patches are indexed per 4^3 sub-brick (one wavefront), in patch order.  For
 // a voxel and a patch, the voxel is mapped (FP64 affine G) into the patch's
 // unmoved pixel frame; the PSF is axis-aligned there, so the candidate pixels
 // are the integer (u, v) inside an ellipse around the mapped point, on the
@@ -48,61 +47,85 @@ k_bp_prep(const PatchDev *__restrict__ patches, const BlockWork *__restrict__ wo
   }
 }
 
+// Contribution of one patch to one voxel mapped to pixel coordinates
+// (pu, pv) with normalised through-plane term qk.  The candidate pixels are
+// rint(p) + [-h, h] on both axes (a superset of the integers inside the
+// in-plane support ellipse); candidates outside the support or the patch get
+// weight 0 and read a clamped, in-patch address.
+template <typename T, typename GEO, typename V2, int HU, int HV>
+__device__ __forceinline__ void adj_patch(const GEO &g, const PatchDev &pt, double pu, double pv,
+                                          T qk, int hu_rt, int hv_rt,
+                                          const V2 *__restrict__ rq, T &sn, T &sd) {
+  const int hu = HU > 0 ? HU : hu_rt, hv = HV > 0 ? HV : hv_rt;
+  const double rud = rint(pu), rvd = rint(pv);
+  const int ru = (int)rud, rv = (int)rvd;
+  const T fu = (T)(pu - rud), fv = (T)(pv - rvd);
+  const T cu = (T)g.cu, cv = (T)g.cv, K2 = (T)g.K2, cut = (T)g.cut;
+  const int x1 = pt.x0 + pt.w - 1, y1 = pt.y0 + pt.h - 1;
+  const V2 *base = rq + pt.off;
+#pragma unroll
+  for (int b = -hv; b <= hv; ++b) {
+    const int v = rv + b;
+    const T wv = ((T)b - fv) * cv;
+    const T qkv = fma(wv, wv, qk);
+    const bool vok = (v >= pt.y0) & (v <= y1);
+    const int vrow = (min(max(v, pt.y0), y1) - pt.y0) * pt.w;
+#pragma unroll
+    for (int a = -hu; a <= hu; ++a) {
+      const int u = ru + a;
+      const T wu = ((T)a - fu) * cu;
+      const T Q = fma(wu, wu, qkv);
+      const bool ok = vok & (u >= pt.x0) & (u <= x1) & (Q <= K2);
+      T gh = fast_exp2<T>(-Q) - cut;
+      gh = ok ? (gh > (T)0 ? gh : (T)0) : (T)0;
+      const V2 r = base[vrow + (min(max(u, pt.x0), x1) - pt.x0)];
+      sn = fma(gh, r.x, sn);
+      sd = fma(gh, r.y, sd);
+    }
+  }
+}
+
+// One workgroup = one 8^3 brick; each wavefront owns one 4^3 sub-brick and
+// walks that sub-brick's patch list (wave-uniform), one voxel per lane.
 template <typename T, bool DEN>
 __global__ void __launch_bounds__(BP_THREADS)
 k_backproject(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patches,
               const typename GeoOf<T>::type *__restrict__ geo, const int *__restrict__ brick_prob,
-              const int *__restrict__ bin_off, const int *__restrict__ bin_patch,
+              const int *__restrict__ sub_off, const int *__restrict__ sub_patch,
               const typename Vec2Of<T>::type *__restrict__ rq, T *__restrict__ num,
               T *__restrict__ den) {
+  using GEO = typename GeoOf<T>::type;
+  using V2 = typename Vec2Of<T>::type;
   const int bi = blockIdx.x;
   const ProbDev pr = probs[brick_prob[bi]];
   const int local = bi - pr.brick_base;
   const int bx = local % pr.nbx, by = (local / pr.nbx) % pr.nby, bz = local / (pr.nbx * pr.nby);
-  const int t = threadIdx.x;
-  const int i = bx * BRICK + (t & 7), jj = by * BRICK + ((t >> 3) & 7), kk = bz * BRICK + (t >> 6);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  const int i = bx * BRICK + (w & 1) * SUB + (l & 3);
+  const int jj = by * BRICK + ((w >> 1) & 1) * SUB + ((l >> 2) & 3);
+  const int kk = bz * BRICK + (w >> 2) * SUB + (l >> 4);
   const bool inside = i < pr.nx && jj < pr.ny && kk < pr.nz;
   T sn = 0, sd = 0;
-  const int q0 = bin_off[bi], q1 = bin_off[bi + 1];
+  const int sbi = bi * 8 + w;
+  const int q0 = sub_off[sbi], q1 = sub_off[sbi + 1];
+  const double fi = i, fj = jj, fk = kk;
+  for (int q = q0; q < q1; ++q) {
+    const int s = sub_patch[q];
+    const GEO &g = geo[s];
+    const PatchDev pt = patches[s];
+    const double pk = fma(g.G[8], fi, fma(g.G[9], fj, fma(g.G[10], fk, g.G[11])));
+    const T wk = (T)(pk - (double)pt.slice) * (T)g.ck;
+    const T qk = wk * wk;
+    if (!(qk <= (T)g.K2)) continue;
+    const double pu = fma(g.G[0], fi, fma(g.G[1], fj, fma(g.G[2], fk, g.G[3])));
+    const double pv = fma(g.G[4], fi, fma(g.G[5], fj, fma(g.G[6], fk, g.G[7])));
+    if (g.hu == 1 && g.hv == 1)
+      adj_patch<T, GEO, V2, 1, 1>(g, pt, pu, pv, qk, 1, 1, rq, sn, sd);
+    else
+      adj_patch<T, GEO, V2, 0, 0>(g, pt, pu, pv, qk, g.hu, g.hv, rq, sn, sd);
+  }
   if (inside) {
-    const double fi = i, fj = jj, fk = kk;
-    for (int q = q0; q < q1; ++q) {
-      const int s = bin_patch[q];
-      const typename GeoOf<T>::type &g = geo[s];
-      const PatchDev pt = patches[s];
-      const double pk = fma(g.G[8], fi, fma(g.G[9], fj, fma(g.G[10], fk, g.G[11])));
-      const T wk = (T)(pk - (double)pt.slice) * (T)g.ck;
-      const T qk = wk * wk;
-      const T K2 = (T)g.K2;
-      if (qk > K2) continue;
-      const double pu = fma(g.G[0], fi, fma(g.G[1], fj, fma(g.G[2], fk, g.G[3])));
-      const double pv = fma(g.G[4], fi, fma(g.G[5], fj, fma(g.G[6], fk, g.G[7])));
-      const T cu = (T)g.cu, cv = (T)g.cv, cut = (T)g.cut;
-      const T ru = sqrt(K2 - qk) * (T)g.inv_cu;
-      const int u_lo = max(pt.x0, (int)ceil(pu - (double)ru));
-      const int u_hi = min(pt.x0 + pt.w - 1, (int)floor(pu + (double)ru));
-      for (int u = u_lo; u <= u_hi; ++u) {
-        const T wu = (T)((double)u - pu) * cu;
-        const T qu = fma(wu, wu, qk);
-        const T rem = K2 - qu;
-        if (rem < (T)0) continue;
-        const T rv = sqrt(rem) * (T)g.inv_cv;
-        const int v_lo = max(pt.y0, (int)ceil(pv - (double)rv));
-        const int v_hi = min(pt.y0 + pt.h - 1, (int)floor(pv + (double)rv));
-        long long j = pt.off + (long long)(v_lo - pt.y0) * pt.w + (u - pt.x0);
-        T dv = (T)((double)v_lo - pv) * cv;
-        for (int v = v_lo; v <= v_hi; ++v) {
-          const T Q = fma(dv, dv, qu);
-          T gh = fast_exp2<T>(-Q) - cut;
-          gh = gh > (T)0 ? gh : (T)0;
-          const typename Vec2Of<T>::type r = rq[j];
-          sn = fma(gh, r.x, sn);
-          if (DEN) sd = fma(gh, r.y, sd);
-          j += pt.w;
-          dv += cv;
-        }
-      }
-    }
     const long long idx = pr.vol_off + ((long long)kk * pr.ny + jj) * pr.nx + i;
     num[idx] = sn;
     if (DEN) den[idx] = sd;
@@ -121,11 +144,11 @@ static pvr_status backproject_impl(const pvr_plan *p, const T *e, const T *pp, c
   if (den)
     hipLaunchKernelGGL((k_backproject<T, true>), dim3(p->n_bricks), dim3(BP_THREADS), 0, stream,
                        p->d_prob, p->d_patch, (const typename GeoOf<T>::type *)geo, p->d_brick_prob,
-                       p->d_bin_off, p->d_bin_patch, rq, num, den);
+                       p->d_sub_off, p->d_sub_patch, rq, num, den);
   else
     hipLaunchKernelGGL((k_backproject<T, false>), dim3(p->n_bricks), dim3(BP_THREADS), 0, stream,
                        p->d_prob, p->d_patch, (const typename GeoOf<T>::type *)geo, p->d_brick_prob,
-                       p->d_bin_off, p->d_bin_patch, rq, num, den);
+                       p->d_sub_off, p->d_sub_patch, rq, num, den);
   HIP_TRY(hipGetLastError());
   return PVR_OK;
 }

@@ -23,56 +23,65 @@ constexpr int EM_T = 256;     // per-patch workgroups
 constexpr int EMP_T = 1024;   // per-problem workgroups
 constexpr int PSTAT = 10;     // doubles per patch in the scratch table
 
-template <int NT>
-__device__ __forceinline__ double bsum(double v, double *lds) {
-  const int t = threadIdx.x;
-  lds[t] = v;
-  __syncthreads();
+// Workgroup reductions in a fixed order: a butterfly inside every wave, then
+// the wave results combined in wave order by every lane.  lds must hold
+// NT / 64 doubles per reduced value.
+enum class Op { Sum, Min, Max };
+
+template <Op OP>
+__device__ __forceinline__ double combine(double a, double b) {
+  if (OP == Op::Sum) return a + b;
+  if (OP == Op::Min) return fmin(a, b);
+  return fmax(a, b);
+}
+
+template <int NT, Op OP>
+__device__ __forceinline__ double breduce(double v, double *lds) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (t < s) lds[t] += lds[t + s];
-    __syncthreads();
-  }
-  const double r = lds[0];
+  for (int o = 32; o > 0; o >>= 1) v = combine<OP>(v, __shfl_xor(v, o, 64));
+  if (lane == 0) lds[wave] = v;
+  __syncthreads();
+  double r = lds[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) r = combine<OP>(r, lds[w]);
   __syncthreads();
   return r;
 }
 
-template <int NT>
-__device__ __forceinline__ double bmin(double v, double *lds) {
-  const int t = threadIdx.x;
-  lds[t] = v;
+// K sums at once (one pair of barriers)
+template <int NT, int K>
+__device__ __forceinline__ void bsumk(double (&v)[K], double *lds) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    double x = v[q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) lds[q * NW + wave] = x;
+  }
   __syncthreads();
 #pragma unroll
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (t < s) lds[t] = fmin(lds[t], lds[t + s]);
-    __syncthreads();
+  for (int q = 0; q < K; ++q) {
+    double r = lds[q * NW];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) r += lds[q * NW + w];
+    v[q] = r;
   }
-  const double r = lds[0];
   __syncthreads();
-  return r;
 }
 
-template <int NT>
-__device__ __forceinline__ double bmax(double v, double *lds) {
-  const int t = threadIdx.x;
-  lds[t] = v;
-  __syncthreads();
-#pragma unroll
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (t < s) lds[t] = fmax(lds[t], lds[t + s]);
-    __syncthreads();
-  }
-  const double r = lds[0];
-  __syncthreads();
-  return r;
-}
+template <int NT> __device__ __forceinline__ double bsum(double v, double *lds) { return breduce<NT, Op::Sum>(v, lds); }
+template <int NT> __device__ __forceinline__ double bmin(double v, double *lds) { return breduce<NT, Op::Min>(v, lds); }
+template <int NT> __device__ __forceinline__ double bmax(double v, double *lds) { return breduce<NT, Op::Max>(v, lds); }
 
 __global__ void __launch_bounds__(EM_T)
 k_em_patch_stats(const PatchDev *__restrict__ patches, const float *__restrict__ invz,
                  const float *__restrict__ e, const float *__restrict__ y,
                  double *__restrict__ pstat) {
-  __shared__ double lds[EM_T];
+  __shared__ double lds[8 * (EM_T / 64)];
   const int s = blockIdx.x;
   const PatchDev pt = patches[s];
   const int n = pt.w * pt.h;
@@ -90,8 +99,9 @@ k_em_patch_stats(const PatchDev *__restrict__ patches, const float *__restrict__
   mn = bmin<EM_T>(mn, lds);
   mx = bmax<EM_T>(mx, lds);
   ym = bmax<EM_T>(ym, lds);
-  se2 = bsum<EM_T>(se2, lds);
-  cnt = bsum<EM_T>(cnt, lds);
+  double red[2] = {se2, cnt};
+  bsumk<EM_T, 2>(red, lds);
+  se2 = red[0]; cnt = red[1];
   if (threadIdx.x == 0) {
     double *o = pstat + PSTAT * s;
     o[0] = mn; o[1] = mx; o[2] = ym; o[3] = se2; o[4] = cnt;
@@ -101,7 +111,7 @@ k_em_patch_stats(const PatchDev *__restrict__ patches, const float *__restrict__
 __global__ void __launch_bounds__(EMP_T)
 k_em_problem(const ProbDev *__restrict__ probs, const double *__restrict__ pstat,
              pvr_em_state *__restrict__ em, int init) {
-  __shared__ double lds[EMP_T];
+  __shared__ double lds[8 * (EMP_T / 64)];
   const ProbDev pr = probs[blockIdx.x];
   double mn = INFINITY, mx = -INFINITY, ym = 0, se2 = 0, cnt = 0;
   for (int s = pr.patch_begin + threadIdx.x; s < pr.patch_end; s += EMP_T) {
@@ -138,7 +148,7 @@ __global__ void __launch_bounds__(EM_T)
 k_em_estep(const PatchDev *__restrict__ patches, const float *__restrict__ invz,
            const float *__restrict__ e, const pvr_em_state *__restrict__ em,
            float *__restrict__ p_out, float *__restrict__ pbar, double *__restrict__ pstat) {
-  __shared__ double lds[EM_T];
+  __shared__ double lds[8 * (EM_T / 64)];
   const int s = blockIdx.x;
   const PatchDev pt = patches[s];
   const pvr_em_state st = em[pt.problem];
@@ -164,10 +174,9 @@ k_em_estep(const PatchDev *__restrict__ patches, const float *__restrict__ invz,
     }
     if (p_out) p_out[j] = pj;
   }
-  ns = bsum<EM_T>(ns, lds);
-  sp2 = bsum<EM_T>(sp2, lds);
-  sp = bsum<EM_T>(sp, lds);
-  spe2 = bsum<EM_T>(spe2, lds);
+  double red[4] = {ns, sp2, sp, spe2};
+  bsumk<EM_T, 4>(red, lds);
+  ns = red[0]; sp2 = red[1]; sp = red[2]; spe2 = red[3];
   if (threadIdx.x == 0) {
     double *o = pstat + PSTAT * s;
     o[5] = ns; o[6] = sp2; o[7] = sp; o[8] = spe2;
@@ -175,15 +184,27 @@ k_em_estep(const PatchDev *__restrict__ patches, const float *__restrict__ invz,
   }
 }
 
-__device__ __forceinline__ double log_normal(double v, double mu, double sd) {
-  const double z = (v - mu) / sd;
-  return -0.5 * z * z - log(sd) - 0.91893853320467274178;  // 0.5 log(2 pi)
+// Inlier responsibility 1 / (1 + exp(l0 - l1)) with
+// l_c = log(weight_c) - log(sd_c) - (v - mu_c)^2 / (2 sd_c^2); the constant
+// 0.5 log(2 pi) cancels.  The per-component constants are computed once per
+// mixture iteration.
+struct Mix {
+  double mu0, mu1, h0, h1, c0, c1;  // h = 1 / (2 sd^2), c = log(weight) - log(sd)
+};
+
+__device__ __forceinline__ Mix make_mix(double mu0, double sd0, double mu1, double sd1, double w1) {
+  Mix m;
+  m.mu0 = mu0; m.mu1 = mu1;
+  m.h0 = 0.5 / (sd0 * sd0); m.h1 = 0.5 / (sd1 * sd1);
+  m.c1 = w1 > 0 ? log(w1) - log(sd1) : -INFINITY;
+  m.c0 = w1 < 1 ? log(1.0 - w1) - log(sd0) : -INFINITY;
+  return m;
 }
 
-__device__ __forceinline__ double inlier_resp(double v, double mu0, double sd0, double mu1,
-                                              double sd1, double w1) {
-  const double l1 = w1 > 0 ? log(w1) + log_normal(v, mu1, sd1) : -INFINITY;
-  const double l0 = w1 < 1 ? log(1.0 - w1) + log_normal(v, mu0, sd0) : -INFINITY;
+__device__ __forceinline__ double inlier_resp(double v, const Mix &m) {
+  const double d0 = v - m.mu0, d1 = v - m.mu1;
+  const double l1 = m.c1 - d1 * d1 * m.h1;
+  const double l0 = m.c0 - d0 * d0 * m.h0;
   return 1.0 / (1.0 + exp(l0 - l1));
 }
 
@@ -197,7 +218,7 @@ k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
              const uint8_t *__restrict__ active, double *__restrict__ pstat,
              double *__restrict__ resp, float *__restrict__ patch_w, pvr_em_state *__restrict__ em,
              int fix_w) {
-  __shared__ double lds[EMP_T];
+  __shared__ double lds[8 * (EMP_T / 64)];
   __shared__ unsigned int hist[256];
   __shared__ unsigned int sel_prefix, sel_rank;
   const ProbDev pr = probs[blockIdx.x];
@@ -248,11 +269,9 @@ k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
       q_all += v * v;
       if (v < tv) { c_lt += 1; s_lt += v; q_lt += v * v; }
     }
-    c_lt = bsum<EMP_T>(c_lt, lds);
-    s_lt = bsum<EMP_T>(s_lt, lds);
-    q_lt = bsum<EMP_T>(q_lt, lds);
-    s_all = bsum<EMP_T>(s_all, lds);
-    q_all = bsum<EMP_T>(q_all, lds);
+    double red5[5] = {c_lt, s_lt, q_lt, s_all, q_all};
+    bsumk<EMP_T, 5>(red5, lds);
+    c_lt = red5[0]; s_lt = red5[1]; q_lt = red5[2]; s_all = red5[3]; q_all = red5[4];
     const double fill = n_lo - c_lt;
     const double s0 = s_lt + fill * tv, q0 = q_lt + fill * tv * tv;
     const double n_hi = nu - n_lo;
@@ -263,20 +282,20 @@ k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
     w1 = 0.9;
     for (int it = 0; it < 20; ++it) {
       double r1s = 0, r0s = 0, r1v = 0, r0v = 0;
+      const Mix mx = make_mix(mu0, sd0, mu1, sd1, w1);
       for (int s = pb + t; s < pe; s += EMP_T) {
         if (!used(s)) continue;
         const double v = pbar[s];
-        const double r1 = inlier_resp(v, mu0, sd0, mu1, sd1, w1);
+        const double r1 = inlier_resp(v, mx);
         resp[s] = r1;
         r1s += r1;
         r0s += 1.0 - r1;
         r1v += r1 * v;
         r0v += (1.0 - r1) * v;
       }
-      r1s = bsum<EMP_T>(r1s, lds);
-      r0s = bsum<EMP_T>(r0s, lds);
-      r1v = bsum<EMP_T>(r1v, lds);
-      r0v = bsum<EMP_T>(r0v, lds);
+      double red4[4] = {r1s, r0s, r1v, r0v};
+      bsumk<EMP_T, 4>(red4, lds);
+      r1s = red4[0]; r0s = red4[1]; r1v = red4[2]; r0v = red4[3];
       if (!(r1s > 0) || !(r0s > 0)) break;
       const double nmu1 = r1v / r1s, nmu0 = r0v / r0s;
       double d1 = 0, d0 = 0;
@@ -287,8 +306,9 @@ k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
         d1 += r1 * (v - nmu1) * (v - nmu1);
         d0 += (1.0 - r1) * (v - nmu0) * (v - nmu0);
       }
-      d1 = bsum<EMP_T>(d1, lds);
-      d0 = bsum<EMP_T>(d0, lds);
+      double red2[2] = {d1, d0};
+      bsumk<EMP_T, 2>(red2, lds);
+      d1 = red2[0]; d0 = red2[1];
       w1 = r1s / nu;
       mu1 = nmu1;
       mu0 = nmu0;
@@ -297,6 +317,7 @@ k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
     }
   }
   const bool swap = fit && mu0 > mu1;
+  const Mix mfin = make_mix(mu0, sd0, mu1, sd1, w1);
   // patch weights, then the M-step sums over the problem's patches
   double swpe2 = 0, swp = 0, sw = 0, nex = 0;
   for (int s = pb + t; s < pe; s += EMP_T) {
@@ -307,7 +328,7 @@ k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
     } else {
       double pi = 0;
       if (u) {
-        pi = fit ? inlier_resp((double)pbar[s], mu0, sd0, mu1, sd1, w1) : 1.0;
+        pi = fit ? inlier_resp((double)pbar[s], mfin) : 1.0;
         if (swap) pi = 1.0 - pi;
       }
       W = (u && pi >= 0.5) ? pi : 0.0;
@@ -320,10 +341,9 @@ k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
     sw += W * o[5];
     nex += (u && W == 0) ? 1.0 : 0.0;
   }
-  swpe2 = bsum<EMP_T>(swpe2, lds);
-  swp = bsum<EMP_T>(swp, lds);
-  sw = bsum<EMP_T>(sw, lds);
-  nex = bsum<EMP_T>(nex, lds);
+  double red4b[4] = {swpe2, swp, sw, nex};
+  bsumk<EMP_T, 4>(red4b, lds);
+  swpe2 = red4b[0]; swp = red4b[1]; sw = red4b[2]; nex = red4b[3];
   if (t == 0) {
     pvr_em_state &st = em[blockIdx.x];
     const double floor2 = (1e-4 * st.y_abs_max) * (1e-4 * st.y_abs_max);

@@ -45,12 +45,81 @@ k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patch
   }
 }
 
+// LDS-staged forward pass: one workgroup per 16x16 tile of a patch.  The
+// workgroup copies the voxel box of the tile's supports into LDS with row-
+// contiguous (coalesced) loads, then every lane walks its sample's support in
+// LDS.  Tiles whose box exceeds the reserved LDS walk the volume in global
+// memory instead.  Tiles are assigned so that each XCD (blocks are dealt to
+// the 8 XCDs round-robin) receives one contiguous run of the patch-major
+// tile list, keeping overlapping tiles in the same L2.
+__global__ void __launch_bounds__(SIM_THREADS)
+k_simulate_tiles(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patches,
+                 const TileWork *__restrict__ tiles, int n_tiles, int per_xcd,
+                 const GeoF *__restrict__ geo, const float *__restrict__ invz,
+                 const float *__restrict__ X, const float *__restrict__ y_obs,
+                 float *__restrict__ y_sim, float *__restrict__ resid, int lds_cap) {
+  extern __shared__ float xs[];
+  const int t = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (t >= n_tiles) return;
+  const TileWork tw = tiles[t];
+  const PatchDev pt = patches[tw.patch];
+  const ProbDev pr = probs[pt.problem];
+  const GeoF &g = geo[tw.patch];
+  const float *Xp = X + pr.vol_off;
+  int lo[3], hi[3];
+  const int cnt = tile_box(g, pr, pt, tw, lo, hi);
+  const bool staged = cnt > 0 && cnt <= lds_cap;
+  const int dx = hi[0] - lo[0] + 1, dy = hi[1] - lo[1] + 1;
+  if (staged) {
+    const int rows = dy * (hi[2] - lo[2] + 1);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int r = wave; r < rows; r += SIM_THREADS / 64) {
+      const int yy = r % dy, zz = r / dy;
+      const float *src = Xp + ((long long)(lo[2] + zz) * pr.ny + (lo[1] + yy)) * pr.nx + lo[0];
+      float *dst = xs + r * dx;
+      for (int x = lane; x < dx; x += 64) dst[x] = src[x];
+    }
+    __syncthreads();
+  }
+  const int tid = threadIdx.x;
+  if (tid >= tw.tw * tw.th) return;
+  const int lu = tw.u0 + tid % tw.tw, lv = tw.v0 + tid / tw.tw;
+  const long long j = pt.off + (long long)lv * pt.w + lu;
+  const float iz = invz[j];
+  float yh = 0.f;
+  if (iz > 0.f) {
+    int b[3];
+    float f[3];
+    sample_centre(g, pr, pt.x0 + lu, pt.y0 + lv, pt.slice, b, f);
+    float z = 0.f, acc = 0.f;
+    if (staged) {
+      const float *Xb = xs + ((b[2] - lo[2]) * dy + (b[1] - lo[1])) * dx + (b[0] - lo[0]);
+      psf_walk_s<float, GeoF, true>(g, lo, hi, b, f, Xb, dx, dx * dy, z, acc);
+    } else {
+      psf_walk<float, GeoF, true>(g, pr, b, f, Xp, z, acc);
+    }
+    yh = acc * iz;
+  }
+  if (y_sim) y_sim[j] = yh;
+  if (resid) resid[j] = iz > 0.f ? y_obs[j] - yh : 0.f;
+}
+
 template <typename T>
 static pvr_status simulate_impl(const pvr_plan *p, const T *X, const T *y_obs, T *y_sim, T *resid,
                                 const T *invz, hipStream_t stream) {
   if (!X) return fail(PVR_EINVAL, "pvr_simulate: X is NULL");
   if (resid && !y_obs) return fail(PVR_EINVAL, "pvr_simulate: resid requires y_obs");
   if (!y_sim && !resid) return PVR_OK;
+  if (sizeof(T) == 4 && p->lds_box > 0) {
+    const int per = (p->n_tiles + 7) / 8;
+    hipLaunchKernelGGL(k_simulate_tiles, dim3(8 * per), dim3(SIM_THREADS),
+                       (size_t)p->lds_box * sizeof(float), stream, p->d_prob, p->d_patch,
+                       p->d_tiles, p->n_tiles, per, p->d_geof, (const float *)invz,
+                       (const float *)X, (const float *)y_obs, (float *)y_sim, (float *)resid,
+                       p->lds_box);
+    HIP_TRY(hipGetLastError());
+    return PVR_OK;
+  }
   hipLaunchKernelGGL(k_simulate<T>, dim3(p->n_sim_blocks), dim3(SIM_THREADS), 0, stream, p->d_prob,
                      p->d_patch, p->d_sim_blocks,
                      (const typename GeoOf<T>::type *)(sizeof(T) == 4 ? (const void *)p->d_geof

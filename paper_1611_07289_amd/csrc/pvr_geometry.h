@@ -105,6 +105,7 @@ __device__ inline void make_geometry(const ProbDev &pr, const StackDev &st, cons
   const double K2 = KAPPA * k * k;
   double ext[3];
   for (int b = 0; b < 3; ++b) ext[b] = sqrt(K2 * Ai[4 * b]);
+  for (int b = 0; b < 3; ++b) { g.ext[b] = ext[b]; gf.ext[b] = (float)ext[b]; }
   int ic = 0;
   if (ext[1] > ext[ic]) ic = 1;
   if (ext[2] > ext[ic]) ic = 2;
@@ -161,6 +162,11 @@ __device__ inline void make_geometry(const ProbDev &pr, const StackDev &st, cons
   gf.K2 = (float)g.K2; gf.cut = (float)g.cut;
   gf.cu = (float)g.cu; gf.cv = (float)g.cv; gf.ck = (float)g.ck;
   g.inv_cu = 1.0 / g.cu; g.inv_cv = 1.0 / g.cv;
+  // integer pixels within the in-plane support radius R of a point p are
+  // among rint(p) + [-h, h] with h = floor(R + 1/2)
+  g.hu = (int)floor(sqrt(K2) / g.cu + 0.5);
+  g.hv = (int)floor(sqrt(K2) / g.cv + 0.5);
+  gf.hu = g.hu; gf.hv = g.hv;
   gf.inv_cu = (float)g.inv_cu; gf.inv_cv = (float)g.inv_cv;
   for (int q = 0; q < 3; ++q) gf.perm[q] = g.perm[q];
 }

@@ -26,6 +26,7 @@
 namespace pvr {
 
 constexpr int BRICK = 8;            // adjoint brick edge (voxels)
+constexpr int SUB = 4;              // sub-brick edge: one wavefront of the adjoint
 constexpr int SIM_CHUNK = 1024;     // samples per forward workgroup
 constexpr int SIM_THREADS = 256;
 constexpr double KAPPA = 0.72134752044448170368;  // log2(e) / 2
@@ -65,9 +66,10 @@ struct GeoD {
   double K2, cut;           // kappa k^2 and 2^-K2
   double cu, cv, ck;        // adjoint: sqrt(kappa) * spacing / sigma
   double inv_cu, inv_cv;
+  double ext[3];            // support half-extent along voxel axes (voxels)
   int perm[3];
   int bb_lo[3], bb_hi[3];   // brick range (inclusive); empty if lo > hi
-  int pad_;
+  int hu, hv;               // adjoint candidate half-widths (pixels)
 };
 
 // The same constants in single precision for the float kernels (G stays in
@@ -80,8 +82,9 @@ struct GeoF {
   float inv_Acc, inv_Sbb, nSab_Sbb;
   float K2, cut;
   float cu, cv, ck, inv_cu, inv_cv;
+  float ext[3];             // support half-extent along voxel axes (voxels)
   int perm[3];
-  int pad_;
+  int hu, hv;               // adjoint candidate half-widths (pixels)
 };
 
 template <typename T> struct GeoOf;
@@ -91,6 +94,14 @@ template <> struct GeoOf<double> { using type = GeoD; };
 struct BlockWork {   // one forward workgroup: a chunk of one patch
   int patch;
   int l0;            // first local sample
+};
+
+constexpr int TILE = 16;            // forward tile edge (pixels)
+constexpr int LDS_BOX_MAX = 16384;  // staged voxels per forward workgroup (64 KiB)
+
+struct TileWork {    // one forward workgroup: a rectangle of one patch
+  int patch;
+  short u0, v0, tw, th;  // patch-local origin and size (tw * th <= 256)
 };
 
 template <typename T> __device__ __forceinline__ T fast_exp2(T x);
@@ -138,18 +149,15 @@ __device__ __forceinline__ bool sample_centre(const GEO &g, const ProbDev &p,
 // the inner axis c are enumerated exactly from the quadratic form: for the
 // outer offset w_a the middle range comes from the Schur complement, for each
 // (w_a, w_b) the inner range from the 1D quadratic in w_c.
+// clo / chi: inclusive voxel bounds the walk is clipped to (the grid, or a
+// staged box inside it); Xb points at voxel b in storage with strides
+// (1, sy, sz).
 template <typename T, typename GEO, bool HAS_X>
-__device__ __forceinline__ void psf_walk(const GEO &g, const ProbDev &p,
-                                         const int b[3], const T f[3],
-                                         const T *__restrict__ X, T &z,
-                                         T &acc) {
+__device__ __forceinline__ void psf_walk_s(const GEO &g, const int clo[3], const int chi[3],
+                                           const int b[3], const T f[3], const T *Xb, int sy,
+                                           int sz, T &z, T &acc) {
   const int ia = g.perm[0], ib = g.perm[1], ic = g.perm[2];
-  const int n_a = sel3(ia, p.nx, p.ny, p.nz), n_b = sel3(ib, p.nx, p.ny, p.nz),
-            n_c = sel3(ic, p.nx, p.ny, p.nz);
-  const long long sx = 1, sy = p.nx, sz = (long long)p.nx * p.ny;
-  const long long st_a = ia == 0 ? sx : (ia == 1 ? sy : sz);
-  const long long st_b = ib == 0 ? sx : (ib == 1 ? sy : sz);
-  const long long st_c = ic == 0 ? sx : (ic == 1 ? sy : sz);
+  const int st_a = sel3(ia, 1, sy, sz), st_b = sel3(ib, 1, sy, sz), st_c = sel3(ic, 1, sy, sz);
   const int b_a = sel3(ia, b[0], b[1], b[2]), b_b = sel3(ib, b[0], b[1], b[2]),
             b_c = sel3(ic, b[0], b[1], b[2]);
   const T f_a = sel3f<T>(ia, f[0], f[1], f[2]), f_b = sel3f<T>(ib, f[0], f[1], f[2]),
@@ -158,17 +166,18 @@ __device__ __forceinline__ void psf_walk(const GEO &g, const ProbDev &p,
           Acb = (T)g.Acb, Saa = (T)g.Saa, Sab = (T)g.Sab, Sbb = (T)g.Sbb,
           iAaa = (T)g.iAinv_aa, ha = (T)g.ha, iAcc = (T)g.inv_Acc,
           iSbb = (T)g.inv_Sbb, nSab = (T)g.nSab_Sbb;
-  const long long base = (long long)b[0] + sy * b[1] + sz * b[2];
-  int lo_a = max((int)ceil(f_a - ha), -b_a);
-  int hi_a = min((int)floor(f_a + ha), n_a - 1 - b_a);
+  const int lo_a = max((int)ceil(f_a - ha), sel3(ia, clo[0], clo[1], clo[2]) - b_a);
+  const int hi_a = min((int)floor(f_a + ha), sel3(ia, chi[0], chi[1], chi[2]) - b_a);
+  const int cl_b = sel3(ib, clo[0], clo[1], clo[2]) - b_b, ch_b = sel3(ib, chi[0], chi[1], chi[2]) - b_b;
+  const int cl_c = sel3(ic, clo[0], clo[1], clo[2]) - b_c, ch_c = sel3(ic, chi[0], chi[1], chi[2]) - b_c;
   for (int oa = lo_a; oa <= hi_a; ++oa) {
     const T wa = (T)oa - f_a;
     const T rem = K2 - wa * wa * iAaa;
     if (rem < (T)0) continue;
     const T wbc = nSab * wa;
     const T rb = sqrt(rem * iSbb);
-    const int lo_b = max((int)ceil(f_b + wbc - rb), -b_b);
-    const int hi_b = min((int)floor(f_b + wbc + rb), n_b - 1 - b_b);
+    const int lo_b = max((int)ceil(f_b + wbc - rb), cl_b);
+    const int hi_b = min((int)floor(f_b + wbc + rb), ch_b);
     const T qa = Saa * wa * wa;
     const T sa2 = (T)2 * Sab * wa;
     for (int ob = lo_b; ob <= hi_b; ++ob) {
@@ -178,23 +187,61 @@ __device__ __forceinline__ void psf_walk(const GEO &g, const ProbDev &p,
       if (rem2 < (T)0) continue;
       const T wcc = -(Aca * wa + Acb * wb) * iAcc;
       const T rc = sqrt(rem2 * iAcc);
-      const int lo_c = max((int)ceil(f_c + wcc - rc), -b_c);
-      const int hi_c = min((int)floor(f_c + wcc + rc), n_c - 1 - b_c);
+      const int lo_c = max((int)ceil(f_c + wcc - rc), cl_c);
+      const int hi_c = min((int)floor(f_c + wcc + rc), ch_c);
       T d = ((T)lo_c - f_c) - wcc;
-      const T *ptr = HAS_X ? X + base + oa * st_a + ob * st_b + lo_c * st_c : nullptr;
+      int off = oa * st_a + ob * st_b + lo_c * st_c;
       for (int oc = lo_c; oc <= hi_c; ++oc) {
         const T Q = fma(Acc * d, d, q1);
         T gh = fast_exp2<T>(-Q) - cut;
         gh = gh > (T)0 ? gh : (T)0;
         z += gh;
-        if (HAS_X) {
-          acc = fma(gh, *ptr, acc);
-          ptr += st_c;
-        }
+        if (HAS_X) acc = fma(gh, Xb[off], acc);
+        off += st_c;
         d += (T)1;
       }
     }
   }
+}
+
+// Walk over the global volume of problem p (X points at the problem's voxel 0).
+template <typename T, typename GEO, bool HAS_X>
+__device__ __forceinline__ void psf_walk(const GEO &g, const ProbDev &p, const int b[3],
+                                         const T f[3], const T *__restrict__ X, T &z, T &acc) {
+  const T *Xb = HAS_X ? X + ((long long)b[2] * p.ny + b[1]) * p.nx + b[0] : nullptr;
+  const int clo[3] = {0, 0, 0}, chi[3] = {p.nx - 1, p.ny - 1, p.nz - 1};
+  psf_walk_s<T, GEO, HAS_X>(g, clo, chi, b, f, Xb, p.nx, p.nx * p.ny, z, acc);
+}
+
+// Voxel box (inclusive, clipped to the grid, padded by one voxel) that holds
+// the PSF supports of every sample of a tile: the tile's corner centres
+// bound all its centres (the pixel -> voxel map is affine), and a support
+// reaches ext voxels from its centre along each axis.  Returns the number of
+// voxels (0 if the box is empty).
+template <typename GEO>
+__device__ __forceinline__ int tile_box(const GEO &g, const ProbDev &pr, const PatchDev &pt,
+                                        const TileWork &tw, int lo[3], int hi[3]) {
+  double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double u = pt.x0 + tw.u0 + ((q & 1) ? tw.tw - 1 : 0);
+    const double v = pt.y0 + tw.v0 + ((q & 2) ? tw.th - 1 : 0);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const double x = g.H[4 * r] * u + g.H[4 * r + 1] * v + g.H[4 * r + 2] * pt.slice + g.H[4 * r + 3];
+      mn[r] = fmin(mn[r], x);
+      mx[r] = fmax(mx[r], x);
+    }
+  }
+  const int n[3] = {pr.nx, pr.ny, pr.nz};
+  int cnt = 1;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    lo[r] = max(0, (int)floor(mn[r] - (double)g.ext[r]) - 1);
+    hi[r] = min(n[r] - 1, (int)ceil(mx[r] + (double)g.ext[r]) + 1);
+    cnt *= max(0, hi[r] - lo[r] + 1);
+  }
+  return cnt;
 }
 
 // Per-thread-slot helpers for deterministic block reductions.
@@ -236,7 +283,13 @@ struct pvr_plan {
   pvr::StackDev *d_stack;
   pvr::PatchDev *d_patch;
   pvr::BlockWork *d_sim_blocks;
+  pvr::TileWork *d_tiles;
+  int n_tiles;
+  int *d_box_max;            // [1] largest tile box (voxels) of the last build
+  int lds_box;               // LDS floats reserved per forward workgroup
   int *d_brick_prob;         // [n_bricks]
+  int *d_plane_prob;         // [n_planes] problem of each z-plane, then [P] first plane
+  int n_planes, max_nx, max_ny;
   // device, per build
   double *d_theta;           // [M][6]
   pvr::GeoD *d_geod;
@@ -246,11 +299,17 @@ struct pvr_plan {
   uint8_t *d_mask;           // [N]
   uint8_t *d_active;         // [M]
   int *d_bb;                 // [M][6] brick range per patch
+  double *d_sbox;            // [M][18] voxel->pixel map and pixel support box
   int *d_bin_count;          // [n_bricks]
   int *d_bin_off;            // [n_bricks + 1]
   int *d_bin_patch;          // [capacity]
   long long bin_cap;
   long long n_pairs;
+  int *d_sub_count;          // [8 n_bricks]
+  int *d_sub_off;            // [8 n_bricks + 1]
+  int *d_sub_patch;          // [sub_cap]
+  long long sub_cap;
+  long long n_sub_pairs;
   bool built, built64;
   // scratch
   float2 *d_rq;              // [N]

@@ -28,15 +28,24 @@ __global__ void k_copy_theta(const double *__restrict__ th, double *__restrict__
 __global__ void k_geometry(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stacks,
                            const PatchDev *__restrict__ patches, const double *__restrict__ theta,
                            int M, double k, GeoD *__restrict__ gd, GeoF *__restrict__ gf,
-                           int *__restrict__ bb) {
+                           int *__restrict__ bb, double *__restrict__ sbox) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= M) return;
   const PatchDev pt = patches[s];
+  const StackDev st = stacks[pt.stack];
   GeoD g;
   GeoF f;
-  make_geometry(probs[pt.problem], stacks[pt.stack], pt, theta + 6 * s, k, g, f, bb + 6 * s);
+  make_geometry(probs[pt.problem], st, pt, theta + 6 * s, k, g, f, bb + 6 * s);
   gd[s] = g;
   gf[s] = f;
+  // voxel -> pixel map and the pixel-frame support box of the patch
+  double *o = sbox + 18 * s;
+  for (int q = 0; q < 12; ++q) o[q] = g.G[q];
+  const double ru = k * st.sigma[0] / st.spacing[0], rv = k * st.sigma[1] / st.spacing[1],
+               rk = k * st.sigma[2] / st.spacing[2];
+  o[12] = pt.x0 - ru; o[13] = pt.x0 + pt.w - 1 + ru;
+  o[14] = pt.y0 - rv; o[15] = pt.y0 + pt.h - 1 + rv;
+  o[16] = pt.slice - rk; o[17] = pt.slice + rk;
 }
 
 // Per-sample inverse normaliser 1/Z_j (0 marks an invalid sample).
@@ -69,36 +78,117 @@ k_normalisers(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ pa
 }
 
 // brick -> patch index: count, scan, fill.  Every brick scans the patches of
-// its problem in order, so each list is sorted by patch (deterministic).
+// its problem in order, so each list is sorted by patch (deterministic).  A
+// patch is listed when the brick is inside its voxel bounding box and the
+// brick's corner voxels, mapped into the patch's pixel frame, overlap the
+// patch's support box on each of the three stack axes (separating-axis
+// test; conservative).
+__device__ __forceinline__ bool box_meets_patch(const double *__restrict__ sb, const double lo[3],
+                                                const double hi[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double *g = sb + 4 * a;
+    double mn = g[3], mx = g[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double p = g[c] * lo[c], q = g[c] * hi[c];
+      mn += fmin(p, q);
+      mx += fmax(p, q);
+    }
+    if (mx < sb[12 + 2 * a] || mn > sb[13 + 2 * a]) return false;
+  }
+  return true;
+}
+
+__device__ __forceinline__ bool brick_meets_patch(const int *__restrict__ r, const double *__restrict__ sb,
+                                                  int bx, int by, int bz) {
+  if (!((bx >= r[0]) & (bx <= r[3]) & (by >= r[1]) & (by <= r[4]) & (bz >= r[2]) & (bz <= r[5])))
+    return false;
+  const double lo[3] = {(double)(bx * BRICK), (double)(by * BRICK), (double)(bz * BRICK)};
+  const double hi[3] = {lo[0] + BRICK - 1, lo[1] + BRICK - 1, lo[2] + BRICK - 1};
+  return box_meets_patch(sb, lo, hi);
+}
+
+// Second level: each brick's 8 sub-bricks (SUB^3 voxels, one wavefront of the
+// adjoint each) keep the patches of the brick's list that reach them.
+__device__ __forceinline__ void sub_box(const ProbDev &pr, int sbi, double lo[3], double hi[3]) {
+  const int bi = sbi >> 3, w = sbi & 7;
+  const int local = bi - pr.brick_base;
+  const int bx = local % pr.nbx, by = (local / pr.nbx) % pr.nby, bz = local / (pr.nbx * pr.nby);
+  lo[0] = bx * BRICK + (w & 1) * SUB;
+  lo[1] = by * BRICK + ((w >> 1) & 1) * SUB;
+  lo[2] = bz * BRICK + (w >> 2) * SUB;
+  for (int a = 0; a < 3; ++a) hi[a] = lo[a] + SUB - 1;
+}
+
+__global__ void k_sub_count(const ProbDev *__restrict__ probs, const int *__restrict__ brick_prob,
+                            const double *__restrict__ sbox, int nsb, const int *__restrict__ off,
+                            const int *__restrict__ list, int *__restrict__ count) {
+  const int sbi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sbi >= nsb) return;
+  const ProbDev pr = probs[brick_prob[sbi >> 3]];
+  double lo[3], hi[3];
+  sub_box(pr, sbi, lo, hi);
+  int c = 0;
+  for (int q = off[sbi >> 3]; q < off[(sbi >> 3) + 1]; ++q)
+    c += box_meets_patch(sbox + 18 * list[q], lo, hi) ? 1 : 0;
+  count[sbi] = c;
+}
+
+__global__ void k_sub_fill(const ProbDev *__restrict__ probs, const int *__restrict__ brick_prob,
+                           const double *__restrict__ sbox, int nsb, const int *__restrict__ off,
+                           const int *__restrict__ list, const int *__restrict__ soff,
+                           int *__restrict__ slist) {
+  const int sbi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sbi >= nsb) return;
+  const ProbDev pr = probs[brick_prob[sbi >> 3]];
+  double lo[3], hi[3];
+  sub_box(pr, sbi, lo, hi);
+  int c = soff[sbi];
+  for (int q = off[sbi >> 3]; q < off[(sbi >> 3) + 1]; ++q) {
+    const int s = list[q];
+    if (box_meets_patch(sbox + 18 * s, lo, hi)) slist[c++] = s;
+  }
+}
+
 __global__ void k_bin_count(const ProbDev *__restrict__ probs, const int *__restrict__ brick_prob,
-                            const int *__restrict__ bb, int nb, int *__restrict__ count) {
+                            const int *__restrict__ bb, const double *__restrict__ sbox, int nb,
+                            int *__restrict__ count) {
   int bi = blockIdx.x * blockDim.x + threadIdx.x;
   if (bi >= nb) return;
   const ProbDev pr = probs[brick_prob[bi]];
   const int local = bi - pr.brick_base;
   const int bx = local % pr.nbx, by = (local / pr.nbx) % pr.nby, bz = local / (pr.nbx * pr.nby);
   int c = 0;
-  for (int s = pr.patch_begin; s < pr.patch_end; ++s) {
-    const int *r = bb + 6 * s;
-    c += (bx >= r[0]) & (bx <= r[3]) & (by >= r[1]) & (by <= r[4]) & (bz >= r[2]) & (bz <= r[5]);
-  }
+  for (int s = pr.patch_begin; s < pr.patch_end; ++s)
+    c += brick_meets_patch(bb + 6 * s, sbox + 18 * s, bx, by, bz) ? 1 : 0;
   count[bi] = c;
 }
 
 __global__ void k_bin_fill(const ProbDev *__restrict__ probs, const int *__restrict__ brick_prob,
-                           const int *__restrict__ bb, int nb, const int *__restrict__ off,
-                           int *__restrict__ list) {
+                           const int *__restrict__ bb, const double *__restrict__ sbox, int nb,
+                           const int *__restrict__ off, int *__restrict__ list) {
   int bi = blockIdx.x * blockDim.x + threadIdx.x;
   if (bi >= nb) return;
   const ProbDev pr = probs[brick_prob[bi]];
   const int local = bi - pr.brick_base;
   const int bx = local % pr.nbx, by = (local / pr.nbx) % pr.nby, bz = local / (pr.nbx * pr.nby);
   int c = off[bi];
-  for (int s = pr.patch_begin; s < pr.patch_end; ++s) {
-    const int *r = bb + 6 * s;
-    if ((bx >= r[0]) & (bx <= r[3]) & (by >= r[1]) & (by <= r[4]) & (bz >= r[2]) & (bz <= r[5]))
-      list[c++] = s;
-  }
+  for (int s = pr.patch_begin; s < pr.patch_end; ++s)
+    if (brick_meets_patch(bb + 6 * s, sbox + 18 * s, bx, by, bz)) list[c++] = s;
+}
+
+// Largest voxel box over the forward tiles (sizes the staged LDS).
+__global__ void k_tile_boxmax(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patches,
+                              const TileWork *__restrict__ tiles, int n_tiles,
+                              const GeoF *__restrict__ geo, int *__restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  const TileWork tw = tiles[t];
+  const PatchDev pt = patches[tw.patch];
+  int lo[3], hi[3];
+  const int c = tile_box(geo[tw.patch], probs[pt.problem], pt, tw, lo, hi);
+  atomicMax(out, c);
 }
 
 // Exclusive scan of count[0..n) into off[0..n], off[n] = total, by one
@@ -210,6 +300,7 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
   long long so = 0;
   int prev_prob = 0;
   std::vector<BlockWork> blocks;
+  std::vector<TileWork> tiles;
   std::vector<int> pcount(n_problems, 0);
   std::vector<long long> scount(n_problems, 0);
   for (int s = 0; s < n_patches; ++s) {
@@ -228,6 +319,13 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
     p->h_sample_off[s] = so;
     const int n = q.w * q.h;
     for (int l0 = 0; l0 < n; l0 += SIM_CHUNK) blocks.push_back(BlockWork{s, l0});
+    {
+      const int tw = std::min(q.w, TILE), th = std::min(q.h, std::max(1, 256 / tw));
+      for (int v0 = 0; v0 < q.h; v0 += th)
+        for (int u0 = 0; u0 < q.w; u0 += tw)
+          tiles.push_back(TileWork{s, (short)u0, (short)v0, (short)std::min(tw, q.w - u0),
+                                   (short)std::min(th, q.h - v0)});
+    }
     so += n;
     pcount[prob] += 1;
     scount[prob] += n;
@@ -246,6 +344,21 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
   p->N = so;
   if (so > 0x7fffffffLL * 4) return fail(PVR_ESHAPE, "pvr_plan_create: too many samples");
   p->n_sim_blocks = (int)blocks.size();
+  p->n_tiles = (int)tiles.size();
+  for (int s = 0; s < n_patches; ++s)
+    if (patches[s].w > 32767 || patches[s].h > 32767) return fail(PVR_ESHAPE, "pvr_plan_create: patch %d too large", s);
+  std::vector<int> plane_prob;
+  std::vector<int> plane_first(n_problems);
+  p->max_nx = p->max_ny = 0;
+  for (int b = 0; b < n_problems; ++b) {
+    plane_first[b] = (int)plane_prob.size();
+    for (int z = 0; z < p->h_prob[b].nz; ++z) plane_prob.push_back(b);
+    p->max_nx = std::max(p->max_nx, p->h_prob[b].nx);
+    p->max_ny = std::max(p->max_ny, p->h_prob[b].ny);
+  }
+  p->n_planes = (int)plane_prob.size();
+  if (p->n_planes > 65535) return fail(PVR_ESHAPE, "pvr_plan_create: more than 65535 z-planes in total");
+  plane_prob.insert(plane_prob.end(), plane_first.begin(), plane_first.end());
   std::vector<int> brick_prob(nbr);
   for (int b = 0; b < n_problems; ++b)
     for (int i = 0; i < p->h_prob[b].n_bricks; ++i) brick_prob[p->h_prob[b].brick_base + i] = b;
@@ -255,16 +368,22 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
   DEV_ALLOC(p, p->d_stack, n_stacks);
   DEV_ALLOC(p, p->d_patch, n_patches);
   DEV_ALLOC(p, p->d_sim_blocks, p->n_sim_blocks);
+  DEV_ALLOC(p, p->d_tiles, p->n_tiles);
+  DEV_ALLOC(p, p->d_box_max, 4);
   DEV_ALLOC(p, p->d_brick_prob, nbr);
+  DEV_ALLOC(p, p->d_plane_prob, plane_prob.size());
   DEV_ALLOC(p, p->d_theta, 6 * (size_t)n_patches);
   DEV_ALLOC(p, p->d_geod, n_patches);
   DEV_ALLOC(p, p->d_geof, n_patches);
   DEV_ALLOC(p, p->d_bb, 6 * (size_t)n_patches);
+  DEV_ALLOC(p, p->d_sbox, 18 * (size_t)n_patches);
   DEV_ALLOC(p, p->d_invz, p->N);
   DEV_ALLOC(p, p->d_mask, p->N);
   DEV_ALLOC(p, p->d_active, n_patches);
   DEV_ALLOC(p, p->d_bin_count, nbr);
   DEV_ALLOC(p, p->d_bin_off, nbr + 1);
+  DEV_ALLOC(p, p->d_sub_count, 8 * (size_t)nbr);
+  DEV_ALLOC(p, p->d_sub_off, 8 * (size_t)nbr + 1);
   DEV_ALLOC(p, p->d_rq, p->N);
   DEV_ALLOC(p, p->d_pstat, 10 * (size_t)n_patches);
   DEV_ALLOC(p, p->d_resp, n_patches);
@@ -275,7 +394,10 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
   HIP_TRY(hipMemcpy(p->d_stack, p->h_stack, sizeof(StackDev) * n_stacks, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(p->d_patch, p->h_patch, sizeof(PatchDev) * n_patches, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(p->d_sim_blocks, blocks.data(), sizeof(BlockWork) * blocks.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p->d_tiles, tiles.data(), sizeof(TileWork) * tiles.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(p->d_brick_prob, brick_prob.data(), sizeof(int) * nbr, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p->d_plane_prob, plane_prob.data(), sizeof(int) * plane_prob.size(),
+                    hipMemcpyHostToDevice));
   HIP_TRY(hipDeviceSynchronize());
   guard.release();
   *out = p;
@@ -297,7 +419,7 @@ extern "C" pvr_status pvr_plan_info(const pvr_plan *p, pvr_plan_sizes *out) {
   out->n_problems = p->P;
   out->n_stacks = p->S;
   out->n_bricks = p->n_bricks;
-  out->n_bin_pairs = p->n_pairs;
+  out->n_bin_pairs = p->n_sub_pairs;
   out->device_bytes = p->device_bytes;
   return PVR_OK;
   PVR_API_END();
@@ -329,7 +451,7 @@ static pvr_status plan_build_common(pvr_plan *p, const uint8_t *active, const ui
     launch_fill_u8(p->d_mask, 1, p->N, stream);
   }
   hipLaunchKernelGGL(k_geometry, dim3((M + T - 1) / T), dim3(T), 0, stream, p->d_prob, p->d_stack,
-                     p->d_patch, p->d_theta, M, p->k, p->d_geod, p->d_geof, p->d_bb);
+                     p->d_patch, p->d_theta, M, p->k, p->d_geod, p->d_geof, p->d_bb, p->d_sbox);
   HIP_TRY(hipGetLastError());
   if (f64) {
     if (!p->d_invz64) DEV_ALLOC(p, p->d_invz64, p->N);
@@ -344,14 +466,24 @@ static pvr_status plan_build_common(pvr_plan *p, const uint8_t *active, const ui
   HIP_TRY(hipGetLastError());
   const int nb = p->n_bricks;
   hipLaunchKernelGGL(k_bin_count, dim3((nb + T - 1) / T), dim3(T), 0, stream, p->d_prob,
-                     p->d_brick_prob, p->d_bb, nb, p->d_bin_count);
+                     p->d_brick_prob, p->d_bb, p->d_sbox, nb, p->d_bin_count);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, stream, p->d_bin_count, nb, p->d_bin_off,
                      p->d_total);
   HIP_TRY(hipGetLastError());
+  launch_fill_i32(p->d_box_max, 0, 1, stream);
+  hipLaunchKernelGGL(k_tile_boxmax, dim3((p->n_tiles + T - 1) / T), dim3(T), 0, stream, p->d_prob,
+                     p->d_patch, p->d_tiles, p->n_tiles, p->d_geof, p->d_box_max);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(p->h_total + 1, p->d_box_max, sizeof(int), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipMemcpyAsync(p->h_total, p->d_total, sizeof(int), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
   const long long pairs = p->h_total[0];
+  {
+    // LDS per forward workgroup: the largest tile box, capped at 64 KiB
+    const int want = p->h_total[1];
+    p->lds_box = std::min(want, LDS_BOX_MAX);
+  }
   if (pairs >= 0x7fffffffLL) return fail(PVR_ESHAPE, "pvr_plan_build: brick index exceeds 2^31 pairs");
   if (pairs > p->bin_cap) {
     if (p->d_bin_patch) { HIP_TRY(hipFree(p->d_bin_patch)); p->device_bytes -= p->bin_cap * 4; }
@@ -362,7 +494,30 @@ static pvr_status plan_build_common(pvr_plan *p, const uint8_t *active, const ui
   }
   p->n_pairs = pairs;
   hipLaunchKernelGGL(k_bin_fill, dim3((nb + T - 1) / T), dim3(T), 0, stream, p->d_prob,
-                     p->d_brick_prob, p->d_bb, nb, p->d_bin_off, p->d_bin_patch);
+                     p->d_brick_prob, p->d_bb, p->d_sbox, nb, p->d_bin_off, p->d_bin_patch);
+  HIP_TRY(hipGetLastError());
+  const int nsb = nb * 8;
+  hipLaunchKernelGGL(k_sub_count, dim3((nsb + T - 1) / T), dim3(T), 0, stream, p->d_prob,
+                     p->d_brick_prob, p->d_sbox, nsb, p->d_bin_off, p->d_bin_patch, p->d_sub_count);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, stream, p->d_sub_count, nsb, p->d_sub_off,
+                     p->d_total);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(p->h_total, p->d_total, sizeof(int), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  const long long spairs = p->h_total[0];
+  if (spairs >= 0x7fffffffLL) return fail(PVR_ESHAPE, "pvr_plan_build: sub-brick index exceeds 2^31 pairs");
+  if (spairs > p->sub_cap) {
+    if (p->d_sub_patch) { HIP_TRY(hipFree(p->d_sub_patch)); p->device_bytes -= p->sub_cap * 4; }
+    p->d_sub_patch = nullptr;
+    long long cap = spairs + spairs / 8 + 1024;
+    DEV_ALLOC(p, p->d_sub_patch, cap);
+    p->sub_cap = cap;
+  }
+  p->n_sub_pairs = spairs;
+  hipLaunchKernelGGL(k_sub_fill, dim3((nsb + T - 1) / T), dim3(T), 0, stream, p->d_prob,
+                     p->d_brick_prob, p->d_sbox, nsb, p->d_bin_off, p->d_bin_patch, p->d_sub_off,
+                     p->d_sub_patch);
   HIP_TRY(hipGetLastError());
   p->built = true;
   p->built64 = f64;

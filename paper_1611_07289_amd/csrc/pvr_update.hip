@@ -7,22 +7,20 @@
 
 using namespace pvr;
 
+// One workgroup = a 64 x 4 tile of one z-plane of one problem (grid
+// x = tiles over x, y = tiles over y, z = planes of all problems stacked).
 __global__ void __launch_bounds__(256)
-k_sr_update(const ProbDev *__restrict__ probs, int P, long long V, const float *__restrict__ X,
-            const float *__restrict__ num, const float *__restrict__ den, pvr_sr_params prm,
-            float *__restrict__ Xo) {
-  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= V) return;
-  int lo = 0, hi = P - 1;  // problem holding gid
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (probs[mid].vol_off <= gid) lo = mid; else hi = mid - 1;
-  }
-  const ProbDev pr = probs[lo];
-  const long long loc = gid - pr.vol_off;
-  const int i = (int)(loc % pr.nx);
-  const int j = (int)((loc / pr.nx) % pr.ny);
-  const int k = (int)(loc / ((long long)pr.nx * pr.ny));
+k_sr_update(const ProbDev *__restrict__ probs, const int *__restrict__ plane_prob,
+            const float *__restrict__ X, const float *__restrict__ num,
+            const float *__restrict__ den, pvr_sr_params prm, float *__restrict__ Xo) {
+  const int zg = blockIdx.z;
+  const ProbDev pr = probs[plane_prob[zg]];
+  const int k = zg - plane_prob[gridDim.z + plane_prob[zg]];
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (i >= pr.nx || j >= pr.ny) return;
+  const int sy = pr.nx, sz = pr.nx * pr.ny;
+  const long long gid = pr.vol_off + (long long)k * sz + (long long)j * sy + i;
   const float x = X[gid];
   const float dn = den[gid];
   const float step = dn > prm.den_eps ? num[gid] / dn : 0.f;
@@ -30,7 +28,6 @@ k_sr_update(const ProbDev *__restrict__ probs, int P, long long V, const float *
   if (prm.lambda != 0.f) {
     const float inv_delta = 1.f / prm.delta;
     const float bw[4] = {0.f, 1.f, 0.70710678118654752f, 0.57735026918962576f};
-    const long long sy = pr.nx, sz = (long long)pr.nx * pr.ny;
 #pragma unroll
     for (int dz = -1; dz <= 1; ++dz) {
 #pragma unroll
@@ -61,10 +58,8 @@ extern "C" pvr_status pvr_sr_update(const pvr_plan *p, const float *X, const flo
   if (!p || !X || !num || !den || !prm || !X_out) return fail(PVR_EINVAL, "pvr_sr_update: NULL argument");
   if (X_out == X) return fail(PVR_EINVAL, "pvr_sr_update: X_out must not alias X");
   if (!(prm->delta > 0)) return fail(PVR_EINVAL, "pvr_sr_update: delta must be > 0");
-  const long long V = p->V;
-  const long long blocks = (V + 255) / 256;
-  hipLaunchKernelGGL(k_sr_update, dim3((unsigned)blocks), dim3(256), 0, stream, p->d_prob, p->P, V,
-                     X, num, den, *prm, X_out);
+  hipLaunchKernelGGL(k_sr_update, dim3((p->max_nx + 63) / 64, (p->max_ny + 3) / 4, p->n_planes),
+                     dim3(256), 0, stream, p->d_prob, p->d_plane_prob, X, num, den, *prm, X_out);
   HIP_TRY(hipGetLastError());
   return PVR_OK;
   PVR_API_END();

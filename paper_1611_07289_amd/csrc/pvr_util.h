@@ -15,6 +15,7 @@ pvr_status fail(pvr_status st, const char *fmt, ...) __attribute__((format(print
 void clear_error();
 void plan_free(pvr_plan *p);
 void launch_fill_u8(uint8_t *dst, uint8_t v, long long n, hipStream_t stream);
+void launch_fill_i32(int *dst, int v, long long n, hipStream_t stream);
 void launch_fill_f32(float *dst, float v, long long n, hipStream_t stream);
 void launch_fill_f64(double *dst, double v, long long n, hipStream_t stream);
 

@@ -36,15 +36,16 @@ static void fill(T *dst, T v, long long n, hipStream_t stream) {
 }
 
 void launch_fill_u8(uint8_t *dst, uint8_t v, long long n, hipStream_t s) { fill<uint8_t>(dst, v, n, s); }
+void launch_fill_i32(int *dst, int v, long long n, hipStream_t s) { fill<int>(dst, v, n, s); }
 void launch_fill_f32(float *dst, float v, long long n, hipStream_t s) { fill<float>(dst, v, n, s); }
 void launch_fill_f64(double *dst, double v, long long n, hipStream_t s) { fill<double>(dst, v, n, s); }
 
 void plan_free(pvr_plan *p) {
   if (!p) return;
   if (p->d_prob) (void)hipDeviceSynchronize();
-  void *dev[] = {p->d_prob, p->d_stack, p->d_patch, p->d_sim_blocks, p->d_brick_prob,
-                 p->d_theta, p->d_geod, p->d_geof, p->d_bb, p->d_invz, p->d_invz64,
-                 p->d_mask, p->d_active, p->d_bin_count, p->d_bin_off, p->d_bin_patch,
+  void *dev[] = {p->d_prob, p->d_stack, p->d_patch, p->d_sim_blocks, p->d_tiles, p->d_box_max, p->d_brick_prob, p->d_plane_prob,
+                 p->d_theta, p->d_geod, p->d_geof, p->d_bb, p->d_sbox, p->d_invz, p->d_invz64,
+                 p->d_mask, p->d_active, p->d_bin_count, p->d_bin_off, p->d_bin_patch, p->d_sub_count, p->d_sub_off, p->d_sub_patch,
                  p->d_rq, p->d_rq64, p->d_pstat, p->d_resp, p->d_pbar, p->d_total};
   for (void *q : dev)
     if (q) (void)hipFree(q);
