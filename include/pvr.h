@@ -182,12 +182,21 @@ pvr_status pvr_plan_offsets(const pvr_plan *plan, int64_t *sample_off,
  * [M][6]): per-patch geometry, per-sample inverse PSF normalisers (0 marks an
  * invalid sample) and the brick -> patch index of the adjoint.  active
  * ([M], nullable = all) and sample_mask ([N], nullable = all) are read here.
- * Synchronises `stream` once (to size the index). */
+ * Synchronises `stream` once.  The adjoint's brick index is rebuilt lazily by
+ * the first pvr_backproject after a build (synchronising `stream` twice), so
+ * loops that only simulate (registration) do not pay for it. */
 pvr_status pvr_plan_build(pvr_plan *plan, const float *theta,
                           const uint8_t *active, const uint8_t *sample_mask,
                           hipStream_t stream);
 pvr_status pvr_plan_build_f64(pvr_plan *plan, const double *theta,
                               const uint8_t *active, const uint8_t *sample_mask,
+                              hipStream_t stream);
+
+/* Forward tile shape: the simulation splits every patch into tile_w x tile_h
+ * pixel rectangles, one workgroup each, and stages each tile's voxel box in
+ * LDS (default 16 x 16; tile_w * tile_h <= 256).  Used by the autotuner.
+ * Synchronises `stream`. */
+pvr_status pvr_plan_set_tiles(pvr_plan *plan, int32_t tile_w, int32_t tile_h,
                               hipStream_t stream);
 
 /* (device) inverse normalisers 1/Z_j of the last build, [N] float
@@ -260,6 +269,33 @@ pvr_status pvr_register_patches(const pvr_plan *plan, const float *X,
                                 const uint8_t *reg,
                                 const pvr_reg_params *params,
                                 hipStream_t stream);
+
+/* Derivative of the forward model with respect to the per-patch motion
+ * (differentiable simulation; the derivative of the PSF weights of
+ * eq. (1)'s W_i = D B T_i through T_i):
+ *   grad_theta[s][k] = sum_{j in s} grad_y[j] * d y_sim_j / d theta_s[k]
+ * at the theta of the last build (radians and mm), with the normalisers
+ * Z_j differentiated too.  The derivative with respect to X is the adjoint:
+ * pvr_backproject(grad_y, NULL, NULL, grad_X, NULL).  X [V], grad_y [N],
+ * grad_theta [M][6] out. */
+pvr_status pvr_simulate_grad_theta(const pvr_plan *plan, const float *X,
+                                   const float *grad_y, float *grad_theta,
+                                   hipStream_t stream);
+pvr_status pvr_simulate_grad_theta_f64(const pvr_plan *plan, const double *X,
+                                       const double *grad_y,
+                                       double *grad_theta, hipStream_t stream);
+
+/* Cross-correlation of every patch with its simulation (Sec. IV-A eq. CC,
+ * population statistics over the samples valid at the last build) and its
+ * derivative with respect to the simulated samples:
+ *   d NCC_s / d y_sim_j = ((y_j - mu_y)/(sd_y sd_sim)
+ *                          - NCC_s (y_sim_j - mu_sim)/sd_sim^2) / n_s.
+ * Chained through pvr_simulate_grad_theta it gives d NCC_s / d theta_s for
+ * gradient-based registration.  y_obs, y_sim [N]; grad_y [N] out (nullable);
+ * ncc [M] out (nullable).  Flat patches give 0. */
+pvr_status pvr_ncc_grad(const pvr_plan *plan, const float *y_obs,
+                        const float *y_sim, float *grad_y, float *ncc,
+                        hipStream_t stream);
 
 #ifdef __cplusplus
 }

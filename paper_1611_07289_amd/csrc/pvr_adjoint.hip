@@ -137,6 +137,10 @@ static pvr_status backproject_impl(const pvr_plan *p, const T *e, const T *pp, c
                                    T *num, T *den, const T *invz, typename Vec2Of<T>::type *rq,
                                    hipStream_t stream) {
   if (!e || !num) return fail(PVR_EINVAL, "pvr_backproject: e and num are required");
+  if (!p->index_valid) {
+    const pvr_status st = plan_build_index(const_cast<pvr_plan *>(p), stream);
+    if (st != PVR_OK) return st;
+  }
   hipLaunchKernelGGL(k_bp_prep<T>, dim3(p->n_sim_blocks), dim3(SIM_THREADS), 0, stream, p->d_patch,
                      p->d_sim_blocks, invz, e, pp, patch_w, rq);
   HIP_TRY(hipGetLastError());

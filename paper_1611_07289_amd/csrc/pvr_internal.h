@@ -284,7 +284,7 @@ struct pvr_plan {
   pvr::PatchDev *d_patch;
   pvr::BlockWork *d_sim_blocks;
   pvr::TileWork *d_tiles;
-  int n_tiles;
+  int n_tiles, tile_cap, tile_w, tile_h;
   int *d_box_max;            // [1] largest tile box (voxels) of the last build
   int lds_box;               // LDS floats reserved per forward workgroup
   int *d_brick_prob;         // [n_bricks]
@@ -310,7 +310,7 @@ struct pvr_plan {
   int *d_sub_patch;          // [sub_cap]
   long long sub_cap;
   long long n_sub_pairs;
-  bool built, built64;
+  bool built, built64, index_valid;
   // scratch
   float2 *d_rq;              // [N]
   double2 *d_rq64;           // [N] (lazy)

@@ -15,6 +15,8 @@
 
 using namespace pvr;
 
+static void make_tiles(const pvr_plan *p, std::vector<TileWork> &tiles);
+
 __global__ void k_theta_to_f64(const float *__restrict__ th, double *__restrict__ out, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = (double)th[i];
@@ -319,13 +321,6 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
     p->h_sample_off[s] = so;
     const int n = q.w * q.h;
     for (int l0 = 0; l0 < n; l0 += SIM_CHUNK) blocks.push_back(BlockWork{s, l0});
-    {
-      const int tw = std::min(q.w, TILE), th = std::min(q.h, std::max(1, 256 / tw));
-      for (int v0 = 0; v0 < q.h; v0 += th)
-        for (int u0 = 0; u0 < q.w; u0 += tw)
-          tiles.push_back(TileWork{s, (short)u0, (short)v0, (short)std::min(tw, q.w - u0),
-                                   (short)std::min(th, q.h - v0)});
-    }
     so += n;
     pcount[prob] += 1;
     scount[prob] += n;
@@ -344,9 +339,12 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
   p->N = so;
   if (so > 0x7fffffffLL * 4) return fail(PVR_ESHAPE, "pvr_plan_create: too many samples");
   p->n_sim_blocks = (int)blocks.size();
-  p->n_tiles = (int)tiles.size();
   for (int s = 0; s < n_patches; ++s)
     if (patches[s].w > 32767 || patches[s].h > 32767) return fail(PVR_ESHAPE, "pvr_plan_create: patch %d too large", s);
+  p->tile_w = TILE;
+  p->tile_h = TILE;
+  make_tiles(p, tiles);
+  p->n_tiles = (int)tiles.size();
   std::vector<int> plane_prob;
   std::vector<int> plane_first(n_problems);
   p->max_nx = p->max_ny = 0;
@@ -369,6 +367,7 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
   DEV_ALLOC(p, p->d_patch, n_patches);
   DEV_ALLOC(p, p->d_sim_blocks, p->n_sim_blocks);
   DEV_ALLOC(p, p->d_tiles, p->n_tiles);
+  p->tile_cap = p->n_tiles;
   DEV_ALLOC(p, p->d_box_max, 4);
   DEV_ALLOC(p, p->d_brick_prob, nbr);
   DEV_ALLOC(p, p->d_plane_prob, plane_prob.size());
@@ -436,34 +435,61 @@ extern "C" pvr_status pvr_plan_offsets(const pvr_plan *p, int64_t *sample_off, i
 
 extern "C" const float *pvr_plan_inv_z(const pvr_plan *p) { return p ? p->d_invz : nullptr; }
 
-static pvr_status plan_build_common(pvr_plan *p, const uint8_t *active, const uint8_t *mask,
-                                    bool f64, hipStream_t stream) {
-  const int M = p->M;
+// Forward tiles: every patch cut into tile_w x tile_h rectangles (edge tiles
+// smaller), patch-major.
+static void make_tiles(const pvr_plan *p, std::vector<TileWork> &tiles) {
+  tiles.clear();
+  for (int s = 0; s < p->M; ++s) {
+    const PatchDev &q = p->h_patch[s];
+    const int tw = std::min(q.w, p->tile_w), th = std::min(q.h, p->tile_h);
+    for (int v0 = 0; v0 < q.h; v0 += th)
+      for (int u0 = 0; u0 < q.w; u0 += tw)
+        tiles.push_back(TileWork{s, (short)u0, (short)v0, (short)std::min(tw, q.w - u0),
+                                 (short)std::min(th, q.h - v0)});
+  }
+}
+
+static pvr_status update_lds_box(pvr_plan *p, hipStream_t stream) {
   const int T = 256;
-  if (active) {
-    HIP_TRY(hipMemcpyAsync(p->d_active, active, M, hipMemcpyDeviceToDevice, stream));
-  } else {
-    launch_fill_u8(p->d_active, 1, M, stream);
-  }
-  if (mask) {
-    HIP_TRY(hipMemcpyAsync(p->d_mask, mask, p->N, hipMemcpyDeviceToDevice, stream));
-  } else {
-    launch_fill_u8(p->d_mask, 1, p->N, stream);
-  }
-  hipLaunchKernelGGL(k_geometry, dim3((M + T - 1) / T), dim3(T), 0, stream, p->d_prob, p->d_stack,
-                     p->d_patch, p->d_theta, M, p->k, p->d_geod, p->d_geof, p->d_bb, p->d_sbox);
+  launch_fill_i32(p->d_box_max, 0, 1, stream);
+  hipLaunchKernelGGL(k_tile_boxmax, dim3((p->n_tiles + T - 1) / T), dim3(T), 0, stream, p->d_prob,
+                     p->d_patch, p->d_tiles, p->n_tiles, p->d_geof, p->d_box_max);
   HIP_TRY(hipGetLastError());
-  if (f64) {
-    if (!p->d_invz64) DEV_ALLOC(p, p->d_invz64, p->N);
-    hipLaunchKernelGGL(k_normalisers<double>, dim3(p->n_sim_blocks), dim3(SIM_THREADS), 0, stream,
-                       p->d_prob, p->d_patch, p->d_sim_blocks, p->d_geod, p->d_mask, p->d_active,
-                       p->d_invz, p->d_invz64);
-  } else {
-    hipLaunchKernelGGL(k_normalisers<float>, dim3(p->n_sim_blocks), dim3(SIM_THREADS), 0, stream,
-                       p->d_prob, p->d_patch, p->d_sim_blocks, p->d_geof, p->d_mask, p->d_active,
-                       p->d_invz, (double *)nullptr);
+  HIP_TRY(hipMemcpyAsync(p->h_total + 1, p->d_box_max, sizeof(int), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  p->lds_box = std::min(p->h_total[1], LDS_BOX_MAX);
+  return PVR_OK;
+}
+
+extern "C" pvr_status pvr_plan_set_tiles(pvr_plan *p, int32_t tile_w, int32_t tile_h,
+                                         hipStream_t stream) {
+  PVR_API_BEGIN();
+  if (!p) return fail(PVR_EINVAL, "pvr_plan_set_tiles: plan is NULL");
+  if (tile_w <= 0 || tile_h <= 0 || tile_w * tile_h > 256)
+    return fail(PVR_EINVAL, "pvr_plan_set_tiles: need 0 < tile_w * tile_h <= 256");
+  HIP_TRY(hipStreamSynchronize(stream));
+  p->tile_w = tile_w;
+  p->tile_h = tile_h;
+  std::vector<TileWork> tiles;
+  make_tiles(p, tiles);
+  if ((int)tiles.size() > p->tile_cap) {
+    HIP_TRY(hipFree(p->d_tiles));
+    p->d_tiles = nullptr;
+    DEV_ALLOC(p, p->d_tiles, tiles.size());
+    p->tile_cap = (int)tiles.size();
   }
-  HIP_TRY(hipGetLastError());
+  p->n_tiles = (int)tiles.size();
+  HIP_TRY(hipMemcpy(p->d_tiles, tiles.data(), sizeof(TileWork) * tiles.size(), hipMemcpyHostToDevice));
+  if (p->built) return update_lds_box(p, stream);
+  return PVR_OK;
+  PVR_API_END();
+}
+
+// brick -> patch and sub-brick -> patch lists of the gather adjoint for the
+// geometry of the last build (synchronises the stream once per level to size
+// the lists).
+pvr_status pvr::plan_build_index(pvr_plan *p, hipStream_t stream) {
+  const int T = 256;
   const int nb = p->n_bricks;
   hipLaunchKernelGGL(k_bin_count, dim3((nb + T - 1) / T), dim3(T), 0, stream, p->d_prob,
                      p->d_brick_prob, p->d_bb, p->d_sbox, nb, p->d_bin_count);
@@ -471,19 +497,9 @@ static pvr_status plan_build_common(pvr_plan *p, const uint8_t *active, const ui
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, stream, p->d_bin_count, nb, p->d_bin_off,
                      p->d_total);
   HIP_TRY(hipGetLastError());
-  launch_fill_i32(p->d_box_max, 0, 1, stream);
-  hipLaunchKernelGGL(k_tile_boxmax, dim3((p->n_tiles + T - 1) / T), dim3(T), 0, stream, p->d_prob,
-                     p->d_patch, p->d_tiles, p->n_tiles, p->d_geof, p->d_box_max);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync(p->h_total + 1, p->d_box_max, sizeof(int), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipMemcpyAsync(p->h_total, p->d_total, sizeof(int), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
   const long long pairs = p->h_total[0];
-  {
-    // LDS per forward workgroup: the largest tile box, capped at 64 KiB
-    const int want = p->h_total[1];
-    p->lds_box = std::min(want, LDS_BOX_MAX);
-  }
   if (pairs >= 0x7fffffffLL) return fail(PVR_ESHAPE, "pvr_plan_build: brick index exceeds 2^31 pairs");
   if (pairs > p->bin_cap) {
     if (p->d_bin_patch) { HIP_TRY(hipFree(p->d_bin_patch)); p->device_bytes -= p->bin_cap * 4; }
@@ -519,6 +535,44 @@ static pvr_status plan_build_common(pvr_plan *p, const uint8_t *active, const ui
                      p->d_brick_prob, p->d_sbox, nsb, p->d_bin_off, p->d_bin_patch, p->d_sub_off,
                      p->d_sub_patch);
   HIP_TRY(hipGetLastError());
+  p->index_valid = true;
+  return PVR_OK;
+}
+
+static pvr_status plan_build_common(pvr_plan *p, const uint8_t *active, const uint8_t *mask,
+                                    bool f64, hipStream_t stream) {
+  const int M = p->M;
+  const int T = 256;
+  if (active) {
+    HIP_TRY(hipMemcpyAsync(p->d_active, active, M, hipMemcpyDeviceToDevice, stream));
+  } else {
+    launch_fill_u8(p->d_active, 1, M, stream);
+  }
+  if (mask) {
+    HIP_TRY(hipMemcpyAsync(p->d_mask, mask, p->N, hipMemcpyDeviceToDevice, stream));
+  } else {
+    launch_fill_u8(p->d_mask, 1, p->N, stream);
+  }
+  hipLaunchKernelGGL(k_geometry, dim3((M + T - 1) / T), dim3(T), 0, stream, p->d_prob, p->d_stack,
+                     p->d_patch, p->d_theta, M, p->k, p->d_geod, p->d_geof, p->d_bb, p->d_sbox);
+  HIP_TRY(hipGetLastError());
+  if (f64) {
+    if (!p->d_invz64) DEV_ALLOC(p, p->d_invz64, p->N);
+    hipLaunchKernelGGL(k_normalisers<double>, dim3(p->n_sim_blocks), dim3(SIM_THREADS), 0, stream,
+                       p->d_prob, p->d_patch, p->d_sim_blocks, p->d_geod, p->d_mask, p->d_active,
+                       p->d_invz, p->d_invz64);
+  } else {
+    hipLaunchKernelGGL(k_normalisers<float>, dim3(p->n_sim_blocks), dim3(SIM_THREADS), 0, stream,
+                       p->d_prob, p->d_patch, p->d_sim_blocks, p->d_geof, p->d_mask, p->d_active,
+                       p->d_invz, (double *)nullptr);
+  }
+  HIP_TRY(hipGetLastError());
+  // forward-tile boxes (LDS size of the staged forward pass)
+  {
+    const pvr_status st = update_lds_box(p, stream);
+    if (st != PVR_OK) return st;
+  }
+  p->index_valid = false;
   p->built = true;
   p->built64 = f64;
   return PVR_OK;

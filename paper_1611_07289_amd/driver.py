@@ -119,3 +119,79 @@ def psnr(X, X_true, plan, dilate_vox: int = 5) -> float:
         imax = float(T.max())
         vals.append(10 * np.log10(imax * imax / mse) if mse > 0 else float("inf"))
     return float(np.mean(vals))
+
+
+def patch_radius(plan):
+    """Half-diagonal (mm) of every patch: the scale of the rotation variables
+    of the registration optimisers (a unit step moves the farthest pixel by
+    about 1 mm)."""
+    import ctypes
+    sp = []
+    for s in plan._s:
+        L = np.asarray(list(s.pix2world), float).reshape(3, 4)[:, :3]
+        sp.append(np.linalg.norm(L, axis=0))
+    rho = np.empty(plan.M)
+    for i in range(plan.M):
+        q = plan._p[i]
+        su, sv = sp[q.stack][0], sp[q.stack][1]
+        rho[i] = 0.5 * np.hypot((q.w - 1) * su, (q.h - 1) * sv)
+    return np.maximum(rho, 1.0)
+
+
+def register_gradient(plan, X, y, theta, iters: int = 30, step0: float = 1.0,
+                      step_min: float = 0.01, min_std: float = 0.0):
+    """Joint gradient-based registration of all patches with the
+    differentiable forward model: d NCC_s / d theta_s is the NCC derivative
+    with respect to the simulated samples (pvr_ncc_grad) pulled back through
+    pvr_simulate_grad_theta.  Each patch takes a normalised ascent step in the
+    radius-scaled variables, kept on strict NCC improvement (the step then
+    doubles, capped at step0) and halved otherwise.  Patches with std(y_s) <
+    min_std and patches whose step fell below step_min stay put.  theta
+    ([M, 6] float32 on the device) is updated in place; the plan is left
+    built at the final theta.  Returns the final per-patch NCC."""
+    import torch
+    dev = theta.device
+    sc = torch.tensor(np.repeat(patch_radius(plan)[:, None], 6, 1), dtype=torch.float32,
+                      device=dev)
+    sc[:, 3:] = 1.0
+    ysim = torch.empty(plan.N, dtype=torch.float32, device=dev)
+    g = torch.empty_like(ysim)
+    ncc = torch.empty(plan.M, dtype=torch.float32, device=dev)
+    ncc_t = torch.empty_like(ncc)
+    G = torch.empty(plan.M, 6, dtype=torch.float32, device=dev)
+    delta = torch.full((plan.M,), float(step0), device=dev)
+    if min_std > 0:
+        off = torch.tensor(plan.sample_off, device=dev)
+        seg = torch.repeat_interleave(torch.arange(plan.M, device=dev), off[1:] - off[:-1])
+        cnt = torch.bincount(seg, minlength=plan.M).float()
+        m1 = torch.bincount(seg, weights=y.double(), minlength=plan.M) / cnt
+        m2 = torch.bincount(seg, weights=y.double() ** 2, minlength=plan.M) / cnt
+        sd = (m2 - m1 ** 2).clamp_min(0).sqrt().float()
+        delta = torch.where(sd >= min_std, delta, torch.zeros_like(delta))
+
+    def evaluate(th, grad):
+        plan.build(th)
+        plan.simulate(X, y_sim=ysim)
+        if grad:
+            plan.ncc_grad(y, ysim, g, ncc)
+            plan.grad_theta(X, g, G)
+        else:
+            plan.ncc_grad(y, ysim, None, ncc_t)
+
+    evaluate(theta, True)
+    for it in range(iters):
+        live = delta >= step_min
+        if not bool(live.any()):
+            break
+        Gq = G / sc
+        n = Gq.norm(dim=1, keepdim=True).clamp_min(1e-30)
+        step = torch.where(live[:, None], delta[:, None] * Gq / n, torch.zeros_like(Gq))
+        trial = theta + step / sc
+        evaluate(trial, False)
+        acc = live & (ncc_t > ncc)
+        theta.copy_(torch.where(acc[:, None], trial, theta))
+        delta = torch.where(acc, torch.clamp(2 * delta, max=step0),
+                            torch.where(live, 0.5 * delta, delta))
+        evaluate(theta, True)
+    plan.build(theta)
+    return ncc

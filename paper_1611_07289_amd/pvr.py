@@ -84,7 +84,10 @@ EXPORTS = ["pvr_last_error", "pvr_version", "pvr_plan_create", "pvr_plan_destroy
            "pvr_plan_info", "pvr_plan_offsets", "pvr_plan_build", "pvr_plan_build_f64",
            "pvr_plan_inv_z", "pvr_simulate", "pvr_simulate_f64", "pvr_backproject",
            "pvr_backproject_f64", "pvr_robust_weights", "pvr_sr_update",
-           "pvr_register_patches"]
+           "pvr_register_patches", "pvr_simulate_grad_theta", "pvr_simulate_grad_theta_f64",
+           "pvr_ncc_grad", "pvr_plan_set_tiles", "pvr_cnn_conv_fwd", "pvr_cnn_conv_dgrad",
+           "pvr_cnn_wgrad_scratch", "pvr_cnn_conv_wgrad", "pvr_cnn_pack_pairs",
+           "pvr_cnn_head_scratch", "pvr_cnn_head", "pvr_cnn_adam"]
 
 _lib = None
 
@@ -117,8 +120,24 @@ def load(path: str = LIB_PATH):
     L.pvr_robust_weights.argtypes = [P, P, P, P, P, P, P, i32, P]
     L.pvr_sr_update.argtypes = [P, P, P, P, P, P, P]
     L.pvr_register_patches.argtypes = [P, P, P, P, P, P, P, P]
+    L.pvr_simulate_grad_theta.argtypes = [P, P, P, P, P]
+    L.pvr_simulate_grad_theta_f64.argtypes = [P, P, P, P, P]
+    L.pvr_ncc_grad.argtypes = [P, P, P, P, P, P]
+    L.pvr_plan_set_tiles.argtypes = [P, i32, i32, P]
+    L.pvr_cnn_conv_fwd.argtypes = [P, P, P, P, i32, i32, i32, i32, i32, i32, i32, P]
+    L.pvr_cnn_conv_dgrad.argtypes = [P, P, P, P, i32, i32, i32, i32, i32, i32, P]
+    L.pvr_cnn_wgrad_scratch.argtypes = [i32, i32, i32, i32, i32, i32]
+    L.pvr_cnn_wgrad_scratch.restype = i64
+    L.pvr_cnn_conv_wgrad.argtypes = [P, P, P, P, P, P, i32, i32, i32, i32, i32, i32, P]
+    L.pvr_cnn_pack_pairs.argtypes = [P, P, i32, P, P, P, P]
+    L.pvr_cnn_head_scratch.argtypes = [i32]
+    L.pvr_cnn_head_scratch.restype = i64
+    L.pvr_cnn_head.argtypes = [P, i32, i32, P, P, P, P, P, P, P, P, P, P, P]
+    L.pvr_cnn_adam.argtypes = [P, P, P, P, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                               ctypes.c_float, i32, P, P, i32, i32, P]
     for name in EXPORTS:
-        if name not in ("pvr_last_error", "pvr_version", "pvr_plan_destroy", "pvr_plan_inv_z"):
+        if name not in ("pvr_last_error", "pvr_version", "pvr_plan_destroy", "pvr_plan_inv_z",
+                        "pvr_cnn_wgrad_scratch", "pvr_cnn_head_scratch"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -219,6 +238,11 @@ class Plan:
         import torch
         f = load().pvr_plan_build_f64 if theta.dtype == torch.float64 else load().pvr_plan_build
         _check(f(self.h, _ptr(theta), _ptr(active), _ptr(mask), _stream()))
+        self.build_id = getattr(self, "build_id", 0) + 1
+
+    def set_tiles(self, tile_w: int, tile_h: int):
+        _check(load().pvr_plan_set_tiles(self.h, int(tile_w), int(tile_h), _stream()))
+        self.tiles = (int(tile_w), int(tile_h))
 
     def inv_z(self):
         """Device pointer of the per-sample inverse normalisers (float [N])."""
@@ -247,6 +271,16 @@ class Plan:
         prm = params or RegParams.make()
         _check(load().pvr_register_patches(self.h, _ptr(X), _ptr(y_obs), _ptr(theta), _ptr(ncc),
                                            _ptr(reg), ctypes.byref(prm), _stream()))
+
+    def grad_theta(self, X, grad_y, grad_theta):
+        import torch
+        f = (load().pvr_simulate_grad_theta_f64 if X.dtype == torch.float64
+             else load().pvr_simulate_grad_theta)
+        _check(f(self.h, _ptr(X), _ptr(grad_y), _ptr(grad_theta), _stream()))
+
+    def ncc_grad(self, y_obs, y_sim, grad_y=None, ncc=None):
+        _check(load().pvr_ncc_grad(self.h, _ptr(y_obs), _ptr(y_sim), _ptr(grad_y), _ptr(ncc),
+                                   _stream()))
 
     # -- EM state helpers ---------------------------------------------------------------
     def em_state(self, device="cuda"):

@@ -417,11 +417,11 @@ def diff_problem(seed_cfg: int = 4) -> Problem:
 
 
 def batched_problems(seed_cfg: int = 3, count: int = 8,
-                     n_range=(96, 192)) -> List[Problem]:
+                     n_range=(96, 192), sizes=(32, 64, 128)) -> List[Problem]:
     """Independent reconstructions: volume n^3 with n ~ U{n_range}; 3-6
     stacks (3 orthogonal + seeded obliques) of n x n x ceil(n/4) slices at
-    thickness 4; patch size per stack ~ U{32, 64, 128} (clamped to the
-    slice), stride a/2; motion <= 10 deg, <= 5 mm; 10 % outliers."""
+    thickness 4; patch size per stack ~ U{sizes} (clamped to the slice),
+    stride a/2; motion <= 10 deg, <= 5 mm; 10 % outliers."""
     base = 1000 * seed_cfg
     rng = np.random.default_rng(base + 7)
     probs = []
@@ -437,7 +437,7 @@ def batched_problems(seed_cfg: int = 3, count: int = 8,
                   for fr in orthogonal_frames(obl)]
         parts = []
         for si, st in enumerate(stacks):
-            a = int(rng.choice([32, 64, 128]))
+            a = int(rng.choice(list(sizes)))
             parts.append(square_patches([st], a, a // 2, stack_base=si))
         P = Patches.concat(parts, [0] * len(parts))
         th = random_motion(P.M, 10.0, 5.0, base + 100 * b + 2)

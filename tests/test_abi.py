@@ -15,8 +15,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    txt = open(os.path.join(ROOT, "include", "pvr.h")).read()
-    return sorted(set(re.findall(r"\b(pvr_[a-z0-9_]+)\s*\(", txt)))
+    names = set()
+    for h in ("pvr.h", "pvr_cnn.h"):
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        names |= set(re.findall(r"^(?:pvr_status|const char|const float|void|int64_t)[\s*]+"
+                                r"(pvr_[a-z0-9_]+)\s*\(", txt, re.M))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():

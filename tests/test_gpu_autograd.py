@@ -1,0 +1,157 @@
+"""Differentiable simulation (the forward model wrapped in
+torch.autograd.Function) against FP64 central finite differences of the
+oracle, step 1e-4, on the 48^3 three-stack case with 24x24 patches.
+
+Tolerances: per-patch relative error of the six theta-derivatives <= 1e-6
+for the FP64 kernels and <= 1e-3 for the FP32 kernels; d/dX equals the
+oracle's A^T g.  Samples whose validity changes within +-h (a centre crossing
+the volume border) are left out of the test loss, because the loss itself is
+discontinuous there.
+"""
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    import torch
+
+import oracle
+from paper_1611_07289_amd import pvr, synth
+
+H = 1e-4
+
+
+@pytest.fixture(scope="module")
+def diff():
+    print("[gpu] diff48 problem", flush=True)
+    P = synth.diff_problem()
+    ctx = oracle.Ctx(P.grid, P.stacks, P.patches)
+    th = P.theta_true.copy()
+    rng = np.random.default_rng(17)
+    g = rng.normal(size=P.N)
+    # patches under test and the samples whose validity is stable around theta
+    test_patches = np.sort(rng.choice(P.M, size=24, replace=False))
+    off = P.patches.sample_off
+    stable = np.ones(P.N, bool)
+    _, _, v0 = ctx.simulate(P.x_true, th)
+    for s in test_patches:
+        idx = np.arange(off[s], off[s + 1])
+        for k in range(6):
+            for sgn in (-1, 1):
+                t2 = th.copy()
+                t2[s, k] += sgn * H
+                _, _, vv = ctx.simulate(P.x_true, t2, samples=idx)
+                stable[idx] &= (vv == v0[idx])
+    g = np.where(stable, g, 0.0)
+    fd = np.zeros((len(test_patches), 6))
+    for q, s in enumerate(test_patches):
+        idx = np.arange(off[s], off[s + 1])
+        for k in range(6):
+            tp, tm = th.copy(), th.copy()
+            tp[s, k] += H
+            tm[s, k] -= H
+            yp, _, _ = ctx.simulate(P.x_true, tp, samples=idx)
+            ym, _, _ = ctx.simulate(P.x_true, tm, samples=idx)
+            fd[q, k] = (g[idx] @ yp - g[idx] @ ym) / (2 * H)
+    return dict(P=P, ctx=ctx, th=th, g=g, test_patches=test_patches, fd=fd)
+
+
+def _grad(d, dtype):
+    from paper_1611_07289_amd.autograd import simulate
+    P = d["P"]
+    plan = pvr.Plan.from_problems([P])
+    X = torch.tensor(np.asarray(P.x_true, np.float64).reshape(-1), dtype=dtype,
+                     device="cuda", requires_grad=True)
+    th = torch.tensor(d["th"], dtype=dtype, device="cuda", requires_grad=True)
+    y = simulate(X, th, plan)
+    gy = torch.tensor(d["g"], dtype=dtype, device="cuda")
+    (y * gy).sum().backward()
+    torch.cuda.synchronize()
+    return X.grad.double().cpu().numpy(), th.grad.double().cpu().numpy(), y.double().cpu().numpy()
+
+
+def _check_theta(d, gth, tol):
+    tp = d["test_patches"]
+    errs = []
+    for q, s in enumerate(tp):
+        ref = d["fd"][q]
+        errs.append(np.linalg.norm(gth[s] - ref) / max(np.linalg.norm(ref), 1e-12))
+    errs = np.array(errs)
+    print(f"[gpu] theta-gradient rel err max {errs.max():.2e} median {np.median(errs):.2e}")
+    assert errs.max() <= tol
+
+
+def test_theta_gradient_fp64_matches_fd(diff):
+    gX, gth, y = _grad(diff, torch.float64)
+    _check_theta(diff, gth, 1e-6)
+    yo, _, _ = diff["ctx"].simulate(diff["P"].x_true, diff["th"])
+    assert np.allclose(y, yo, rtol=1e-12, atol=1e-9)
+
+
+def test_theta_gradient_fp32_matches_fd(diff):
+    gX, gth, y = _grad(diff, torch.float32)
+    # the FP32 path sees the FP32-rounded motion; the derivative is smooth, so
+    # the FP64 finite differences at the FP64 motion are the reference
+    _check_theta(diff, gth, 1e-3)
+
+
+def test_volume_gradient_is_the_adjoint(diff):
+    P, ctx = diff["P"], diff["ctx"]
+    gX, _, _ = _grad(diff, torch.float64)
+    ref = ctx.backproject(diff["th"], diff["g"]).reshape(-1)
+    absr = ctx.backproject(diff["th"], np.abs(diff["g"])).reshape(-1)
+    err = np.abs(gX - ref) / (absr + 1e-300)
+    assert err.max() <= 1e-12
+
+
+def test_volume_gradient_matches_fd(diff):
+    """d/dX checked directly: L(X) = g . A X is linear, so a central
+    difference along a random direction is exact up to rounding."""
+    P, ctx = diff["P"], diff["ctx"]
+    gX, _, _ = _grad(diff, torch.float64)
+    dX = np.random.default_rng(3).normal(size=P.grid.n_voxels)
+    X = np.asarray(P.x_true, np.float64).reshape(-1)
+    yp, _, _ = ctx.simulate(X + H * dX, diff["th"])
+    ym, _, _ = ctx.simulate(X - H * dX, diff["th"])
+    fd = (diff["g"] @ yp - diff["g"] @ ym) / (2 * H)
+    assert gX @ dX == pytest.approx(fd, rel=1e-8)
+
+
+def test_gradient_joint_registration_recovers_motion():
+    """Gradient-based joint registration through the adjoint: every patch's
+    NCC is non-decreasing and the motion error falls well below the start."""
+    from scipy.ndimage import gaussian_filter
+
+    from paper_1611_07289_amd import driver
+    P = synth.tiny_problem()
+    X = gaussian_filter(np.random.default_rng(5).uniform(0, 1000, (32, 32, 32)), 1.5)
+    X = ((X - X.min()) / (X.max() - X.min()) * 1000.0).astype(np.float32)
+    ctx = oracle.Ctx(P.grid, P.stacks, P.patches)
+    th_true = P.theta_true.astype(np.float32).astype(np.float64)
+    y, _, _ = ctx.simulate(X, th_true)
+    th0 = (P.theta_true + synth.random_motion(P.M, 3.0, 1.0, 99)).astype(np.float32)
+    plan = pvr.Plan.from_problems([P])
+    Xd = torch.from_numpy(X.reshape(-1)).cuda()
+    yd = torch.from_numpy(y.astype(np.float32)).cuda()
+    th = torch.from_numpy(th0).cuda()
+    plan.build(th)
+    n0 = torch.empty(plan.M, device="cuda")
+    ys = torch.empty(plan.N, device="cuda")
+    plan.simulate(Xd, y_sim=ys)
+    plan.ncc_grad(yd, ys, None, n0)
+    ncc = driver.register_gradient(plan, Xd, yd, th, iters=60)
+    torch.cuda.synchronize()
+    thg = th.cpu().numpy().astype(np.float64)
+    assert np.all(ncc.cpu().numpy() >= n0.cpu().numpy() - 1e-6)
+    drot = np.degrees(np.abs(thg[:, :3] - th_true[:, :3])).max(1)
+    dtr = np.abs(thg[:, 3:] - th_true[:, 3:]).max(1)
+    drot0 = np.degrees(np.abs(th0[:, :3] - th_true[:, :3])).max(1)
+    dtr0 = np.abs(th0[:, 3:] - th_true[:, 3:]).max(1)
+    print(f"[gpu] gradient registration: median rot {np.median(drot0):.3f} -> {np.median(drot):.3f} deg, "
+          f"trans {np.median(dtr0):.3f} -> {np.median(dtr):.3f} mm, ncc {float(n0.mean()):.4f} -> "
+          f"{float(ncc.mean()):.4f}")
+    assert np.median(dtr) < 0.25 * np.median(dtr0)
+    assert np.median(drot) < 0.5 * np.median(drot0)
