@@ -5,12 +5,9 @@ problem, and the graph-captured SR iteration against eager execution.
 import numpy as np
 import pytest
 
-from tests.conftest import gpu_available
-
 pytestmark = pytest.mark.gpu
 
-if gpu_available():
-    import torch
+import torch  # noqa: E402  (CPU import is fine; GPU use is gated by the marker)
 
 import oracle
 from oracle import recon
