@@ -129,6 +129,9 @@ def main():
     ap.add_argument("--workload", default="uterus256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--full-pvr", action="store_true")
+    ap.add_argument("--learned-pairs", type=int, default=0,
+                    help="with --full-pvr: train the learned initialiser on this many pairs "
+                         "and time the learned-init reconstruction too")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (for counter scaling)")
     args = ap.parse_args()
@@ -145,6 +148,9 @@ def main():
     t0 = time.time()
     probs = make_workload(args.workload)
     log(f"[bench] workload {args.workload}: generated in {time.time() - t0:.1f} s")
+    if args.workload == "batched":
+        batched_bench(args, probs, dev)
+        return
     plan = pvr.Plan.from_problems(probs)
     log(f"[bench] plan: N={plan.N} M={plan.M} V={plan.V} problems={plan.P}")
 
@@ -267,7 +273,7 @@ def main():
     }
 
     if args.full_pvr:
-        out["full_pvr"] = full_pvr(plan, probs, y, Xtrue, dev)
+        out["full_pvr"] = full_pvr(plan, probs, y, Xtrue, dev, learned_pairs=args.learned_pairs)
 
     if args.copy_calibration:
         a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev)
@@ -285,23 +291,128 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def batched_bench(args, probs, dev):
+    """Batched form: all problems in one plan, autotuned forward tiles, two SR
+    iterations per HIP-graph replay; compared with the same problems run one
+    after another, each in its own plan, eagerly."""
+    import torch
+    from paper_1611_07289_amd import autotune, pvr, synth
+    from paper_1611_07289_amd.batch import GraphedSR
+    plan = pvr.Plan.from_problems(probs)
+    theta = torch.from_numpy(np.concatenate([P.theta_true for P in probs]).astype(np.float32)).to(dev)
+    Xt = torch.from_numpy(np.concatenate([P.x_true.reshape(-1) for P in probs])).to(dev)
+    plan.build(theta)
+    yc = torch.empty(plan.N, dtype=torch.float32, device=dev)
+    plan.simulate(Xt, y_sim=yc)
+    ych = yc.cpu().numpy()
+    parts = []
+    for b, P in enumerate(probs):
+        a = plan.sample_off[plan_patch_begin(plan, probs, b)]
+        z = plan.sample_off[plan_patch_begin(plan, probs, b + 1)]
+        parts.append(synth.corrupt(ych[a:z], P.patches, P.outlier_patch, P.noise_frac,
+                                   P.seed_base + 3, P.seed_base + 5))
+    y = torch.from_numpy(np.concatenate(parts)).to(dev)
+    ones = torch.ones(plan.V, dtype=torch.float32, device=dev)
+    plan.simulate(ones, y_sim=yc)
+    n_valid = int((yc > 0.5).sum().item())
+    X0 = Xt * 0.9
+    tiles, tile_ms = autotune.tune_tiles(plan, X0, y, cache=None)
+    log(f"[bench] batched: {plan.P} problems, N={plan.N} M={plan.M} V={plan.V}; tiles {tiles}")
+    gs = GraphedSR(plan, y, X0.clone())
+    gs.start()
+    gs.capture()
+    pairs = max(1, args.steps // 2)
+    gs.replay_pairs(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gs.replay_pairs(pairs)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    it = 2 * pairs
+    value = n_valid * it / el
+    # the same problems one after another, eagerly, each in its own plan
+    seq_t = 0.0
+    for b, P in enumerate(probs):
+        pl = pvr.Plan.from_problems([P])
+        pl.build(torch.from_numpy(P.theta_true.astype(np.float32)).to(dev))
+        a = plan.sample_off[plan_patch_begin(plan, probs, b)]
+        z = plan.sample_off[plan_patch_begin(plan, probs, b + 1)]
+        yb = y[a:z].contiguous()
+        g1 = GraphedSR(pl, yb, torch.from_numpy(P.x_true.reshape(-1) * 0.9).to(dev))
+        g1.start()
+        g1._iter(g1.X, g1.Xn)
+        g1._iter(g1.Xn, g1.X)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(pairs):
+            g1._iter(g1.X, g1.Xn)
+            g1._iter(g1.Xn, g1.X)
+        torch.cuda.synchronize()
+        seq_t += time.perf_counter() - t1
+        pl.close()
+    out = {
+        "metric": "SR-iteration patch-samples/s (batched, graph)",
+        "value": value, "unit": "patch-samples/s", "n_gpus": 1, "steps": it,
+        "warmup": 2, "ms_per_step": el * 1e3 / it, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched", "problems": plan.P, "patches": plan.M,
+                   "samples": plan.N, "valid_samples": n_valid, "voxels": plan.V,
+                   "sizes": [P.grid.nx for P in probs],
+                   "stacks": [len(P.stacks) for P in probs], "parallelism": "single GPU"},
+        "tiles": list(tiles), "tile_ms": tile_ms,
+        "sequential_ms_per_step": seq_t * 1e3 / it,
+        "speedup_vs_sequential": seq_t / el,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def plan_patch_begin(plan, probs, b):
     return int(sum(P.M for P in probs[:b]))
 
 
-def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10):
-    """Seconds of a whole reconstruction from the motion-corrupted start."""
+def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10, learned_pairs=0):
+    """Seconds and PSNR of a whole reconstruction from the motion-corrupted
+    start (zero motion): plain registration, and with learned_pairs > 0 also
+    the learned initialiser (trained first, on a phantom of another seed)."""
     import torch
-    from paper_1611_07289_amd import driver
+    from paper_1611_07289_amd import driver, learned, pvr, synth
+    res = {}
+    ymax = float(y.abs().max())
     th0 = torch.zeros(plan.M, 6, dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     X, th, hist = driver.reconstruct(plan, y, th0, cycles=cycles, n_sr=n_sr)
     torch.cuda.synchronize()
-    secs = time.perf_counter() - t0
-    psnr = driver.psnr(X, Xtrue, plan)
-    return {"seconds": secs, "cycles": cycles, "sr_iterations": n_sr, "psnr_db": psnr,
-            "init": "plain", "timings": hist.get("timings")}
+    res["plain"] = {"seconds": time.perf_counter() - t0, "psnr_db": driver.psnr(X, Xtrue, plan),
+                    "timings": hist["timings"], "mean_ncc": hist["ncc"]}
+    if learned_pairs > 0:
+        P = probs[0]
+        Xtr = torch.from_numpy(synth.phantom_uterus(P.grid.nx, 7700, 7701).reshape(-1)).to(dev)
+        net = learned.Net(seed=5005)
+        tr = learned.train(net, plan, [Xtr], n_pairs=learned_pairs, batch=256, lr=1e-3,
+                           seed=7800, log=log)
+        del Xtr
+        init_fn = learned.init_fn_factory(net)
+        rp = pvr.RegParams.make(step0=0.5, min_std=0.01 * ymax, max_iter=20)
+        th0 = torch.zeros(plan.M, 6, dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X2, th2, hist2 = driver.reconstruct(plan, y, th0, cycles=cycles, n_sr=n_sr,
+                                            reg_params=rp, init_fn=init_fn)
+        torch.cuda.synchronize()
+        res["learned"] = {"seconds": time.perf_counter() - t0,
+                          "psnr_db": driver.psnr(X2, Xtrue, plan),
+                          "timings": hist2["timings"], "mean_ncc": hist2["ncc"],
+                          "training": {"pairs": tr["pairs"], "seconds": tr["seconds"],
+                                       "data_seconds": tr["data_seconds"],
+                                       "loss_first_last": [tr["loss"][0][1], tr["loss"][-1][1]]
+                                       if tr["loss"] else None}}
+        res["delta_psnr_db"] = res["learned"]["psnr_db"] - res["plain"]["psnr_db"]
+        res["speedup"] = res["plain"]["seconds"] / res["learned"]["seconds"]
+    res["cycles"] = cycles
+    res["sr_iterations"] = n_sr
+    res["paper_runtime_s"] = "2000-4000 (whole PVR, unspecified NVIDIA GPU machines; Sec. V)"
+    return res
 
 
 if __name__ == "__main__":

@@ -177,16 +177,23 @@ __device__ __forceinline__ void block_sum6(double v[6], double (*lds)[REG_THREAD
 struct RegShared {
   GeoF g;
   double red[6][REG_THREADS / 64];
+  // optimiser state (uniform across the workgroup; kept out of registers)
+  double th[6];     // transform evaluated next
+  double q[6];      // current point, scaled variables
+  double grad[6];
+  double sc[6];
+  double fval;      // result of the last evaluation
 };
 
-// NCC of the patch against its simulation at theta (valid samples only).
+// NCC of the patch against its simulation at sh.th (valid samples only);
+// every lane returns the same value.
 __device__ double reg_eval(RegShared &sh, const ProbDev &pr, const StackDev &st, const PatchDev &pt,
-                           const double th[6], double k, const float *__restrict__ Xp,
-                           const float *__restrict__ y, const uint8_t *__restrict__ mask) {
+                           double k, const float *__restrict__ Xp, const float *__restrict__ y,
+                           const uint8_t *__restrict__ mask) {
   if (threadIdx.x == 0) {
     GeoD gd;
     int bb[6];
-    make_geometry(pr, st, pt, th, k, gd, sh.g, bb);
+    make_geometry(pr, st, pt, sh.th, k, gd, sh.g, bb);
   }
   __syncthreads();
   const GeoF &g = sh.g;
@@ -220,6 +227,8 @@ __device__ double reg_eval(RegShared &sh, const ProbDev &pr, const StackDev &st,
   return cv / sqrt(vy * vh);
 }
 
+// One workgroup per patch; the optimiser's control flow is uniform (every
+// lane sees the same reduced NCC values), its state lives in LDS.
 __global__ void __launch_bounds__(REG_THREADS)
 k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stacks,
            const PatchDev *__restrict__ patches, const float *__restrict__ X,
@@ -232,9 +241,6 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
   const StackDev st = stacks[pt.stack];
   const ProbDev pr = probs[pt.problem];
   const float *Xp = X + pr.vol_off;
-  double th[6];
-#pragma unroll
-  for (int a = 0; a < 6; ++a) th[a] = (double)theta[6 * s + a];
   // observed standard deviation over unmasked samples
   double sy[6] = {0, 0, 0, 0, 0, 0};
   const int n = pt.w * pt.h;
@@ -252,47 +258,53 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
     const double m = sy[1] / sy[0];
     sd = sqrt(fmax(sy[2] / sy[0] - m * m, 0.0));
   }
-  double f0 = reg_eval(sh, pr, st, pt, th, k, Xp, y, mask);
-  const bool do_reg = (reg ? reg[s] != 0 : true) && sd >= prm.min_std && prm.max_iter > 0;
-  if (do_reg) {
+  if (threadIdx.x == 0) {
     const double su = st.spacing[0], sv = st.spacing[1];
     double rho = 0.5 * sqrt((pt.w - 1) * (pt.w - 1) * su * su + (pt.h - 1) * (pt.h - 1) * sv * sv);
     rho = rho < 1.0 ? 1.0 : rho;
-    const double sc[6] = {rho, rho, rho, 1.0, 1.0, 1.0};
-    double q[6], grad[6], tt[6];
-#pragma unroll
-    for (int a = 0; a < 6; ++a) q[a] = th[a] * sc[a];
+    for (int a = 0; a < 6; ++a) {
+      sh.th[a] = (double)theta[6 * s + a];
+      sh.sc[a] = a < 3 ? rho : 1.0;
+      sh.q[a] = sh.th[a] * sh.sc[a];
+    }
+  }
+  __syncthreads();
+  double f0 = reg_eval(sh, pr, st, pt, k, Xp, y, mask);
+  const bool do_reg = (reg ? reg[s] != 0 : true) && sd >= prm.min_std && prm.max_iter > 0;
+  if (do_reg) {
     double delta = prm.step0;
     bool have_grad = false, moved = false;
     for (int it = 0; it < prm.max_iter; ++it) {
       if (delta < prm.step_min) break;
       if (!have_grad) {
         for (int a = 0; a < 6; ++a) {
-#pragma unroll
-          for (int b = 0; b < 6; ++b) tt[b] = q[b] / sc[b];
-          tt[a] = (q[a] + prm.fd_h) / sc[a];
-          const double fp = reg_eval(sh, pr, st, pt, tt, k, Xp, y, mask);
-          tt[a] = (q[a] - prm.fd_h) / sc[a];
-          const double fm = reg_eval(sh, pr, st, pt, tt, k, Xp, y, mask);
-          grad[a] = (fp - fm) / (2.0 * prm.fd_h);
+          double fp, fm;
+          __syncthreads();
+          if (threadIdx.x == 0) {
+            for (int b = 0; b < 6; ++b) sh.th[b] = sh.q[b] / sh.sc[b];
+            sh.th[a] = (sh.q[a] + prm.fd_h) / sh.sc[a];
+          }
+          fp = reg_eval(sh, pr, st, pt, k, Xp, y, mask);
+          __syncthreads();
+          if (threadIdx.x == 0) sh.th[a] = (sh.q[a] - prm.fd_h) / sh.sc[a];
+          fm = reg_eval(sh, pr, st, pt, k, Xp, y, mask);
+          if (threadIdx.x == 0) sh.grad[a] = (fp - fm) / (2.0 * prm.fd_h);
         }
         have_grad = true;
       }
+      __syncthreads();
       double gn = 0;
-#pragma unroll
-      for (int a = 0; a < 6; ++a) gn += grad[a] * grad[a];
+      for (int a = 0; a < 6; ++a) gn += sh.grad[a] * sh.grad[a];
       gn = sqrt(gn);
       if (!(gn > 0)) break;
-      double trial[6];
-#pragma unroll
-      for (int a = 0; a < 6; ++a) {
-        trial[a] = q[a] + delta * grad[a] / gn;
-        tt[a] = trial[a] / sc[a];
-      }
-      const double ft = reg_eval(sh, pr, st, pt, tt, k, Xp, y, mask);
+      __syncthreads();
+      if (threadIdx.x == 0)
+        for (int a = 0; a < 6; ++a) sh.th[a] = (sh.q[a] + delta * sh.grad[a] / gn) / sh.sc[a];
+      const double ft = reg_eval(sh, pr, st, pt, k, Xp, y, mask);
       if (ft > f0) {
-#pragma unroll
-        for (int a = 0; a < 6; ++a) q[a] = trial[a];
+        __syncthreads();
+        if (threadIdx.x == 0)
+          for (int a = 0; a < 6; ++a) sh.q[a] = sh.q[a] + delta * sh.grad[a] / gn;
         f0 = ft;
         have_grad = false;
         moved = true;
@@ -301,9 +313,9 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
         delta *= 0.5;
       }
     }
+    __syncthreads();
     if (moved && threadIdx.x == 0) {
-#pragma unroll
-      for (int a = 0; a < 6; ++a) theta[6 * s + a] = (float)(q[a] / sc[a]);
+      for (int a = 0; a < 6; ++a) theta[6 * s + a] = (float)(sh.q[a] / sh.sc[a]);
     }
   }
   if (ncc_out && threadIdx.x == 0) ncc_out[s] = (float)f0;
