@@ -182,7 +182,8 @@ pvr_status pvr_plan_offsets(const pvr_plan *plan, int64_t *sample_off,
  * [M][6]): per-patch geometry, per-sample inverse PSF normalisers (0 marks an
  * invalid sample) and the brick -> patch index of the adjoint.  active
  * ([M], nullable = all) and sample_mask ([N], nullable = all) are read here.
- * Synchronises `stream` once.  The adjoint's brick index is rebuilt lazily by
+ * Synchronises `stream` once if LDS forward tiles are enabled
+ * (pvr_plan_set_tiles), else not at all.  The adjoint's brick index is rebuilt lazily by
  * the first pvr_backproject after a build (synchronising `stream` twice), so
  * loops that only simulate (registration) do not pay for it. */
 pvr_status pvr_plan_build(pvr_plan *plan, const float *theta,
@@ -192,10 +193,13 @@ pvr_status pvr_plan_build_f64(pvr_plan *plan, const double *theta,
                               const uint8_t *active, const uint8_t *sample_mask,
                               hipStream_t stream);
 
-/* Forward tile shape: the simulation splits every patch into tile_w x tile_h
+/* Forward tile shape.  By default the simulation walks every sample's PSF
+ * support in global memory (one workgroup per 1024-sample chunk of a patch).
+ * With tile_w x tile_h > 0 it instead splits every patch into tile_w x tile_h
  * pixel rectangles, one workgroup each, and stages each tile's voxel box in
- * LDS (default 16 x 16; tile_w * tile_h <= 256).  Used by the autotuner.
- * Synchronises `stream`. */
+ * LDS (tile_w * tile_h <= 256; tiles whose box exceeds 64 KiB walk global
+ * memory); 0 x 0 returns to the global walk.  Used by the autotuner.
+ * Synchronises `stream` when tiles are enabled. */
 pvr_status pvr_plan_set_tiles(pvr_plan *plan, int32_t tile_w, int32_t tile_h,
                               hipStream_t stream);
 

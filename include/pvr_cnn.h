@@ -10,8 +10,9 @@
  * replaces it when its NCC is worse than the unchanged motion.
  *
  * Network: 8 convolutions 3x3 (pad 1, ReLU) with channels 32, 32, 64, 64, 64,
- * 64, 64, 64 and stride 2 at layers 2, 4 and 6, global average pooling, one
- * fully connected layer to 6 outputs.  Activations and weights BF16 (MFMA),
+ * 64, 64, 64 and stride 2 at layers 2, 4 and 6, then one fully connected
+ * layer from the whole 8 x 8 x 64 map to 6 outputs (position-dependent
+ * weights: a rotation displaces the image differently across the patch).  Activations and weights BF16 (MFMA),
  * accumulation and training state FP32.
  *
  * Conventions: device pointers; BF16 values are stored as uint16_t (upper
@@ -76,11 +77,12 @@ pvr_status pvr_cnn_pack_pairs(const pvr_plan *plan, const int32_t *patch_ids,
 /* Bytes of FP32 scratch pvr_cnn_head needs in training (host). */
 int64_t pvr_cnn_head_scratch(int32_t B);
 
-/* Head: global average pool of act [B][hw][64], pred = feat wfc + bfc with
- * wfc [64][6], bfc [6], pred [B][6].  With target [B][6] (nullable for
- * inference) and per-output loss weights loss_w [6]: loss [1] =
- * sum_b sum_k loss_w[k] (pred - target)^2 / (2 B), and the gradients gact
- * (w.r.t. act, BF16), dwfc [64][6], dbfc [6]. */
+/* Head: pred[b][k] = sum_{q,c} act[b][q][c] wfc[q][c][k] + bfc[k] with act
+ * [B][hw][64], wfc [hw][64][6] FP32, bfc [6], pred [B][6].  With target
+ * [B][6] (nullable for inference) and per-output loss weights loss_w [6]:
+ * loss [1] = sum_b sum_k loss_w[k] (pred - target)^2 / (2 B), and the
+ * gradients gact (w.r.t. act, BF16), dwfc [hw][64][6], dbfc [6] (sums over
+ * the batch in sample order). */
 pvr_status pvr_cnn_head(const uint16_t *act, int32_t B, int32_t hw,
                         const float *wfc, const float *bfc, const float *target,
                         const float *loss_w, float *pred, float *loss,

@@ -3,7 +3,8 @@ INFRASTRUCTURE ONLY.
 
 3x3 convolution (padding 1, stride s, bias, ReLU) on NHWC tensors through
 torch.nn.functional.conv2d in float64, its gradients through autograd, and
-the head (global average pool, fully connected layer, weighted squared loss).
+the head (fully connected layer from the whole last feature map, weighted
+squared loss).
 Weights are [Cout][3][3][Cin].  Pinned against a brute-force loop and finite
 differences in tests/test_oracle_cnn.py.
 """
@@ -44,16 +45,16 @@ def conv_grads(x, w, b, stride, gout, out_mask=None):
 
 
 def head(act, wfc, bfc, target=None, loss_w=None):
-    """act [B][hw][64]; pred = mean_hw(act) wfc + bfc; with a target, the loss
-    sum_b sum_k w_k (pred - target)^2 / (2B) and its gradients."""
+    """act [B][hw][64], wfc [hw][64][6]; pred[b] = sum_{q,c} act[b,q,c]
+    wfc[q,c] + bfc; with a target, the loss sum_b sum_k w_k (pred - target)^2
+    / (2B) and its gradients (wfc's in its own shape)."""
     A = _t(act).requires_grad_(True)
     Wf = _t(wfc).requires_grad_(True)
     bf = _t(bfc).requires_grad_(True)
-    feat = A.mean(dim=1)
-    pred = feat @ Wf + bf
+    B = A.shape[0]
+    pred = A.reshape(B, -1) @ Wf.reshape(-1, 6) + bf
     if target is None:
         return pred.detach().numpy()
-    B = A.shape[0]
     loss = ((pred - _t(target)) ** 2 * _t(loss_w)).sum() / (2 * B)
     loss.backward()
     return (pred.detach().numpy(), float(loss), A.grad.numpy(), Wf.grad.numpy(), bf.grad.numpy())

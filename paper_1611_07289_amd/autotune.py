@@ -1,7 +1,8 @@
 """Autotuner for the forward tile shape of a plan.
 
-Every candidate tile shape (tile_w x tile_h pixels per workgroup) is applied
-with pvr_plan_set_tiles and the simulation is timed with HIP events; the
+Every candidate tile shape (tile_w x tile_h pixels per workgroup with the
+tile's voxel box staged in LDS, or 0 x 0 for the global-memory walk) is
+applied with pvr_plan_set_tiles and the simulation is timed with HIP events; the
 fastest shape is kept and remembered in a JSON cache keyed by the workload
 signature (problem sizes, patch sizes, stack frames), so later plans of the
 same workload skip the search.
@@ -15,7 +16,8 @@ from typing import Dict, Optional, Tuple
 
 import numpy as np
 
-CANDIDATES = [(16, 16), (32, 8), (8, 32), (64, 4), (16, 8), (8, 16), (8, 8)]
+# (0, 0) is the untiled global-memory walk
+CANDIDATES = [(0, 0), (16, 16), (32, 8), (8, 32), (64, 4), (16, 8), (8, 16), (8, 8)]
 CACHE = os.environ.get("PVR_AUTOTUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "pvr_mi355x",
                                     "autotune.json"))

@@ -426,43 +426,79 @@ k_pack_pairs(const PatchDev *__restrict__ patches, const int *__restrict__ ids,
 }
 
 // ---------------------------------------------------------------------------
-// head: global average pool over the last feature map, fully connected layer
-// to 6 outputs, weighted squared loss and its gradients.  One workgroup of 64
-// lanes per sample (lane = channel, C = 64).
+// head: fully connected layer from the whole last feature map (hw positions
+// x 64 channels, so the weights can depend on position) to 6 outputs,
+// weighted squared loss and its gradients.  One workgroup of 256 lanes per
+// sample; lane t owns the flattened inputs t, t + 256, ...
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64)
-k_head(const uint16_t *__restrict__ act, int HW, const float *__restrict__ Wfc,
+constexpr int HEAD_THREADS = 256;
+
+__global__ void __launch_bounds__(HEAD_THREADS)
+k_head(const uint16_t *__restrict__ act, int n_in, const float *__restrict__ Wfc,
        const float *__restrict__ bfc, const float *__restrict__ target,
        const float *__restrict__ lw, float *__restrict__ pred, float *__restrict__ loss_part,
-       uint16_t *__restrict__ gact, float *__restrict__ dWpart, float *__restrict__ dbpart,
-       float inv_batch) {
-  constexpr int C = 64;
-  __shared__ float feat[C];
+       float *__restrict__ dp_out, uint16_t *__restrict__ gact, float inv_batch) {
+  __shared__ float red[6][HEAD_THREADS / 64];
   __shared__ float dp[6];
-  const int b = blockIdx.x, c = threadIdx.x;
-  float s = 0.f;
-  for (int q = 0; q < HW; ++q) s += bf2f(act[((long long)b * HW + q) * C + c]);
-  feat[c] = s / HW;
-  __syncthreads();
-  if (c < 6) {
-    float o = bfc[c];
-    for (int k = 0; k < C; ++k) o += feat[k] * Wfc[k * 6 + c];
-    pred[b * 6 + c] = o;
-    if (target) {
-      const float d = o - target[b * 6 + c];
-      dp[c] = lw[c] * d * inv_batch;
-      loss_part[b * 6 + c] = 0.5f * lw[c] * d * d * inv_batch;
-    }
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const uint16_t *a = act + (long long)b * n_in;
+  float s[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int e = t; e < n_in; e += HEAD_THREADS) {
+    const float x = bf2f(a[e]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s[k] = fmaf(x, Wfc[e * 6 + k], s[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    float x = s[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) red[k][wave] = x;
   }
   __syncthreads();
+  if (t < 6) {
+    float o = bfc[t];
+    for (int w = 0; w < HEAD_THREADS / 64; ++w) o += red[t][w];
+    pred[b * 6 + t] = o;
+    if (target) {
+      const float d = o - target[b * 6 + t];
+      dp[t] = lw[t] * d * inv_batch;
+      dp_out[b * 6 + t] = dp[t];
+      loss_part[b * 6 + t] = 0.5f * lw[t] * d * d * inv_batch;
+    }
+  }
   if (!target) return;
-  // dL/dWfc[k][j] = feat[k] dp[j]; dL/dfeat[k] = sum_j Wfc[k][j] dp[j]
-  for (int j = 0; j < 6; ++j) dWpart[((long long)b * C + c) * 6 + j] = feat[c] * dp[j];
-  if (c < 6) dbpart[b * 6 + c] = dp[c];
-  float gf = 0.f;
-  for (int j = 0; j < 6; ++j) gf += Wfc[c * 6 + j] * dp[j];
-  const uint16_t g = f2bf(gf / HW);
-  for (int q = 0; q < HW; ++q) gact[((long long)b * HW + q) * C + c] = g;
+  __syncthreads();
+  // dL/dact[e] = sum_k Wfc[e][k] dp[k]
+  for (int e = t; e < n_in; e += HEAD_THREADS) {
+    float g = 0.f;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) g = fmaf(Wfc[e * 6 + k], dp[k], g);
+    gact[(long long)b * n_in + e] = f2bf(g);
+  }
+}
+
+// dL/dWfc[e][k] = sum_b act[b][e] dp[b][k] (samples in order), dL/dbfc[k] =
+// sum_b dp[b][k]; one lane per input e (lanes n_in.. n_in + 5 take the bias).
+__global__ void k_head_wgrad(const uint16_t *__restrict__ act, const float *__restrict__ dp,
+                             int B, int n_in, float *__restrict__ dW, float *__restrict__ db) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n_in) {
+    float g[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < B; ++b) {
+      const float x = bf2f(act[(long long)b * n_in + e]);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) g[k] = fmaf(x, dp[b * 6 + k], g[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) dW[e * 6 + k] = g[k];
+  } else if (e < n_in + 6) {
+    const int k = e - n_in;
+    float g = 0.f;
+    for (int b = 0; b < B; ++b) g += dp[b * 6 + k];
+    db[k] = g;
+  }
 }
 
 // sum of per-sample partials (fixed order)
@@ -636,17 +672,18 @@ extern "C" pvr_status pvr_cnn_head(const uint16_t *act, int32_t B, int32_t hw, c
                                    float *dbfc, float *scratch, hipStream_t stream) {
   PVR_API_BEGIN();
   if (!act || !wfc || !bfc || !pred || B <= 0 || hw <= 0) return fail(PVR_EINVAL, "pvr_cnn_head: invalid argument");
+  if ((long long)hw * 64 > (1 << 24)) return fail(PVR_ESHAPE, "pvr_cnn_head: hw too large");
   if (target && (!loss_w || !loss || !gact || !dwfc || !dbfc || !scratch))
     return fail(PVR_EINVAL, "pvr_cnn_head: training needs loss weights, outputs and scratch");
-  float *lp = scratch, *dwp = scratch ? scratch + (long long)B * 6 : nullptr,
-        *dbp = scratch ? dwp + (long long)B * 64 * 6 : nullptr;
-  hipLaunchKernelGGL(k_head, dim3(B), dim3(64), 0, stream, act, hw, wfc, bfc, target, loss_w, pred,
-                     lp, gact, dwp, dbp, 1.0f / B);
+  const int n_in = hw * 64;
+  float *lp = scratch, *dp = scratch ? scratch + (long long)B * 6 : nullptr;
+  hipLaunchKernelGGL(k_head, dim3(B), dim3(HEAD_THREADS), 0, stream, act, n_in, wfc, bfc, target,
+                     loss_w, pred, lp, dp, gact, 1.0f / B);
   HIP_TRY(hipGetLastError());
   if (target) {
     hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, stream, lp, B * 6, 1, loss);
-    hipLaunchKernelGGL(k_sum_rows, dim3(2), dim3(256), 0, stream, dwp, B, 64 * 6, dwfc);
-    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, stream, dbp, B, 6, dbfc);
+    hipLaunchKernelGGL(k_head_wgrad, dim3((n_in + 6 + 255) / 256), dim3(256), 0, stream, act, dp,
+                       B, n_in, dwfc, dbfc);
     HIP_TRY(hipGetLastError());
   }
   return PVR_OK;
@@ -654,7 +691,7 @@ extern "C" pvr_status pvr_cnn_head(const uint16_t *act, int32_t B, int32_t hw, c
 }
 
 extern "C" int64_t pvr_cnn_head_scratch(int32_t B) {
-  return ((long long)B * 6 + (long long)B * 64 * 6 + (long long)B * 6) * (long long)sizeof(float);
+  return (long long)B * 12 * (long long)sizeof(float);
 }
 
 extern "C" pvr_status pvr_cnn_adam(float *w, const float *g, float *m, float *v, int32_t n,

@@ -71,13 +71,14 @@ k_simulate_tiles(const ProbDev *__restrict__ probs, const PatchDev *__restrict__
   const bool staged = cnt > 0 && cnt <= lds_cap;
   const int dx = hi[0] - lo[0] + 1, dy = hi[1] - lo[1] + 1;
   if (staged) {
-    const int rows = dy * (hi[2] - lo[2] + 1);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int r = wave; r < rows; r += SIM_THREADS / 64) {
+    // the box as one flat index range: consecutive lanes take consecutive x
+    // of a row and continue into the next row, so no lane idles on short rows
+    const float *src0 = Xp + ((long long)lo[2] * pr.ny + lo[1]) * pr.nx + lo[0];
+    const long long zstride = (long long)pr.ny * pr.nx;
+    for (int e = threadIdx.x; e < cnt; e += SIM_THREADS) {
+      const int r = e / dx, x = e - r * dx;
       const int yy = r % dy, zz = r / dy;
-      const float *src = Xp + ((long long)(lo[2] + zz) * pr.ny + (lo[1] + yy)) * pr.nx + lo[0];
-      float *dst = xs + r * dx;
-      for (int x = lane; x < dx; x += 64) dst[x] = src[x];
+      xs[e] = src0[zz * zstride + (long long)yy * pr.nx + x];
     }
     __syncthreads();
   }
@@ -110,7 +111,7 @@ static pvr_status simulate_impl(const pvr_plan *p, const T *X, const T *y_obs, T
   if (!X) return fail(PVR_EINVAL, "pvr_simulate: X is NULL");
   if (resid && !y_obs) return fail(PVR_EINVAL, "pvr_simulate: resid requires y_obs");
   if (!y_sim && !resid) return PVR_OK;
-  if (sizeof(T) == 4 && p->lds_box > 0) {
+  if (sizeof(T) == 4 && p->use_tiles && p->lds_box > 0) {
     const int per = (p->n_tiles + 7) / 8;
     hipLaunchKernelGGL(k_simulate_tiles, dim3(8 * per), dim3(SIM_THREADS),
                        (size_t)p->lds_box * sizeof(float), stream, p->d_prob, p->d_patch,

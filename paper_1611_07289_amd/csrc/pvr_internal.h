@@ -285,6 +285,7 @@ struct pvr_plan {
   pvr::BlockWork *d_sim_blocks;
   pvr::TileWork *d_tiles;
   int n_tiles, tile_cap, tile_w, tile_h;
+  bool use_tiles;            // forward pass staged per tile in LDS (else global walk)
   int *d_box_max;            // [1] largest tile box (voxels) of the last build
   int lds_box;               // LDS floats reserved per forward workgroup
   int *d_brick_prob;         // [n_bricks]

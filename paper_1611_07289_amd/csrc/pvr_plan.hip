@@ -343,6 +343,7 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
     if (patches[s].w > 32767 || patches[s].h > 32767) return fail(PVR_ESHAPE, "pvr_plan_create: patch %d too large", s);
   p->tile_w = TILE;
   p->tile_h = TILE;
+  p->use_tiles = false;
   make_tiles(p, tiles);
   p->n_tiles = (int)tiles.size();
   std::vector<int> plane_prob;
@@ -465,9 +466,14 @@ extern "C" pvr_status pvr_plan_set_tiles(pvr_plan *p, int32_t tile_w, int32_t ti
                                          hipStream_t stream) {
   PVR_API_BEGIN();
   if (!p) return fail(PVR_EINVAL, "pvr_plan_set_tiles: plan is NULL");
+  if (tile_w == 0 && tile_h == 0) {
+    p->use_tiles = false;
+    return PVR_OK;
+  }
   if (tile_w <= 0 || tile_h <= 0 || tile_w * tile_h > 256)
-    return fail(PVR_EINVAL, "pvr_plan_set_tiles: need 0 < tile_w * tile_h <= 256");
+    return fail(PVR_EINVAL, "pvr_plan_set_tiles: need 0 < tile_w * tile_h <= 256 (or 0 x 0)");
   HIP_TRY(hipStreamSynchronize(stream));
+  p->use_tiles = true;
   p->tile_w = tile_w;
   p->tile_h = tile_h;
   std::vector<TileWork> tiles;
@@ -568,7 +574,7 @@ static pvr_status plan_build_common(pvr_plan *p, const uint8_t *active, const ui
   }
   HIP_TRY(hipGetLastError());
   // forward-tile boxes (LDS size of the staged forward pass)
-  {
+  if (p->use_tiles) {
     const pvr_status st = update_lds_box(p, stream);
     if (st != PVR_OK) return st;
   }

@@ -7,8 +7,8 @@ the unchanged motion when the proposal scores worse.
 Training pairs come from the library's own forward model: the observed patch
 is simulated at a reference motion, the second patch at that motion minus a
 random offset (rotation <= 10 deg, translation <= 5 mm); the target is the
-offset in radius-scaled units (rotation x patch half-diagonal, translation in
-mm).  Every arithmetic step runs in libpvr.so (include/pvr_cnn.h); torch
+offset expressed in the patch's own frame (in-plane u, v, slice normal), with
+rotations scaled by the patch half-diagonal (mm of displacement).  Every arithmetic step runs in libpvr.so (include/pvr_cnn.h); torch
 holds the device buffers.
 """
 from __future__ import annotations
@@ -26,6 +26,17 @@ from . import pvr
 LAYERS = [(2, 32, 1), (32, 32, 2), (32, 64, 1), (64, 64, 2),
           (64, 64, 1), (64, 64, 2), (64, 64, 1), (64, 64, 1)]
 SIDE = 64
+
+
+def _final_hw() -> int:
+    h = SIDE
+    for _, _, s in LAYERS:
+        h = (h - 1) // s + 1
+    return h * h
+
+
+HW = _final_hw()          # positions of the last feature map (8 x 8)
+N_FC = HW * 64 * 6        # head weights [HW][64][6]
 
 
 def _p(t):
@@ -65,13 +76,13 @@ class Net:
                                0.0, 0.9, 0.999, 1e-8, 0, _p(layer["wb"]), _p(layer["wt"]),
                                cout, cin, _s()))
             self.conv.append(layer)
-        self.wfc = (torch.randn(64 * 6, generator=g) * math.sqrt(1.0 / 64)).to(device)
+        self.wfc = (torch.randn(N_FC, generator=g) * math.sqrt(1.0 / (HW * 64))).to(device)
         self.bfc = torch.zeros(6, device=device)
-        self.mfc = torch.zeros(64 * 6, device=device)
-        self.vfc = torch.zeros(64 * 6, device=device)
+        self.mfc = torch.zeros(N_FC, device=device)
+        self.vfc = torch.zeros(N_FC, device=device)
         self.mbf = torch.zeros(6, device=device)
         self.vbf = torch.zeros(6, device=device)
-        self.dwfc = torch.zeros(64 * 6, device=device)
+        self.dwfc = torch.zeros(N_FC, device=device)
         self.dbfc = torch.zeros(6, device=device)
         self.loss_w = torch.ones(6, device=device)
         self.step_no = 0
@@ -145,7 +156,7 @@ class Net:
                                _p(layer["wt"]), layer["cout"], layer["cin"], _s()))
             _ck(L.pvr_cnn_adam(_p(layer["b"]), _p(layer["db"]), _p(layer["mb"]), _p(layer["vb"]),
                                layer["cout"], lr, 0.9, 0.999, 1e-8, t, None, None, 0, 0, _s()))
-        _ck(L.pvr_cnn_adam(_p(self.wfc), _p(self.dwfc), _p(self.mfc), _p(self.vfc), 64 * 6, lr,
+        _ck(L.pvr_cnn_adam(_p(self.wfc), _p(self.dwfc), _p(self.mfc), _p(self.vfc), N_FC, lr,
                            0.9, 0.999, 1e-8, t, None, None, 0, 0, _s()))
         _ck(L.pvr_cnn_adam(_p(self.bfc), _p(self.dbfc), _p(self.mbf), _p(self.vbf), 6, lr,
                            0.9, 0.999, 1e-8, t, None, None, 0, 0, _s()))
@@ -162,14 +173,34 @@ class Net:
         return self.forward(B).view(B, 6)
 
 
-def scale_vector(plan):
-    """Per-patch factors turning theta differences into the network's
-    targets: (rho, rho, rho, 1, 1, 1) with rho the patch half-diagonal."""
+def target_maps(plan):
+    """Per-patch linear maps between motion offsets and network targets:
+    target = A offset with A = diag(rho F^T, F^T), F the patch's stack frame
+    (columns: in-plane u, in-plane v, slice normal) and rho the patch
+    half-diagonal.  In the patch's own frame the same image change means the
+    same target on every stack orientation, which the network can learn;
+    rho turns rotations into the displacement (mm) of the farthest pixel.
+    Returns (A, A^-1) as float32 arrays [M][6][6]."""
     from .driver import patch_radius
     rho = patch_radius(plan)
-    sc = np.ones((plan.M, 6), np.float32)
-    sc[:, :3] = rho[:, None]
-    return sc
+    frames = []
+    for st in plan._s:
+        L = np.asarray(list(st.pix2world), float).reshape(3, 4)[:, :3]
+        frames.append(L / np.linalg.norm(L, axis=0))
+    A = np.zeros((plan.M, 6, 6))
+    Ai = np.zeros((plan.M, 6, 6))
+    for i in range(plan.M):
+        F = frames[plan._p[i].stack]
+        A[i, :3, :3] = rho[i] * F.T
+        A[i, 3:, 3:] = F.T
+        Ai[i, :3, :3] = F / rho[i]
+        Ai[i, 3:, 3:] = F
+    return A.astype(np.float32), Ai.astype(np.float32)
+
+
+def apply_maps(maps, v):
+    """maps [M][6][6] (device), v [M][6] -> [M][6]."""
+    return (maps @ v.unsqueeze(-1)).squeeze(-1)
 
 
 def make_pairs(plan, X, theta_ref, offsets, noise_sd: float, seed: int):
@@ -198,7 +229,7 @@ def train(net: Net, plan, volumes: List, n_pairs: int, batch: int = 256, lr: flo
     import torch
     from . import synth
     dev = volumes[0].device
-    sc = torch.from_numpy(scale_vector(plan)).to(dev)
+    A = torch.from_numpy(target_maps(plan)[0]).to(dev)
     M = plan.M
     rounds = max(1, int(math.ceil(n_pairs / M)))
     hist = []
@@ -214,7 +245,7 @@ def train(net: Net, plan, volumes: List, n_pairs: int, batch: int = 256, lr: flo
         off = torch.from_numpy(synth.random_motion(M, max_rot_deg, max_trans,
                                                    seed + 2 * r + 1).astype(np.float32)).to(dev)
         y_obs, y_sim = make_pairs(plan, X, ref, off, 0.01 * float(X.max()), seed + r)
-        target = off * sc
+        target = apply_maps(A, off)
         perm = torch.from_numpy(rng.permutation(M).astype(np.int32)).to(dev)
         torch.cuda.synchronize()
         t_data += time.perf_counter() - td
@@ -230,7 +261,7 @@ def train(net: Net, plan, volumes: List, n_pairs: int, batch: int = 256, lr: flo
             net.backward(batch)
             net.adam(lr)
             seen += batch
-            if (seen // batch) % 50 == 0:
+            if seen == batch or (seen // batch) % 50 == 0:
                 hist.append((seen, float(bf["loss"].item())))
                 if log:
                     log(f"[learned] pairs {seen} loss {hist[-1][1]:.4f}")
@@ -248,7 +279,7 @@ def init_fn_factory(net: Net, batch: int = 1024):
 
     def init_fn(plan, X, y, theta):
         dev = X.device
-        sc = torch.from_numpy(scale_vector(plan)).to(dev)
+        Ai = torch.from_numpy(target_maps(plan)[1]).to(dev)
         ysim = torch.empty(plan.N, dtype=torch.float32, device=dev)
         plan.build(theta)
         plan.simulate(X, y_sim=ysim)
@@ -261,7 +292,7 @@ def init_fn_factory(net: Net, batch: int = 1024):
             bf = net.buffers(B)
             bf["ids"].copy_(ids_all[b0:b0 + B])
             delta[b0:b0 + B] = net.predict(plan, y, ysim, bf["ids"], B)
-        prop = theta + delta / sc
+        prop = theta + apply_maps(Ai, delta)
         plan.build(prop)
         plan.simulate(X, y_sim=ysim)
         n_new = torch.empty(plan.M, device=dev)

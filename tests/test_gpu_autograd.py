@@ -1,12 +1,18 @@
 """Differentiable simulation (the forward model wrapped in
 torch.autograd.Function) against FP64 central finite differences of the
-oracle, step 1e-4, on the 48^3 three-stack case with 24x24 patches.
+oracle, step 3e-5, on the 48^3 three-stack case with 24x24 patches.
+
+The truncated Gaussian has a kink where a voxel enters or leaves a sample's
+support, and a sample's validity jumps where its centre crosses the volume
+border; a central difference across either is not a derivative.  Samples
+whose support voxel set or validity changes within +-h for any of the six
+parameters are therefore left out of the test loss (about 2 % at this step).
+With that, the differences converge as O(h^2) (relative change below 1e-7
+from h = 3e-5 to 3e-6 on this case).
 
 Tolerances: per-patch relative error of the six theta-derivatives <= 1e-6
 for the FP64 kernels and <= 1e-3 for the FP32 kernels; d/dX equals the
-oracle's A^T g.  Samples whose validity changes within +-h (a centre crossing
-the volume border) are left out of the test loss, because the loss itself is
-discontinuous there.
+oracle's A^T g.
 """
 import numpy as np
 import pytest
@@ -18,30 +24,33 @@ import torch  # noqa: E402  (CPU import is fine; GPU use is gated by the marker)
 import oracle
 from paper_1611_07289_amd import pvr, synth
 
-H = 1e-4
+H = 3e-5
 
 
 @pytest.fixture(scope="module")
 def diff():
-    print("[gpu] diff48 problem", flush=True)
+    print("[gpu] diff48 problem: finite differences", flush=True)
     P = synth.diff_problem()
     ctx = oracle.Ctx(P.grid, P.stacks, P.patches)
     th = P.theta_true.copy()
     rng = np.random.default_rng(17)
     g = rng.normal(size=P.N)
-    # patches under test and the samples whose validity is stable around theta
-    test_patches = np.sort(rng.choice(P.M, size=24, replace=False))
+    test_patches = np.sort(rng.choice(P.M, size=16, replace=False))
     off = P.patches.sample_off
     stable = np.ones(P.N, bool)
     _, _, v0 = ctx.simulate(P.x_true, th)
     for s in test_patches:
         idx = np.arange(off[s], off[s + 1])
+        base = [ctx.sample_row(th, j)[0] for j in idx]
         for k in range(6):
             for sgn in (-1, 1):
                 t2 = th.copy()
                 t2[s, k] += sgn * H
                 _, _, vv = ctx.simulate(P.x_true, t2, samples=idx)
                 stable[idx] &= (vv == v0[idx])
+                for q, j in enumerate(idx):
+                    if stable[j]:
+                        stable[j] = np.array_equal(ctx.sample_row(t2, j)[0], base[q])
     g = np.where(stable, g, 0.0)
     fd = np.zeros((len(test_patches), 6))
     for q, s in enumerate(test_patches):
@@ -53,6 +62,8 @@ def diff():
             yp, _, _ = ctx.simulate(P.x_true, tp, samples=idx)
             ym, _, _ = ctx.simulate(P.x_true, tm, samples=idx)
             fd[q, k] = (g[idx] @ yp - g[idx] @ ym) / (2 * H)
+    kept = stable[np.concatenate([np.arange(off[s], off[s + 1]) for s in test_patches])].mean()
+    print(f"[gpu] finite differences ready ({kept:.3f} of the tested samples kept)", flush=True)
     return dict(P=P, ctx=ctx, th=th, g=g, test_patches=test_patches, fd=fd)
 
 
@@ -67,7 +78,7 @@ def _grad(d, dtype):
     gy = torch.tensor(d["g"], dtype=dtype, device="cuda")
     (y * gy).sum().backward()
     torch.cuda.synchronize()
-    return X.grad.double().cpu().numpy(), th.grad.double().cpu().numpy(), y.double().cpu().numpy()
+    return X.grad.double().cpu().numpy(), th.grad.double().cpu().numpy(), y.detach().double().cpu().numpy()
 
 
 def _check_theta(d, gth, tol):
@@ -111,9 +122,10 @@ def test_volume_gradient_matches_fd(diff):
     gX, _, _ = _grad(diff, torch.float64)
     dX = np.random.default_rng(3).normal(size=P.grid.n_voxels)
     X = np.asarray(P.x_true, np.float64).reshape(-1)
-    yp, _, _ = ctx.simulate(X + H * dX, diff["th"])
-    ym, _, _ = ctx.simulate(X - H * dX, diff["th"])
-    fd = (diff["g"] @ yp - diff["g"] @ ym) / (2 * H)
+    hx = 1.0  # the loss is linear in X: any step is exact up to rounding
+    yp, _, _ = ctx.simulate(X + hx * dX, diff["th"])
+    ym, _, _ = ctx.simulate(X - hx * dX, diff["th"])
+    fd = (diff["g"] @ yp - diff["g"] @ ym) / (2 * hx)
     assert gX @ dX == pytest.approx(fd, rel=1e-8)
 
 

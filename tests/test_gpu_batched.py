@@ -13,6 +13,8 @@ import oracle
 from oracle import recon
 from paper_1611_07289_amd import pvr, synth
 
+from tests._tolerance import adjoint_bar
+
 
 @pytest.fixture(scope="module")
 def batch():
@@ -60,9 +62,11 @@ def test_batched_simulate_and_backproject_match_oracle(batch):
         assert (np.abs(yg - yo) / scale).max() <= 1e-5, b
         rb = _split(plan, probs, r, "s")[b].astype(np.float64)
         bo = ctx.backproject(batch["th64"][b], rb).reshape(-1)
-        ba = ctx.backproject(batch["th64"][b], np.abs(rb)).reshape(-1)
+        bar = adjoint_bar(ctx, batch["th64"][b], rb)
         bg = _split(plan, probs, num.cpu().numpy(), "v")[b]
-        assert (np.abs(bg - bo) / (ba + 1e-30)).max() <= 1e-5, b
+        worst = (np.abs(bg - bo) / (bar + 1e-30)).max()
+        print(f"[gpu] problem {b}: backproject worst error / bar {worst:.2e}")
+        assert worst <= 1.0, b
 
 
 class Eager:

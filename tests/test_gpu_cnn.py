@@ -81,7 +81,7 @@ def test_head_matches_reference():
     rng = np.random.default_rng(9)
     B, hw = 5, 64
     act = _bf(np.abs(rng.normal(size=(B, hw, 64))))
-    wfc = rng.normal(size=(64, 6)).astype(np.float32) * 0.2
+    wfc = rng.normal(size=(hw, 64, 6)).astype(np.float32) * 0.02
     bfc = rng.normal(size=6).astype(np.float32)
     tgt = rng.normal(size=(B, 6)).astype(np.float32)
     lw = np.array([1, 1, 1, 2, 2, 2], np.float32)
@@ -91,7 +91,7 @@ def test_head_matches_reference():
     pred = torch.empty(B * 6, device="cuda")
     loss = torch.empty(1, device="cuda")
     gact = torch.empty(B * hw * 64, dtype=torch.bfloat16, device="cuda")
-    dwfc = torch.empty(64 * 6, device="cuda")
+    dwfc = torch.empty(hw * 64 * 6, device="cuda")
     dbfc = torch.empty(6, device="cuda")
     scr = torch.empty(L.pvr_cnn_head_scratch(B) // 4 + 16, device="cuda")
     tw, tb, tt, tl = t(wfc), t(bfc), t(tgt), t(lw)
@@ -116,33 +116,45 @@ def small():
     return P, plan, X
 
 
-def test_training_reduces_loss_and_prediction_helps(small):
-    """Training on forward-model pairs lowers the loss, and on held-out
-    offsets the predicted correction leaves a clearly smaller motion error
-    than no correction at all."""
-    P, plan, X = small
-    net = learned.Net(seed=7)
-    res = learned.train(net, plan, [X], n_pairs=60_000, batch=128, lr=2e-3, seed=600,
-                        log=lambda m: print(m, flush=True))
-    losses = [l for _, l in res["loss"]]
-    print(f"[gpu] training: {res['pairs']} pairs in {res['seconds']:.1f} s; loss {losses[0]:.3f} -> "
-          f"{losses[-1]:.3f}")
-    assert losses[-1] < 0.6 * losses[0]
-    # held-out offsets on the same volume
+def _heldout_rel_mse(net, plan, X):
+    """Per-component mean squared error of the prediction over held-out
+    offsets, relative to the targets' mean square (1 = no better than
+    predicting no correction)."""
     dev = X.device
-    sc = torch.from_numpy(learned.scale_vector(plan)).to(dev)
+    A = torch.from_numpy(learned.target_maps(plan)[0]).to(dev)
     ref = torch.from_numpy(synth.random_motion(plan.M, 10, 5, 9001).astype(np.float32)).to(dev)
     off = torch.from_numpy(synth.random_motion(plan.M, 10, 5, 9002).astype(np.float32)).to(dev)
     y_obs, y_sim = learned.make_pairs(plan, X, ref, off, 0.01 * float(X.max()), 9003)
+    tgt = learned.apply_maps(A, off)
     B = 128
-    errs0, errs1 = [], []
+    se = torch.zeros(6, device=dev, dtype=torch.float64)
+    ms = torch.zeros(6, device=dev, dtype=torch.float64)
     for b0 in range(0, plan.M - B + 1, B):
         ids = torch.arange(b0, b0 + B, dtype=torch.int32, device=dev)
-        pred = net.predict(plan, y_obs, y_sim, ids, B).clone()
-        tgt = (off * sc)[b0:b0 + B]
-        errs0.append(tgt.norm(dim=1))
-        errs1.append((tgt - pred).norm(dim=1))
-    e0 = torch.cat(errs0).median().item()
-    e1 = torch.cat(errs1).median().item()
-    print(f"[gpu] held-out median scaled motion error: none {e0:.3f}, learned {e1:.3f}")
-    assert e1 < 0.6 * e0
+        pred = net.predict(plan, y_obs, y_sim, ids, B).double()
+        t = tgt[b0:b0 + B].double()
+        se += ((t - pred) ** 2).sum(0)
+        ms += (t ** 2).sum(0)
+    return (se / ms).cpu().numpy()
+
+
+def test_training_reduces_loss_and_prediction_helps(small):
+    """Training on forward-model pairs lowers the loss, and on held-out
+    offsets the prediction recovers the in-plane components of the offset
+    (translation along u and v, rotation about the slice normal), which a
+    single observed / simulated pair determines.  The out-of-plane
+    components are reported only: from one pair the sign of a through-plane
+    shift is ambiguous."""
+    P, plan, X = small
+    net = learned.Net(seed=7)
+    before = _heldout_rel_mse(net, plan, X)
+    res = learned.train(net, plan, [X], n_pairs=300_000, batch=128, lr=1e-3, seed=600)
+    losses = [l for _, l in res["loss"]]
+    after = _heldout_rel_mse(net, plan, X)
+    print(f"[gpu] training: {res['pairs']} pairs in {res['seconds']:.1f} s; batch loss "
+          f"{losses[0]:.3f} -> {np.mean(losses[-5:]):.3f} (mean of the last 5 logs)")
+    print(f"[gpu] held-out relative MSE (rot u, rot v, rot n, t u, t v, t n): before "
+          f"{np.round(before, 3)}, after {np.round(after, 3)}")
+    assert np.mean(losses[-5:]) < 0.7 * losses[0]
+    assert np.all(after[2:5] < 0.6)
+    assert after.mean() < 0.8

@@ -2,9 +2,10 @@
 
 Tolerances (per-sample and volume bars of the hot path):
   * simulated samples: |y_gpu - y_ora| <= 1e-5 * max(|y_ora|, 1e-3 max|y_ora|);
-  * adjoint voxels: |b_gpu - b_ora| <= 1e-5 * (A^T |r|)_i + 1e-30 (error
+  * adjoint voxels: |b_gpu - b_ora| <= 1e-5 * ((A^T |r|)_i + edge) (error
     relative to the sum of absolute contributions, so cancellation in signed
-    sums cannot hide or fake a mismatch);
+    sums cannot hide or fake a mismatch, plus one sample's support-edge term
+    exp(-k^2/2) max |r_j| / Z_j, tests/_tolerance.py);
   * volumes after SR iterations: relative L2 <= 1e-4;
   * integer decisions (sample validity, patch exclusion) exactly, except
     patches whose mixture posterior lies within 1e-3 of the 0.5 threshold.
@@ -23,6 +24,7 @@ from oracle import em as oem
 from oracle import recon
 from oracle.update import sr_update as ora_update
 from paper_1611_07289_amd import pvr, synth
+from tests._tolerance import adjoint_bar
 
 
 def dev(a, dtype=None):
@@ -89,6 +91,26 @@ def test_simulate_matches_oracle(tiny):
     assert np.allclose(rr[val], tiny["y"][val] - host(ys)[val], atol=1e-3)
 
 
+@pytest.mark.parametrize("tile", [(16, 16), (8, 32), (64, 4), (5, 7)])
+def test_lds_tiled_simulate_matches_oracle(tiny, tile):
+    """The LDS-staged forward pass (whole tiles, ragged edge tiles, a shape
+    that divides no patch) against the oracle; afterwards the global walk is
+    restored."""
+    P, ctx, plan, th32 = tiny["P"], tiny["ctx"], tiny["plan"], tiny["th32"]
+    X = dev(P.x_true)
+    ys = torch.empty(plan.N, dtype=torch.float32, device="cuda")
+    try:
+        plan.set_tiles(*tile)
+        plan.simulate(X, y_sim=ys)
+        got = host(ys)
+    finally:
+        plan.set_tiles(0, 0)
+    yo, _, _ = ctx.simulate(P.x_true, th32)
+    worst, _ = sample_close(got, yo)
+    print(f"[gpu] tiles {tile}: simulate worst per-sample rel err {worst:.2e}")
+    assert worst <= 1e-5
+
+
 def test_backproject_matches_oracle_and_is_deterministic(tiny):
     P, ctx, plan, th32 = tiny["P"], tiny["ctx"], tiny["plan"], tiny["th32"]
     rng = np.random.default_rng(0)
@@ -103,13 +125,12 @@ def test_backproject_matches_oracle_and_is_deterministic(tiny):
     assert np.array_equal(host(num), n1) and np.array_equal(host(den), d1), "not bitwise repeatable"
     ws = w.astype(np.float64)[ctx.patch_of_sample]
     ro = ctx.backproject(th32, ws * p * r).reshape(-1)
-    rabs = ctx.backproject(th32, np.abs(ws * p * r)).reshape(-1)
     do = ctx.backproject(th32, ws * p).reshape(-1)
-    err = np.abs(n1 - ro) / (rabs + 1e-30)
-    print(f"[gpu] backproject worst rel err (vs sum |contrib|) {err.max():.2e}")
-    assert err.max() <= 1e-5
-    errd = np.abs(d1 - do) / (do + 1e-30)
-    assert errd.max() <= 1e-5
+    err = np.abs(n1 - ro) / (adjoint_bar(ctx, th32, ws * p * r) + 1e-30)
+    print(f"[gpu] backproject worst error / bar {err.max():.2e}")
+    assert err.max() <= 1.0
+    errd = np.abs(d1 - do) / (adjoint_bar(ctx, th32, ws * p) + 1e-30)
+    assert errd.max() <= 1.0
 
 
 def test_adjoint_identity_fp32(tiny):

@@ -42,14 +42,36 @@ def test_conv_gradients_match_finite_differences():
 
 
 def test_head_gradients():
+    """Prediction against a plain loop; loss and every gradient against
+    central differences of the loss (the loss is quadratic in each argument,
+    so central differences are exact up to rounding)."""
     rng = np.random.default_rng(2)
-    act = rng.normal(size=(3, 4, 64))
-    wfc, bfc = rng.normal(size=(64, 6)), rng.normal(size=6)
-    tgt, lw = rng.normal(size=(3, 6)), np.array([1, 2, 1, 1, 0.5, 1.0])
+    B, hw = 3, 4
+    act = rng.normal(size=(B, hw, 64))
+    wfc, bfc = rng.normal(size=(hw, 64, 6)), rng.normal(size=6)
+    tgt, lw = rng.normal(size=(B, 6)), np.array([1, 2, 1, 1, 0.5, 1.0])
     pred, loss, ga, gw, gb = cnn.head(act, wfc, bfc, tgt, lw)
-    assert np.allclose(pred, act.mean(1) @ wfc + bfc)
-    assert loss == pytest.approx(((pred - tgt) ** 2 * lw).sum() / 6)
-    d = (pred - tgt) * lw / 3
-    assert np.allclose(gb, d.sum(0))
-    assert np.allclose(gw, act.mean(1).T @ d)
-    assert np.allclose(ga, np.repeat((d @ wfc.T)[:, None, :] / 4, 4, axis=1))
+    ref = np.zeros((B, 6))
+    for b in range(B):
+        for k in range(6):
+            ref[b, k] = bfc[k] + sum(act[b, q, c] * wfc[q, c, k] for q in range(hw) for c in range(64))
+    assert np.allclose(pred, ref, rtol=1e-12, atol=1e-12)
+    assert loss == pytest.approx(sum(lw[k] * (ref[b, k] - tgt[b, k]) ** 2
+                                     for b in range(B) for k in range(6)) / (2 * B))
+
+    def L(a=act, w=wfc, bb=bfc):
+        return cnn.head(a, w, bb, tgt, lw)[1]
+
+    h = 1e-3
+    for idx in [(0, 0, 0), (2, 3, 63), (1, 2, 17)]:
+        ap, am = act.copy(), act.copy()
+        ap[idx] += h; am[idx] -= h
+        assert ga[idx] == pytest.approx((L(a=ap) - L(a=am)) / (2 * h), rel=1e-7, abs=1e-10)
+    for idx in [(0, 0, 0), (3, 63, 5), (1, 30, 2)]:
+        wp, wm = wfc.copy(), wfc.copy()
+        wp[idx] += h; wm[idx] -= h
+        assert gw[idx] == pytest.approx((L(w=wp) - L(w=wm)) / (2 * h), rel=1e-7, abs=1e-10)
+    for k in range(6):
+        bp, bm = bfc.copy(), bfc.copy()
+        bp[k] += h; bm[k] -= h
+        assert gb[k] == pytest.approx((L(bb=bp) - L(bb=bm)) / (2 * h), rel=1e-7, abs=1e-10)
