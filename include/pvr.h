@@ -66,6 +66,10 @@
 extern "C" {
 #endif
 
+/* Largest number of patches of one problem (the patch classification keeps
+ * a problem's patch potentials in one workgroup's registers). */
+#define PVR_MAX_PROBLEM_PATCHES 65536
+
 typedef enum {
   PVR_OK = 0,
   PVR_EINVAL = 1,       /* null / inconsistent argument */
@@ -161,7 +165,9 @@ const char *pvr_version(void);
  * valid stacks and lie inside their slice; every stack names a valid problem.
  * cutoff_k: PSF support radius in standard deviations (> 0, default 3).
  * Errors: PVR_EINVAL for null pointers or out-of-range indices, PVR_ESHAPE
- * for non-orthogonal stack axes or empty sizes, PVR_ENOMEM, PVR_EHIP. */
+ * for non-orthogonal stack axes, empty sizes, a grid beyond 2^29 voxels, a
+ * problem with more than PVR_MAX_PROBLEM_PATCHES patches, or a patch beyond
+ * 32767 pixels per side or 2^26 pixels, PVR_ENOMEM, PVR_EHIP. */
 pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
                            const pvr_stack *stacks, int32_t n_stacks,
                            const pvr_patch *patches, int32_t n_patches,

@@ -58,6 +58,9 @@ def lib():
         L.ora_sample_row.argtypes = [P, P, i64, P, P, ctypes.c_int]
         L.ora_backproject.argtypes = [P, P, P, P, P, P]
         L.ora_backproject_voxels.argtypes = [P, P, P, P, P, i64, P, P]
+        L.ora_support_backproject.argtypes = [P, P, P, P, P, P]
+        L.ora_valid.argtypes = [P, P, P, P, P]
+        L.ora_support_backproject_voxels.argtypes = [P, P, P, P, P, i64, P, P]
         L.ora_ncc.argtypes = [P, P, P, P, P, P]
         L.ora_register.argtypes = [P, P, P, P, P, P, ctypes.c_double,
                                    ctypes.c_double, ctypes.c_double,
@@ -146,6 +149,13 @@ class Ctx:
                            _p(Z), _p(val))
         return yh, Z, val.astype(bool)
 
+    def valid(self, theta, mask=None, active=None):
+        """Validity of every sample (as simulate reports it), cheaply."""
+        th = _f64(theta).reshape(-1)
+        out = np.zeros(self.N, np.uint8)
+        lib().ora_valid(self._h, _p(th), _p(_u8(mask)), _p(_u8(active)), _p(out))
+        return out.astype(bool)
+
     def sample_row(self, theta, j: int, cap: int = 4096):
         th = _f64(theta).reshape(-1)
         idx = np.zeros(cap, np.int64); w = np.zeros(cap)
@@ -154,24 +164,27 @@ class Ctx:
             raise RuntimeError("row capacity too small")
         return idx[:n].copy(), w[:n].copy()
 
-    def backproject(self, theta, r, mask=None, active=None):
-        """A^T r over the whole grid, shape (nz, ny, nx)."""
+    def backproject(self, theta, r, mask=None, active=None, support=False):
+        """A^T r over the whole grid, shape (nz, ny, nx).  support=True
+        replaces every weight psi_ji by 1/Z_j on the support."""
         th = _f64(theta).reshape(-1)
         r = _f64(r).reshape(-1)
         out = np.zeros(self.V)
         m = _u8(mask); a = _u8(active)
-        lib().ora_backproject(self._h, _p(th), _p(m), _p(a), _p(r), _p(out))
+        f = lib().ora_support_backproject if support else lib().ora_backproject
+        f(self._h, _p(th), _p(m), _p(a), _p(r), _p(out))
         return out.reshape(self.shape)
 
-    def backproject_voxels(self, theta, r, voxels, mask=None, active=None):
-        """(A^T r)_i for the listed flat voxel indices, one at a time."""
+    def backproject_voxels(self, theta, r, voxels, mask=None, active=None, support=False):
+        """(A^T r)_i for the listed flat voxel indices, one at a time
+        (support=True: as in backproject)."""
         th = _f64(theta).reshape(-1)
         r = _f64(r).reshape(-1)
         vox = np.ascontiguousarray(voxels, np.int64)
         out = np.zeros(vox.size)
         m = _u8(mask); a = _u8(active)
-        lib().ora_backproject_voxels(self._h, _p(th), _p(m), _p(a), _p(r),
-                                     vox.size, _p(vox), _p(out))
+        f = lib().ora_support_backproject_voxels if support else lib().ora_backproject_voxels
+        f(self._h, _p(th), _p(m), _p(a), _p(r), vox.size, _p(vox), _p(out))
         return out
 
     # -- registration -----------------------------------------------------------

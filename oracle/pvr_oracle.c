@@ -285,6 +285,44 @@ static int patch_of(const ora_ctx *C, int64_t j) {
   return lo;
 }
 
+/* Validity of every sample by the rule of sim_sample (centre inside the
+ * voxel box and Z > 0, unmasked, patch active), without the support walk
+ * where it is not needed: Z >= the weight of any one voxel, so a positive
+ * weight at the nearest voxel settles Z > 0; only otherwise is Z summed. */
+void ora_valid(const ora_ctx *C, const double *theta, const uint8_t *mask,
+               const uint8_t *active, uint8_t *valid) {
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int s = 0; s < C->M; ++s) {
+    pgeo g;
+    patch_geometry(C, s, theta + 6 * s, &g);
+    for (int64_t l = 0; l < (int64_t)g.w * g.h; ++l) {
+      const int64_t j = C->off[s] + l;
+      int ok = !(mask && !mask[j]) && !(active && !active[s]);
+      if (ok) {
+        const int u = g.x0 + (int)(l % g.w), v = g.y0 + (int)(l / g.w);
+        double x[3], xv[3];
+        int lo[3], hi[3];
+        sample_centre(&g, u, v, x);
+        ok = support_box(C, &g, x, lo, hi);
+        if (ok) {
+          apply_affine(C->w2v, x, xv);
+          int n[3];
+          for (int b = 0; b < 3; ++b) {
+            n[b] = (int)floor(xv[b] + 0.5);
+            if (n[b] < 0) n[b] = 0;
+            if (n[b] > C->dims[b] - 1) n[b] = C->dims[b] - 1;
+          }
+          if (!(psf_hat(C, &g, x, n[0], n[1], n[2]) > 0)) {
+            double yh, Z;
+            ok = sim_sample(C, &g, NULL, u, v, &yh, &Z);
+          }
+        }
+      }
+      valid[j] = (uint8_t)ok;
+    }
+  }
+}
+
 /* y_hat = A X for the listed samples (all when list == NULL); Z and valid
  * are written for the same samples.  theta is [M][6]. */
 void ora_simulate(const ora_ctx *C, const double *X, const double *theta,
@@ -343,8 +381,13 @@ int ora_sample_row(const ora_ctx *C, const double *theta, int64_t j,
  * adds psi_ji * r_j to voxel i.  Patches are split into a fixed number of
  * chunks with private accumulators summed in chunk order, so the result does
  * not depend on the thread count. */
-void ora_backproject(const ora_ctx *C, const double *theta, const uint8_t *mask,
-                     const uint8_t *active, const double *r, double *out) {
+/* indicator = 0: (A^T r)_i = sum_j psi_ji r_j.  indicator = 1: the same sum
+ * with psi_ji replaced by 1/Z_j on the support (the transpose of the
+ * support indicator, scaled by 1/Z_j), used to size the rounding error of
+ * the weights near the support edge. */
+static void backproject_impl(const ora_ctx *C, const double *theta, const uint8_t *mask,
+                             const uint8_t *active, const double *r, int indicator,
+                             double *out) {
   const int64_t V = (int64_t)C->dims[0] * C->dims[1] * C->dims[2];
   const int NCH = 8;
   double *buf = (double *)calloc((size_t)NCH * V, sizeof(double));
@@ -371,7 +414,7 @@ void ora_backproject(const ora_ctx *C, const double *theta, const uint8_t *mask,
             for (int i = lo[0]; i <= hi[0]; ++i) {
               double w = psf_hat(C, &g, x, i, jj, kk);
               if (w < 0) continue;
-              acc[((int64_t)kk * ny + jj) * nx + i] += w / Z * r[j];
+              acc[((int64_t)kk * ny + jj) * nx + i] += (indicator ? 1.0 : w) / Z * r[j];
             }
       }
     }
@@ -388,10 +431,10 @@ void ora_backproject(const ora_ctx *C, const double *theta, const uint8_t *mask,
  * the definition: every sample whose support holds the voxel contributes
  * psi_ji r_j.  A patch is skipped only when the voxel is farther from its
  * centre than the patch half-diagonal plus the largest support radius. */
-void ora_backproject_voxels(const ora_ctx *C, const double *theta,
-                            const uint8_t *mask, const uint8_t *active,
-                            const double *r, int64_t n_vox,
-                            const int64_t *vox, double *out) {
+static void backproject_voxels_impl(const ora_ctx *C, const double *theta,
+                                    const uint8_t *mask, const uint8_t *active,
+                                    const double *r, int indicator, int64_t n_vox,
+                                    const int64_t *vox, double *out) {
   const int nx = C->dims[0], ny = C->dims[1];
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t q = 0; q < n_vox; ++q) {
@@ -425,11 +468,35 @@ void ora_backproject_voxels(const ora_ctx *C, const double *theta,
         if (w < 0) continue;
         double yh, Z;
         if (!sim_sample(C, &g, NULL, u, v, &yh, &Z)) continue;
-        acc += w / Z * r[j];
+        acc += (indicator ? 1.0 : w) / Z * r[j];
       }
     }
     out[q] = acc;
   }
+}
+
+void ora_backproject(const ora_ctx *C, const double *theta, const uint8_t *mask,
+                     const uint8_t *active, const double *r, double *out) {
+  backproject_impl(C, theta, mask, active, r, 0, out);
+}
+
+void ora_support_backproject(const ora_ctx *C, const double *theta, const uint8_t *mask,
+                             const uint8_t *active, const double *r, double *out) {
+  backproject_impl(C, theta, mask, active, r, 1, out);
+}
+
+void ora_backproject_voxels(const ora_ctx *C, const double *theta,
+                            const uint8_t *mask, const uint8_t *active,
+                            const double *r, int64_t n_vox,
+                            const int64_t *vox, double *out) {
+  backproject_voxels_impl(C, theta, mask, active, r, 0, n_vox, vox, out);
+}
+
+void ora_support_backproject_voxels(const ora_ctx *C, const double *theta,
+                                    const uint8_t *mask, const uint8_t *active,
+                                    const double *r, int64_t n_vox,
+                                    const int64_t *vox, double *out) {
+  backproject_voxels_impl(C, theta, mask, active, r, 1, n_vox, vox, out);
 }
 
 /* Cross-correlation of the observed patch and its simulation at th

@@ -47,40 +47,106 @@ k_bp_prep(const PatchDev *__restrict__ patches, const BlockWork *__restrict__ wo
   }
 }
 
+// Raw buffer view of one patch's n rq entries plus one entry on either side
+// (the neighbouring patches' entries, or the zero guards around the whole
+// array), so byte offset (i + 1) sizeof(V2) addresses entry i, i in [-1, n].
+// A buffer load never faults: outside the view it returns 0, so candidate
+// pixels off the patch need no address clamp.  Their weights are zeroed
+// explicitly, so whatever such a load returns never contributes.  The one
+// entry of margin matters because the compiler merges the loads of two
+// adjacent candidates into one 16-byte load, and a partly out-of-range load
+// may return 0 for all of it: with the margin, a pair holding an in-patch
+// entry is always wholly in range.
+template <typename V2>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t patch_rsrc(const V2 *patch_base, int n) {
+  return __builtin_amdgcn_make_buffer_rsrc((void *)(patch_base - 1), (short)0,
+                                           (n + 2) * (int)sizeof(V2), 0x00020000);
+}
+
+template <typename V2> __device__ __forceinline__ V2 load_rq(__amdgpu_buffer_rsrc_t r, int off);
+template <> __device__ __forceinline__ float2 load_rq<float2>(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ double2 load_rq<double2>(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
+// max(a b - c, 0) for a b - c in [-1, 1]: one FMA with the output clamp.
+template <typename T> __device__ __forceinline__ T fma_clamp0(T a, T b, T c);
+template <> __device__ __forceinline__ float fma_clamp0<float>(float a, float b, float c) {
+  return __builtin_amdgcn_fmed3f(fmaf(a, b, -c), 0.f, 1.f);
+}
+template <> __device__ __forceinline__ double fma_clamp0<double>(double a, double b, double c) {
+  return fmax(fma(a, b, -c), 0.0);
+}
+
 // Contribution of one patch to one voxel mapped to pixel coordinates
 // (pu, pv) with normalised through-plane term qk.  The candidate pixels are
-// rint(p) + [-h, h] on both axes (a superset of the integers inside the
-// in-plane support ellipse); candidates outside the support or the patch get
-// weight 0 and read a clamped, in-patch address.
-template <typename T, typename GEO, typename V2, int HU, int HV>
+// rint(p) + [-HU, HU] x [-HV, HV] (a superset of the integers inside the
+// in-plane support ellipse).  The weight factorises over the axes of the
+// patch frame, 2^-Q = 2^-(qk + wv^2) 2^-(wu^2), so a candidate costs one
+// product; rows and columns outside the patch get the factor 0, and
+// 2^-Q - 2^-K2 is clamped at 0 outside the support (every value lies in
+// [-1, 1], so the clamp to [0, 1] is exact).
+template <typename T, typename GEO, typename V2, int HU, int HV, bool DEN>
 __device__ __forceinline__ void adj_patch(const GEO &g, const PatchDev &pt, double pu, double pv,
-                                          T qk, int hu_rt, int hv_rt,
-                                          const V2 *__restrict__ rq, T &sn, T &sd) {
-  const int hu = HU > 0 ? HU : hu_rt, hv = HV > 0 ? HV : hv_rt;
+                                          T qk, const V2 *__restrict__ rq, T &sn, T &sd) {
   const double rud = rint(pu), rvd = rint(pv);
-  const int ru = (int)rud, rv = (int)rvd;
+  const int ru = (int)rud - pt.x0, rv = (int)rvd - pt.y0;  // patch-local nearest pixel
   const T fu = (T)(pu - rud), fv = (T)(pv - rvd);
-  const T cu = (T)g.cu, cv = (T)g.cv, K2 = (T)g.K2, cut = (T)g.cut;
-  const int x1 = pt.x0 + pt.w - 1, y1 = pt.y0 + pt.h - 1;
-  const V2 *base = rq + pt.off;
+  const T cu = (T)g.cu, cv = (T)g.cv, cut = (T)g.cut;
+  T U[2 * HU + 1], E[2 * HV + 1];
 #pragma unroll
+  for (int a = -HU; a <= HU; ++a) {
+    const T wu = ((T)a - fu) * cu;
+    const bool in = (unsigned)(ru + a) < (unsigned)pt.w;
+    U[a + HU] = in ? fast_exp2<T>(-wu * wu) : (T)0;
+  }
+#pragma unroll
+  for (int b = -HV; b <= HV; ++b) {
+    const T wv = ((T)b - fv) * cv;
+    const bool in = (unsigned)(rv + b) < (unsigned)pt.h;
+    E[b + HV] = in ? fast_exp2<T>(-fma(wv, wv, qk)) : (T)0;
+  }
+  const __amdgpu_buffer_rsrc_t r = patch_rsrc(rq + pt.off, pt.w * pt.h);
+  const int row_bytes = pt.w * (int)sizeof(V2);
+  int off = ((rv - HV) * pt.w + (ru - HU) + 1) * (int)sizeof(V2);
+#pragma unroll
+  for (int b = 0; b < 2 * HV + 1; ++b) {
+#pragma unroll
+    for (int a = 0; a < 2 * HU + 1; ++a) {
+      const T gh = fma_clamp0<T>(E[b], U[a], cut);
+      const V2 q = load_rq<V2>(r, off + a * (int)sizeof(V2));
+      sn = fma(gh, q.x, sn);
+      if (DEN) sd = fma(gh, q.y, sd);
+    }
+    off += row_bytes;
+  }
+}
+
+// Candidate grids wider than the unrolled shapes (PSF much wider than a
+// pixel): the same arithmetic with run-time half-widths, one exponential
+// per candidate.
+template <typename T, typename GEO, typename V2, bool DEN>
+__device__ __forceinline__ void adj_patch_rt(const GEO &g, const PatchDev &pt, double pu, double pv,
+                                             T qk, const V2 *__restrict__ rq, T &sn, T &sd) {
+  const int hu = g.hu, hv = g.hv;
+  const double rud = rint(pu), rvd = rint(pv);
+  const int ru = (int)rud - pt.x0, rv = (int)rvd - pt.y0;
+  const T fu = (T)(pu - rud), fv = (T)(pv - rvd);
+  const T cu = (T)g.cu, cv = (T)g.cv, cut = (T)g.cut;
+  const __amdgpu_buffer_rsrc_t r = patch_rsrc(rq + pt.off, pt.w * pt.h);
   for (int b = -hv; b <= hv; ++b) {
-    const int v = rv + b;
     const T wv = ((T)b - fv) * cv;
     const T qkv = fma(wv, wv, qk);
-    const bool vok = (v >= pt.y0) & (v <= y1);
-    const int vrow = (min(max(v, pt.y0), y1) - pt.y0) * pt.w;
-#pragma unroll
+    const int row = (rv + b) * pt.w;
     for (int a = -hu; a <= hu; ++a) {
-      const int u = ru + a;
       const T wu = ((T)a - fu) * cu;
-      const T Q = fma(wu, wu, qkv);
-      const bool ok = vok & (u >= pt.x0) & (u <= x1) & (Q <= K2);
-      T gh = fast_exp2<T>(-Q) - cut;
-      gh = ok ? (gh > (T)0 ? gh : (T)0) : (T)0;
-      const V2 r = base[vrow + (min(max(u, pt.x0), x1) - pt.x0)];
-      sn = fma(gh, r.x, sn);
-      sd = fma(gh, r.y, sd);
+      const bool in = ((unsigned)(ru + a) < (unsigned)pt.w) & ((unsigned)(rv + b) < (unsigned)pt.h);
+      const T gh = in ? fma_clamp0<T>(fast_exp2<T>(-fma(wu, wu, qkv)), (T)1, cut) : (T)0;
+      const V2 q = load_rq<V2>(r, (row + ru + a + 1) * (int)sizeof(V2));
+      sn = fma(gh, q.x, sn);
+      if (DEN) sd = fma(gh, q.y, sd);
     }
   }
 }
@@ -121,9 +187,11 @@ k_backproject(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ pa
     const double pu = fma(g.G[0], fi, fma(g.G[1], fj, fma(g.G[2], fk, g.G[3])));
     const double pv = fma(g.G[4], fi, fma(g.G[5], fj, fma(g.G[6], fk, g.G[7])));
     if (g.hu == 1 && g.hv == 1)
-      adj_patch<T, GEO, V2, 1, 1>(g, pt, pu, pv, qk, 1, 1, rq, sn, sd);
+      adj_patch<T, GEO, V2, 1, 1, DEN>(g, pt, pu, pv, qk, rq, sn, sd);
+    else if (g.hu <= 2 && g.hv <= 2)
+      adj_patch<T, GEO, V2, 2, 2, DEN>(g, pt, pu, pv, qk, rq, sn, sd);
     else
-      adj_patch<T, GEO, V2, 0, 0>(g, pt, pu, pv, qk, g.hu, g.hv, rq, sn, sd);
+      adj_patch_rt<T, GEO, V2, DEN>(g, pt, pu, pv, qk, rq, sn, sd);
   }
   if (inside) {
     const long long idx = pr.vol_off + ((long long)kk * pr.ny + jj) * pr.nx + i;
@@ -163,7 +231,7 @@ extern "C" pvr_status pvr_backproject(const pvr_plan *p, const float *e, const f
   PVR_API_BEGIN();
   if (!p) return fail(PVR_EINVAL, "pvr_backproject: plan is NULL");
   if (!p->built) return fail(PVR_EINVAL, "pvr_backproject: plan has not been built");
-  return backproject_impl<float>(p, e, pp, patch_w, num, den, p->d_invz, p->d_rq, stream);
+  return backproject_impl<float>(p, e, pp, patch_w, num, den, p->d_invz, p->d_rq + 1, stream);
   PVR_API_END();
 }
 
@@ -174,7 +242,10 @@ extern "C" pvr_status pvr_backproject_f64(const pvr_plan *p, const double *e, co
   if (!p) return fail(PVR_EINVAL, "pvr_backproject_f64: plan is NULL");
   if (!p->built || !p->built64) return fail(PVR_EINVAL, "pvr_backproject_f64: plan needs pvr_plan_build_f64");
   pvr_plan *mp = const_cast<pvr_plan *>(p);
-  if (!mp->d_rq64) DEV_ALLOC(mp, mp->d_rq64, mp->N);
-  return backproject_impl<double>(p, e, pp, patch_w, num, den, p->d_invz64, mp->d_rq64, stream);
+  if (!mp->d_rq64) {
+    DEV_ALLOC(mp, mp->d_rq64, mp->N + 2);  // guard entries as for d_rq
+    launch_fill_f64((double *)mp->d_rq64, 0.0, 2 * (mp->N + 2), stream);
+  }
+  return backproject_impl<double>(p, e, pp, patch_w, num, den, p->d_invz64, mp->d_rq64 + 1, stream);
   PVR_API_END();
 }

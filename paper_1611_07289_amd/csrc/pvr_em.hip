@@ -22,6 +22,7 @@ using namespace pvr;
 constexpr int EM_T = 256;     // per-patch workgroups
 constexpr int EMP_T = 1024;   // per-problem workgroups
 constexpr int PSTAT = 10;     // doubles per patch in the scratch table
+constexpr int EMP_LDS = 12288; // patches per problem whose potentials fit the LDS copy
 
 // Workgroup reductions in a fixed order: a butterfly inside every wave, then
 // the wave results combined in wave order by every lane.  lds must hold
@@ -213,24 +214,48 @@ __device__ __forceinline__ double inlier_resp(double v, const Mix &m) {
 // form the low component.  The split value is found exactly by a radix select
 // on the float bit patterns (potentials are >= 0, so the patterns are ordered
 // like the values).
+//
+// The potentials of the problem's patches are first copied to a compact
+// array (-1 marks a patch that takes no part): in LDS when the problem has
+// at most EMP_LDS patches, else in the plan's scratch array, so the 20
+// mixture iterations touch only that array.  One pass per iteration gathers
+// the high component's sums of r, r v and r v^2; the low component's follow
+// from the totals (sum 1, sum v, sum v^2), and each variance is
+// E[v^2] - mean^2 (values in [0, 1], FP64: the cancellation costs ~1e-16 /
+// var relative, against a floor of 1e-6 on the variance).
 __global__ void __launch_bounds__(EMP_T)
 k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
-             const uint8_t *__restrict__ active, double *__restrict__ pstat,
-             double *__restrict__ resp, float *__restrict__ patch_w, pvr_em_state *__restrict__ em,
-             int fix_w) {
+             const uint8_t *__restrict__ active, const double *__restrict__ pstat,
+             float *__restrict__ gval, float *__restrict__ patch_w, pvr_em_state *__restrict__ em,
+             int fix_w, int use_lds) {
   __shared__ double lds[8 * (EMP_T / 64)];
   __shared__ unsigned int hist[256];
   __shared__ unsigned int sel_prefix, sel_rank;
+  extern __shared__ float sval[];
   const ProbDev pr = probs[blockIdx.x];
   const int t = threadIdx.x;
-  const int pb = pr.patch_begin, pe = pr.patch_end;
-  auto used = [&](int s) -> bool { return pstat[PSTAT * s + 5] > 0 && active[s] != 0; };
-  double n = 0;
-  for (int s = pb + t; s < pe; s += EMP_T) n += used(s) ? 1.0 : 0.0;
-  n = bsum<EMP_T>(n, lds);
+  const int pb = pr.patch_begin, np = pr.patch_end - pr.patch_begin;
+  float *V = use_lds ? sval : gval + pb;
+  double n = 0, s_all = 0, q_all = 0;
+  for (int q = t; q < np; q += EMP_T) {
+    const int s = pb + q;
+    float v = -1.f;
+    if (pstat[PSTAT * s + 5] > 0 && active[s] != 0) v = pbar[s];
+    V[q] = v;
+    if (v >= 0.f) {
+      n += 1.0;
+      s_all += (double)v;
+      q_all += (double)v * (double)v;
+    }
+  }
+  {
+    double r3[3] = {n, s_all, q_all};
+    bsumk<EMP_T, 3>(r3, lds);  // its barriers also publish V
+    n = r3[0]; s_all = r3[1]; q_all = r3[2];
+  }
   const int nu = (int)n;
   double mu0 = 0, sd0 = 1, mu1 = 0, sd1 = 1, w1 = 0.9;
-  bool fit = nu >= 2;
+  const bool fit = nu >= 2;
   if (fit) {
     const int n_lo = nu / 2;
     // radix select of the value of rank n_lo - 1
@@ -242,9 +267,10 @@ k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
       __syncthreads();
       const unsigned pref = sel_prefix;
       const unsigned mask_hi = pass == 0 ? 0u : (0xffffffffu << (32 - 8 * pass));
-      for (int s = pb + t; s < pe; s += EMP_T) {
-        if (!used(s)) continue;
-        const unsigned bits = __float_as_uint(pbar[s]);
+      for (int q = t; q < np; q += EMP_T) {
+        const float v = V[q];
+        if (!(v >= 0.f)) continue;
+        const unsigned bits = __float_as_uint(v);
         if ((bits & mask_hi) == pref) atomicAdd(&hist[(bits >> shift) & 255u], 1u);
       }
       __syncthreads();
@@ -261,17 +287,14 @@ k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
       __syncthreads();
     }
     const double tv = (double)__uint_as_float(sel_prefix);
-    double c_lt = 0, s_lt = 0, q_lt = 0, s_all = 0, q_all = 0;
-    for (int s = pb + t; s < pe; s += EMP_T) {
-      if (!used(s)) continue;
-      const double v = pbar[s];
-      s_all += v;
-      q_all += v * v;
-      if (v < tv) { c_lt += 1; s_lt += v; q_lt += v * v; }
+    double c_lt = 0, s_lt = 0, q_lt = 0;
+    for (int q = t; q < np; q += EMP_T) {
+      const double v = V[q];
+      if (v >= 0 && v < tv) { c_lt += 1; s_lt += v; q_lt += v * v; }
     }
-    double red5[5] = {c_lt, s_lt, q_lt, s_all, q_all};
-    bsumk<EMP_T, 5>(red5, lds);
-    c_lt = red5[0]; s_lt = red5[1]; q_lt = red5[2]; s_all = red5[3]; q_all = red5[4];
+    double red3[3] = {c_lt, s_lt, q_lt};
+    bsumk<EMP_T, 3>(red3, lds);
+    c_lt = red3[0]; s_lt = red3[1]; q_lt = red3[2];
     const double fill = n_lo - c_lt;
     const double s0 = s_lt + fill * tv, q0 = q_lt + fill * tv * tv;
     const double n_hi = nu - n_lo;
@@ -281,54 +304,42 @@ k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
     sd1 = fmax(sqrt(fmax((q_all - q0) / n_hi - mu1 * mu1, 0.0)), 1e-3);
     w1 = 0.9;
     for (int it = 0; it < 20; ++it) {
-      double r1s = 0, r0s = 0, r1v = 0, r0v = 0;
+      double r1s = 0, r1v = 0, r1q = 0;
       const Mix mx = make_mix(mu0, sd0, mu1, sd1, w1);
-      for (int s = pb + t; s < pe; s += EMP_T) {
-        if (!used(s)) continue;
-        const double v = pbar[s];
+      for (int q = t; q < np; q += EMP_T) {
+        const double v = V[q];
+        if (!(v >= 0)) continue;
         const double r1 = inlier_resp(v, mx);
-        resp[s] = r1;
         r1s += r1;
-        r0s += 1.0 - r1;
         r1v += r1 * v;
-        r0v += (1.0 - r1) * v;
+        r1q += r1 * v * v;
       }
-      double red4[4] = {r1s, r0s, r1v, r0v};
-      bsumk<EMP_T, 4>(red4, lds);
-      r1s = red4[0]; r0s = red4[1]; r1v = red4[2]; r0v = red4[3];
+      double red[3] = {r1s, r1v, r1q};
+      bsumk<EMP_T, 3>(red, lds);
+      r1s = red[0]; r1v = red[1]; r1q = red[2];
+      const double r0s = nu - r1s;
       if (!(r1s > 0) || !(r0s > 0)) break;
-      const double nmu1 = r1v / r1s, nmu0 = r0v / r0s;
-      double d1 = 0, d0 = 0;
-      for (int s = pb + t; s < pe; s += EMP_T) {
-        if (!used(s)) continue;
-        const double v = pbar[s];
-        const double r1 = resp[s];
-        d1 += r1 * (v - nmu1) * (v - nmu1);
-        d0 += (1.0 - r1) * (v - nmu0) * (v - nmu0);
-      }
-      double red2[2] = {d1, d0};
-      bsumk<EMP_T, 2>(red2, lds);
-      d1 = red2[0]; d0 = red2[1];
+      mu1 = r1v / r1s;
+      mu0 = (s_all - r1v) / r0s;
+      sd1 = fmax(sqrt(fmax(r1q / r1s - mu1 * mu1, 0.0)), 1e-3);
+      sd0 = fmax(sqrt(fmax((q_all - r1q) / r0s - mu0 * mu0, 0.0)), 1e-3);
       w1 = r1s / nu;
-      mu1 = nmu1;
-      mu0 = nmu0;
-      sd1 = fmax(sqrt(d1 / r1s), 1e-3);
-      sd0 = fmax(sqrt(d0 / r0s), 1e-3);
     }
   }
   const bool swap = fit && mu0 > mu1;
   const Mix mfin = make_mix(mu0, sd0, mu1, sd1, w1);
   // patch weights, then the M-step sums over the problem's patches
   double swpe2 = 0, swp = 0, sw = 0, nex = 0;
-  for (int s = pb + t; s < pe; s += EMP_T) {
+  for (int q = t; q < np; q += EMP_T) {
+    const int s = pb + q;
     double W;
-    const bool u = used(s);
+    const bool u = V[q] >= 0.f;
     if (fix_w) {
       W = patch_w[s];
     } else {
       double pi = 0;
       if (u) {
-        pi = fit ? inlier_resp((double)pbar[s], mfin) : 1.0;
+        pi = fit ? inlier_resp((double)V[q], mfin) : 1.0;
         if (swap) pi = 1.0 - pi;
       }
       W = (u && pi >= 0.5) ? pi : 0.0;
@@ -376,8 +387,10 @@ extern "C" pvr_status pvr_robust_weights(pvr_plan *p, const float *resid, const 
   hipLaunchKernelGGL(k_em_estep, dim3(p->M), dim3(EM_T), 0, stream, p->d_patch, p->d_invz, resid,
                      em, pp, pb, p->d_pstat);
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_em_patches, dim3(p->P), dim3(EMP_T), 0, stream, p->d_prob, pb, p->d_active,
-                     p->d_pstat, p->d_resp, patch_w, em, fix);
+  const int use_lds = p->max_problem_patches <= EMP_LDS;
+  hipLaunchKernelGGL(k_em_patches, dim3(p->P), dim3(EMP_T),
+                     use_lds ? (size_t)p->max_problem_patches * sizeof(float) : 0, stream,
+                     p->d_prob, pb, p->d_active, p->d_pstat, p->d_pval, patch_w, em, fix, use_lds);
   HIP_TRY(hipGetLastError());
   return PVR_OK;
   PVR_API_END();

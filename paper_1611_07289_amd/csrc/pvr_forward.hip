@@ -24,7 +24,8 @@ k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patch
   const PatchDev pt = patches[wk.patch];
   const ProbDev pr = probs[pt.problem];
   const typename GeoOf<T>::type &g = geo[wk.patch];
-  const T *Xp = X + pr.vol_off;
+  const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+      (void *)(X + pr.vol_off), (short)0, pr.nx * pr.ny * pr.nz * (int)sizeof(T), 0x00020000);
   const int n = pt.w * pt.h;
   const int l1 = min(n, wk.l0 + SIM_CHUNK);
   for (int l = wk.l0 + threadIdx.x; l < l1; l += SIM_THREADS) {
@@ -36,9 +37,7 @@ k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patch
       int b[3];
       T f[3];
       sample_centre(g, pr, u, v, pt.slice, b, f);
-      T z = 0, acc = 0;
-      psf_walk<T, typename GeoOf<T>::type, true>(g, pr, b, f, Xp, z, acc);
-      yh = acc * iz;
+      yh = psf_walk_fwd<T, typename GeoOf<T>::type>(g, pr, b, f, xr) * iz;
     }
     if (y_sim) y_sim[j] = yh;
     if (resid) resid[j] = iz > (T)0 ? y_obs[j] - yh : (T)0;

@@ -213,6 +213,97 @@ __device__ __forceinline__ void psf_walk(const GEO &g, const ProbDev &p, const i
   psf_walk_s<T, GEO, HAS_X>(g, clo, chi, b, f, Xb, p.nx, p.nx * p.ny, z, acc);
 }
 
+// Forward-only walk (the normaliser comes from the build): sum g_hat X over
+// the support of one sample, X read through a raw buffer of the problem's
+// volume.  Same enumeration as psf_walk_s, tuned for the simulation:
+//  * each row's loads are issued four at a time before their use, so a
+//    lane keeps several volume reads in flight instead of one;
+//  * a buffer load never faults, so the group of four reads past the row
+//    end without an address clamp (those voxels get weight 0);
+//  * the row bounds use the hardware square root, widened by a relative
+//    1e-6: voxels the wider range adds lie outside the support, where
+//    2^-Q - 2^-K2 <= 0 clamps to 0.
+template <typename T> __device__ __forceinline__ T load_vox(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <> __device__ __forceinline__ float load_vox<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+template <> __device__ __forceinline__ double load_vox<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+template <typename T> __device__ __forceinline__ T fast_sqrt(T x);
+template <> __device__ __forceinline__ float fast_sqrt<float>(float x) {
+  return __builtin_amdgcn_sqrtf(x) * 1.000001f;
+}
+template <> __device__ __forceinline__ double fast_sqrt<double>(double x) { return sqrt(x); }
+// max(x, 0) for x in [-1, 1] (the output clamp of the producing instruction)
+template <typename T> __device__ __forceinline__ T clamp01(T x);
+template <> __device__ __forceinline__ float clamp01<float>(float x) {
+  return __builtin_amdgcn_fmed3f(x, 0.f, 1.f);
+}
+template <> __device__ __forceinline__ double clamp01<double>(double x) { return fmax(x, 0.0); }
+
+template <typename T, typename GEO>
+__device__ __forceinline__ T psf_walk_fwd(const GEO &g, const ProbDev &p, const int b[3],
+                                          const T f[3], __amdgpu_buffer_rsrc_t xr) {
+  const int sy = p.nx, sz = p.nx * p.ny;
+  const int ia = g.perm[0], ib = g.perm[1], ic = g.perm[2];
+  const int st_a = sel3(ia, 1, sy, sz), st_b = sel3(ib, 1, sy, sz), st_c = sel3(ic, 1, sy, sz);
+  const int b_a = sel3(ia, b[0], b[1], b[2]), b_b = sel3(ib, b[0], b[1], b[2]),
+            b_c = sel3(ic, b[0], b[1], b[2]);
+  const int n_a = sel3(ia, p.nx, p.ny, p.nz), n_b = sel3(ib, p.nx, p.ny, p.nz),
+            n_c = sel3(ic, p.nx, p.ny, p.nz);
+  const T f_a = sel3f<T>(ia, f[0], f[1], f[2]), f_b = sel3f<T>(ib, f[0], f[1], f[2]),
+          f_c = sel3f<T>(ic, f[0], f[1], f[2]);
+  const T K2 = (T)g.K2, cut = (T)g.cut, Acc = (T)g.Acc, Aca = (T)g.Aca,
+          Acb = (T)g.Acb, Saa = (T)g.Saa, Sab = (T)g.Sab, Sbb = (T)g.Sbb,
+          iAaa = (T)g.iAinv_aa, ha = (T)g.ha, iAcc = (T)g.inv_Acc,
+          iSbb = (T)g.inv_Sbb, nSab = (T)g.nSab_Sbb;
+  const int lo_a = max((int)ceil(f_a - ha), -b_a);
+  const int hi_a = min((int)floor(f_a + ha), n_a - 1 - b_a);
+  const int cl_b = -b_b, ch_b = n_b - 1 - b_b, cl_c = -b_c, ch_c = n_c - 1 - b_c;
+  const int vb = (b[2] * p.ny + b[1]) * p.nx + b[0];
+  const unsigned step = (unsigned)st_c * (unsigned)sizeof(T);
+  T acc = (T)0;
+  for (int oa = lo_a; oa <= hi_a; ++oa) {
+    const T wa = (T)oa - f_a;
+    const T rem = K2 - wa * wa * iAaa;
+    if (rem < (T)0) continue;
+    const T wbc = nSab * wa;
+    const T rb = fast_sqrt<T>(rem * iSbb);
+    const int lo_b = max((int)ceil(f_b + wbc - rb), cl_b);
+    const int hi_b = min((int)floor(f_b + wbc + rb), ch_b);
+    const T qa = Saa * wa * wa;
+    const T sa2 = (T)2 * Sab * wa;
+    for (int ob = lo_b; ob <= hi_b; ++ob) {
+      const T wb = (T)ob - f_b;
+      const T q1 = qa + wb * (sa2 + Sbb * wb);
+      const T rem2 = K2 - q1;
+      if (rem2 < (T)0) continue;
+      const T wcc = -(Aca * wa + Acb * wb) * iAcc;
+      const T rc = fast_sqrt<T>(rem2 * iAcc);
+      const int lo_c = max((int)ceil(f_c + wcc - rc), cl_c);
+      const int hi_c = min((int)floor(f_c + wcc + rc), ch_c);
+      const int n = hi_c - lo_c + 1;
+      T d = ((T)lo_c - f_c) - wcc;
+      unsigned off = (unsigned)(vb + oa * st_a + ob * st_b + lo_c * st_c) * (unsigned)sizeof(T);
+      for (int k0 = 0; k0 < n; k0 += 4) {
+        T x[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) x[k] = load_vox<T>(xr, off + (unsigned)k * step);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const T Q = fma(Acc * d, d, q1);
+          const T gh = clamp01<T>(fast_exp2<T>(-Q) - cut);
+          acc = fma(k0 + k < n ? gh : (T)0, x[k], acc);
+          d += (T)1;
+        }
+        off += 4 * step;
+      }
+    }
+  }
+  return acc;
+}
+
 // Voxel box (inclusive, clipped to the grid, padded by one voxel) that holds
 // the PSF supports of every sample of a tile: the tile's corner centres
 // bound all its centres (the pixel -> voxel map is affine), and a support
@@ -268,6 +359,7 @@ __device__ __forceinline__ T block_sum(T v, T *lds) {
 struct pvr_plan {
   int device;
   int P, S, M;
+  int max_problem_patches;
   long long N, V;
   int n_bricks;
   double k;
@@ -313,11 +405,11 @@ struct pvr_plan {
   long long n_sub_pairs;
   bool built, built64, index_valid;
   // scratch
-  float2 *d_rq;              // [N]
-  double2 *d_rq64;           // [N] (lazy)
+  float2 *d_rq;              // [N + 2]: zero guard, N entries, zero guard
+  double2 *d_rq64;           // [N + 2] likewise (lazy)
   double *d_pstat;           // [M][10] per-patch EM partials
-  double *d_resp;            // [M] mixture responsibilities
   float *d_pbar;             // [M] potentials when the caller passes none
+  float *d_pval;             // [M] classification scratch (problems beyond the LDS copy)
   int *d_total;              // [1] pinned readback target (device side)
   int *h_total;              // pinned host
   long long device_bytes;

@@ -255,6 +255,8 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
   for (int b = 0; b < n_problems; ++b) {
     const pvr_grid &g = grids[b];
     if (g.nx <= 0 || g.ny <= 0 || g.nz <= 0) return fail(PVR_ESHAPE, "pvr_plan_create: grid %d has an empty size", b);
+    if ((long long)g.nx * g.ny * g.nz > (1LL << 29))
+      return fail(PVR_ESHAPE, "pvr_plan_create: grid %d has more than 2^29 voxels", b);
     ProbDev &d = p->h_prob[b];
     d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
     d.nbx = (g.nx + BRICK - 1) / BRICK; d.nby = (g.ny + BRICK - 1) / BRICK; d.nbz = (g.nz + BRICK - 1) / BRICK;
@@ -328,7 +330,12 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
   {
     int pb = 0;
     long long sb = 0;
+    p->max_problem_patches = 0;
     for (int b = 0; b < n_problems; ++b) {
+      if (pcount[b] > PVR_MAX_PROBLEM_PATCHES)
+        return fail(PVR_ESHAPE, "pvr_plan_create: problem %d has more than %d patches", b,
+                    PVR_MAX_PROBLEM_PATCHES);
+      p->max_problem_patches = std::max(p->max_problem_patches, pcount[b]);
       p->h_prob[b].patch_begin = pb; p->h_prob[b].patch_end = pb + pcount[b];
       p->h_prob[b].sample_begin = sb; p->h_prob[b].sample_end = sb + scount[b];
       pb += pcount[b];
@@ -340,7 +347,9 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
   if (so > 0x7fffffffLL * 4) return fail(PVR_ESHAPE, "pvr_plan_create: too many samples");
   p->n_sim_blocks = (int)blocks.size();
   for (int s = 0; s < n_patches; ++s)
-    if (patches[s].w > 32767 || patches[s].h > 32767) return fail(PVR_ESHAPE, "pvr_plan_create: patch %d too large", s);
+    if (patches[s].w > 32767 || patches[s].h > 32767 ||
+        (long long)patches[s].w * patches[s].h > (1LL << 26))
+      return fail(PVR_ESHAPE, "pvr_plan_create: patch %d too large (w, h <= 32767, w * h <= 2^26)", s);
   p->tile_w = TILE;
   p->tile_h = TILE;
   p->use_tiles = false;
@@ -384,10 +393,15 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
   DEV_ALLOC(p, p->d_bin_off, nbr + 1);
   DEV_ALLOC(p, p->d_sub_count, 8 * (size_t)nbr);
   DEV_ALLOC(p, p->d_sub_off, 8 * (size_t)nbr + 1);
-  DEV_ALLOC(p, p->d_rq, p->N);
+  // one guard entry (zero) before and after the N entries: the adjoint's
+  // wide loads may pair a patch's first or last entry with its neighbour
+  DEV_ALLOC(p, p->d_rq, p->N + 2);
+  launch_fill_f32((float *)p->d_rq, 0.f, 2 * (p->N + 2), nullptr);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(nullptr));
   DEV_ALLOC(p, p->d_pstat, 10 * (size_t)n_patches);
-  DEV_ALLOC(p, p->d_resp, n_patches);
   DEV_ALLOC(p, p->d_pbar, n_patches);
+  DEV_ALLOC(p, p->d_pval, n_patches);
   DEV_ALLOC(p, p->d_total, 4);
   HIP_TRY(hipHostMalloc((void **)&p->h_total, sizeof(int) * 4, hipHostMallocDefault));
   HIP_TRY(hipMemcpy(p->d_prob, p->h_prob, sizeof(ProbDev) * n_problems, hipMemcpyHostToDevice));

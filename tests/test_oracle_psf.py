@@ -105,6 +105,23 @@ def test_bruteforce_dense_A_equals_oracle_rows(brute):
     assert nnz > 0
 
 
+def test_support_backprojection_is_the_indicator_transpose(brute):
+    """The support form of the adjoint (1/Z_j on every support voxel, used
+    for the FP32 error bars) equals S^T (r / Z) with S the support pattern of
+    the brute-force dense matrix; the per-voxel form agrees with the full one."""
+    P, ctx = brute
+    A, valid = _dense_A(P)
+    _, Z, val = ctx.simulate(np.zeros(P.grid.n_voxels), P.theta_true)
+    r = np.random.default_rng(4).normal(size=P.N)
+    rz = np.where(val, r / np.where(val, Z, 1.0), 0.0)
+    ref = (A > 0).T.astype(np.float64) @ rz
+    got = ctx.backproject(P.theta_true, r, support=True).reshape(-1)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-14)
+    vox = np.random.default_rng(5).choice(P.grid.n_voxels, 40, replace=False)
+    gv = ctx.backproject_voxels(P.theta_true, r, vox, support=True)
+    assert np.allclose(gv, got[vox], rtol=1e-12, atol=1e-14)
+
+
 def test_rows_sum_to_one_and_constant_volume(brute):
     P, ctx = brute
     yh, Z, val = ctx.simulate(np.full(P.grid.n_voxels, 321.0), P.theta_true)
@@ -186,3 +203,15 @@ def test_integer_translation_equivariance():
         assert y2[j] == pytest.approx(y1[j], rel=1e-10, abs=1e-9)
         ok += 1
     assert ok > 100
+
+
+def test_cheap_validity_equals_simulate_validity(brute):
+    """The oracle's validity shortcut (nearest-voxel weight, else the full Z)
+    reports exactly what simulate reports, with a mask and inactive patches."""
+    for P, ctx in (brute, (tiny(), oracle.Ctx(tiny().grid, tiny().stacks, tiny().patches))):
+        rng = np.random.default_rng(6)
+        mask = (rng.uniform(size=P.N) > 0.1).astype(np.uint8)
+        active = (rng.uniform(size=P.M) > 0.2).astype(np.uint8)
+        for m, a in ((None, None), (mask, active)):
+            _, _, v = ctx.simulate(np.zeros(P.grid.n_voxels), P.theta_true, m, a)
+            assert np.array_equal(ctx.valid(P.theta_true, m, a), v)
