@@ -159,10 +159,11 @@ k_backproject(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ pa
               const typename GeoOf<T>::type *__restrict__ geo, const int *__restrict__ brick_prob,
               const int *__restrict__ sub_off, const int *__restrict__ sub_patch,
               const typename Vec2Of<T>::type *__restrict__ rq, T *__restrict__ num,
-              T *__restrict__ den) {
+              T *__restrict__ den, int n_bricks, int per) {
   using GEO = typename GeoOf<T>::type;
   using V2 = typename Vec2Of<T>::type;
-  const int bi = blockIdx.x;
+  const int bi = xcd_work(blockIdx.x, per);
+  if (bi >= n_bricks) return;
   const ProbDev pr = probs[brick_prob[bi]];
   const int local = bi - pr.brick_base;
   const int bx = local % pr.nbx, by = (local / pr.nbx) % pr.nby, bz = local / (pr.nbx * pr.nby);
@@ -213,14 +214,15 @@ static pvr_status backproject_impl(const pvr_plan *p, const T *e, const T *pp, c
                      p->d_sim_blocks, invz, e, pp, patch_w, rq);
   HIP_TRY(hipGetLastError());
   const void *geo = sizeof(T) == 4 ? (const void *)p->d_geof : (const void *)p->d_geod;
+  const int per = xcd_per(p->n_bricks);
   if (den)
-    hipLaunchKernelGGL((k_backproject<T, true>), dim3(p->n_bricks), dim3(BP_THREADS), 0, stream,
+    hipLaunchKernelGGL((k_backproject<T, true>), dim3(N_XCD * per), dim3(BP_THREADS), 0, stream,
                        p->d_prob, p->d_patch, (const typename GeoOf<T>::type *)geo, p->d_brick_prob,
-                       p->d_sub_off, p->d_sub_patch, rq, num, den);
+                       p->d_sub_off, p->d_sub_patch, rq, num, den, p->n_bricks, per);
   else
-    hipLaunchKernelGGL((k_backproject<T, false>), dim3(p->n_bricks), dim3(BP_THREADS), 0, stream,
+    hipLaunchKernelGGL((k_backproject<T, false>), dim3(N_XCD * per), dim3(BP_THREADS), 0, stream,
                        p->d_prob, p->d_patch, (const typename GeoOf<T>::type *)geo, p->d_brick_prob,
-                       p->d_sub_off, p->d_sub_patch, rq, num, den);
+                       p->d_sub_off, p->d_sub_patch, rq, num, den, p->n_bricks, per);
   HIP_TRY(hipGetLastError());
   return PVR_OK;
 }

@@ -19,8 +19,10 @@ __global__ void __launch_bounds__(SIM_THREADS)
 k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patches,
            const BlockWork *__restrict__ work, const typename GeoOf<T>::type *__restrict__ geo,
            const T *__restrict__ invz, const T *__restrict__ X, const T *__restrict__ y_obs,
-           T *__restrict__ y_sim, T *__restrict__ resid) {
-  const BlockWork wk = work[blockIdx.x];
+           T *__restrict__ y_sim, T *__restrict__ resid, int n_work, int per) {
+  const int wi = xcd_work(blockIdx.x, per);
+  if (wi >= n_work) return;
+  const BlockWork wk = work[wi];
   const PatchDev pt = patches[wk.patch];
   const ProbDev pr = probs[pt.problem];
   const typename GeoOf<T>::type &g = geo[wk.patch];
@@ -48,9 +50,8 @@ k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patch
 // workgroup copies the voxel box of the tile's supports into LDS with row-
 // contiguous (coalesced) loads, then every lane walks its sample's support in
 // LDS.  Tiles whose box exceeds the reserved LDS walk the volume in global
-// memory instead.  Tiles are assigned so that each XCD (blocks are dealt to
-// the 8 XCDs round-robin) receives one contiguous run of the patch-major
-// tile list, keeping overlapping tiles in the same L2.
+// memory instead.  Each XCD receives one contiguous run of the patch-major
+// tile list (xcd_work), keeping overlapping tiles in the same L2.
 __global__ void __launch_bounds__(SIM_THREADS)
 k_simulate_tiles(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patches,
                  const TileWork *__restrict__ tiles, int n_tiles, int per_xcd,
@@ -58,7 +59,7 @@ k_simulate_tiles(const ProbDev *__restrict__ probs, const PatchDev *__restrict__
                  const float *__restrict__ X, const float *__restrict__ y_obs,
                  float *__restrict__ y_sim, float *__restrict__ resid, int lds_cap) {
   extern __shared__ float xs[];
-  const int t = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  const int t = xcd_work(blockIdx.x, per_xcd);
   if (t >= n_tiles) return;
   const TileWork tw = tiles[t];
   const PatchDev pt = patches[tw.patch];
@@ -111,8 +112,8 @@ static pvr_status simulate_impl(const pvr_plan *p, const T *X, const T *y_obs, T
   if (resid && !y_obs) return fail(PVR_EINVAL, "pvr_simulate: resid requires y_obs");
   if (!y_sim && !resid) return PVR_OK;
   if (sizeof(T) == 4 && p->use_tiles && p->lds_box > 0) {
-    const int per = (p->n_tiles + 7) / 8;
-    hipLaunchKernelGGL(k_simulate_tiles, dim3(8 * per), dim3(SIM_THREADS),
+    const int per = xcd_per(p->n_tiles);
+    hipLaunchKernelGGL(k_simulate_tiles, dim3(N_XCD * per), dim3(SIM_THREADS),
                        (size_t)p->lds_box * sizeof(float), stream, p->d_prob, p->d_patch,
                        p->d_tiles, p->n_tiles, per, p->d_geof, (const float *)invz,
                        (const float *)X, (const float *)y_obs, (float *)y_sim, (float *)resid,
@@ -120,11 +121,12 @@ static pvr_status simulate_impl(const pvr_plan *p, const T *X, const T *y_obs, T
     HIP_TRY(hipGetLastError());
     return PVR_OK;
   }
-  hipLaunchKernelGGL(k_simulate<T>, dim3(p->n_sim_blocks), dim3(SIM_THREADS), 0, stream, p->d_prob,
+  const int per = xcd_per(p->n_sim_blocks);
+  hipLaunchKernelGGL(k_simulate<T>, dim3(N_XCD * per), dim3(SIM_THREADS), 0, stream, p->d_prob,
                      p->d_patch, p->d_sim_blocks,
                      (const typename GeoOf<T>::type *)(sizeof(T) == 4 ? (const void *)p->d_geof
                                                                       : (const void *)p->d_geod),
-                     invz, X, y_obs, y_sim, resid);
+                     invz, X, y_obs, y_sim, resid, p->n_sim_blocks, per);
   HIP_TRY(hipGetLastError());
   return PVR_OK;
 }

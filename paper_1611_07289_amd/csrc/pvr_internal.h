@@ -96,6 +96,15 @@ struct BlockWork {   // one forward workgroup: a chunk of one patch
   int l0;            // first local sample
 };
 
+// Workgroups are dealt to the 8 XCDs round-robin by block index, and every
+// XCD has its own L2.  A grid of N_XCD * per blocks maps block b to work item
+// (b mod 8) * per + b / 8, so each XCD takes one contiguous run of the work
+// list (neighbouring chunks of a patch, neighbouring bricks) and the data
+// they share stays in one L2; items >= n are empty.
+constexpr int N_XCD = 8;
+__host__ __device__ __forceinline__ int xcd_per(int n) { return (n + N_XCD - 1) / N_XCD; }
+__device__ __forceinline__ int xcd_work(int b, int per) { return (b % N_XCD) * per + b / N_XCD; }
+
 constexpr int TILE = 16;            // forward tile edge (pixels)
 constexpr int LDS_BOX_MAX = 16384;  // staged voxels per forward workgroup (64 KiB)
 

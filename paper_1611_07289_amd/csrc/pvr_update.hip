@@ -9,6 +9,11 @@ using namespace pvr;
 
 // One workgroup = a 64 x 4 tile of one z-plane of one problem (grid
 // x = tiles over x, y = tiles over y, z = planes of all problems stacked).
+// A neighbour outside the grid (whose term the Neumann border drops) is not
+// branched around: its load reads the centre voxel instead, so its
+// difference D is exactly 0 and so is its term, and every load stays inside
+// the problem's volume.  1/sqrt uses the hardware reciprocal square root
+// (about 1 ulp).
 __global__ void __launch_bounds__(256)
 k_sr_update(const ProbDev *__restrict__ probs, const int *__restrict__ plane_prob,
             const float *__restrict__ X, const float *__restrict__ num,
@@ -20,14 +25,21 @@ k_sr_update(const ProbDev *__restrict__ probs, const int *__restrict__ plane_pro
   const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
   if (i >= pr.nx || j >= pr.ny) return;
   const int sy = pr.nx, sz = pr.nx * pr.ny;
-  const long long gid = pr.vol_off + (long long)k * sz + (long long)j * sy + i;
-  const float x = X[gid];
-  const float dn = den[gid];
-  const float step = dn > prm.den_eps ? num[gid] / dn : 0.f;
+  const int c = k * sz + j * sy + i;
+  const float *Xp = X + pr.vol_off;
+  const float x = Xp[c];
+  const float dn = den[pr.vol_off + c];
+  const float step = dn > prm.den_eps ? num[pr.vol_off + c] / dn : 0.f;
   float R = 0.f;
   if (prm.lambda != 0.f) {
+    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)Xp, (short)0, sz * pr.nz * (int)sizeof(float), 0x00020000);
     const float inv_delta = 1.f / prm.delta;
     const float bw[4] = {0.f, 1.f, 0.70710678118654752f, 0.57735026918962576f};
+    const bool okx[3] = {i > 0, true, i < pr.nx - 1};
+    const bool oky[3] = {j > 0, true, j < pr.ny - 1};
+    const bool okz[3] = {k > 0, true, k < pr.nz - 1};
+    const int vo = c * (int)sizeof(float);
 #pragma unroll
     for (int dz = -1; dz <= 1; ++dz) {
 #pragma unroll
@@ -36,11 +48,13 @@ k_sr_update(const ProbDev *__restrict__ probs, const int *__restrict__ plane_pro
         for (int dx = -1; dx <= 1; ++dx) {
           const int nnz = (dx != 0) + (dy != 0) + (dz != 0);
           if (nnz == 0) continue;
-          const int ii = i + dx, jj = j + dy, kk = k + dz;
-          if (ii < 0 || ii >= pr.nx || jj < 0 || jj >= pr.ny || kk < 0 || kk >= pr.nz) continue;
-          const float D = X[gid + dx + dy * sy + dz * sz] - x;
+          const bool ok = okx[dx + 1] & oky[dy + 1] & okz[dz + 1];
+          const int so = (dx + dy * sy + dz * sz) * (int)sizeof(float);
+          const float v = __builtin_bit_cast(
+              float, __builtin_amdgcn_raw_buffer_load_b32(xr, ok ? vo + so : vo, 0, 0));
+          const float D = v - x;
           const float t = D * inv_delta;
-          R = fmaf(bw[nnz] * D, 1.f / sqrtf(fmaf(t, t, 1.f)), R);
+          R = fmaf(bw[nnz] * D, __builtin_amdgcn_rsqf(fmaf(t, t, 1.f)), R);
         }
       }
     }
@@ -48,7 +62,7 @@ k_sr_update(const ProbDev *__restrict__ probs, const int *__restrict__ plane_pro
   float out = fmaf(prm.alpha, step, x);
   out = fmaf(prm.alpha * prm.lambda, R, out);
   if (prm.use_clamp) out = fmaxf(out, prm.clamp_min);
-  Xo[gid] = out;
+  Xo[pr.vol_off + c] = out;
 }
 
 extern "C" pvr_status pvr_sr_update(const pvr_plan *p, const float *X, const float *num,
