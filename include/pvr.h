@@ -165,7 +165,7 @@ const char *pvr_version(void);
  * valid stacks and lie inside their slice; every stack names a valid problem.
  * cutoff_k: PSF support radius in standard deviations (> 0, default 3).
  * Errors: PVR_EINVAL for null pointers or out-of-range indices, PVR_ESHAPE
- * for non-orthogonal stack axes, empty sizes, a grid beyond 2^29 voxels, a
+ * for non-orthogonal stack axes, empty sizes, a grid beyond 2^28 voxels, a
  * problem with more than PVR_MAX_PROBLEM_PATCHES patches, or a patch beyond
  * 32767 pixels per side or 2^26 pixels, PVR_ENOMEM, PVR_EHIP. */
 pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,

@@ -59,8 +59,7 @@ k_bp_prep(const PatchDev *__restrict__ patches, const BlockWork *__restrict__ wo
 // entry is always wholly in range.
 template <typename V2>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t patch_rsrc(const V2 *patch_base, int n) {
-  return __builtin_amdgcn_make_buffer_rsrc((void *)(patch_base - 1), (short)0,
-                                           (n + 2) * (int)sizeof(V2), 0x00020000);
+  return raw_buffer(patch_base - 1, (unsigned)(n + 2) * (unsigned)sizeof(V2));
 }
 
 template <typename V2> __device__ __forceinline__ V2 load_rq(__amdgpu_buffer_rsrc_t r, int off);

@@ -26,8 +26,8 @@ k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patch
   const PatchDev pt = patches[wk.patch];
   const ProbDev pr = probs[pt.problem];
   const typename GeoOf<T>::type &g = geo[wk.patch];
-  const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
-      (void *)(X + pr.vol_off), (short)0, pr.nx * pr.ny * pr.nz * (int)sizeof(T), 0x00020000);
+  const __amdgpu_buffer_rsrc_t xr =
+      raw_buffer(X + pr.vol_off, (unsigned)(pr.nx * pr.ny * pr.nz) * (unsigned)sizeof(T));
   const int n = pt.w * pt.h;
   const int l1 = min(n, wk.l0 + SIM_CHUNK);
   for (int l = wk.l0 + threadIdx.x; l < l1; l += SIM_THREADS) {
@@ -190,7 +190,7 @@ struct RegShared {
 // NCC of the patch against its simulation at sh.th (valid samples only);
 // every lane returns the same value.
 __device__ double reg_eval(RegShared &sh, const ProbDev &pr, const StackDev &st, const PatchDev &pt,
-                           double k, const float *__restrict__ Xp, const float *__restrict__ y,
+                           double k, __amdgpu_buffer_rsrc_t xr, const float *__restrict__ y,
                            const uint8_t *__restrict__ mask) {
   if (threadIdx.x == 0) {
     GeoD gd;
@@ -208,8 +208,8 @@ __device__ double reg_eval(RegShared &sh, const ProbDev &pr, const StackDev &st,
     int b[3];
     float f[3];
     if (!sample_centre(g, pr, u, v, pt.slice, b, f)) continue;
-    float z = 0.f, a = 0.f;
-    psf_walk<float, GeoF, true>(g, pr, b, f, Xp, z, a);
+    float z = 0.f;
+    const float a = psf_walk_fwd<float, GeoF, true>(g, pr, b, f, xr, &z);
     if (!(z > 0.f)) continue;
     const double yh = (double)(a / z), yo = (double)y[j];
     acc6[0] += 1.0;
@@ -242,7 +242,8 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
   const PatchDev pt = patches[s];
   const StackDev st = stacks[pt.stack];
   const ProbDev pr = probs[pt.problem];
-  const float *Xp = X + pr.vol_off;
+  const __amdgpu_buffer_rsrc_t xr =
+      raw_buffer(X + pr.vol_off, (unsigned)(pr.nx * pr.ny * pr.nz) * (unsigned)sizeof(float));
   // observed standard deviation over unmasked samples
   double sy[6] = {0, 0, 0, 0, 0, 0};
   const int n = pt.w * pt.h;
@@ -271,7 +272,7 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
     }
   }
   __syncthreads();
-  double f0 = reg_eval(sh, pr, st, pt, k, Xp, y, mask);
+  double f0 = reg_eval(sh, pr, st, pt, k, xr, y, mask);
   const bool do_reg = (reg ? reg[s] != 0 : true) && sd >= prm.min_std && prm.max_iter > 0;
   if (do_reg) {
     double delta = prm.step0;
@@ -286,10 +287,10 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
             for (int b = 0; b < 6; ++b) sh.th[b] = sh.q[b] / sh.sc[b];
             sh.th[a] = (sh.q[a] + prm.fd_h) / sh.sc[a];
           }
-          fp = reg_eval(sh, pr, st, pt, k, Xp, y, mask);
+          fp = reg_eval(sh, pr, st, pt, k, xr, y, mask);
           __syncthreads();
           if (threadIdx.x == 0) sh.th[a] = (sh.q[a] - prm.fd_h) / sh.sc[a];
-          fm = reg_eval(sh, pr, st, pt, k, Xp, y, mask);
+          fm = reg_eval(sh, pr, st, pt, k, xr, y, mask);
           if (threadIdx.x == 0) sh.grad[a] = (fp - fm) / (2.0 * prm.fd_h);
         }
         have_grad = true;
@@ -302,7 +303,7 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
       __syncthreads();
       if (threadIdx.x == 0)
         for (int a = 0; a < 6; ++a) sh.th[a] = (sh.q[a] + delta * sh.grad[a] / gn) / sh.sc[a];
-      const double ft = reg_eval(sh, pr, st, pt, k, Xp, y, mask);
+      const double ft = reg_eval(sh, pr, st, pt, k, xr, y, mask);
       if (ft > f0) {
         __syncthreads();
         if (threadIdx.x == 0)

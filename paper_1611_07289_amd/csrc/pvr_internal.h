@@ -232,6 +232,11 @@ __device__ __forceinline__ void psf_walk(const GEO &g, const ProbDev &p, const i
 //  * the row bounds use the hardware square root, widened by a relative
 //    1e-6: voxels the wider range adds lie outside the support, where
 //    2^-Q - 2^-K2 <= 0 clamps to 0.
+// Raw buffer over `bytes` bytes from `base` (bytes < 2^32; the count is a
+// 32-bit unsigned field of the resource).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_buffer(const void *base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)bytes, 0x00020000);
+}
 template <typename T> __device__ __forceinline__ T load_vox(__amdgpu_buffer_rsrc_t r, unsigned off);
 template <> __device__ __forceinline__ float load_vox<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
@@ -251,9 +256,11 @@ template <> __device__ __forceinline__ float clamp01<float>(float x) {
 }
 template <> __device__ __forceinline__ double clamp01<double>(double x) { return fmax(x, 0.0); }
 
-template <typename T, typename GEO>
+// WITH_Z also sums the weights (the normaliser Z over in-volume voxels).
+template <typename T, typename GEO, bool WITH_Z = false>
 __device__ __forceinline__ T psf_walk_fwd(const GEO &g, const ProbDev &p, const int b[3],
-                                          const T f[3], __amdgpu_buffer_rsrc_t xr) {
+                                          const T f[3], __amdgpu_buffer_rsrc_t xr,
+                                          T *z_out = nullptr) {
   const int sy = p.nx, sz = p.nx * p.ny;
   const int ia = g.perm[0], ib = g.perm[1], ic = g.perm[2];
   const int st_a = sel3(ia, 1, sy, sz), st_b = sel3(ib, 1, sy, sz), st_c = sel3(ic, 1, sy, sz);
@@ -272,7 +279,7 @@ __device__ __forceinline__ T psf_walk_fwd(const GEO &g, const ProbDev &p, const 
   const int cl_b = -b_b, ch_b = n_b - 1 - b_b, cl_c = -b_c, ch_c = n_c - 1 - b_c;
   const int vb = (b[2] * p.ny + b[1]) * p.nx + b[0];
   const unsigned step = (unsigned)st_c * (unsigned)sizeof(T);
-  T acc = (T)0;
+  T acc = (T)0, z = (T)0;
   for (int oa = lo_a; oa <= hi_a; ++oa) {
     const T wa = (T)oa - f_a;
     const T rem = K2 - wa * wa * iAaa;
@@ -302,14 +309,16 @@ __device__ __forceinline__ T psf_walk_fwd(const GEO &g, const ProbDev &p, const 
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const T Q = fma(Acc * d, d, q1);
-          const T gh = clamp01<T>(fast_exp2<T>(-Q) - cut);
-          acc = fma(k0 + k < n ? gh : (T)0, x[k], acc);
+          const T gh = k0 + k < n ? clamp01<T>(fast_exp2<T>(-Q) - cut) : (T)0;
+          acc = fma(gh, x[k], acc);
+          if (WITH_Z) z += gh;
           d += (T)1;
         }
         off += 4 * step;
       }
     }
   }
+  if (WITH_Z) *z_out = z;
   return acc;
 }
 

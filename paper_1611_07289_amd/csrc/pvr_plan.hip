@@ -255,8 +255,8 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
   for (int b = 0; b < n_problems; ++b) {
     const pvr_grid &g = grids[b];
     if (g.nx <= 0 || g.ny <= 0 || g.nz <= 0) return fail(PVR_ESHAPE, "pvr_plan_create: grid %d has an empty size", b);
-    if ((long long)g.nx * g.ny * g.nz > (1LL << 29))
-      return fail(PVR_ESHAPE, "pvr_plan_create: grid %d has more than 2^29 voxels", b);
+    if ((long long)g.nx * g.ny * g.nz > (1LL << 28))
+      return fail(PVR_ESHAPE, "pvr_plan_create: grid %d has more than 2^28 voxels", b);
     ProbDev &d = p->h_prob[b];
     d.nx = g.nx; d.ny = g.ny; d.nz = g.nz;
     d.nbx = (g.nx + BRICK - 1) / BRICK; d.nby = (g.ny + BRICK - 1) / BRICK; d.nbz = (g.nz + BRICK - 1) / BRICK;

@@ -32,8 +32,7 @@ k_sr_update(const ProbDev *__restrict__ probs, const int *__restrict__ plane_pro
   const float step = dn > prm.den_eps ? num[pr.vol_off + c] / dn : 0.f;
   float R = 0.f;
   if (prm.lambda != 0.f) {
-    const __amdgpu_buffer_rsrc_t xr = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)Xp, (short)0, sz * pr.nz * (int)sizeof(float), 0x00020000);
+    const __amdgpu_buffer_rsrc_t xr = raw_buffer(Xp, (unsigned)(sz * pr.nz) * (unsigned)sizeof(float));
     const float inv_delta = 1.f / prm.delta;
     const float bw[4] = {0.f, 1.f, 0.70710678118654752f, 0.57735026918962576f};
     const bool okx[3] = {i > 0, true, i < pr.nx - 1};
