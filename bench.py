@@ -13,10 +13,14 @@ of libpvr.so with inputs resident in HBM.  Reported value: valid patch
 samples processed per second (whole job).
 
 Extra objects on the JSON line:
-  roofline      dominant kernel: algorithmic work per launch / its average
-                event-timed duration, against the chip's peak;
+  roofline      dominant kernel (k_simulate or k_backproject): algorithmic
+                work per launch / its average duration from the event pairs
+                the library records around each launch on its stream, against
+                the chip's peak; traffic = counter-measured HBM-side bytes
+                per launch when taken on the current library sources;
   kernels_ms    average duration of every call of the step (HIP events on
                 the library's stream);
+  hot_kernels_ms  the two PSF kernels alone;
   cpu_baseline  the FP64 oracle timed on the host on a bounded sample;
   full_pvr      (with --full-pvr) seconds of a whole reconstruction:
                 initial volume, then 3 cycles of [registration, 10 SR
@@ -47,6 +51,36 @@ HBM_PEAK_GBS = 8000.0
 # 1 + weighted value 2; adjoint: two weighted sums 4).
 FLOP_PER_NNZ_FWD = 16
 FLOP_PER_NNZ_ADJ = 17
+# HBM-side bytes per launch of the hot kernels, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes scaled by a 1 GiB device copy; valid only for the library
+# sources they were taken on (their SHA-256 is stored beside the figures).
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_uterus256.json")
+
+
+def library_source_sha() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1611_07289_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """Counter-measured bytes per launch of `kernel`, or None when none were
+    taken on the current sources for this workload."""
+    if workload != "uterus256":
+        return None
+    try:
+        with open(TRAFFIC_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha256") != library_source_sha():
+        return None
+    e = d.get("kernels", {}).get(kernel)
+    return None if e is None else float(e["fetch_bytes"]) + float(e["write_bytes"])
 
 
 def log(msg):
@@ -221,6 +255,9 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] warmup {args.warmup} steps done")
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    plan.set_timing(True)
+    for kid in (pvr.PVR_KERNEL_SIMULATE, pvr.PVR_KERNEL_BACKPROJECT):
+        plan.kernel_time(kid)  # start the counts at the timed region
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
@@ -238,15 +275,23 @@ def main():
     log(f"[bench] {ms_step:.3f} ms/step, {value / 1e9:.3f} G samples/s; "
         + ", ".join(f"{n} {v:.3f} ms" for n, v in per.items()))
 
+    # the hot kernels alone (event pairs the library records around each
+    # launch on its stream during the timed steps)
+    kern = {}
+    for name, kid in (("k_simulate", pvr.PVR_KERNEL_SIMULATE),
+                      ("k_backproject", pvr.PVR_KERNEL_BACKPROJECT)):
+        tot, n = plan.kernel_time(kid)
+        kern[name] = tot / max(n, 1)
+    plan.set_timing(False)
     nnz = nnz_estimate(probs, n_valid)
-    dom = max(["simulate", "backproject"], key=lambda n: per[n])
-    fl = nnz * (FLOP_PER_NNZ_FWD if dom == "simulate" else FLOP_PER_NNZ_ADJ)
-    achieved = fl / (per[dom] * 1e-3) / 1e12
+    dom = max(kern, key=kern.get)
+    fpn = FLOP_PER_NNZ_FWD if dom == "k_simulate" else FLOP_PER_NNZ_ADJ
+    achieved = nnz * fpn / (kern[dom] * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved,
                 "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": None,
-                "nnz_per_launch": nnz,
-                "flop_per_nnz": FLOP_PER_NNZ_FWD if dom == "simulate" else FLOP_PER_NNZ_ADJ}
+                "frac": achieved / FP32_VALU_PEAK_TFLOPS,
+                "traffic": measured_traffic(dom, args.workload),
+                "kernel_ms": kern[dom], "nnz_per_launch": nnz, "flop_per_nnz": fpn}
 
     st = pvr.Plan.read_em(em)
     out = {
@@ -267,6 +312,7 @@ def main():
                    "patch": "64x64 stride 32" if args.workload == "uterus256" else "mixed",
                    "psf_fwhm_mm": [1, 1, 4], "parallelism": "single GPU"},
         "kernels_ms": per,
+        "hot_kernels_ms": kern,
         "build_ms": t_build * 1e3,
         "roofline": roofline,
         "em": {"sigma2": st[0].sigma2, "c": st[0].c, "excluded": st[0].n_excluded},

@@ -209,6 +209,21 @@ pvr_status pvr_plan_build_f64(pvr_plan *plan, const double *theta,
 pvr_status pvr_plan_set_tiles(pvr_plan *plan, int32_t tile_w, int32_t tile_h,
                               hipStream_t stream);
 
+/* Kernel timing, a profiling aid.  With on != 0 the plan records a HIP
+ * event pair on the launch stream around every launch of the kernel named by
+ * `kernel` (PVR_KERNEL_SIMULATE: the forward kernel of pvr_simulate;
+ * PVR_KERNEL_BACKPROJECT: the gather kernel of pvr_backproject, without its
+ * operand preparation), up to 256 launches per kernel between reads.
+ * pvr_plan_kernel_time synchronises on the recorded events and returns the
+ * summed milliseconds and the launch count since the previous read, then
+ * starts a new count.  Not for use while a stream is being captured into a
+ * graph.  Enabling creates the events (host call); disabling keeps them. */
+#define PVR_KERNEL_SIMULATE 0
+#define PVR_KERNEL_BACKPROJECT 1
+pvr_status pvr_plan_set_timing(pvr_plan *plan, int32_t on);
+pvr_status pvr_plan_kernel_time(pvr_plan *plan, int32_t kernel, double *total_ms,
+                                int32_t *launches);
+
 /* (device) inverse normalisers 1/Z_j of the last build, [N] float
  * (0 for invalid samples).  The pointer stays valid until the next build. */
 const float *pvr_plan_inv_z(const pvr_plan *plan);

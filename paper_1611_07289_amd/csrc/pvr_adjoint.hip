@@ -158,10 +158,10 @@ k_backproject(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ pa
               const typename GeoOf<T>::type *__restrict__ geo, const int *__restrict__ brick_prob,
               const int *__restrict__ sub_off, const int *__restrict__ sub_patch,
               const typename Vec2Of<T>::type *__restrict__ rq, T *__restrict__ num,
-              T *__restrict__ den, int n_bricks, int per) {
+              T *__restrict__ den, int n_bricks) {
   using GEO = typename GeoOf<T>::type;
   using V2 = typename Vec2Of<T>::type;
-  const int bi = xcd_work(blockIdx.x, per);
+  const int bi = xcd_work(blockIdx.x, BP_XCD_GRANULE);
   if (bi >= n_bricks) return;
   const ProbDev pr = probs[brick_prob[bi]];
   const int local = bi - pr.brick_base;
@@ -213,16 +213,19 @@ static pvr_status backproject_impl(const pvr_plan *p, const T *e, const T *pp, c
                      p->d_sim_blocks, invz, e, pp, patch_w, rq);
   HIP_TRY(hipGetLastError());
   const void *geo = sizeof(T) == 4 ? (const void *)p->d_geof : (const void *)p->d_geod;
-  const int per = xcd_per(p->n_bricks);
+  const dim3 grid(xcd_blocks(p->n_bricks, BP_XCD_GRANULE));
+  hipEvent_t *ev = timing_slot(p, PVR_KERNEL_BACKPROJECT);
+  if (ev) HIP_TRY(hipEventRecord(ev[0], stream));
   if (den)
-    hipLaunchKernelGGL((k_backproject<T, true>), dim3(N_XCD * per), dim3(BP_THREADS), 0, stream,
+    hipLaunchKernelGGL((k_backproject<T, true>), grid, dim3(BP_THREADS), 0, stream,
                        p->d_prob, p->d_patch, (const typename GeoOf<T>::type *)geo, p->d_brick_prob,
-                       p->d_sub_off, p->d_sub_patch, rq, num, den, p->n_bricks, per);
+                       p->d_sub_off, p->d_sub_patch, rq, num, den, p->n_bricks);
   else
-    hipLaunchKernelGGL((k_backproject<T, false>), dim3(N_XCD * per), dim3(BP_THREADS), 0, stream,
+    hipLaunchKernelGGL((k_backproject<T, false>), grid, dim3(BP_THREADS), 0, stream,
                        p->d_prob, p->d_patch, (const typename GeoOf<T>::type *)geo, p->d_brick_prob,
-                       p->d_sub_off, p->d_sub_patch, rq, num, den, p->n_bricks, per);
+                       p->d_sub_off, p->d_sub_patch, rq, num, den, p->n_bricks);
   HIP_TRY(hipGetLastError());
+  if (ev) HIP_TRY(hipEventRecord(ev[1], stream));
   return PVR_OK;
 }
 

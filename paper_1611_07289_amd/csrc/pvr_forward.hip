@@ -19,8 +19,8 @@ __global__ void __launch_bounds__(SIM_THREADS)
 k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patches,
            const BlockWork *__restrict__ work, const typename GeoOf<T>::type *__restrict__ geo,
            const T *__restrict__ invz, const T *__restrict__ X, const T *__restrict__ y_obs,
-           T *__restrict__ y_sim, T *__restrict__ resid, int n_work, int per) {
-  const int wi = xcd_work(blockIdx.x, per);
+           T *__restrict__ y_sim, T *__restrict__ resid, int n_work) {
+  const int wi = xcd_work(blockIdx.x, SIM_XCD_GRANULE);
   if (wi >= n_work) return;
   const BlockWork wk = work[wi];
   const PatchDev pt = patches[wk.patch];
@@ -50,16 +50,16 @@ k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patch
 // workgroup copies the voxel box of the tile's supports into LDS with row-
 // contiguous (coalesced) loads, then every lane walks its sample's support in
 // LDS.  Tiles whose box exceeds the reserved LDS walk the volume in global
-// memory instead.  Each XCD receives one contiguous run of the patch-major
-// tile list (xcd_work), keeping overlapping tiles in the same L2.
+// memory instead.  Tiles are dealt to the XCDs in granules of neighbouring
+// tiles (xcd_work), keeping overlapping tiles in the same L2.
 __global__ void __launch_bounds__(SIM_THREADS)
 k_simulate_tiles(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patches,
-                 const TileWork *__restrict__ tiles, int n_tiles, int per_xcd,
+                 const TileWork *__restrict__ tiles, int n_tiles,
                  const GeoF *__restrict__ geo, const float *__restrict__ invz,
                  const float *__restrict__ X, const float *__restrict__ y_obs,
                  float *__restrict__ y_sim, float *__restrict__ resid, int lds_cap) {
   extern __shared__ float xs[];
-  const int t = xcd_work(blockIdx.x, per_xcd);
+  const int t = xcd_work(blockIdx.x, SIM_XCD_GRANULE);
   if (t >= n_tiles) return;
   const TileWork tw = tiles[t];
   const PatchDev pt = patches[tw.patch];
@@ -112,22 +112,27 @@ static pvr_status simulate_impl(const pvr_plan *p, const T *X, const T *y_obs, T
   if (resid && !y_obs) return fail(PVR_EINVAL, "pvr_simulate: resid requires y_obs");
   if (!y_sim && !resid) return PVR_OK;
   if (sizeof(T) == 4 && p->use_tiles && p->lds_box > 0) {
-    const int per = xcd_per(p->n_tiles);
-    hipLaunchKernelGGL(k_simulate_tiles, dim3(N_XCD * per), dim3(SIM_THREADS),
+    hipEvent_t *ev = timing_slot(p, PVR_KERNEL_SIMULATE);
+    if (ev) HIP_TRY(hipEventRecord(ev[0], stream));
+    hipLaunchKernelGGL(k_simulate_tiles, dim3(xcd_blocks(p->n_tiles, SIM_XCD_GRANULE)), dim3(SIM_THREADS),
                        (size_t)p->lds_box * sizeof(float), stream, p->d_prob, p->d_patch,
-                       p->d_tiles, p->n_tiles, per, p->d_geof, (const float *)invz,
+                       p->d_tiles, p->n_tiles, p->d_geof, (const float *)invz,
                        (const float *)X, (const float *)y_obs, (float *)y_sim, (float *)resid,
                        p->lds_box);
     HIP_TRY(hipGetLastError());
+    if (ev) HIP_TRY(hipEventRecord(ev[1], stream));
     return PVR_OK;
   }
-  const int per = xcd_per(p->n_sim_blocks);
-  hipLaunchKernelGGL(k_simulate<T>, dim3(N_XCD * per), dim3(SIM_THREADS), 0, stream, p->d_prob,
+  hipEvent_t *ev = timing_slot(p, PVR_KERNEL_SIMULATE);
+  if (ev) HIP_TRY(hipEventRecord(ev[0], stream));
+  hipLaunchKernelGGL(k_simulate<T>, dim3(xcd_blocks(p->n_sim_blocks, SIM_XCD_GRANULE)),
+                     dim3(SIM_THREADS), 0, stream, p->d_prob,
                      p->d_patch, p->d_sim_blocks,
                      (const typename GeoOf<T>::type *)(sizeof(T) == 4 ? (const void *)p->d_geof
                                                                       : (const void *)p->d_geod),
-                     invz, X, y_obs, y_sim, resid, p->n_sim_blocks, per);
+                     invz, X, y_obs, y_sim, resid, p->n_sim_blocks);
   HIP_TRY(hipGetLastError());
+  if (ev) HIP_TRY(hipEventRecord(ev[1], stream));
   return PVR_OK;
 }
 

@@ -97,13 +97,22 @@ struct BlockWork {   // one forward workgroup: a chunk of one patch
 };
 
 // Workgroups are dealt to the 8 XCDs round-robin by block index, and every
-// XCD has its own L2.  A grid of N_XCD * per blocks maps block b to work item
-// (b mod 8) * per + b / 8, so each XCD takes one contiguous run of the work
-// list (neighbouring chunks of a patch, neighbouring bricks) and the data
-// they share stays in one L2; items >= n are empty.
+// XCD has its own L2.  xcd_work regroups the work list into granules of g
+// consecutive items: XCD x takes granules x, x + 8, x + 16, ..., so the items
+// of a granule (neighbouring chunks of a patch, neighbouring bricks) share one
+// L2 while every XCD still sees a uniform mix of the whole list.  The grid
+// has xcd_blocks(n, g) blocks; items >= n are empty.  g = 1 is the plain
+// round-robin order.
 constexpr int N_XCD = 8;
-__host__ __device__ __forceinline__ int xcd_per(int n) { return (n + N_XCD - 1) / N_XCD; }
-__device__ __forceinline__ int xcd_work(int b, int per) { return (b % N_XCD) * per + b / N_XCD; }
+__host__ __device__ __forceinline__ int xcd_blocks(int n, int g) {
+  return (n + N_XCD * g - 1) / (N_XCD * g) * (N_XCD * g);
+}
+__device__ __forceinline__ int xcd_work(int b, int g) {
+  const int i = b / N_XCD;
+  return (i / g) * (N_XCD * g) + (b % N_XCD) * g + i % g;
+}
+constexpr int SIM_XCD_GRANULE = 1;   // forward chunks: plain round-robin measured fastest
+constexpr int BP_XCD_GRANULE = 64;   // adjoint bricks (z-slab pieces)
 
 constexpr int TILE = 16;            // forward tile edge (pixels)
 constexpr int LDS_BOX_MAX = 16384;  // staged voxels per forward workgroup (64 KiB)
@@ -374,6 +383,15 @@ __device__ __forceinline__ T block_sum(T v, T *lds) {
 // ---------------------------------------------------------------------------
 // host-side plan object
 // ---------------------------------------------------------------------------
+namespace pvr {
+constexpr int TIMING_KERNELS = 2;
+constexpr int TIMING_CAP = 256;  // event pairs per kernel between reads
+struct KernelTimer {
+  hipEvent_t ev[TIMING_CAP][2];
+  int n;
+};
+}  // namespace pvr
+
 struct pvr_plan {
   int device;
   int P, S, M;
@@ -396,6 +414,8 @@ struct pvr_plan {
   pvr::TileWork *d_tiles;
   int n_tiles, tile_cap, tile_w, tile_h;
   bool use_tiles;            // forward pass staged per tile in LDS (else global walk)
+  bool timing;               // record event pairs around the hot kernels
+  pvr::KernelTimer *timers;  // [TIMING_KERNELS] (created on first enable)
   int *d_box_max;            // [1] largest tile box (voxels) of the last build
   int lds_box;               // LDS floats reserved per forward workgroup
   int *d_brick_prob;         // [n_bricks]

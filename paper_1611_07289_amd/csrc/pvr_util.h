@@ -19,6 +19,9 @@ void launch_fill_u8(uint8_t *dst, uint8_t v, long long n, hipStream_t stream);
 void launch_fill_i32(int *dst, int v, long long n, hipStream_t stream);
 void launch_fill_f32(float *dst, float v, long long n, hipStream_t stream);
 void launch_fill_f64(double *dst, double v, long long n, hipStream_t stream);
+// The event pair to record around the next launch of kernel k, or nullptr
+// when the plan is not timing (or the kernel's slots are full).
+hipEvent_t *timing_slot(const pvr_plan *p, int k);
 
 struct PlanGuard {
   pvr_plan *p;

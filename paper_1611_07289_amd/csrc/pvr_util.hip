@@ -50,6 +50,13 @@ void plan_free(pvr_plan *p) {
   for (void *q : dev)
     if (q) (void)hipFree(q);
   if (p->h_total) (void)hipHostFree(p->h_total);
+  if (p->timers) {
+    for (int k = 0; k < TIMING_KERNELS; ++k)
+      for (int i = 0; i < TIMING_CAP; ++i)
+        for (int j = 0; j < 2; ++j)
+          if (p->timers[k].ev[i][j]) (void)hipEventDestroy(p->timers[k].ev[i][j]);
+    free(p->timers);
+  }
   free(p->h_prob);
   free(p->h_stack);
   free(p->h_patch);

@@ -16,6 +16,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpvr.so")
 
+PVR_KERNEL_SIMULATE = 0
+PVR_KERNEL_BACKPROJECT = 1
 PVR_EM_INIT = 1
 PVR_EM_FIX_W = 2
 
@@ -85,7 +87,8 @@ EXPORTS = ["pvr_last_error", "pvr_version", "pvr_plan_create", "pvr_plan_destroy
            "pvr_plan_inv_z", "pvr_simulate", "pvr_simulate_f64", "pvr_backproject",
            "pvr_backproject_f64", "pvr_robust_weights", "pvr_sr_update",
            "pvr_register_patches", "pvr_simulate_grad_theta", "pvr_simulate_grad_theta_f64",
-           "pvr_ncc_grad", "pvr_plan_set_tiles", "pvr_cnn_conv_fwd", "pvr_cnn_conv_dgrad",
+           "pvr_ncc_grad", "pvr_plan_set_tiles", "pvr_plan_set_timing", "pvr_plan_kernel_time",
+           "pvr_cnn_conv_fwd", "pvr_cnn_conv_dgrad",
            "pvr_cnn_wgrad_scratch", "pvr_cnn_conv_wgrad", "pvr_cnn_pack_pairs",
            "pvr_cnn_head_scratch", "pvr_cnn_head", "pvr_cnn_adam"]
 
@@ -124,6 +127,8 @@ def load(path: str = LIB_PATH):
     L.pvr_simulate_grad_theta_f64.argtypes = [P, P, P, P, P]
     L.pvr_ncc_grad.argtypes = [P, P, P, P, P, P]
     L.pvr_plan_set_tiles.argtypes = [P, i32, i32, P]
+    L.pvr_plan_set_timing.argtypes = [P, i32]
+    L.pvr_plan_kernel_time.argtypes = [P, i32, P, P]
     L.pvr_cnn_conv_fwd.argtypes = [P, P, P, P, i32, i32, i32, i32, i32, i32, i32, P]
     L.pvr_cnn_conv_dgrad.argtypes = [P, P, P, P, i32, i32, i32, i32, i32, i32, P]
     L.pvr_cnn_wgrad_scratch.argtypes = [i32, i32, i32, i32, i32, i32]
@@ -239,6 +244,16 @@ class Plan:
         f = load().pvr_plan_build_f64 if theta.dtype == torch.float64 else load().pvr_plan_build
         _check(f(self.h, _ptr(theta), _ptr(active), _ptr(mask), _stream()))
         self.build_id = getattr(self, "build_id", 0) + 1
+
+    def set_timing(self, on: bool = True):
+        _check(load().pvr_plan_set_timing(self.h, 1 if on else 0))
+
+    def kernel_time(self, kernel: int):
+        """(summed ms, launches) of the timed kernel since the last read
+        (kernel: PVR_KERNEL_SIMULATE or PVR_KERNEL_BACKPROJECT)."""
+        ms, n = ctypes.c_double(), ctypes.c_int32()
+        _check(load().pvr_plan_kernel_time(self.h, int(kernel), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def set_tiles(self, tile_w: int, tile_h: int):
         _check(load().pvr_plan_set_tiles(self.h, int(tile_w), int(tile_h), _stream()))
