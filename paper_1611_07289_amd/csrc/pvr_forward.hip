@@ -26,8 +26,8 @@ k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patch
   const PatchDev pt = patches[wk.patch];
   const ProbDev pr = probs[pt.problem];
   const typename GeoOf<T>::type &g = geo[wk.patch];
-  const __amdgpu_buffer_rsrc_t xr =
-      raw_buffer(X + pr.vol_off, (unsigned)(pr.nx * pr.ny * pr.nz) * (unsigned)sizeof(T));
+  const unsigned nbytes = (unsigned)(pr.nx * pr.ny * pr.nz) * (unsigned)sizeof(T);
+  const __amdgpu_buffer_rsrc_t xr = raw_buffer(X + pr.vol_off, nbytes);
   const int n = pt.w * pt.h;
   const int l1 = min(n, wk.l0 + SIM_CHUNK);
   for (int l = wk.l0 + threadIdx.x; l < l1; l += SIM_THREADS) {
@@ -39,7 +39,7 @@ k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patch
       int b[3];
       T f[3];
       sample_centre(g, pr, u, v, pt.slice, b, f);
-      yh = psf_walk_fwd<T, typename GeoOf<T>::type>(g, pr, b, f, xr) * iz;
+      yh = psf_walk_fwd<T, typename GeoOf<T>::type>(g, pr, b, f, xr, nbytes) * iz;
     }
     if (y_sim) y_sim[j] = yh;
     if (resid) resid[j] = iz > (T)0 ? y_obs[j] - yh : (T)0;
@@ -195,7 +195,8 @@ struct RegShared {
 // NCC of the patch against its simulation at sh.th (valid samples only);
 // every lane returns the same value.
 __device__ double reg_eval(RegShared &sh, const ProbDev &pr, const StackDev &st, const PatchDev &pt,
-                           double k, __amdgpu_buffer_rsrc_t xr, const float *__restrict__ y,
+                           double k, __amdgpu_buffer_rsrc_t xr, unsigned nbytes,
+                           const float *__restrict__ y,
                            const uint8_t *__restrict__ mask) {
   if (threadIdx.x == 0) {
     GeoD gd;
@@ -214,7 +215,7 @@ __device__ double reg_eval(RegShared &sh, const ProbDev &pr, const StackDev &st,
     float f[3];
     if (!sample_centre(g, pr, u, v, pt.slice, b, f)) continue;
     float z = 0.f;
-    const float a = psf_walk_fwd<float, GeoF, true>(g, pr, b, f, xr, &z);
+    const float a = psf_walk_fwd<float, GeoF, true>(g, pr, b, f, xr, nbytes, &z);
     if (!(z > 0.f)) continue;
     const double yh = (double)(a / z), yo = (double)y[j];
     acc6[0] += 1.0;
@@ -247,8 +248,8 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
   const PatchDev pt = patches[s];
   const StackDev st = stacks[pt.stack];
   const ProbDev pr = probs[pt.problem];
-  const __amdgpu_buffer_rsrc_t xr =
-      raw_buffer(X + pr.vol_off, (unsigned)(pr.nx * pr.ny * pr.nz) * (unsigned)sizeof(float));
+  const unsigned nbytes = (unsigned)(pr.nx * pr.ny * pr.nz) * (unsigned)sizeof(float);
+  const __amdgpu_buffer_rsrc_t xr = raw_buffer(X + pr.vol_off, nbytes);
   // observed standard deviation over unmasked samples
   double sy[6] = {0, 0, 0, 0, 0, 0};
   const int n = pt.w * pt.h;
@@ -277,7 +278,7 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
     }
   }
   __syncthreads();
-  double f0 = reg_eval(sh, pr, st, pt, k, xr, y, mask);
+  double f0 = reg_eval(sh, pr, st, pt, k, xr, nbytes, y, mask);
   const bool do_reg = (reg ? reg[s] != 0 : true) && sd >= prm.min_std && prm.max_iter > 0;
   if (do_reg) {
     double delta = prm.step0;
@@ -292,10 +293,10 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
             for (int b = 0; b < 6; ++b) sh.th[b] = sh.q[b] / sh.sc[b];
             sh.th[a] = (sh.q[a] + prm.fd_h) / sh.sc[a];
           }
-          fp = reg_eval(sh, pr, st, pt, k, xr, y, mask);
+          fp = reg_eval(sh, pr, st, pt, k, xr, nbytes, y, mask);
           __syncthreads();
           if (threadIdx.x == 0) sh.th[a] = (sh.q[a] - prm.fd_h) / sh.sc[a];
-          fm = reg_eval(sh, pr, st, pt, k, xr, y, mask);
+          fm = reg_eval(sh, pr, st, pt, k, xr, nbytes, y, mask);
           if (threadIdx.x == 0) sh.grad[a] = (fp - fm) / (2.0 * prm.fd_h);
         }
         have_grad = true;
@@ -308,7 +309,7 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
       __syncthreads();
       if (threadIdx.x == 0)
         for (int a = 0; a < 6; ++a) sh.th[a] = (sh.q[a] + delta * sh.grad[a] / gn) / sh.sc[a];
-      const double ft = reg_eval(sh, pr, st, pt, k, xr, y, mask);
+      const double ft = reg_eval(sh, pr, st, pt, k, xr, nbytes, y, mask);
       if (ft > f0) {
         __syncthreads();
         if (threadIdx.x == 0)
