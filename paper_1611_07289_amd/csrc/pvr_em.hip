@@ -209,6 +209,23 @@ __device__ __forceinline__ double inlier_resp(double v, const Mix &m) {
   return 1.0 / (1.0 + exp(l0 - l1));
 }
 
+// The same in single precision for the mixture iterations (the sums over
+// patches stay FP64; the responsibilities differ from the FP64 ones by ~1e-7
+// relative, which moves the fitted parameters by as little).  The final
+// patch posteriors use inlier_resp.
+struct MixF {
+  float mu0, mu1, h0, h1, c0, c1;
+};
+__device__ __forceinline__ MixF to_f32(const Mix &m) {
+  return MixF{(float)m.mu0, (float)m.mu1, (float)m.h0, (float)m.h1, (float)m.c0, (float)m.c1};
+}
+__device__ __forceinline__ float inlier_resp_f(float v, const MixF &m) {
+  const float d0 = v - m.mu0, d1 = v - m.mu1;
+  const float l = (m.c0 - d0 * d0 * m.h0) - (m.c1 - d1 * d1 * m.h1);
+  // l = +-inf when a component has zero weight: exp gives inf or 0, 1/(1+inf) = 0
+  return __builtin_amdgcn_rcpf(1.f + __expf(l));
+}
+
 // Two-component mixture on the potentials of one problem, patch weights and
 // the M-step.  The start splits the potentials at the median: the n/2 smallest
 // form the low component.  The split value is found exactly by a radix select
@@ -222,7 +239,8 @@ __device__ __forceinline__ double inlier_resp(double v, const Mix &m) {
 // the high component's sums of r, r v and r v^2; the low component's follow
 // from the totals (sum 1, sum v, sum v^2), and each variance is
 // E[v^2] - mean^2 (values in [0, 1], FP64: the cancellation costs ~1e-16 /
-// var relative, against a floor of 1e-6 on the variance).
+// var relative, against a floor of 1e-6 on the variance).  Inside the
+// iterations the responsibilities are single precision (inlier_resp_f).
 __global__ void __launch_bounds__(EMP_T)
 k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
              const uint8_t *__restrict__ active, const double *__restrict__ pstat,
@@ -305,11 +323,12 @@ k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
     w1 = 0.9;
     for (int it = 0; it < 20; ++it) {
       double r1s = 0, r1v = 0, r1q = 0;
-      const Mix mx = make_mix(mu0, sd0, mu1, sd1, w1);
+      const MixF mx = to_f32(make_mix(mu0, sd0, mu1, sd1, w1));
       for (int q = t; q < np; q += EMP_T) {
-        const double v = V[q];
-        if (!(v >= 0)) continue;
-        const double r1 = inlier_resp(v, mx);
+        const float vf = V[q];
+        if (!(vf >= 0.f)) continue;
+        const double v = vf;
+        const double r1 = inlier_resp_f(vf, mx);
         r1s += r1;
         r1v += r1 * v;
         r1q += r1 * v * v;
