@@ -240,10 +240,10 @@ def train(net: Net, plan, volumes: List, n_pairs: int, batch: int = 256, lr: flo
     for r in range(rounds):
         td = time.perf_counter()
         X = volumes[r % len(volumes)]
-        ref = torch.from_numpy(synth.random_motion(M, max_rot_deg, max_trans,
-                                                   seed + 2 * r).astype(np.float32)).to(dev)
-        off = torch.from_numpy(synth.random_motion(M, max_rot_deg, max_trans,
-                                                   seed + 2 * r + 1).astype(np.float32)).to(dev)
+        ref = torch.from_numpy(synth.random_motion_batch(M, max_rot_deg, max_trans,
+                                                         seed + 2 * r).astype(np.float32)).to(dev)
+        off = torch.from_numpy(synth.random_motion_batch(M, max_rot_deg, max_trans,
+                                                         seed + 2 * r + 1).astype(np.float32)).to(dev)
         y_obs, y_sim = make_pairs(plan, X, ref, off, 0.01 * float(X.max()), seed + r)
         target = apply_maps(A, off)
         perm = torch.from_numpy(rng.permutation(M).astype(np.int32)).to(dev)

@@ -336,6 +336,35 @@ def random_motion(M: int, max_rot_deg: float, max_trans: float,
     return th
 
 
+def random_motion_batch(M: int, max_rot_deg: float, max_trans: float,
+                        seed: int) -> np.ndarray:
+    """The distribution of random_motion, drawn for all patches at once (a
+    different random stream; used for the learned initialiser's training
+    pairs, where thousands of draws per second are needed)."""
+    rng = np.random.default_rng(seed)
+    ax = rng.normal(size=(M, 3))
+    ax /= np.linalg.norm(ax, axis=1, keepdims=True)
+    ang = np.radians(rng.uniform(0.0, max_rot_deg, size=M))
+    K = np.zeros((M, 3, 3))
+    K[:, 0, 1], K[:, 0, 2], K[:, 1, 2] = -ax[:, 2], ax[:, 1], -ax[:, 0]
+    K[:, 1, 0], K[:, 2, 0], K[:, 2, 1] = ax[:, 2], -ax[:, 1], ax[:, 0]
+    R = (np.eye(3)[None] + np.sin(ang)[:, None, None] * K
+         + (1 - np.cos(ang))[:, None, None] * (K @ K))
+    th = np.zeros((M, 6))
+    th[:, 1] = np.arcsin(np.clip(-R[:, 2, 0], -1.0, 1.0))
+    th[:, 0] = np.arctan2(R[:, 2, 1], R[:, 2, 2])
+    th[:, 2] = np.arctan2(R[:, 1, 0], R[:, 0, 0])
+    t = np.zeros((M, 3))
+    todo = np.arange(M)
+    while todo.size:
+        c = rng.uniform(-1, 1, size=(todo.size, 3))
+        ok = (c ** 2).sum(axis=1) <= 1
+        t[todo[ok]] = c[ok]
+        todo = todo[~ok]
+    th[:, 3:] = t * max_trans
+    return th
+
+
 def choose_outliers(M: int, frac: float, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     k = int(round(frac * M))
