@@ -242,7 +242,8 @@ def main():
         plan.simulate(X_ref[0], y_obs=y, resid=e)
         if ev is not None:
             ev[1].record()
-        plan.robust_weights(e, y, em, p, pbar, W, pvr.PVR_EM_INIT if first else 0)
+        plan.robust_weights(e, y, em, p, pbar, W,
+                            (pvr.PVR_EM_INIT if first else 0) | pvr.PVR_EM_RESID_FRESH)
         if ev is not None:
             ev[2].record()
         plan.backproject(e, p, W, num, den)

@@ -134,6 +134,13 @@ typedef struct {
 /* pvr_robust_weights flags */
 #define PVR_EM_INIT  1      /* start of a cycle: sigma^2 = mean(e^2), c = 0.9 */
 #define PVR_EM_FIX_W 2      /* use patch_w as given instead of classifying */
+#define PVR_EM_RESID_FRESH 4 /* resid (with y_obs) is exactly what the plan's last
+                                pvr_simulate wrote, unmodified: its residual
+                                statistics, reduced by the forward kernel, are
+                                reused instead of a pass over resid (the
+                                library also checks the two pointers; with a
+                                mismatch, LDS-tiled simulation or a build in
+                                between it passes over resid as usual) */
 
 typedef struct {
   float alpha;              /* step length (default 1) */

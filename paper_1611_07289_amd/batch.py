@@ -37,7 +37,8 @@ class GraphedSR:
     def _iter(self, src, dst, flags=0):
         pl = self.plan
         pl.simulate(src, y_obs=self.y, resid=self.e)
-        pl.robust_weights(self.e, self.y, self.em, self.p, self.pbar, self.W, flags)
+        pl.robust_weights(self.e, self.y, self.em, self.p, self.pbar, self.W,
+                          flags | pvr.PVR_EM_RESID_FRESH)
         pl.backproject(self.e, self.p, self.W, self.num, self.den)
         pl.sr_update(src, self.num, self.den, dst, self.prm)
 

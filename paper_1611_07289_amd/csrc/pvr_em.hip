@@ -109,14 +109,19 @@ k_em_patch_stats(const PatchDev *__restrict__ patches, const float *__restrict__
   }
 }
 
+// Per-problem reduction of the residual statistics: from the per-patch table
+// (pstat, stride PSTAT), or with chunk_stats from the forward kernel's
+// per-chunk records (stride 5) over the problem's chunk range.
 __global__ void __launch_bounds__(EMP_T)
 k_em_problem(const ProbDev *__restrict__ probs, const double *__restrict__ pstat,
-             pvr_em_state *__restrict__ em, int init) {
+             const double *__restrict__ chunk_stats, pvr_em_state *__restrict__ em, int init) {
   __shared__ double lds[8 * (EMP_T / 64)];
   const ProbDev pr = probs[blockIdx.x];
   double mn = INFINITY, mx = -INFINITY, ym = 0, se2 = 0, cnt = 0;
-  for (int s = pr.patch_begin + threadIdx.x; s < pr.patch_end; s += EMP_T) {
-    const double *o = pstat + PSTAT * s;
+  const int r0 = chunk_stats ? pr.chunk_begin : pr.patch_begin;
+  const int r1 = chunk_stats ? pr.chunk_end : pr.patch_end;
+  for (int s = r0 + threadIdx.x; s < r1; s += EMP_T) {
+    const double *o = chunk_stats ? chunk_stats + 5 * (long long)s : pstat + PSTAT * s;
     mn = fmin(mn, o[0]);
     mx = fmax(mx, o[1]);
     ym = fmax(ym, o[2]);
@@ -249,6 +254,9 @@ k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
   __shared__ double lds[8 * (EMP_T / 64)];
   __shared__ unsigned int hist[256];
   __shared__ unsigned int sel_prefix, sel_rank;
+  __shared__ double mixp[5];  // mu0, sd0, mu1, sd1, w1
+  __shared__ MixF mixf;
+  __shared__ int mix_stop;
   extern __shared__ float sval[];
   const ProbDev pr = probs[blockIdx.x];
   const int t = threadIdx.x;
@@ -313,17 +321,26 @@ k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
     double red3[3] = {c_lt, s_lt, q_lt};
     bsumk<EMP_T, 3>(red3, lds);
     c_lt = red3[0]; s_lt = red3[1]; q_lt = red3[2];
-    const double fill = n_lo - c_lt;
-    const double s0 = s_lt + fill * tv, q0 = q_lt + fill * tv * tv;
-    const double n_hi = nu - n_lo;
-    mu0 = s0 / n_lo;
-    sd0 = fmax(sqrt(fmax(q0 / n_lo - mu0 * mu0, 0.0)), 1e-3);
-    mu1 = (s_all - s0) / n_hi;
-    sd1 = fmax(sqrt(fmax((q_all - q0) / n_hi - mu1 * mu1, 0.0)), 1e-3);
-    w1 = 0.9;
+    // the mixture state lives in LDS and is updated by one lane: its FP64
+    // divisions, square roots and logarithms would otherwise run in all 16
+    // waves of the workgroup
+    if (t == 0) {
+      const double fill = n_lo - c_lt;
+      const double s0 = s_lt + fill * tv, q0 = q_lt + fill * tv * tv;
+      const double n_hi = nu - n_lo;
+      const double m0 = s0 / n_lo, m1 = (s_all - s0) / n_hi;
+      mixp[0] = m0;
+      mixp[1] = fmax(sqrt(fmax(q0 / n_lo - m0 * m0, 0.0)), 1e-3);
+      mixp[2] = m1;
+      mixp[3] = fmax(sqrt(fmax((q_all - q0) / n_hi - m1 * m1, 0.0)), 1e-3);
+      mixp[4] = 0.9;
+      mixf = to_f32(make_mix(mixp[0], mixp[1], mixp[2], mixp[3], mixp[4]));
+      mix_stop = 0;
+    }
+    __syncthreads();
     for (int it = 0; it < 20; ++it) {
       double r1s = 0, r1v = 0, r1q = 0;
-      const MixF mx = to_f32(make_mix(mu0, sd0, mu1, sd1, w1));
+      const MixF mx = mixf;
       for (int q = t; q < np; q += EMP_T) {
         const float vf = V[q];
         if (!(vf >= 0.f)) continue;
@@ -335,15 +352,25 @@ k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
       }
       double red[3] = {r1s, r1v, r1q};
       bsumk<EMP_T, 3>(red, lds);
-      r1s = red[0]; r1v = red[1]; r1q = red[2];
-      const double r0s = nu - r1s;
-      if (!(r1s > 0) || !(r0s > 0)) break;
-      mu1 = r1v / r1s;
-      mu0 = (s_all - r1v) / r0s;
-      sd1 = fmax(sqrt(fmax(r1q / r1s - mu1 * mu1, 0.0)), 1e-3);
-      sd0 = fmax(sqrt(fmax((q_all - r1q) / r0s - mu0 * mu0, 0.0)), 1e-3);
-      w1 = r1s / nu;
+      if (t == 0) {
+        r1s = red[0]; r1v = red[1]; r1q = red[2];
+        const double r0s = nu - r1s;
+        if (!(r1s > 0) || !(r0s > 0)) {
+          mix_stop = 1;
+        } else {
+          const double m1 = r1v / r1s, m0 = (s_all - r1v) / r0s;
+          mixp[2] = m1;
+          mixp[0] = m0;
+          mixp[3] = fmax(sqrt(fmax(r1q / r1s - m1 * m1, 0.0)), 1e-3);
+          mixp[1] = fmax(sqrt(fmax((q_all - r1q) / r0s - m0 * m0, 0.0)), 1e-3);
+          mixp[4] = r1s / nu;
+          mixf = to_f32(make_mix(mixp[0], mixp[1], mixp[2], mixp[3], mixp[4]));
+        }
+      }
+      __syncthreads();
+      if (mix_stop) break;
     }
+    mu0 = mixp[0]; sd0 = mixp[1]; mu1 = mixp[2]; sd1 = mixp[3]; w1 = mixp[4];
   }
   const bool swap = fit && mu0 > mu1;
   const Mix mfin = make_mix(mu0, sd0, mu1, sd1, w1);
@@ -397,11 +424,17 @@ extern "C" pvr_status pvr_robust_weights(pvr_plan *p, const float *resid, const 
   const int fix = (flags & PVR_EM_FIX_W) != 0;
   // p_bar is needed by the classification even when the caller does not want it
   float *pb = pbar ? pbar : p->d_pbar;
-  hipLaunchKernelGGL(k_em_patch_stats, dim3(p->M), dim3(EM_T), 0, stream, p->d_patch, p->d_invz,
-                     resid, y_obs, p->d_pstat);
-  HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_em_problem, dim3(p->P), dim3(EMP_T), 0, stream, p->d_prob, p->d_pstat, em,
-                     init);
+  // residual statistics: reused from the forward kernel when the caller vouches
+  // that resid is unchanged since the plan's last pvr_simulate wrote it
+  const bool fresh = (flags & PVR_EM_RESID_FRESH) && p->stats_valid && p->stats_resid == resid &&
+                     p->stats_y == y_obs;
+  if (!fresh) {
+    hipLaunchKernelGGL(k_em_patch_stats, dim3(p->M), dim3(EM_T), 0, stream, p->d_patch, p->d_invz,
+                       resid, y_obs, p->d_pstat);
+    HIP_TRY(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_em_problem, dim3(p->P), dim3(EMP_T), 0, stream, p->d_prob, p->d_pstat,
+                     fresh ? (const double *)p->d_chunk_stats : nullptr, em, init);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_em_estep, dim3(p->M), dim3(EM_T), 0, stream, p->d_patch, p->d_invz, resid,
                      em, pp, pb, p->d_pstat);

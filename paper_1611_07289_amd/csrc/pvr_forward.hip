@@ -14,12 +14,17 @@
 
 using namespace pvr;
 
+// With resid and chunk_stats, the workgroup also reduces its chunk's
+// residual statistics over valid samples -- min e, max e, max |y|, sum e^2
+// and the count (FP64, fixed order) -- into chunk_stats[5 * chunk], which the
+// robust weights then read instead of passing over e once more.
 template <typename T>
 __global__ void __launch_bounds__(SIM_THREADS)
 k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patches,
            const BlockWork *__restrict__ work, const typename GeoOf<T>::type *__restrict__ geo,
            const T *__restrict__ invz, const T *__restrict__ X, const T *__restrict__ y_obs,
-           T *__restrict__ y_sim, T *__restrict__ resid, int n_work) {
+           T *__restrict__ y_sim, T *__restrict__ resid, double *__restrict__ chunk_stats,
+           int n_work) {
   const int wi = xcd_work(blockIdx.x, SIM_XCD_GRANULE);
   if (wi >= n_work) return;
   const BlockWork wk = work[wi];
@@ -30,6 +35,7 @@ k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patch
   const __amdgpu_buffer_rsrc_t xr = raw_buffer(X + pr.vol_off, nbytes);
   const int n = pt.w * pt.h;
   const int l1 = min(n, wk.l0 + SIM_CHUNK);
+  double st[5] = {INFINITY, -INFINITY, 0.0, 0.0, 0.0};  // min e, max e, max|y|, sum e^2, count
   for (int l = wk.l0 + threadIdx.x; l < l1; l += SIM_THREADS) {
     const long long j = pt.off + l;
     const T iz = invz[j];
@@ -42,7 +48,44 @@ k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patch
       yh = psf_walk_fwd<T, typename GeoOf<T>::type>(g, pr, b, f, xr, nbytes) * iz;
     }
     if (y_sim) y_sim[j] = yh;
-    if (resid) resid[j] = iz > (T)0 ? y_obs[j] - yh : (T)0;
+    if (resid) {
+      const T e = iz > (T)0 ? y_obs[j] - yh : (T)0;
+      resid[j] = e;
+      if (chunk_stats && iz > (T)0) {
+        const double ev = (double)e;
+        st[0] = fmin(st[0], ev);
+        st[1] = fmax(st[1], ev);
+        st[2] = fmax(st[2], fabs((double)y_obs[j]));
+        st[3] += ev * ev;
+        st[4] += 1.0;
+      }
+    }
+  }
+  if (chunk_stats) {
+    __shared__ double red[5][SIM_THREADS / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      st[0] = fmin(st[0], __shfl_xor(st[0], o, 64));
+      st[1] = fmax(st[1], __shfl_xor(st[1], o, 64));
+      st[2] = fmax(st[2], __shfl_xor(st[2], o, 64));
+      st[3] += __shfl_xor(st[3], o, 64);
+      st[4] += __shfl_xor(st[4], o, 64);
+    }
+    if (lane == 0)
+      for (int k = 0; k < 5; ++k) red[k][wave] = st[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double r[5] = {red[0][0], red[1][0], red[2][0], red[3][0], red[4][0]};
+      for (int w = 1; w < SIM_THREADS / 64; ++w) {
+        r[0] = fmin(r[0], red[0][w]);
+        r[1] = fmax(r[1], red[1][w]);
+        r[2] = fmax(r[2], red[2][w]);
+        r[3] += red[3][w];
+        r[4] += red[4][w];
+      }
+      for (int k = 0; k < 5; ++k) chunk_stats[5 * (long long)wi + k] = r[k];
+    }
   }
 }
 
@@ -121,8 +164,10 @@ static pvr_status simulate_impl(const pvr_plan *p, const T *X, const T *y_obs, T
                        p->lds_box);
     HIP_TRY(hipGetLastError());
     if (ev) HIP_TRY(hipEventRecord(ev[1], stream));
+    const_cast<pvr_plan *>(p)->stats_valid = false;
     return PVR_OK;
   }
+  double *stats = (sizeof(T) == 4 && resid) ? p->d_chunk_stats : nullptr;
   hipEvent_t *ev = timing_slot(p, PVR_KERNEL_SIMULATE);
   if (ev) HIP_TRY(hipEventRecord(ev[0], stream));
   hipLaunchKernelGGL(k_simulate<T>, dim3(xcd_blocks(p->n_sim_blocks, SIM_XCD_GRANULE)),
@@ -130,9 +175,14 @@ static pvr_status simulate_impl(const pvr_plan *p, const T *X, const T *y_obs, T
                      p->d_patch, p->d_sim_blocks,
                      (const typename GeoOf<T>::type *)(sizeof(T) == 4 ? (const void *)p->d_geof
                                                                       : (const void *)p->d_geod),
-                     invz, X, y_obs, y_sim, resid, p->n_sim_blocks);
+                     invz, X, y_obs, y_sim, resid, stats, p->n_sim_blocks);
   HIP_TRY(hipGetLastError());
   if (ev) HIP_TRY(hipEventRecord(ev[1], stream));
+  // the residual statistics describe these buffers until the next build
+  pvr_plan *mp = const_cast<pvr_plan *>(p);
+  mp->stats_valid = stats != nullptr;
+  mp->stats_resid = resid;
+  mp->stats_y = y_obs;
   return PVR_OK;
 }
 

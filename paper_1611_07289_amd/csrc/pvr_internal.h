@@ -36,6 +36,7 @@ struct ProbDev {
   int nbx, nby, nbz;
   int brick_base, n_bricks;
   int patch_begin, patch_end;
+  int chunk_begin, chunk_end;   // forward work chunks (BlockWork) of the problem
   long long vol_off;
   long long sample_begin, sample_end;
   double v2w[12];
@@ -471,6 +472,9 @@ struct pvr_plan {
   double *d_pstat;           // [M][10] per-patch EM partials
   float *d_pbar;             // [M] potentials when the caller passes none
   float *d_pval;             // [M] classification scratch (problems beyond the LDS copy)
+  double *d_chunk_stats;     // [n_sim_blocks][5] residual statistics of the last simulate
+  const void *stats_resid, *stats_y;  // ... and the buffers they describe
+  bool stats_valid;
   int *d_total;              // [1] pinned readback target (device side)
   int *h_total;              // pinned host
   long long device_bytes;

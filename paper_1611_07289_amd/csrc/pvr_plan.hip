@@ -342,6 +342,15 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
       sb += scount[b];
     }
   }
+  {
+    // forward chunks are patch-major, so every problem's chunks form a range
+    int c = 0;
+    for (int b = 0; b < n_problems; ++b) {
+      p->h_prob[b].chunk_begin = c;
+      while (c < (int)blocks.size() && blocks[c].patch < p->h_prob[b].patch_end) ++c;
+      p->h_prob[b].chunk_end = c;
+    }
+  }
   p->h_sample_off[n_patches] = so;
   p->N = so;
   if (so > 0x7fffffffLL * 4) return fail(PVR_ESHAPE, "pvr_plan_create: too many samples");
@@ -402,6 +411,7 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
   DEV_ALLOC(p, p->d_pstat, 10 * (size_t)n_patches);
   DEV_ALLOC(p, p->d_pbar, n_patches);
   DEV_ALLOC(p, p->d_pval, n_patches);
+  DEV_ALLOC(p, p->d_chunk_stats, 5 * (size_t)p->n_sim_blocks);
   DEV_ALLOC(p, p->d_total, 4);
   HIP_TRY(hipHostMalloc((void **)&p->h_total, sizeof(int) * 4, hipHostMallocDefault));
   HIP_TRY(hipMemcpy(p->d_prob, p->h_prob, sizeof(ProbDev) * n_problems, hipMemcpyHostToDevice));
@@ -593,6 +603,7 @@ static pvr_status plan_build_common(pvr_plan *p, const uint8_t *active, const ui
     if (st != PVR_OK) return st;
   }
   p->index_valid = false;
+  p->stats_valid = false;
   p->built = true;
   p->built64 = f64;
   return PVR_OK;

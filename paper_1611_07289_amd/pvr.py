@@ -20,6 +20,7 @@ PVR_KERNEL_SIMULATE = 0
 PVR_KERNEL_BACKPROJECT = 1
 PVR_EM_INIT = 1
 PVR_EM_FIX_W = 2
+PVR_EM_RESID_FRESH = 4
 
 _STATUS = {0: "PVR_OK", 1: "PVR_EINVAL", 2: "PVR_ESHAPE", 3: "PVR_ENOMEM",
            4: "PVR_EHIP", 5: "PVR_ENUMERIC", 6: "PVR_EUNSUPPORTED"}

@@ -177,6 +177,37 @@ def test_robust_weights_match_oracle(tiny):
     print(f"[gpu] EM sigma2={st.sigma2:.4f} c={st.c:.6f} excluded={st.n_excluded}")
 
 
+def test_robust_weights_reuse_forward_statistics(tiny):
+    """PVR_EM_RESID_FRESH: the residual statistics the forward kernel reduced
+    give the same EM outcome as a separate pass over resid (to FP64 rounding
+    of the differently ordered sums); with a resid the plan's last simulate
+    did not write, the flag falls back to that pass exactly."""
+    P, plan, th32, y = tiny["P"], tiny["plan"], tiny["th32"], tiny["y"]
+    ctx = tiny["ctx"]
+    X0 = recon.initial_volume(ctx, y, th32).astype(np.float32)
+    yd = dev(y.astype(np.float32))
+    e = torch.empty(plan.N, dtype=torch.float32, device="cuda")
+    plan.simulate(dev(X0), y_obs=yd, resid=e)
+
+    def run(resid, flags):
+        em = plan.em_state()
+        pg = torch.empty(plan.N, dtype=torch.float32, device="cuda")
+        pb = torch.empty(plan.M, dtype=torch.float32, device="cuda")
+        W = torch.empty(plan.M, dtype=torch.float32, device="cuda")
+        plan.robust_weights(resid, yd, em, pg, pb, W, flags)
+        return host(pg).copy(), host(W).copy(), pvr.Plan.read_em(em)[0]
+
+    p0, W0, s0 = run(e, pvr.PVR_EM_INIT)
+    p1, W1, s1 = run(e, pvr.PVR_EM_INIT | pvr.PVR_EM_RESID_FRESH)
+    assert s1.m == pytest.approx(s0.m, rel=1e-12)
+    assert s1.sigma2 == pytest.approx(s0.sigma2, rel=1e-9)
+    assert np.allclose(p1, p0, rtol=1e-6, atol=1e-7)
+    assert np.array_equal(W1 > 0, W0 > 0)
+    e2 = e.clone()  # same values, not the buffer the simulate wrote
+    p2, W2, s2 = run(e2, pvr.PVR_EM_INIT | pvr.PVR_EM_RESID_FRESH)
+    assert np.array_equal(p2, p0) and np.array_equal(W2, W0) and s2.sigma2 == s0.sigma2
+
+
 def test_sr_update_matches_oracle(tiny):
     plan = tiny["plan"]
     rng = np.random.default_rng(2)
