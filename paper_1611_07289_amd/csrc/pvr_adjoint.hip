@@ -157,8 +157,8 @@ __global__ void __launch_bounds__(BP_THREADS)
 k_backproject(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patches,
               const typename GeoOf<T>::type *__restrict__ geo, const int *__restrict__ brick_prob,
               const int *__restrict__ sub_off, const int *__restrict__ sub_patch,
-              const typename Vec2Of<T>::type *__restrict__ rq, T *__restrict__ num,
-              T *__restrict__ den, int n_bricks) {
+              const typename Vec2Of<T>::type *__restrict__ rq, const T *__restrict__ patch_w,
+              T *__restrict__ num, T *__restrict__ den, int n_bricks) {
   using GEO = typename GeoOf<T>::type;
   using V2 = typename Vec2Of<T>::type;
   const int bi = xcd_work(blockIdx.x, BP_XCD_GRANULE);
@@ -178,6 +178,8 @@ k_backproject(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ pa
   const double fi = i, fj = jj, fk = kk;
   for (int q = q0; q < q1; ++q) {
     const int s = sub_patch[q];
+    // an excluded patch (weight 0) contributes exactly 0: its rq entries are 0
+    if (patch_w && patch_w[s] == (T)0) continue;
     const GEO &g = geo[s];
     const PatchDev pt = patches[s];
     const double pk = fma(g.G[8], fi, fma(g.G[9], fj, fma(g.G[10], fk, g.G[11])));
@@ -219,11 +221,11 @@ static pvr_status backproject_impl(const pvr_plan *p, const T *e, const T *pp, c
   if (den)
     hipLaunchKernelGGL((k_backproject<T, true>), grid, dim3(BP_THREADS), 0, stream,
                        p->d_prob, p->d_patch, (const typename GeoOf<T>::type *)geo, p->d_brick_prob,
-                       p->d_sub_off, p->d_sub_patch, rq, num, den, p->n_bricks);
+                       p->d_sub_off, p->d_sub_patch, rq, patch_w, num, den, p->n_bricks);
   else
     hipLaunchKernelGGL((k_backproject<T, false>), grid, dim3(BP_THREADS), 0, stream,
                        p->d_prob, p->d_patch, (const typename GeoOf<T>::type *)geo, p->d_brick_prob,
-                       p->d_sub_off, p->d_sub_patch, rq, num, den, p->n_bricks);
+                       p->d_sub_off, p->d_sub_patch, rq, patch_w, num, den, p->n_bricks);
   HIP_TRY(hipGetLastError());
   if (ev) HIP_TRY(hipEventRecord(ev[1], stream));
   return PVR_OK;
