@@ -152,7 +152,9 @@ __device__ __forceinline__ void adj_patch_rt(const GEO &g, const PatchDev &pt, d
 
 // One workgroup = one 8^3 brick; each wavefront owns one 4^3 sub-brick and
 // walks that sub-brick's patch list (wave-uniform), one voxel per lane.
-template <typename T, bool DEN>
+// HW: the candidate half-width every patch of the plan fits (1 or 2, fixed
+// at compile time), or 0 to read it per patch.
+template <typename T, bool DEN, int HW>
 __global__ void __launch_bounds__(BP_THREADS)
 k_backproject(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patches,
               const typename GeoOf<T>::type *__restrict__ geo, const int *__restrict__ brick_prob,
@@ -188,9 +190,9 @@ k_backproject(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ pa
     if (!(qk <= (T)g.K2)) continue;
     const double pu = fma(g.G[0], fi, fma(g.G[1], fj, fma(g.G[2], fk, g.G[3])));
     const double pv = fma(g.G[4], fi, fma(g.G[5], fj, fma(g.G[6], fk, g.G[7])));
-    if (g.hu == 1 && g.hv == 1)
+    if (HW == 1)
       adj_patch<T, GEO, V2, 1, 1, DEN>(g, pt, pu, pv, qk, rq, sn, sd);
-    else if (g.hu <= 2 && g.hv <= 2)
+    else if (HW == 2)
       adj_patch<T, GEO, V2, 2, 2, DEN>(g, pt, pu, pv, qk, rq, sn, sd);
     else
       adj_patch_rt<T, GEO, V2, DEN>(g, pt, pu, pv, qk, rq, sn, sd);
@@ -218,14 +220,22 @@ static pvr_status backproject_impl(const pvr_plan *p, const T *e, const T *pp, c
   const dim3 grid(xcd_blocks(p->n_bricks, BP_XCD_GRANULE));
   hipEvent_t *ev = timing_slot(p, PVR_KERNEL_BACKPROJECT);
   if (ev) HIP_TRY(hipEventRecord(ev[0], stream));
-  if (den)
-    hipLaunchKernelGGL((k_backproject<T, true>), grid, dim3(BP_THREADS), 0, stream,
-                       p->d_prob, p->d_patch, (const typename GeoOf<T>::type *)geo, p->d_brick_prob,
-                       p->d_sub_off, p->d_sub_patch, rq, patch_w, num, den, p->n_bricks);
-  else
-    hipLaunchKernelGGL((k_backproject<T, false>), grid, dim3(BP_THREADS), 0, stream,
-                       p->d_prob, p->d_patch, (const typename GeoOf<T>::type *)geo, p->d_brick_prob,
-                       p->d_sub_off, p->d_sub_patch, rq, patch_w, num, den, p->n_bricks);
+  const int hw = (p->max_hu <= 1 && p->max_hv <= 1) ? 1 : (p->max_hu <= 2 && p->max_hv <= 2) ? 2 : 0;
+  const auto *geot = (const typename GeoOf<T>::type *)geo;
+#define BP_LAUNCH(D, H)                                                                         \
+  hipLaunchKernelGGL((k_backproject<T, D, H>), grid, dim3(BP_THREADS), 0, stream, p->d_prob,    \
+                     p->d_patch, geot, p->d_brick_prob, p->d_sub_off, p->d_sub_patch, rq,        \
+                     patch_w, num, den, p->n_bricks)
+  if (den) {
+    if (hw == 1) BP_LAUNCH(true, 1);
+    else if (hw == 2) BP_LAUNCH(true, 2);
+    else BP_LAUNCH(true, 0);
+  } else {
+    if (hw == 1) BP_LAUNCH(false, 1);
+    else if (hw == 2) BP_LAUNCH(false, 2);
+    else BP_LAUNCH(false, 0);
+  }
+#undef BP_LAUNCH
   HIP_TRY(hipGetLastError());
   if (ev) HIP_TRY(hipEventRecord(ev[1], stream));
   return PVR_OK;

@@ -55,6 +55,14 @@ __host__ __device__ static inline void aff_inv(const double *a, double *o) {
   aff_join(Li, ti, o);
 }
 
+// Integer pixels within the in-plane support radius sqrt(K2) / c of a point
+// lie among rint(p) + [-h, h] with h = floor(R + 1/2); c = sqrt(kappa) *
+// spacing / sigma along the axis.  Depends on the stack only (not on the
+// motion), so the plan sizes the adjoint's candidate grid from it.
+__host__ __device__ static inline int cand_halfwidth(double K2, double c) {
+  return (int)floor(sqrt(K2) / c + 0.5);
+}
+
 // R = Rz(rz) Ry(ry) Rx(rx)
 __host__ __device__ static inline void rot_zyx(const double *th, double *R) {
   double cx = cos(th[0]), sx = sin(th[0]), cy = cos(th[1]), sy = sin(th[1]);
@@ -164,8 +172,8 @@ __device__ inline void make_geometry(const ProbDev &pr, const StackDev &st, cons
   g.inv_cu = 1.0 / g.cu; g.inv_cv = 1.0 / g.cv;
   // integer pixels within the in-plane support radius R of a point p are
   // among rint(p) + [-h, h] with h = floor(R + 1/2)
-  g.hu = (int)floor(sqrt(K2) / g.cu + 0.5);
-  g.hv = (int)floor(sqrt(K2) / g.cv + 0.5);
+  g.hu = cand_halfwidth(K2, g.cu);
+  g.hv = cand_halfwidth(K2, g.cv);
   gf.hu = g.hu; gf.hv = g.hv;
   gf.inv_cu = (float)g.inv_cu; gf.inv_cv = (float)g.inv_cv;
   for (int q = 0; q < 3; ++q) gf.perm[q] = g.perm[q];

@@ -420,6 +420,7 @@ struct pvr_plan {
   int device;
   int P, S, M;
   int max_problem_patches;
+  int max_hu, max_hv;         // adjoint candidate half-widths over all stacks
   long long N, V;
   int n_bricks;
   double k;

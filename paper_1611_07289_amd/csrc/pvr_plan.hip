@@ -300,6 +300,16 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
         if (fabs(dt) > 1e-9) return fail(PVR_ESHAPE, "pvr_plan_create: stack %d axes %d and %d are not orthogonal", s, a, c);
       }
   }
+  // the adjoint's candidate grid depends on the stacks only
+  p->max_hu = p->max_hv = 0;
+  {
+    const double sk = sqrt(KAPPA), K2 = KAPPA * cutoff_k * cutoff_k;
+    for (int s = 0; s < n_stacks; ++s) {
+      const StackDev &d = p->h_stack[s];
+      p->max_hu = std::max(p->max_hu, cand_halfwidth(K2, sk * d.spacing[0] / d.sigma[0]));
+      p->max_hv = std::max(p->max_hv, cand_halfwidth(K2, sk * d.spacing[1] / d.sigma[1]));
+    }
+  }
   // patches: grouped by problem in problem order, each inside its slice
   long long so = 0;
   int prev_prob = 0;
