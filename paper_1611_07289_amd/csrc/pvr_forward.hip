@@ -45,7 +45,11 @@ k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patch
       int b[3];
       T f[3];
       sample_centre(g, pr, u, v, pt.slice, b, f);
-      yh = psf_walk_fwd<T, typename GeoOf<T>::type>(g, pr, b, f, xr, nbytes) * iz;
+      // the patch's rows run along x or not for all its samples: one branch
+      // per chunk picks the matching walk
+      using G = typename GeoOf<T>::type;
+      yh = (g.perm[2] == 0 ? psf_walk_fwd<T, G, false, 1>(g, pr, b, f, xr, nbytes)
+                           : psf_walk_fwd<T, G, false, 2>(g, pr, b, f, xr, nbytes)) * iz;
     }
     if (y_sim) y_sim[j] = yh;
     if (resid) {
@@ -265,7 +269,8 @@ __device__ double reg_eval(RegShared &sh, const ProbDev &pr, const StackDev &st,
     float f[3];
     if (!sample_centre(g, pr, u, v, pt.slice, b, f)) continue;
     float z = 0.f;
-    const float a = psf_walk_fwd<float, GeoF, true>(g, pr, b, f, xr, nbytes, &z);
+    const float a = g.perm[2] == 0 ? psf_walk_fwd<float, GeoF, true, 1>(g, pr, b, f, xr, nbytes, &z)
+                                   : psf_walk_fwd<float, GeoF, true, 2>(g, pr, b, f, xr, nbytes, &z);
     if (!(z > 0.f)) continue;
     const double yh = (double)(a / z), yo = (double)y[j];
     acc6[0] += 1.0;

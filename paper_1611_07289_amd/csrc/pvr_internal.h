@@ -259,11 +259,13 @@ template <> __device__ __forceinline__ double load_vox<double>(__amdgpu_buffer_r
 // load fetches them: a lane then touches one cache line per group instead of
 // issuing four loads, which matters for stacks whose pixel rows run across
 // x, where the 64 lanes of a wave hit 64 different lines.
-template <typename T>
+// ROW: 1 = rows run along x (one float apart), 2 = they do not, 0 = decide
+// from step at run time.
+template <typename T, int ROW>
 __device__ __forceinline__ void load_group(__amdgpu_buffer_rsrc_t r, unsigned off, unsigned step,
                                            unsigned nbytes, T x[4]) {
-  if constexpr (sizeof(T) == 4) {
-    if (step == 4 && off + 16 <= nbytes) {
+  if constexpr (sizeof(T) == 4 && ROW != 2) {
+    if ((ROW == 1 || step == 4) && off + 16 <= nbytes) {
       typedef float f4 __attribute__((ext_vector_type(4)));
       const f4 v = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
       x[0] = v.x;
@@ -290,8 +292,9 @@ template <> __device__ __forceinline__ float clamp01<float>(float x) {
 template <> __device__ __forceinline__ double clamp01<double>(double x) { return fmax(x, 0.0); }
 
 // WITH_Z also sums the weights (the normaliser Z over in-volume voxels).
-// xr views the problem's volume (nbytes bytes).
-template <typename T, typename GEO, bool WITH_Z = false>
+// xr views the problem's volume (nbytes bytes).  ROW as for load_group (the
+// inner axis is x exactly when g.perm[2] == 0).
+template <typename T, typename GEO, bool WITH_Z = false, int ROW = 0>
 __device__ __forceinline__ T psf_walk_fwd(const GEO &g, const ProbDev &p, const int b[3],
                                           const T f[3], __amdgpu_buffer_rsrc_t xr,
                                           unsigned nbytes, T *z_out = nullptr) {
@@ -338,7 +341,7 @@ __device__ __forceinline__ T psf_walk_fwd(const GEO &g, const ProbDev &p, const 
       unsigned off = (unsigned)(vb + oa * st_a + ob * st_b + lo_c * st_c) * (unsigned)sizeof(T);
       for (int k0 = 0; k0 < n; k0 += 4) {
         T x[4];
-        load_group<T>(xr, off, step, nbytes, x);
+        load_group<T, ROW>(xr, off, step, nbytes, x);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const T Q = fma(Acc * d, d, q1);
