@@ -48,6 +48,7 @@ if ROOT not in sys.path:
 # disabled): 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz.
 FP32_VALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense
 # Algorithmic FP32 work of one PSF nonzero (one sample-voxel pair): offset
 # along the 3 stack axes (3), scaling by 1/sigma (3), squared norm (5), the
 # exponential (1), cut-off shift (1), and the accumulation (forward: weight sum
@@ -98,6 +99,10 @@ def make_workload(name: str):
         return [synth.tiny_problem()]
     if name == "batched":
         return synth.batched_problems()
+    if name == "diff48":
+        return [synth.diff_problem()]
+    if name == "learned":
+        return [synth.full_problem()]
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -188,6 +193,12 @@ def main():
     log(f"[bench] workload {args.workload}: generated in {time.time() - t0:.1f} s")
     if args.workload == "batched":
         batched_bench(args, probs, dev)
+        return
+    if args.workload == "diff48":
+        diff_bench(args, probs[0], dev)
+        return
+    if args.workload == "learned":
+        learned_bench(args, probs[0], dev)
         return
     plan = pvr.Plan.from_problems(probs)
     log(f"[bench] plan: N={plan.N} M={plan.M} V={plan.V} problems={plan.P}")
@@ -414,6 +425,111 @@ def batched_bench(args, probs, dev):
         "sequential_ms_per_step": seq_t * 1e3 / it,
         "speedup_vs_sequential": seq_t / el,
     }
+    print(json.dumps(out), flush=True)
+
+
+def diff_bench(args, P, dev):
+    """Differentiable simulation on the 48^3 case: one forward + backward of
+    the autograd function (y = A(theta) X, then d/dX and d/dtheta of a scalar
+    loss) per step, FP64 and FP32."""
+    import torch
+    from paper_1611_07289_amd import pvr
+    from paper_1611_07289_amd.autograd import simulate
+    plan = pvr.Plan.from_problems([P])
+    res = {}
+    for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        X = torch.tensor(P.x_true.reshape(-1), dtype=dt, device=dev, requires_grad=True)
+        th = torch.tensor(P.theta_true, dtype=dt, device=dev, requires_grad=True)
+        g = torch.randn(plan.N, dtype=dt, device=dev, generator=torch.Generator(device=dev).manual_seed(1))
+
+        def one():
+            X.grad = None
+            th.grad = None
+            (simulate(X, th, plan) * g).sum().backward()
+
+        for _ in range(args.warmup):
+            one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            one()
+        torch.cuda.synchronize()
+        res[name] = args.steps / (time.perf_counter() - t0)
+        log(f"[bench] diff48 {name}: {res[name]:.1f} gradient evaluations/s")
+    out = {"metric": "gradient evaluations/s (forward + d/dX + d/dtheta)", "value": res["f32"],
+           "unit": "evaluations/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 / res["f32"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "diff48", "patches": plan.M, "samples": plan.N,
+                      "voxels": plan.V, "parallelism": "single GPU"},
+           "f64_evaluations_per_s": res["f64"]}
+    print(json.dumps(out), flush=True)
+
+
+def learned_bench(args, P, dev):
+    """The learned initialiser's network on MFMA: inference over all 11 760
+    patches of the uterus workload and training steps (forward, backward,
+    Adam) at batch 256; TFLOP/s against the dense BF16 MFMA peak."""
+    import torch
+    from paper_1611_07289_amd import learned, pvr, synth
+    plan = pvr.Plan.from_problems([P])
+    X = torch.from_numpy(P.x_true.reshape(-1)).to(dev)
+    ref = torch.from_numpy(P.theta_true.astype(np.float32)).to(dev)
+    off = torch.from_numpy(synth.random_motion_batch(plan.M, 10.0, 5.0, 77).astype(np.float32)).to(dev)
+    y_obs, y_sim = learned.make_pairs(plan, X, ref, off, 0.01 * float(X.max()), 78)
+    net = learned.Net(seed=5)
+    flop_fwd = 2 * learned.macs_per_pair()
+    # inference, batches of 1024
+    B = 1024
+    ids = torch.arange(plan.M, dtype=torch.int32, device=dev)
+
+    def infer():
+        for b0 in range(0, plan.M, B):
+            n = min(B, plan.M - b0)
+            net.predict(plan, y_obs, y_sim, ids[b0:b0 + n].contiguous(), n)
+
+    infer()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infer()
+    torch.cuda.synchronize()
+    t_inf = (time.perf_counter() - t0) / args.steps
+    tf_inf = flop_fwd * plan.M / t_inf / 1e12
+    # training steps
+    Bt = 256
+    tgt = torch.zeros(Bt * 6, device=dev)
+    bf = net.buffers(Bt)
+    bf["ids"].copy_(ids[:Bt])
+    net.pack(plan, bf["ids"], y_obs, y_sim, Bt)
+
+    def train_step():
+        net.forward(Bt, tgt)
+        net.backward(Bt)
+        net.adam(1e-4)
+
+    train_step()
+    torch.cuda.synchronize()
+    n_tr = 20 * args.steps
+    t0 = time.perf_counter()
+    for _ in range(n_tr):
+        train_step()
+    torch.cuda.synchronize()
+    t_tr = (time.perf_counter() - t0) / n_tr
+    tf_tr = 3 * flop_fwd * Bt / t_tr / 1e12
+    log(f"[bench] learned: inference {plan.M / t_inf:.0f} pairs/s ({tf_inf:.1f} TFLOP/s), "
+        f"training {Bt / t_tr:.0f} pairs/s ({tf_tr:.1f} TFLOP/s)")
+    out = {"metric": "learned-initialiser inference pairs/s (BF16 MFMA)", "value": plan.M / t_inf,
+           "unit": "pairs/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+           "ms_per_step": t_inf * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "learned", "pairs_per_step": plan.M, "batch": B,
+                      "parallelism": "single GPU"},
+           "roofline": {"bound": "mfma", "achieved": tf_inf, "peak": BF16_MFMA_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": tf_inf / BF16_MFMA_PEAK_TFLOPS,
+                        "traffic": None},
+           "training": {"pairs_per_s": Bt / t_tr, "tflops": tf_tr,
+                        "frac": tf_tr / BF16_MFMA_PEAK_TFLOPS, "batch": Bt}}
     print(json.dumps(out), flush=True)
 
 

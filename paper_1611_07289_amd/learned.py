@@ -36,6 +36,15 @@ def _final_hw() -> int:
 
 
 HW = _final_hw()          # positions of the last feature map (8 x 8)
+
+
+def macs_per_pair() -> int:
+    """Multiply-accumulates of one forward pass (convolutions and head)."""
+    h, total = SIDE, 0
+    for cin, cout, s in LAYERS:
+        h = (h - 1) // s + 1
+        total += h * h * cout * 9 * cin
+    return total + HW * 64 * 6
 N_FC = HW * 64 * 6        # head weights [HW][64][6]
 
 
