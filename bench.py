@@ -243,7 +243,7 @@ def main():
     X = torch.zeros(plan.V, dtype=torch.float32, device=dev)
     Xn = torch.empty_like(X)
     plan.backproject(y, None, None, num, den)
-    plan.sr_update(X, num, den, Xn, pvr.SRParams.make(lam=0.0))
+    plan.sr_update(X, num, den, Xn, pvr.SRParams.make(lam=0.0, use_clamp=False))
     X, Xn = Xn, X
     prm = pvr.SRParams.make()
 

@@ -37,8 +37,29 @@ def initial_volume(plan, y, buf: Buffers):
     import torch
     X = torch.zeros(plan.V, dtype=torch.float32, device=y.device)
     plan.backproject(y, None, None, buf.num, buf.den)
-    plan.sr_update(X, buf.num, buf.den, buf.Xn, pvr.SRParams.make(lam=0.0))
+    # X_0 = A^T y / A^T 1 as it stands (no clamp at 0: noisy background can
+    # average below 0, and the update's clamp belongs to the SR iterations)
+    plan.sr_update(X, buf.num, buf.den, buf.Xn, pvr.SRParams.make(lam=0.0, use_clamp=False))
     return buf.Xn.clone()
+
+
+def uncertainty_maps(plan, p, pbar, buf: Buffers):
+    """Rigidity / uncertainty maps (paper Sec. II, "Patch Potentials"): the
+    sample posteriors p and the patch potentials p_bar integrated into the
+    volume with the reconstruction's PSF, each normalised by A^T 1:
+    map_p = A^T p / A^T 1 and map_pbar = A^T p_bar(s) / A^T 1 (zero where
+    A^T 1 <= 1e-6).  High values mark regions that fit the rigid patch
+    model.  Returns (map_p, map_pbar) as new tensors [V]."""
+    import torch
+    zero = torch.zeros(plan.V, dtype=torch.float32, device=p.device)
+    prm = pvr.SRParams.make(lam=0.0)
+    plan.backproject(p, None, None, buf.num, buf.den)  # A^T p and A^T 1
+    plan.sr_update(zero, buf.num, buf.den, buf.Xn, prm)
+    map_p = buf.Xn.clone()
+    ones = torch.ones(plan.N, dtype=torch.float32, device=p.device)
+    plan.backproject(ones, None, pbar, buf.num, None)  # A^T p_bar(s), den kept
+    plan.sr_update(zero, buf.num, buf.den, buf.Xn, prm)
+    return map_p, buf.Xn.clone()
 
 
 def sr_iterations(plan, X, y, buf: Buffers, n_sr: int, params: Optional[pvr.SRParams] = None,
@@ -61,21 +82,28 @@ def sr_iterations(plan, X, y, buf: Buffers, n_sr: int, params: Optional[pvr.SRPa
 def reconstruct(plan, y, theta0, cycles: int = 3, n_sr: int = 10,
                 reg_params: Optional[pvr.RegParams] = None,
                 sr_params: Optional[pvr.SRParams] = None, register: bool = True,
-                init_fn=None):
+                init_fn=None, active_schedule=None):
     """Full reconstruction; theta0 is [M, 6] float32 on the device and is
     updated in place.  ``init_fn(plan, X, y, theta)``, when given, runs before
-    each registration (a learned initialiser).  Returns (X, theta, history)."""
+    each registration (a learned initialiser).  ``active_schedule``, when
+    given, is a list of per-patch uint8 device masks used cycle by cycle (in
+    turn): multi-scale patches (paper Sec. II, eq. Y_i), where cycle c
+    registers and reconstructs from the patches of one scale only.
+    Returns (X, theta, history)."""
     import torch
     buf = Buffers(plan, y.device)
     theta = theta0
     timings = {"build": 0.0, "register": 0.0, "sr": 0.0, "init_fn": 0.0}
+
+    def active(c):
+        return None if not active_schedule else active_schedule[c % len(active_schedule)]
 
     def tick():
         torch.cuda.synchronize()
         return time.perf_counter()
 
     t = tick()
-    plan.build(theta)
+    plan.build(theta, active=active(0))
     X = initial_volume(plan, y, buf)
     t1 = tick(); timings["build"] += t1 - t
     hist = {"ncc": [], "excluded": []}
@@ -88,12 +116,14 @@ def reconstruct(plan, y, theta0, cycles: int = 3, n_sr: int = 10,
                 init_fn(plan, X, y, theta)
                 timings["init_fn"] += tick() - t
             t = tick()
-            plan.register(X, y, theta, buf.ncc, params=rp)
+            plan.register(X, y, theta, buf.ncc, reg=active(c), params=rp)
             t1 = tick(); timings["register"] += t1 - t
             hist["ncc"].append(float(buf.ncc.mean()))
             t = tick()
-            plan.build(theta)
+            plan.build(theta, active=active(c))
             timings["build"] += tick() - t
+        elif active_schedule:
+            plan.build(theta, active=active(c))
         t = tick()
         sr_iterations(plan, X, y, buf, n_sr, sr_params)
         timings["sr"] += tick() - t

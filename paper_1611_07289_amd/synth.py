@@ -429,6 +429,33 @@ def full_problem(seed_cfg: int = 2, n: int = 256, slices: int = 60,
     return Problem("uterus256", g, stacks, P, x, th, out, base, 0.01, 0.10)
 
 
+def concat_patches(parts: Sequence[Patches]) -> Patches:
+    return Patches(*[np.concatenate([getattr(p, k) for p in parts]).astype(np.int32)
+                     for k in ("stack", "slice", "x0", "y0", "w", "h")])
+
+
+def multiscale_problem(seed_cfg: int = 6, n: int = 96, slices: int = 24,
+                       sizes=(32, 64)):
+    """Multi-scale patches (paper Sec. II, eq. Y_i): the uterus phantom at n^3
+    with 4 stacks of n x n x slices (3 orthogonal + 1 oblique), and square
+    patches of every size a in `sizes` with stride a/2 on every slice, all in
+    one table; returns (problem, scale index per patch).  Each patch has its
+    own motion (<= 10 deg, <= 5 mm); 10 % outlier patches."""
+    base = 1000 * seed_cfg
+    g = iso_grid(n)
+    x = phantom_uterus(n, base + 0, base + 1)
+    c = grid_center(g)
+    stacks = [make_stack(c, *fr, n, n, slices, (1, 1), 4.0, (1.0, 1.0, 4.0))
+              for fr in orthogonal_frames([30.0])]
+    parts = [square_patches(stacks, a, max(1, a // 2)) for a in sizes]
+    P = concat_patches(parts)
+    scale = np.concatenate([np.full(p.M, i, np.int32) for i, p in enumerate(parts)])
+    th = random_motion(P.M, 10.0, 5.0, base + 2)
+    out = choose_outliers(P.M, 0.10, base + 4)
+    name = f"multiscale{n}_" + "_".join(str(a) for a in sizes)
+    return Problem(name, g, stacks, P, x, th, out, base, 0.01, 0.10), scale
+
+
 def diff_problem(seed_cfg: int = 4) -> Problem:
     """48^3 phantom; 3 orthogonal stacks of 48x48x12 (thickness 4);
     24x24 patches stride 12 (M = 324, N = 186 624)."""

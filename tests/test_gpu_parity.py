@@ -283,6 +283,11 @@ def test_initial_volume_matches_oracle(tiny):
     Xo = recon.initial_volume(ctx, y, th32).reshape(-1)
     rel = np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo)
     assert rel <= 1e-5
+    # the driver's X_0 (the division in the update kernel, no clamp at 0)
+    from paper_1611_07289_amd import driver
+    Xd = host(driver.initial_volume(plan, dev(y.astype(np.float32)), driver.Buffers(plan)))
+    assert np.any(Xo < 0), "the case should hold negative background averages"
+    assert np.linalg.norm(Xd - Xo) / np.linalg.norm(Xo) <= 1e-5
 
 
 def test_ncc_at_fixed_theta_matches_oracle(tiny):
