@@ -103,6 +103,8 @@ def make_workload(name: str):
         return [synth.diff_problem()]
     if name == "learned":
         return [synth.full_problem()]
+    if name == "multiscale":
+        return [synth.multiscale_problem(n=128, slices=32, sizes=(32, 64))]
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -199,6 +201,9 @@ def main():
         return
     if args.workload == "learned":
         learned_bench(args, probs[0], dev)
+        return
+    if args.workload == "multiscale":
+        multiscale_bench(args, *probs[0], dev)
         return
     plan = pvr.Plan.from_problems(probs)
     log(f"[bench] plan: N={plan.N} M={plan.M} V={plan.V} problems={plan.P}")
@@ -530,6 +535,43 @@ def learned_bench(args, P, dev):
                         "traffic": None},
            "training": {"pairs_per_s": Bt / t_tr, "tflops": tf_tr,
                         "frac": tf_tr / BF16_MFMA_PEAK_TFLOPS, "batch": Bt}}
+    print(json.dumps(out), flush=True)
+
+
+def multiscale_bench(args, P, scale, dev):
+    """Multi-scale patches: whole reconstructions (3 cycles x 10 SR
+    iterations from zero motion) with the 64-pixel patches only, and with the
+    scales alternating cycle by cycle (32, 64, 32), in one plan holding both."""
+    import torch
+    from paper_1611_07289_amd import driver, pvr, synth
+    plan = pvr.Plan.from_problems([P])
+    th = torch.from_numpy(P.theta_true.astype(np.float32)).to(dev)
+    Xt = torch.from_numpy(P.x_true.reshape(-1)).to(dev)
+    plan.build(th)
+    yc = torch.empty(plan.N, dtype=torch.float32, device=dev)
+    plan.simulate(Xt, y_sim=yc)
+    y = torch.from_numpy(synth.corrupt(yc.cpu().numpy(), P.patches, P.outlier_patch, 0.01,
+                                       P.seed_base + 3, P.seed_base + 5)).to(dev)
+    masks = [torch.from_numpy((scale == k).astype(np.uint8)).to(dev) for k in (0, 1)]
+    res = {}
+    for name, sched in (("single_64", [masks[1]]), ("alternating_32_64", [masks[0], masks[1]])):
+        th0 = torch.zeros(plan.M, 6, dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X, _, hist = driver.reconstruct(plan, y, th0, cycles=3, n_sr=10, active_schedule=sched)
+        torch.cuda.synchronize()
+        res[name] = {"seconds": time.perf_counter() - t0, "psnr_db": driver.psnr(X, Xt, plan),
+                     "timings": hist["timings"]}
+        log(f"[bench] multiscale {name}: {res[name]['seconds']:.2f} s, PSNR {res[name]['psnr_db']:.2f} dB")
+    out = {"metric": "full PVR seconds (multi-scale schedule vs single scale)",
+           "value": res["alternating_32_64"]["seconds"], "unit": "s", "n_gpus": 1, "steps": 1,
+           "warmup": 0, "ms_per_step": res["alternating_32_64"]["seconds"] * 1e3,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "multiscale", "voxels": plan.V, "patches": plan.M,
+                      "patches_32": int((scale == 0).sum()), "patches_64": int((scale == 1).sum()),
+                      "parallelism": "single GPU"},
+           "runs": res}
     print(json.dumps(out), flush=True)
 
 
