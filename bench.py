@@ -27,7 +27,8 @@ Extra objects on the JSON line:
                 cycles of [registration, 10 SR iterations] -- with plain
                 registration and with the learned initialiser (trained first
                 on --learned-pairs forward-model pairs of another phantom;
-                training time reported apart).
+                training time reported apart), each with the registration
+                gradient by central differences and exact ("_exact").
 """
 from __future__ import annotations
 
@@ -587,13 +588,22 @@ def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10, learned_pairs=0):
     from paper_1611_07289_amd import driver, learned, pvr, synth
     res = {}
     ymax = float(y.abs().max())
-    th0 = torch.zeros(plan.M, 6, dtype=torch.float32, device=dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    X, th, hist = driver.reconstruct(plan, y, th0, cycles=cycles, n_sr=n_sr)
-    torch.cuda.synchronize()
-    res["plain"] = {"seconds": time.perf_counter() - t0, "psnr_db": driver.psnr(X, Xtrue, plan),
+
+    def run(key, rp, init_fn=None):
+        th0 = torch.zeros(plan.M, 6, dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X, th, hist = driver.reconstruct(plan, y, th0, cycles=cycles, n_sr=n_sr, reg_params=rp,
+                                         init_fn=init_fn)
+        torch.cuda.synchronize()
+        res[key] = {"seconds": time.perf_counter() - t0, "psnr_db": driver.psnr(X, Xtrue, plan),
                     "timings": hist["timings"], "mean_ncc": hist["ncc"]}
+        log(f"full PVR {key}: {res[key]['seconds']:.3f} s, PSNR {res[key]['psnr_db']:.2f} dB")
+
+    # plain registration: central-difference gradient (12 NCC evaluations per
+    # gradient), then the exact gradient (one evaluation)
+    run("plain", pvr.RegParams.make(min_std=0.01 * ymax))
+    run("plain_exact", pvr.RegParams.make(min_std=0.01 * ymax, exact=True))
     if learned_pairs > 0:
         P = probs[0]
         Xtr = torch.from_numpy(synth.phantom_uterus(P.grid.nx, 7700, 7701).reshape(-1)).to(dev)
@@ -602,22 +612,16 @@ def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10, learned_pairs=0):
                            seed=7800, log=log)
         del Xtr
         init_fn = learned.init_fn_factory(net)
-        rp = pvr.RegParams.make(step0=0.5, min_std=0.01 * ymax, max_iter=20)
-        th0 = torch.zeros(plan.M, 6, dtype=torch.float32, device=dev)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        X2, th2, hist2 = driver.reconstruct(plan, y, th0, cycles=cycles, n_sr=n_sr,
-                                            reg_params=rp, init_fn=init_fn)
-        torch.cuda.synchronize()
-        res["learned"] = {"seconds": time.perf_counter() - t0,
-                          "psnr_db": driver.psnr(X2, Xtrue, plan),
-                          "timings": hist2["timings"], "mean_ncc": hist2["ncc"],
-                          "training": {"pairs": tr["pairs"], "seconds": tr["seconds"],
-                                       "data_seconds": tr["data_seconds"],
-                                       "loss_first_last": [tr["loss"][0][1], tr["loss"][-1][1]]
-                                       if tr["loss"] else None}}
-        res["delta_psnr_db"] = res["learned"]["psnr_db"] - res["plain"]["psnr_db"]
-        res["speedup"] = res["plain"]["seconds"] / res["learned"]["seconds"]
+        run("learned", pvr.RegParams.make(step0=0.5, min_std=0.01 * ymax, max_iter=20), init_fn)
+        run("learned_exact", pvr.RegParams.make(step0=0.5, min_std=0.01 * ymax, max_iter=20,
+                                                exact=True), init_fn)
+        res["training"] = {"pairs": tr["pairs"], "seconds": tr["seconds"],
+                           "data_seconds": tr["data_seconds"],
+                           "loss_first_last": [tr["loss"][0][1], tr["loss"][-1][1]]
+                           if tr["loss"] else None}
+        for sfx in ("", "_exact"):
+            res["delta_psnr_db" + sfx] = res["learned" + sfx]["psnr_db"] - res["plain" + sfx]["psnr_db"]
+            res["speedup" + sfx] = res["plain" + sfx]["seconds"] / res["learned" + sfx]["seconds"]
     res["cycles"] = cycles
     res["sr_iterations"] = n_sr
     res["paper_runtime_s"] = "2000-4000 (whole PVR, unspecified NVIDIA GPU machines; Sec. V)"

@@ -157,8 +157,15 @@ typedef struct {
   double fd_h;              /* central-difference step (0.05) */
   double min_std;           /* patches with std(y) below keep theta */
   int32_t max_iter;         /* trial steps (40) */
-  int32_t pad_;
+  int32_t gradient;         /* PVR_REG_GRAD_FD (0, default) or PVR_REG_GRAD_EXACT */
 } pvr_reg_params;
+
+/* Gradient of the registration optimiser: central differences of the NCC
+ * with step fd_h (12 NCC evaluations), or the exact derivative of the NCC
+ * through every PSF weight of the simulated patch (one evaluation that walks
+ * each sample's support twice; fd_h is then unused). */
+#define PVR_REG_GRAD_FD 0
+#define PVR_REG_GRAD_EXACT 1
 
 typedef struct pvr_plan pvr_plan;
 
@@ -289,7 +296,8 @@ pvr_status pvr_sr_update(const pvr_plan *plan, const float *X,
  * NCC(y_s, A_s(theta) X) over the six parameters, where the simulated patch
  * uses the full PSF forward model and NCC runs over samples valid at theta.
  * Optimiser: variables (rho * angles, translations) with rho the patch
- * half-diagonal in mm; central differences with step fd_h; a normalised
+ * half-diagonal in mm; gradient by central differences with step fd_h or
+ * exact (params->gradient, PVR_REG_GRAD_*); a normalised
  * step of length delta is accepted on strict improvement (delta doubles,
  * capped at step0) or delta halves; stop below step_min or after max_iter
  * trial steps.  Patches with std(y_s) < min_std keep theta.

@@ -64,7 +64,8 @@ def lib():
         L.ora_ncc.argtypes = [P, P, P, P, P, P]
         L.ora_register.argtypes = [P, P, P, P, P, P, ctypes.c_double,
                                    ctypes.c_double, ctypes.c_double,
-                                   ctypes.c_int, ctypes.c_double, P]
+                                   ctypes.c_int, ctypes.c_double, ctypes.c_int, P]
+        L.ora_ncc_grad.argtypes = [P, P, P, P, P, P, P]
         L.ora_ncc_patch.restype = ctypes.c_double
         L.ora_ncc_patch.argtypes = [P, ctypes.c_int, P, P, P, P]
         L.ora_num_threads.restype = ctypes.c_int
@@ -195,13 +196,28 @@ class Ctx:
         lib().ora_ncc(self._h, _p(X), _p(y), _p(th), _p(_u8(mask)), _p(out))
         return out
 
+    def ncc_grad(self, X, y, theta, mask=None):
+        """Per-patch NCC and its exact gradient with respect to the six
+        motion parameters: (ncc (M,), grad (M, 6))."""
+        X = _f64(X).reshape(-1); y = _f64(y).reshape(-1)
+        th = _f64(theta).reshape(-1)
+        out = np.zeros(self.M)
+        g = np.zeros(6 * self.M)
+        lib().ora_ncc_grad(self._h, _p(X), _p(y), _p(th), _p(_u8(mask)), _p(out), _p(g))
+        return out, g.reshape(-1, 6)
+
     def register(self, X, y, theta, mask=None, reg=None, step0=1.0,
-                 step_min=0.01, fd_h=0.05, max_iter=40, min_std=0.0):
-        """Returns (theta_out (M, 6), ncc (M,)); theta is not modified."""
+                 step_min=0.01, fd_h=0.05, max_iter=40, min_std=0.0,
+                 gradient: str = "fd"):
+        """Returns (theta_out (M, 6), ncc (M,)); theta is not modified.
+        gradient: "fd" (central differences with step fd_h) or "analytic"."""
+        if gradient not in ("fd", "analytic"):
+            raise ValueError(f"gradient must be 'fd' or 'analytic', not {gradient!r}")
         X = _f64(X).reshape(-1); y = _f64(y).reshape(-1)
         th = _f64(theta).reshape(-1).copy()
         out = np.zeros(self.M)
         lib().ora_register(self._h, _p(X), _p(y), _p(th), _p(_u8(mask)),
                            _p(_u8(reg)), float(step0), float(step_min),
-                           float(fd_h), int(max_iter), float(min_std), _p(out))
+                           float(fd_h), int(max_iter), float(min_std),
+                           1 if gradient == "analytic" else 0, _p(out))
         return th.reshape(-1, 6), out

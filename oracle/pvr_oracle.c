@@ -62,6 +62,7 @@ typedef struct {
   double t[3];          /* translation */
   double A[9];          /* stack pix2world linear part */
   double o[3];          /* stack pix2world origin */
+  double E[9];          /* [e1 e2 n]: unit stack axes as columns */
   double F[9];          /* R * [e1 e2 n] : columns are the moved PSF axes */
   double sig[3];        /* PSF standard deviations (mm) */
   double ext[3];        /* support half-extent along voxel axes (voxels) */
@@ -174,7 +175,7 @@ static void patch_geometry(const ora_ctx *C, int s, const double *th,
   ora_rotation(th, g->R);
   for (int a = 0; a < 3; ++a) g->t[a] = th[3 + a];
   /* unit stack axes e_a = column a of A / |column a| */
-  double E[9];
+  double *E = g->E;
   for (int a = 0; a < 3; ++a) {
     double n = sqrt(g->A[a] * g->A[a] + g->A[3 + a] * g->A[3 + a] +
                     g->A[6 + a] * g->A[6 + a]);
@@ -548,6 +549,158 @@ void ora_ncc(const ora_ctx *C, const double *X, const double *y,
   for (int s = 0; s < C->M; ++s) ncc[s] = patch_ncc(C, s, theta + 6 * s, X, y, mask);
 }
 
+/* Partial derivatives of R = Rz Ry Rx with respect to rx, ry, rz, each the
+ * product with the one elementary factor replaced by its derivative. */
+static void rotation_derivatives(const double *th, double dR[3][9]) {
+  double cx = cos(th[0]), sx = sin(th[0]);
+  double cy = cos(th[1]), sy = sin(th[1]);
+  double cz = cos(th[2]), sz = sin(th[2]);
+  double Rx[9] = {1, 0, 0, 0, cx, -sx, 0, sx, cx};
+  double Ry[9] = {cy, 0, sy, 0, 1, 0, -sy, 0, cy};
+  double Rz[9] = {cz, -sz, 0, sz, cz, 0, 0, 0, 1};
+  double dRx[9] = {0, 0, 0, 0, -sx, -cx, 0, cx, -sx};
+  double dRy[9] = {-sy, 0, cy, 0, 0, 0, -cy, 0, -sy};
+  double dRz[9] = {-sz, -cz, 0, cz, -sz, 0, 0, 0, 0};
+  const double *f[3][3] = {{Rz, Ry, dRx}, {Rz, dRy, Rx}, {dRz, Ry, Rx}};
+  for (int k = 0; k < 3; ++k) {
+    double T[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double s = 0;
+        for (int m = 0; m < 3; ++m) s += f[k][1][3 * i + m] * f[k][2][3 * m + j];
+        T[3 * i + j] = s;
+      }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double s = 0;
+        for (int m = 0; m < 3; ++m) s += f[k][0][3 * i + m] * T[3 * m + j];
+        dR[k][3 * i + j] = s;
+      }
+  }
+}
+
+/* Cross-correlation of patch s at th (as patch_ncc) and its exact gradient
+ * with respect to th (the six raw parameters), by the chain rule through
+ * every simulated sample:
+ *   d NCC / d b_q = (a_q - mean a) / sqrt(va vb) - NCC (b_q - mean b) / vb
+ * (va, vb: sums of squared deviations), b_q = A_q / Z_q with
+ * A_q = sum_i g_i X_i and Z_q = sum_i g_i over the sample's support, and
+ *   d g_i / d th = -1/2 exp(-Q_i / 2) dQ_i / d th,
+ *   Q = sum_a (d_a / sigma_a)^2,  d_a = F_a . (v_i - x),
+ *   d d_a / d r_k = (dR_k E)_a . (v_i - x) - F_a . (dR_k (P - c)),
+ *   d d_a / d t_m = -F[m][a].
+ * The support and the set of valid samples are held fixed (their changes
+ * have measure zero in th).  grad is zero where NCC is defined as zero. */
+static double patch_ncc_grad(const ora_ctx *C, int s, const double *th,
+                             const double *X, const double *y,
+                             const uint8_t *mask, double grad[6]) {
+  pgeo g;
+  patch_geometry(C, s, th, &g);
+  double dR[3][9], dF[3][9];
+  rotation_derivatives(th, dR);
+  for (int k = 0; k < 3; ++k)
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double acc = 0;
+        for (int m = 0; m < 3; ++m) acc += dR[k][3 * i + m] * g.E[3 * m + j];
+        dF[k][3 * i + j] = acc;
+      }
+  int64_t n = (int64_t)g.w * g.h, cnt = 0;
+  double *a = (double *)malloc(sizeof(double) * n);
+  double *b = (double *)malloc(sizeof(double) * n);
+  double *db = (double *)malloc(sizeof(double) * 6 * n);
+  const int nx = C->dims[0], ny = C->dims[1];
+  for (int64_t l = 0; l < n; ++l) {
+    int64_t j = C->off[s] + l;
+    if (mask && !mask[j]) continue;
+    int u = g.x0 + (int)(l % g.w), v = g.y0 + (int)(l / g.w);
+    double yh, Z;
+    if (!sim_sample(C, &g, X, u, v, &yh, &Z)) continue;
+    /* the sample centre and its derivatives */
+    double P[3], d[3], x[3], dx[6][3];
+    for (int r = 0; r < 3; ++r)
+      P[r] = g.A[3 * r] * u + g.A[3 * r + 1] * v + g.A[3 * r + 2] * g.slice + g.o[r];
+    for (int r = 0; r < 3; ++r) d[r] = P[r] - g.c[r];
+    for (int r = 0; r < 3; ++r)
+      x[r] = g.R[3 * r] * d[0] + g.R[3 * r + 1] * d[1] + g.R[3 * r + 2] * d[2] +
+             g.c[r] + g.t[r];
+    for (int k = 0; k < 3; ++k)
+      for (int r = 0; r < 3; ++r)
+        dx[k][r] = dR[k][3 * r] * d[0] + dR[k][3 * r + 1] * d[1] + dR[k][3 * r + 2] * d[2];
+    for (int m = 0; m < 3; ++m)
+      for (int r = 0; r < 3; ++r) dx[3 + m][r] = r == m ? 1.0 : 0.0;
+    int lo[3], hi[3];
+    support_box(C, &g, x, lo, hi);
+    double A = 0, Zs = 0, dA[6] = {0}, dZ[6] = {0};
+    for (int kk = lo[2]; kk <= hi[2]; ++kk)
+      for (int jj = lo[1]; jj <= hi[1]; ++jj)
+        for (int ii = lo[0]; ii <= hi[0]; ++ii) {
+          double w = psf_hat(C, &g, x, ii, jj, kk);
+          if (w < 0) continue;
+          double ip[3] = {(double)ii, (double)jj, (double)kk}, vw[3], dv[3];
+          apply_affine(C->v2w, ip, vw);
+          for (int r = 0; r < 3; ++r) dv[r] = vw[r] - x[r];
+          double pr[3], Q = 0;
+          for (int q = 0; q < 3; ++q) {
+            pr[q] = g.F[q] * dv[0] + g.F[3 + q] * dv[1] + g.F[6 + q] * dv[2];
+            Q += (pr[q] / g.sig[q]) * (pr[q] / g.sig[q]);
+          }
+          const double e = exp(-0.5 * Q);
+          const double Xi = X[((int64_t)kk * ny + jj) * nx + ii];
+          A += w * Xi;
+          Zs += w;
+          for (int p = 0; p < 6; ++p) {
+            double dQ = 0;
+            for (int q = 0; q < 3; ++q) {
+              double dp = -(g.F[q] * dx[p][0] + g.F[3 + q] * dx[p][1] + g.F[6 + q] * dx[p][2]);
+              if (p < 3)
+                dp += dF[p][q] * dv[0] + dF[p][3 + q] * dv[1] + dF[p][6 + q] * dv[2];
+              dQ += 2.0 * pr[q] * dp / (g.sig[q] * g.sig[q]);
+            }
+            const double dg = -0.5 * e * dQ;
+            dA[p] += dg * Xi;
+            dZ[p] += dg;
+          }
+        }
+    a[cnt] = y[j];
+    b[cnt] = A / Zs;
+    for (int p = 0; p < 6; ++p) db[6 * cnt + p] = (dA[p] * Zs - A * dZ[p]) / (Zs * Zs);
+    ++cnt;
+  }
+  double res = 0;
+  for (int p = 0; p < 6; ++p) grad[p] = 0;
+  if (cnt > 0) {
+    double ma = 0, mb = 0;
+    for (int64_t q = 0; q < cnt; ++q) { ma += a[q]; mb += b[q]; }
+    ma /= cnt; mb /= cnt;
+    double va = 0, vb = 0, cab = 0;
+    for (int64_t q = 0; q < cnt; ++q) {
+      va += (a[q] - ma) * (a[q] - ma);
+      vb += (b[q] - mb) * (b[q] - mb);
+      cab += (a[q] - ma) * (b[q] - mb);
+    }
+    if (va > 0 && vb > 0) {
+      res = cab / sqrt(va * vb);
+      for (int64_t q = 0; q < cnt; ++q) {
+        const double dn = (a[q] - ma) / sqrt(va * vb) - res * (b[q] - mb) / vb;
+        for (int p = 0; p < 6; ++p) grad[p] += dn * db[6 * q + p];
+      }
+    }
+  }
+  free(a);
+  free(b);
+  free(db);
+  return res;
+}
+
+void ora_ncc_grad(const ora_ctx *C, const double *X, const double *y,
+                  const double *theta, const uint8_t *mask, double *ncc,
+                  double *grad) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int s = 0; s < C->M; ++s)
+    ncc[s] = patch_ncc_grad(C, s, theta + 6 * s, X, y, mask, grad + 6 * s);
+}
+
 /* Per-patch rigid registration by gradient ascent on NCC.  The paper names
  * "patch-wise gradient descent" (Sec. III, level I) and CC as the cost
  * (Sec. II); the optimiser is a reading.  Variables are q = (rho * angles,
@@ -557,13 +710,15 @@ void ora_ncc(const ora_ctx *C, const double *X, const double *y,
  * with step fd_h; a normalised trial step of length delta is accepted only on
  * strict improvement (then delta doubles, capped at step0, and the gradient is
  * recomputed), otherwise delta is halved; stop when delta < step_min, the
- * gradient vanishes, or after max_iter trial steps.  Patches whose observed
+ * gradient vanishes, or after max_iter trial steps.  With grad_mode = 1 the
+ * gradient is the exact one of patch_ncc_grad instead of the central
+ * differences (d/dq_a = d/dth_a / scale_a).  Patches whose observed
  * standard deviation is below min_std keep their parameters.  Only patches
  * with reg[s] != 0 are registered (all when reg == NULL). */
 void ora_register(const ora_ctx *C, const double *X, const double *y,
                   double *theta, const uint8_t *mask, const uint8_t *reg,
                   double step0, double step_min, double fd_h, int max_iter,
-                  double min_std, double *ncc_out) {
+                  double min_std, int grad_mode, double *ncc_out) {
 #pragma omp parallel for schedule(dynamic, 1)
   for (int s = 0; s < C->M; ++s) {
     double *th = theta + 6 * s;
@@ -605,7 +760,13 @@ void ora_register(const ora_ctx *C, const double *X, const double *y,
     int have_grad = 0, moved = 0;
     for (int it = 0; it < max_iter; ++it) {
       if (delta < step_min) break;
-      if (!have_grad) {
+      if (!have_grad && grad_mode == 1) {
+        for (int b = 0; b < 6; ++b) tt[b] = q[b] / sc[b];
+        double gth[6];
+        patch_ncc_grad(C, s, tt, X, y, mask, gth);
+        for (int a = 0; a < 6; ++a) grad[a] = gth[a] / sc[a];
+        have_grad = 1;
+      } else if (!have_grad) {
         for (int a = 0; a < 6; ++a) {
           for (int b = 0; b < 6; ++b) tt[b] = q[b] / sc[b];
           tt[a] = (q[a] + fd_h) / sc[a];

@@ -9,6 +9,7 @@
 #include <math.h>
 
 #include "pvr_geometry.h"
+#include "pvr_grad.h"
 #include "pvr_internal.h"
 #include "pvr_util.h"
 
@@ -213,12 +214,13 @@ extern "C" pvr_status pvr_simulate_f64(const pvr_plan *p, const double *X, const
 // ---------------------------------------------------------------------------
 constexpr int REG_THREADS = 256;
 
-// Sum of 6 doubles over the workgroup (fixed order: wave butterflies, then
+// Sum of N doubles over the workgroup (fixed order: wave butterflies, then
 // the 4 wave results in order).
-__device__ __forceinline__ void block_sum6(double v[6], double (*lds)[REG_THREADS / 64]) {
+template <int N>
+__device__ __forceinline__ void block_sum(double v[N], double (*lds)[REG_THREADS / 64]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int q = 0; q < 6; ++q) {
+  for (int q = 0; q < N; ++q) {
     double x = v[q];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
@@ -226,7 +228,7 @@ __device__ __forceinline__ void block_sum6(double v[6], double (*lds)[REG_THREAD
   }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < 6; ++q) {
+  for (int q = 0; q < N; ++q) {
     double x = 0;
 #pragma unroll
     for (int w = 0; w < REG_THREADS / 64; ++w) x += lds[q][w];
@@ -235,9 +237,24 @@ __device__ __forceinline__ void block_sum6(double v[6], double (*lds)[REG_THREAD
   __syncthreads();
 }
 
+// Copy of a workgroup-uniform struct held in LDS into scalar registers: every
+// 32-bit word passes through readfirstlane, so the walks read the constants
+// from SGPRs instead of holding a VGPR copy per lane.
+template <typename S>
+__device__ __forceinline__ S wave_uniform(const S &src) {
+  static_assert(sizeof(S) % 4 == 0, "uniform copy works on 32-bit words");
+  S dst;
+  const uint32_t *a = reinterpret_cast<const uint32_t *>(&src);
+  uint32_t *d = reinterpret_cast<uint32_t *>(&dst);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(S) / 4); ++i) d[i] = __builtin_amdgcn_readfirstlane(a[i]);
+  return dst;
+}
+
 struct RegShared {
   GeoF g;
-  double red[6][REG_THREADS / 64];
+  GradConst gc;     // exact-gradient constants of the evaluated transform
+  double red[24][REG_THREADS / 64];
   // optimiser state (uniform across the workgroup; kept out of registers)
   double th[6];     // transform evaluated next
   double q[6];      // current point, scaled variables
@@ -258,7 +275,7 @@ __device__ double reg_eval(RegShared &sh, const ProbDev &pr, const StackDev &st,
     make_geometry(pr, st, pt, sh.th, k, gd, sh.g, bb);
   }
   __syncthreads();
-  const GeoF &g = sh.g;
+  const GeoF g = wave_uniform(sh.g);
   double acc6[6] = {0, 0, 0, 0, 0, 0};
   const int n = pt.w * pt.h;
   for (int l = threadIdx.x; l < n; l += REG_THREADS) {
@@ -280,7 +297,7 @@ __device__ double reg_eval(RegShared &sh, const ProbDev &pr, const StackDev &st,
     acc6[4] += yh * yh;
     acc6[5] += yo * yh;
   }
-  block_sum6(acc6, sh.red);
+  block_sum<6>(acc6, sh.red);
   const double cnt = acc6[0];
   if (!(cnt > 0)) return 0.0;
   const double my = acc6[1] / cnt, mh = acc6[3] / cnt;
@@ -290,8 +307,96 @@ __device__ double reg_eval(RegShared &sh, const ProbDev &pr, const StackDev &st,
   return cv / sqrt(vy * vh);
 }
 
+// NCC of the patch at sh.th and its exact gradient with respect to the six
+// parameters of sh.th.  Per valid sample the forward walk gives y_hat = A / Z,
+// a second walk gives d y_hat / d theta = sum_i (X_i - y_hat) dg_i / Z
+// (pvr_grad.h); with n valid samples, S_a = sum (y - mean y)^2 and
+// S_b = sum (y_hat - mean y_hat)^2,
+//   d NCC / d theta = sum_j [(y_j - mean y) / sqrt(S_a S_b)
+//                            - NCC (y_hat_j - mean y_hat) / S_b] d y_hat_j,
+// which needs only the per-patch sums of d y_hat, y d y_hat and
+// y_hat d y_hat beside the six NCC sums.  Every lane returns the same values.
+__device__ double reg_eval_exact(RegShared &sh, const ProbDev &pr, const StackDev &st,
+                                 const PatchDev &pt, double k, __amdgpu_buffer_rsrc_t xr,
+                                 unsigned nbytes, const float *__restrict__ Xp,
+                                 const float *__restrict__ y, const uint8_t *__restrict__ mask,
+                                 double gth[6]) {
+  if (threadIdx.x == 0) {
+    GeoD gd;
+    int bb[6];
+    make_geometry(pr, st, pt, sh.th, k, gd, sh.g, bb);
+    make_grad_const(pr, st, pt, sh.th, sh.gc);
+  }
+  __syncthreads();
+  const GeoF g = wave_uniform(sh.g);
+  const GradConst gc = wave_uniform(sh.gc);
+  double acc[24];
+#pragma unroll
+  for (int q = 0; q < 24; ++q) acc[q] = 0.0;
+  const int n = pt.w * pt.h;
+  for (int l = threadIdx.x; l < n; l += REG_THREADS) {
+    const long long j = pt.off + l;
+    if (mask && !mask[j]) continue;
+    const int u = pt.x0 + l % pt.w, v = pt.y0 + l / pt.w;
+    int b[3];
+    float f[3];
+    if (!sample_centre(g, pr, u, v, pt.slice, b, f)) continue;
+    float z = 0.f;
+    const float a = g.perm[2] == 0 ? psf_walk_fwd<float, GeoF, true, 1>(g, pr, b, f, xr, nbytes, &z)
+                                   : psf_walk_fwd<float, GeoF, true, 2>(g, pr, b, f, xr, nbytes, &z);
+    if (!(z > 0.f)) continue;
+    const float yhf = a / z;
+    // q = x_world - (c + t) of the unmoved sample centre's world position
+    double xv[3], q[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      xv[r] = fma(g.H[4 * r], (double)u,
+                  fma(g.H[4 * r + 1], (double)v, fma(g.H[4 * r + 2], (double)pt.slice, g.H[4 * r + 3])));
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      q[r] = gc.Vl[3 * r] * xv[0] + gc.Vl[3 * r + 1] * xv[1] + gc.Vl[3 * r + 2] * xv[2] +
+             gc.v2w_o[r] - gc.ct[r];
+    const float qt[3] = {(float)q[0], (float)q[1], (float)q[2]};
+    float a6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    grad_walk<float>(g, pr, gc, b, f, qt, Xp, yhf, a6);
+    const float iz = 1.f / z;
+    const double yh = (double)yhf, yo = (double)y[j];
+    acc[0] += 1.0;
+    acc[1] += yo;
+    acc[2] += yo * yo;
+    acc[3] += yh;
+    acc[4] += yh * yh;
+    acc[5] += yo * yh;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const double d = (double)(a6[c] * iz);
+      acc[6 + c] += d;
+      acc[12 + c] += yo * d;
+      acc[18 + c] += yh * d;
+    }
+  }
+  block_sum<24>(acc, sh.red);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) gth[c] = 0.0;
+  const double cnt = acc[0];
+  if (!(cnt > 0)) return 0.0;
+  const double my = acc[1] / cnt, mh = acc[3] / cnt;
+  const double vy = acc[2] / cnt - my * my, vh = acc[4] / cnt - mh * mh;
+  const double cv = acc[5] / cnt - my * mh;
+  if (!(vy > 1e-12 * my * my) || !(vh > 1e-12 * mh * mh) || !(vy > 0) || !(vh > 0)) return 0.0;
+  const double ncc = cv / sqrt(vy * vh);
+  const double sab = cnt * sqrt(vy * vh), sb = cnt * vh;
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+    gth[c] = (acc[12 + c] - my * acc[6 + c]) / sab - ncc * (acc[18 + c] - mh * acc[6 + c]) / sb;
+  return ncc;
+}
+
 // One workgroup per patch; the optimiser's control flow is uniform (every
-// lane sees the same reduced NCC values), its state lives in LDS.
+// lane sees the same reduced NCC values), its state lives in LDS.  EXACT
+// selects the exact gradient (one reg_eval_exact) over central differences
+// (twelve reg_eval).
+template <bool EXACT>
 __global__ void __launch_bounds__(REG_THREADS)
 k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stacks,
            const PatchDev *__restrict__ patches, const float *__restrict__ X,
@@ -316,7 +421,7 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
     sy[1] += yo;
     sy[2] += yo * yo;
   }
-  block_sum6(sy, sh.red);
+  block_sum<6>(sy, sh.red);
   double sd = 0;
   if (sy[0] > 0) {
     const double m = sy[1] / sy[0];
@@ -340,7 +445,16 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
     bool have_grad = false, moved = false;
     for (int it = 0; it < prm.max_iter; ++it) {
       if (delta < prm.step_min) break;
-      if (!have_grad) {
+      if (!have_grad && EXACT) {
+        __syncthreads();
+        if (threadIdx.x == 0)
+          for (int b = 0; b < 6; ++b) sh.th[b] = sh.q[b] / sh.sc[b];
+        double gth[6];
+        reg_eval_exact(sh, pr, st, pt, k, xr, nbytes, X + pr.vol_off, y, mask, gth);
+        if (threadIdx.x == 0)
+          for (int a = 0; a < 6; ++a) sh.grad[a] = gth[a] / sh.sc[a];
+        have_grad = true;
+      } else if (!have_grad) {
         for (int a = 0; a < 6; ++a) {
           double fp, fm;
           __syncthreads();
@@ -393,8 +507,14 @@ extern "C" pvr_status pvr_register_patches(const pvr_plan *p, const float *X, co
   if (!p->built) return fail(PVR_EINVAL, "pvr_register_patches: plan has not been built");
   if (prm->max_iter < 0 || !(prm->step0 > 0) || !(prm->step_min > 0) || !(prm->fd_h > 0))
     return fail(PVR_EINVAL, "pvr_register_patches: invalid optimiser parameters");
-  hipLaunchKernelGGL(k_register, dim3(p->M), dim3(REG_THREADS), 0, stream, p->d_prob, p->d_stack,
-                     p->d_patch, X, y_obs, p->d_mask, theta, ncc, reg, *prm, p->k);
+  if (prm->gradient != PVR_REG_GRAD_FD && prm->gradient != PVR_REG_GRAD_EXACT)
+    return fail(PVR_EINVAL, "pvr_register_patches: gradient must be PVR_REG_GRAD_FD or PVR_REG_GRAD_EXACT");
+  if (prm->gradient == PVR_REG_GRAD_EXACT)
+    hipLaunchKernelGGL(k_register<true>, dim3(p->M), dim3(REG_THREADS), 0, stream, p->d_prob,
+                       p->d_stack, p->d_patch, X, y_obs, p->d_mask, theta, ncc, reg, *prm, p->k);
+  else
+    hipLaunchKernelGGL(k_register<false>, dim3(p->M), dim3(REG_THREADS), 0, stream, p->d_prob,
+                       p->d_stack, p->d_patch, X, y_obs, p->d_mask, theta, ncc, reg, *prm, p->k);
   HIP_TRY(hipGetLastError());
   return PVR_OK;
   PVR_API_END();

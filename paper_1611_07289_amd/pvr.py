@@ -21,6 +21,8 @@ PVR_KERNEL_BACKPROJECT = 1
 PVR_EM_INIT = 1
 PVR_EM_FIX_W = 2
 PVR_EM_RESID_FRESH = 4
+PVR_REG_GRAD_FD = 0
+PVR_REG_GRAD_EXACT = 1
 
 _STATUS = {0: "PVR_OK", 1: "PVR_EINVAL", 2: "PVR_ESHAPE", 3: "PVR_ENOMEM",
            4: "PVR_EHIP", 5: "PVR_ENUMERIC", 6: "PVR_EUNSUPPORTED"}
@@ -76,11 +78,13 @@ class SRParams(ctypes.Structure):
 class RegParams(ctypes.Structure):
     _fields_ = [("step0", ctypes.c_double), ("step_min", ctypes.c_double),
                 ("fd_h", ctypes.c_double), ("min_std", ctypes.c_double),
-                ("max_iter", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("max_iter", ctypes.c_int32), ("gradient", ctypes.c_int32)]
 
     @staticmethod
-    def make(step0=1.0, step_min=0.01, fd_h=0.05, min_std=0.0, max_iter=40):
-        return RegParams(step0, step_min, fd_h, min_std, max_iter, 0)
+    def make(step0=1.0, step_min=0.01, fd_h=0.05, min_std=0.0, max_iter=40, exact=False):
+        """exact: the exact NCC gradient instead of central differences."""
+        return RegParams(step0, step_min, fd_h, min_std, max_iter,
+                         PVR_REG_GRAD_EXACT if exact else PVR_REG_GRAD_FD)
 
 
 EXPORTS = ["pvr_last_error", "pvr_version", "pvr_plan_create", "pvr_plan_destroy",

@@ -304,7 +304,7 @@ def test_ncc_at_fixed_theta_matches_oracle(tiny):
     assert err.max() <= 1e-5
 
 
-def test_registration_outcome_matches_oracle():
+def _textured_registration_case():
     from scipy.ndimage import gaussian_filter
     P = synth.tiny_problem()
     X = gaussian_filter(np.random.default_rng(5).uniform(0, 1000, (32, 32, 32)), 1.5)
@@ -312,14 +312,20 @@ def test_registration_outcome_matches_oracle():
     ctx = oracle.Ctx(P.grid, P.stacks, P.patches)
     th_true = P.theta_true.astype(np.float32).astype(np.float64)
     y, _, _ = ctx.simulate(X, th_true)
-    y = y.astype(np.float32)
+    return P, ctx, X, y.astype(np.float32), th_true
+
+
+@pytest.mark.parametrize("gradient", ["fd", "exact"])
+def test_registration_outcome_matches_oracle(gradient):
+    P, ctx, X, y, th_true = _textured_registration_case()
     th0 = (P.theta_true + synth.random_motion(P.M, 3.0, 1.0, 99)).astype(np.float32)
-    tho, nco = ctx.register(X, y, th0.astype(np.float64))
+    tho, nco = ctx.register(X, y, th0.astype(np.float64),
+                            gradient="analytic" if gradient == "exact" else "fd")
     plan = pvr.Plan.from_problems([P])
     plan.build(dev(th0))
     tt = dev(th0)
     ncc = torch.empty(plan.M, dtype=torch.float32, device="cuda")
-    plan.register(dev(X), dev(y), tt, ncc)
+    plan.register(dev(X), dev(y), tt, ncc, params=pvr.RegParams.make(exact=gradient == "exact"))
     thg = host(tt).astype(np.float64)
     ncg = host(ncc)
     n0 = ctx.ncc(X, y, th0.astype(np.float64))
@@ -329,14 +335,42 @@ def test_registration_outcome_matches_oracle():
     drot_o = np.degrees(np.abs(tho[:, :3] - th_true[:, :3])).max(1)
     dtr_g = np.abs(thg[:, 3:] - th_true[:, 3:]).max(1)
     dtr_o = np.abs(tho[:, 3:] - th_true[:, 3:]).max(1)
-    print(f"[gpu] reg median rot err gpu {np.median(drot_g):.3f} ora {np.median(drot_o):.3f}; "
+    print(f"[gpu] reg ({gradient}) median rot err gpu {np.median(drot_g):.3f} ora {np.median(drot_o):.3f}; "
           f"trans gpu {np.median(dtr_g):.4f} ora {np.median(dtr_o):.4f}; "
           f"ncc>0.999 gpu {np.mean(ncg > 0.999):.3f} ora {np.mean(nco > 0.999):.3f}")
     assert np.median(drot_g) <= max(0.35, 1.25 * np.median(drot_o))
     assert np.median(dtr_g) <= max(0.03, 1.25 * np.median(dtr_o))
     assert np.mean(ncg > 0.999) >= np.mean(nco > 0.999) - 0.05
     same = (np.abs(thg - tho)[:, :3].max(1) < math.radians(0.25)) & (np.abs(thg - tho)[:, 3:].max(1) < 0.1)
-    print(f"[gpu] reg agreement with oracle (0.25 deg, 0.1 mm): {same.mean():.3f}")
+    print(f"[gpu] reg ({gradient}) agreement with oracle (0.25 deg, 0.1 mm): {same.mean():.3f}")
+
+
+def test_exact_registration_gradient_matches_oracle():
+    """One short trial step along the normalised exact gradient: where it is
+    accepted, the step reveals the kernel's gradient direction, which must be
+    the oracle's (FP64 chain rule, pinned by finite differences)."""
+    from paper_1611_07289_amd import driver
+    P, ctx, X, y, th_true = _textured_registration_case()
+    th0 = (P.theta_true + synth.random_motion(P.M, 3.0, 1.0, 17)).astype(np.float32)
+    plan = pvr.Plan.from_problems([P])
+    plan.build(dev(th0))
+    delta = 0.02
+    tt = dev(th0)
+    plan.register(dev(X), dev(y), tt, None,
+                  params=pvr.RegParams.make(step0=delta, step_min=1e-3, max_iter=1, exact=True))
+    th1 = host(tt).astype(np.float64)
+    sc = np.repeat(driver.patch_radius(plan)[:, None], 6, 1)
+    sc[:, 3:] = 1.0
+    dq = (th1 - th0.astype(np.float64)) * sc / delta
+    moved = np.abs(dq).max(1) > 0
+    _, g = ctx.ncc_grad(X, y, th0.astype(np.float64))
+    gq = g / sc
+    d_ora = gq / np.linalg.norm(gq, axis=1, keepdims=True)
+    err = np.abs(dq - d_ora).max(1)[moved]
+    print(f"[gpu] exact gradient direction: {moved.sum()} of {P.M} patches stepped; "
+          f"worst component error {err.max():.2e}, median {np.median(err):.2e}")
+    assert moved.mean() > 0.8
+    assert np.median(err) < 2e-4 and err.max() < 5e-3
 
 
 def test_f64_path_matches_oracle(tiny):

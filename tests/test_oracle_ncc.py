@@ -4,7 +4,10 @@ The similarity is the cross-correlation of paper Sec. IV-A (eq. CC), also used
 as the 2D-3D registration cost (Sec. II); registration is per-patch gradient
 ascent (Sec. III, level I).  Pinned by: numpy's corrcoef on the valid samples,
 NCC(y, y) = 1, invariance to a y + b, the truth being a fixed point, the
-monotone objective, and recovery of known motion on a textured phantom.
+monotone objective, and recovery of known motion on a textured phantom.  The
+exact NCC gradient (chain rule through every PSF weight) is pinned by central
+differences of the NCC itself with a step small enough that the support and
+the valid set rarely change within it.
 """
 import math
 
@@ -75,3 +78,41 @@ def test_flat_patches_keep_parameters():
     th0 = P.theta_true + 0.01
     th, _ = ctx.register(X, y, th0, min_std=1.0)
     assert np.array_equal(th, th0)
+
+
+def test_exact_ncc_gradient_matches_central_differences(tex):
+    P, ctx, X, y, val = tex
+    th = P.theta_true + synth.random_motion(P.M, 3.0, 1.0, 7)
+    ncc, g = ctx.ncc_grad(X, y, th)
+    assert np.array_equal(ncc, ctx.ncc(X, y, th))
+    h = 1e-6
+    fd = np.zeros_like(g)
+    for a in range(6):
+        tp, tm = th.copy(), th.copy()
+        tp[:, a] += h
+        tm[:, a] -= h
+        fd[:, a] = (ctx.ncc(X, y, tp) - ctx.ncc(X, y, tm)) / (2 * h)
+    rel = np.abs(fd - g).max(1) / np.maximum(np.abs(g).max(1), 1e-12)
+    # a patch whose support or valid set changes within +-h has a kink there;
+    # every other patch agrees to the FD truncation and rounding error
+    assert np.median(rel) < 1e-7
+    assert np.quantile(rel, 0.9) < 1e-6
+    assert np.mean(np.abs(g).max(1) > 1e-4) > 0.9  # the offsets give a real slope
+
+
+def test_register_with_exact_gradient_recovers_known_motion(tex):
+    P, ctx, X, y, val = tex
+    th0 = P.theta_true + synth.random_motion(P.M, 3.0, 1.0, 99)
+    n0 = ctx.ncc(X, y, th0)
+    th, ncc = ctx.register(X, y, th0, gradient="analytic")
+    assert np.all(ncc >= n0 - 1e-15)
+    assert np.allclose(ncc, ctx.ncc(X, y, th), atol=1e-14)
+    drot = np.degrees(np.abs(th[:, :3] - P.theta_true[:, :3])).max(1)
+    dtr = np.abs(th[:, 3:] - P.theta_true[:, 3:]).max(1)
+    assert np.median(dtr) < 0.03
+    assert np.median(drot) < 0.35
+    assert np.mean(ncc > 0.999) > 0.8
+    th_t, _ = ctx.register(X, y, P.theta_true, gradient="analytic")
+    assert np.allclose(th_t, P.theta_true, atol=1e-6)
+    with pytest.raises(ValueError):
+        ctx.register(X, y, th0, gradient="newton")
