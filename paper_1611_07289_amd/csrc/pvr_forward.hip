@@ -254,6 +254,7 @@ __device__ __forceinline__ S wave_uniform(const S &src) {
 struct RegShared {
   GeoF g;
   GradConst gc;     // exact-gradient constants of the evaluated transform
+  GradMom gm;
   double red[24][REG_THREADS / 64];
   // optimiser state (uniform across the workgroup; kept out of registers)
   double th[6];     // transform evaluated next
@@ -308,28 +309,27 @@ __device__ double reg_eval(RegShared &sh, const ProbDev &pr, const StackDev &st,
 }
 
 // NCC of the patch at sh.th and its exact gradient with respect to the six
-// parameters of sh.th.  Per valid sample the forward walk gives y_hat = A / Z,
-// a second walk gives d y_hat / d theta = sum_i (X_i - y_hat) dg_i / Z
-// (pvr_grad.h); with n valid samples, S_a = sum (y - mean y)^2 and
-// S_b = sum (y_hat - mean y_hat)^2,
+// parameters of sh.th.  One walk per valid sample gives y_hat and, through
+// the moments of pvr_grad.h, d y_hat / d theta = sum_i (X_i - y_hat) dg_i / Z;
+// with n valid samples, S_a = sum (y - mean y)^2 and S_b = sum (y_hat -
+// mean y_hat)^2,
 //   d NCC / d theta = sum_j [(y_j - mean y) / sqrt(S_a S_b)
 //                            - NCC (y_hat_j - mean y_hat) / S_b] d y_hat_j,
 // which needs only the per-patch sums of d y_hat, y d y_hat and
 // y_hat d y_hat beside the six NCC sums.  Every lane returns the same values.
 __device__ double reg_eval_exact(RegShared &sh, const ProbDev &pr, const StackDev &st,
                                  const PatchDev &pt, double k, __amdgpu_buffer_rsrc_t xr,
-                                 unsigned nbytes, const float *__restrict__ Xp,
-                                 const float *__restrict__ y, const uint8_t *__restrict__ mask,
-                                 double gth[6]) {
+                                 unsigned nbytes, const float *__restrict__ y,
+                                 const uint8_t *__restrict__ mask, double gth[6]) {
   if (threadIdx.x == 0) {
     GeoD gd;
     int bb[6];
     make_geometry(pr, st, pt, sh.th, k, gd, sh.g, bb);
     make_grad_const(pr, st, pt, sh.th, sh.gc);
+    make_grad_mom(sh.gc, gd.perm, sh.gm);
   }
   __syncthreads();
   const GeoF g = wave_uniform(sh.g);
-  const GradConst gc = wave_uniform(sh.gc);
   double acc[24];
 #pragma unroll
   for (int q = 0; q < 24; ++q) acc[q] = 0.0;
@@ -341,25 +341,31 @@ __device__ double reg_eval_exact(RegShared &sh, const ProbDev &pr, const StackDe
     int b[3];
     float f[3];
     if (!sample_centre(g, pr, u, v, pt.slice, b, f)) continue;
-    float z = 0.f;
-    const float a = g.perm[2] == 0 ? psf_walk_fwd<float, GeoF, true, 1>(g, pr, b, f, xr, nbytes, &z)
-                                   : psf_walk_fwd<float, GeoF, true, 2>(g, pr, b, f, xr, nbytes, &z);
+    float xb, a, z, mx[9], me[9];
+    if (g.perm[2] == 0)
+      psf_walk_grad<1>(g, pr, b, f, xr, nbytes, xb, a, z, mx, me);
+    else
+      psf_walk_grad<2>(g, pr, b, f, xr, nbytes, xb, a, z, mx, me);
     if (!(z > 0.f)) continue;
-    const float yhf = a / z;
-    // q = x_world - (c + t) of the unmoved sample centre's world position
-    double xv[3], q[3];
+    const float iz = 1.f / z;
+    const float dl = a * iz;  // y_hat - X_b
+    const float yhf = xb + dl;
+    float m[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) m[c] = fma(-dl, me[c], mx[c]);
+    // q = x_j - (c + t)
+    double xv[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
       xv[r] = fma(g.H[4 * r], (double)u,
                   fma(g.H[4 * r + 1], (double)v, fma(g.H[4 * r + 2], (double)pt.slice, g.H[4 * r + 3])));
+    float qt[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
-      q[r] = gc.Vl[3 * r] * xv[0] + gc.Vl[3 * r + 1] * xv[1] + gc.Vl[3 * r + 2] * xv[2] +
-             gc.v2w_o[r] - gc.ct[r];
-    const float qt[3] = {(float)q[0], (float)q[1], (float)q[2]};
-    float a6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    grad_walk<float>(g, pr, gc, b, f, qt, Xp, yhf, a6);
-    const float iz = 1.f / z;
+      qt[r] = (float)(sh.gc.Vl[3 * r] * xv[0] + sh.gc.Vl[3 * r + 1] * xv[1] +
+                      sh.gc.Vl[3 * r + 2] * xv[2] + sh.gc.v2w_o[r] - sh.gc.ct[r]);
+    float a6[6];
+    grad_from_moments(sh.gm, m, qt, a6);
     const double yh = (double)yhf, yo = (double)y[j];
     acc[0] += 1.0;
     acc[1] += yo;
@@ -406,8 +412,8 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
   __shared__ RegShared sh;
   const int s = blockIdx.x;
   const PatchDev pt = patches[s];
-  const StackDev st = stacks[pt.stack];
   const ProbDev pr = probs[pt.problem];
+  const StackDev st = stacks[pt.stack];
   const unsigned nbytes = (unsigned)(pr.nx * pr.ny * pr.nz) * (unsigned)sizeof(float);
   const __amdgpu_buffer_rsrc_t xr = raw_buffer(X + pr.vol_off, nbytes);
   // observed standard deviation over unmasked samples
@@ -450,7 +456,7 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
         if (threadIdx.x == 0)
           for (int b = 0; b < 6; ++b) sh.th[b] = sh.q[b] / sh.sc[b];
         double gth[6];
-        reg_eval_exact(sh, pr, st, pt, k, xr, nbytes, X + pr.vol_off, y, mask, gth);
+        reg_eval_exact(sh, pr, st, pt, k, xr, nbytes, y, mask, gth);
         if (threadIdx.x == 0)
           for (int a = 0; a < 6; ++a) sh.grad[a] = gth[a] / sh.sc[a];
         have_grad = true;

@@ -136,4 +136,162 @@ __device__ __forceinline__ void grad_walk(const GEO &g, const ProbDev &p, const 
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Moment form of the derivative sums, for one sample x_j.  With voxel offsets
+// u = (w_a, w_b, w_c) from the sample centre along the walk's permuted voxel
+// axes and V the world step per unit of each (so D = V u), the derivative
+// weights w_i = e^{-Q_i/2} (X_i - y_hat) over the support enter only through
+//   n = sum_i w_i u_i  and  S = sum_i w_i u_i u_i^T:
+//   sum_i w_i z_i          = M V n = P n                    (translations),
+//   sum_i w_i z_i x y_i    = c + (P n) x q,  c_r = eps_rst (P S V^T)_st,
+// with q = x_j - (c_s + t), since z x y = (M D) x D + (M D) x q.  The walk
+// therefore accumulates nine moments per weight set instead of evaluating
+// the derivative at every voxel.
+struct GradMom {
+  float V[9];   // V[3 r + a]: world component r of the step along walk axis a
+  float P[9];   // M V
+  float om[9];  // rotation axes omega_k as rows
+};
+
+__device__ inline void make_grad_mom(const GradConst &gc, const int perm[3], GradMom &gm) {
+  for (int r = 0; r < 3; ++r)
+    for (int a = 0; a < 3; ++a) gm.V[3 * r + a] = (float)gc.Vl[3 * r + perm[a]];
+  for (int r = 0; r < 3; ++r)
+    for (int a = 0; a < 3; ++a) {
+      double s = 0;
+      for (int m = 0; m < 3; ++m) s += gc.M[3 * r + m] * gc.Vl[3 * m + perm[a]];
+      gm.P[3 * r + a] = (float)s;
+    }
+  for (int q = 0; q < 9; ++q) gm.om[q] = (float)gc.om[q];
+}
+
+// One walk over the support of a sample (as psf_walk_fwd, FP32): the PSF sums
+// relative to the centre voxel's value X_b (A' = sum g_hat (X - X_b),
+// Z = sum g_hat, so y_hat = X_b + A'/Z) and the nine offset moments of
+// e^{-Q/2} (X - X_b) and of e^{-Q/2} (first moments a, b, c, then the second
+// moments aa, ab, ac, bb, bc, cc).  The moments of the weights w_i follow as
+// mx - (y_hat - X_b) me; the reference X_b keeps that difference accurate.
+template <int ROW>
+__device__ __forceinline__ void psf_walk_grad(const GeoF &g, const ProbDev &p, const int b[3],
+                                              const float f[3], __amdgpu_buffer_rsrc_t xr,
+                                              unsigned nbytes, float &xb_out, float &a_out,
+                                              float &z_out, float mx[9], float me[9]) {
+  const int sy = p.nx, sz = p.nx * p.ny;
+  const int ia = g.perm[0], ib = g.perm[1], ic = g.perm[2];
+  const int st_a = sel3(ia, 1, sy, sz), st_b = sel3(ib, 1, sy, sz), st_c = sel3(ic, 1, sy, sz);
+  const int b_a = sel3(ia, b[0], b[1], b[2]), b_b = sel3(ib, b[0], b[1], b[2]),
+            b_c = sel3(ic, b[0], b[1], b[2]);
+  const int n_a = sel3(ia, p.nx, p.ny, p.nz), n_b = sel3(ib, p.nx, p.ny, p.nz),
+            n_c = sel3(ic, p.nx, p.ny, p.nz);
+  const float f_a = sel3f<float>(ia, f[0], f[1], f[2]), f_b = sel3f<float>(ib, f[0], f[1], f[2]),
+              f_c = sel3f<float>(ic, f[0], f[1], f[2]);
+  const float K2 = g.K2, cut = g.cut, Acc = g.Acc, Aca = g.Aca, Acb = g.Acb, Saa = g.Saa,
+              Sab = g.Sab, Sbb = g.Sbb, iAaa = g.iAinv_aa, ha = g.ha, iAcc = g.inv_Acc,
+              iSbb = g.inv_Sbb, nSab = g.nSab_Sbb;
+  const int lo_a = max((int)ceil(f_a - ha), -b_a);
+  const int hi_a = min((int)floor(f_a + ha), n_a - 1 - b_a);
+  const int cl_b = -b_b, ch_b = n_b - 1 - b_b, cl_c = -b_c, ch_c = n_c - 1 - b_c;
+  const int vb = (b[2] * p.ny + b[1]) * p.nx + b[0];
+  const unsigned step = (unsigned)st_c * 4u;
+  const float xb = load_vox<float>(xr, (unsigned)vb * 4u);
+  float acc = 0.f, z = 0.f;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) { mx[q] = 0.f; me[q] = 0.f; }
+  for (int oa = lo_a; oa <= hi_a; ++oa) {
+    const float wa = (float)oa - f_a;
+    const float rem = K2 - wa * wa * iAaa;
+    if (rem < 0.f) continue;
+    const float wbc = nSab * wa;
+    const float rb = fast_sqrt<float>(rem * iSbb);
+    const int lo_b = max((int)ceil(f_b + wbc - rb), cl_b);
+    const int hi_b = min((int)floor(f_b + wbc + rb), ch_b);
+    const float qa = Saa * wa * wa;
+    const float sa2 = 2.f * Sab * wa;
+    for (int ob = lo_b; ob <= hi_b; ++ob) {
+      const float wb = (float)ob - f_b;
+      const float q1 = qa + wb * (sa2 + Sbb * wb);
+      const float rem2 = K2 - q1;
+      if (rem2 < 0.f) continue;
+      const float wcc = -(Aca * wa + Acb * wb) * iAcc;
+      const float rc = fast_sqrt<float>(rem2 * iAcc);
+      const int lo_c = max((int)ceil(f_c + wcc - rc), cl_c);
+      const int hi_c = min((int)floor(f_c + wcc + rc), ch_c);
+      const int n = hi_c - lo_c + 1;
+      float d = ((float)lo_c - f_c) - wcc;
+      float wc = (float)lo_c - f_c;
+      unsigned off = (unsigned)(vb + oa * st_a + ob * st_b + lo_c * st_c) * 4u;
+      float r0x = 0.f, r1x = 0.f, r2x = 0.f, r0e = 0.f, r1e = 0.f, r2e = 0.f;
+      for (int k0 = 0; k0 < n; k0 += 4) {
+        float x[4];
+        load_group<float, ROW>(xr, off, step, nbytes, x);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const float Q = fma(Acc * d, d, q1);
+          const float e2 = fast_exp2<float>(-Q);
+          const float gh = k0 + k < n ? clamp01<float>(e2 - cut) : 0.f;
+          const float em = gh > 0.f ? e2 : 0.f;
+          const float xd = x[k] - xb;
+          acc = fma(gh, xd, acc);
+          z += gh;
+          const float ex = em * xd;
+          const float tx = ex * wc, te = em * wc;
+          r0x += ex;
+          r1x += tx;
+          r2x = fma(tx, wc, r2x);
+          r0e += em;
+          r1e += te;
+          r2e = fma(te, wc, r2e);
+          d += 1.f;
+          wc += 1.f;
+        }
+        off += 4 * step;
+      }
+      const float wab = wa * wb, waa = wa * wa, wbb = wb * wb;
+      mx[0] = fma(wa, r0x, mx[0]);  me[0] = fma(wa, r0e, me[0]);
+      mx[1] = fma(wb, r0x, mx[1]);  me[1] = fma(wb, r0e, me[1]);
+      mx[2] += r1x;                 me[2] += r1e;
+      mx[3] = fma(waa, r0x, mx[3]); me[3] = fma(waa, r0e, me[3]);
+      mx[4] = fma(wab, r0x, mx[4]); me[4] = fma(wab, r0e, me[4]);
+      mx[5] = fma(wa, r1x, mx[5]);  me[5] = fma(wa, r1e, me[5]);
+      mx[6] = fma(wbb, r0x, mx[6]); me[6] = fma(wbb, r0e, me[6]);
+      mx[7] = fma(wb, r1x, mx[7]);  me[7] = fma(wb, r1e, me[7]);
+      mx[8] += r2x;                 me[8] += r2e;
+    }
+  }
+  xb_out = xb;
+  a_out = acc;
+  z_out = z;
+}
+
+// The six derivative sums sum_i w_i d g_hat_i / d theta (rotations, then
+// translations) from the nine moments m of the weights w_i (see GradMom).
+__device__ __forceinline__ void grad_from_moments(const GradMom &gm, const float m[9],
+                                                  const float q[3], float a6[6]) {
+  // t = P n
+  float t[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) t[r] = gm.P[3 * r] * m[0] + gm.P[3 * r + 1] * m[1] + gm.P[3 * r + 2] * m[2];
+  const float S[9] = {m[3], m[4], m[5], m[4], m[6], m[7], m[5], m[7], m[8]};
+  // T = S V^T: T[u][c] = sum_v S[u][v] V[c][v]
+  float T[9];
+#pragma unroll
+  for (int u = 0; u < 3; ++u)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      T[3 * u + c] = S[3 * u] * gm.V[3 * c] + S[3 * u + 1] * gm.V[3 * c + 1] + S[3 * u + 2] * gm.V[3 * c + 2];
+  // C = P T; only its antisymmetric part enters
+  auto C = [&](int r, int c) {
+    return gm.P[3 * r] * T[c] + gm.P[3 * r + 1] * T[3 + c] + gm.P[3 * r + 2] * T[6 + c];
+  };
+  const float c0 = C(1, 2) - C(2, 1) + (t[1] * q[2] - t[2] * q[1]);
+  const float c1 = C(2, 0) - C(0, 2) + (t[2] * q[0] - t[0] * q[2]);
+  const float c2 = C(0, 1) - C(1, 0) + (t[0] * q[1] - t[1] * q[0]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) a6[k] = -(gm.om[3 * k] * c0 + gm.om[3 * k + 1] * c1 + gm.om[3 * k + 2] * c2);
+  a6[3] = t[0];
+  a6[4] = t[1];
+  a6[5] = t[2];
+}
+
 }  // namespace pvr

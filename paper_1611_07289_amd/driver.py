@@ -151,20 +151,21 @@ def psnr(X, X_true, plan, dilate_vox: int = 5) -> float:
     return float(np.mean(vals))
 
 
+def patch_table(plan) -> np.ndarray:
+    """The plan's patch descriptors as an int32 array [M][6] (stack, slice,
+    x0, y0, w, h; stack indices global over the plan's problems)."""
+    return np.frombuffer(plan._p, dtype=np.int32).reshape(-1, 6)
+
+
 def patch_radius(plan):
     """Half-diagonal (mm) of every patch: the scale of the rotation variables
     of the registration optimisers (a unit step moves the farthest pixel by
     about 1 mm)."""
-    import ctypes
-    sp = []
-    for s in plan._s:
-        L = np.asarray(list(s.pix2world), float).reshape(3, 4)[:, :3]
-        sp.append(np.linalg.norm(L, axis=0))
-    rho = np.empty(plan.M)
-    for i in range(plan.M):
-        q = plan._p[i]
-        su, sv = sp[q.stack][0], sp[q.stack][1]
-        rho[i] = 0.5 * np.hypot((q.w - 1) * su, (q.h - 1) * sv)
+    sp = np.array([np.linalg.norm(np.asarray(list(s.pix2world), float).reshape(3, 4)[:, :3], axis=0)
+                   for s in plan._s])
+    tab = patch_table(plan)
+    su, sv = sp[tab[:, 0], 0], sp[tab[:, 0], 1]
+    rho = 0.5 * np.hypot((tab[:, 4] - 1) * su, (tab[:, 5] - 1) * sv)
     return np.maximum(rho, 1.0)
 
 

@@ -190,20 +190,18 @@ def target_maps(plan):
     same target on every stack orientation, which the network can learn;
     rho turns rotations into the displacement (mm) of the farthest pixel.
     Returns (A, A^-1) as float32 arrays [M][6][6]."""
-    from .driver import patch_radius
+    from .driver import patch_radius, patch_table
     rho = patch_radius(plan)
-    frames = []
-    for st in plan._s:
-        L = np.asarray(list(st.pix2world), float).reshape(3, 4)[:, :3]
-        frames.append(L / np.linalg.norm(L, axis=0))
+    frames = np.array([np.asarray(list(st.pix2world), float).reshape(3, 4)[:, :3] for st in plan._s])
+    frames /= np.linalg.norm(frames, axis=1, keepdims=True)
+    F = frames[patch_table(plan)[:, 0]]                     # [M][3][3]
+    Ft = np.swapaxes(F, 1, 2)
     A = np.zeros((plan.M, 6, 6))
     Ai = np.zeros((plan.M, 6, 6))
-    for i in range(plan.M):
-        F = frames[plan._p[i].stack]
-        A[i, :3, :3] = rho[i] * F.T
-        A[i, 3:, 3:] = F.T
-        Ai[i, :3, :3] = F / rho[i]
-        Ai[i, 3:, 3:] = F
+    A[:, :3, :3] = rho[:, None, None] * Ft
+    A[:, 3:, 3:] = Ft
+    Ai[:, :3, :3] = F / rho[:, None, None]
+    Ai[:, 3:, 3:] = F
     return A.astype(np.float32), Ai.astype(np.float32)
 
 
@@ -286,9 +284,15 @@ def init_fn_factory(net: Net, batch: int = 1024):
     proposed motion has the higher NCC (the registration refines it next)."""
     import torch
 
+    maps = {}
+
     def init_fn(plan, X, y, theta):
         dev = X.device
-        Ai = torch.from_numpy(target_maps(plan)[1]).to(dev)
+        key = (id(plan), str(dev))
+        if key not in maps:
+            maps.clear()
+            maps[key] = torch.from_numpy(target_maps(plan)[1]).to(dev)
+        Ai = maps[key]
         ysim = torch.empty(plan.N, dtype=torch.float32, device=dev)
         plan.build(theta)
         plan.simulate(X, y_sim=ysim)

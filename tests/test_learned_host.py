@@ -4,7 +4,7 @@ import types
 
 import numpy as np
 
-from paper_1611_07289_amd import learned, synth
+from paper_1611_07289_amd import learned, pvr, synth
 
 
 def _fake_plan():
@@ -14,8 +14,8 @@ def _fake_plan():
     P = synth.square_patches(stacks, 16, 8)
     S = [types.SimpleNamespace(pix2world=np.asarray(st.pix2world, float).reshape(-1)[:12])
          for st in stacks]
-    Q = [types.SimpleNamespace(stack=int(P.stack[i]), w=int(P.w[i]), h=int(P.h[i]))
-         for i in range(P.M)]
+    tab = np.ascontiguousarray(np.asarray(P.table(), dtype=np.int32))
+    Q = (pvr.Patch * P.M).from_buffer_copy(tab.tobytes())
     return types.SimpleNamespace(_s=S, _p=Q, M=P.M), stacks, P
 
 
