@@ -221,8 +221,19 @@ __device__ __forceinline__ double inlier_resp(double v, const Mix &m) {
 struct MixF {
   float mu0, mu1, h0, h1, c0, c1;
 };
-__device__ __forceinline__ MixF to_f32(const Mix &m) {
-  return MixF{(float)m.mu0, (float)m.mu1, (float)m.h0, (float)m.h1, (float)m.c0, (float)m.c1};
+// The constants of make_mix in single precision from the FP64 parameters
+// (single-precision logarithms: the constants only enter inlier_resp_f).
+__device__ __forceinline__ MixF make_mix_f(double mu0, double sd0, double mu1, double sd1,
+                                          double w1) {
+  const float s0 = (float)sd0, s1 = (float)sd1, wf = (float)w1;
+  MixF m;
+  m.mu0 = (float)mu0;
+  m.mu1 = (float)mu1;
+  m.h0 = 0.5f / (s0 * s0);
+  m.h1 = 0.5f / (s1 * s1);
+  m.c1 = w1 > 0 ? __logf(wf) - __logf(s1) : -INFINITY;
+  m.c0 = w1 < 1 ? __logf(1.f - wf) - __logf(s0) : -INFINITY;
+  return m;
 }
 __device__ __forceinline__ float inlier_resp_f(float v, const MixF &m) {
   const float d0 = v - m.mu0, d1 = v - m.mu1;
@@ -300,15 +311,32 @@ k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
         if ((bits & mask_hi) == pref) atomicAdd(&hist[(bits >> shift) & 255u], 1u);
       }
       __syncthreads();
-      if (t == 0) {
-        unsigned r = sel_rank, acc = 0;
-        int b = 0;
-        for (; b < 256; ++b) {
-          if (acc + hist[b] > r) break;
-          acc += hist[b];
+      // the bin holding rank r: wave 0 scans the 256 counts (4 per lane)
+      if (t < 64) {
+        const unsigned r = sel_rank;
+        const unsigned h0 = hist[4 * t], h1 = hist[4 * t + 1], h2 = hist[4 * t + 2],
+                       h3 = hist[4 * t + 3];
+        const unsigned tot = h0 + h1 + h2 + h3;
+        unsigned incl = tot;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const unsigned v = __shfl_up(incl, o, 64);
+          if (t >= o) incl += v;
         }
-        sel_prefix = pref | ((unsigned)b << shift);
-        sel_rank = r - acc;
+        const unsigned long long hit = __ballot(incl > r);
+        if (hit != 0ull && t == __ffsll((long long)hit) - 1) {
+          unsigned acc = incl - tot;
+          int b = 4 * t;
+          if (acc + h0 <= r) {
+            acc += h0; ++b;
+            if (acc + h1 <= r) {
+              acc += h1; ++b;
+              if (acc + h2 <= r) { acc += h2; ++b; }
+            }
+          }
+          sel_prefix = pref | ((unsigned)b << shift);
+          sel_rank = r - acc;
+        }
       }
       __syncthreads();
     }
@@ -334,7 +362,7 @@ k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
       mixp[2] = m1;
       mixp[3] = fmax(sqrt(fmax((q_all - q0) / n_hi - m1 * m1, 0.0)), 1e-3);
       mixp[4] = 0.9;
-      mixf = to_f32(make_mix(mixp[0], mixp[1], mixp[2], mixp[3], mixp[4]));
+      mixf = make_mix_f(mixp[0], mixp[1], mixp[2], mixp[3], mixp[4]);
       mix_stop = 0;
     }
     __syncthreads();
@@ -364,7 +392,7 @@ k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
           mixp[3] = fmax(sqrt(fmax(r1q / r1s - m1 * m1, 0.0)), 1e-3);
           mixp[1] = fmax(sqrt(fmax((q_all - r1q) / r0s - m0 * m0, 0.0)), 1e-3);
           mixp[4] = r1s / nu;
-          mixf = to_f32(make_mix(mixp[0], mixp[1], mixp[2], mixp[3], mixp[4]));
+          mixf = make_mix_f(mixp[0], mixp[1], mixp[2], mixp[3], mixp[4]);
         }
       }
       __syncthreads();

@@ -153,31 +153,51 @@ __global__ void k_sub_fill(const ProbDev *__restrict__ probs, const int *__restr
   }
 }
 
-__global__ void k_bin_count(const ProbDev *__restrict__ probs, const int *__restrict__ brick_prob,
-                            const int *__restrict__ bb, const double *__restrict__ sbox, int nb,
-                            int *__restrict__ count) {
-  int bi = blockIdx.x * blockDim.x + threadIdx.x;
-  if (bi >= nb) return;
+// One wavefront per brick: the lanes test 64 consecutive patches of the
+// brick's problem at a time.  The count is a wave sum; the fill writes the
+// meeting patches in ascending patch order (ballot prefix counts), the order
+// that fixes the adjoint's summation order.
+constexpr int BIN_THREADS = 256;
+
+__global__ void __launch_bounds__(BIN_THREADS)
+k_bin_count(const ProbDev *__restrict__ probs, const int *__restrict__ brick_prob,
+            const int *__restrict__ bb, const double *__restrict__ sbox, int nb,
+            int *__restrict__ count) {
+  const int lane = threadIdx.x & 63;
+  const int bi = blockIdx.x * (BIN_THREADS / 64) + (threadIdx.x >> 6);
+  if (bi >= nb) return;  // uniform over the wavefront
   const ProbDev pr = probs[brick_prob[bi]];
   const int local = bi - pr.brick_base;
   const int bx = local % pr.nbx, by = (local / pr.nbx) % pr.nby, bz = local / (pr.nbx * pr.nby);
   int c = 0;
-  for (int s = pr.patch_begin; s < pr.patch_end; ++s)
-    c += brick_meets_patch(bb + 6 * s, sbox + 18 * s, bx, by, bz) ? 1 : 0;
-  count[bi] = c;
+  for (int s0 = pr.patch_begin; s0 < pr.patch_end; s0 += 64) {
+    const int s = s0 + lane;
+    if (s < pr.patch_end && brick_meets_patch(bb + 6 * s, sbox + 18 * s, bx, by, bz)) ++c;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if (lane == 0) count[bi] = c;
 }
 
-__global__ void k_bin_fill(const ProbDev *__restrict__ probs, const int *__restrict__ brick_prob,
-                           const int *__restrict__ bb, const double *__restrict__ sbox, int nb,
-                           const int *__restrict__ off, int *__restrict__ list) {
-  int bi = blockIdx.x * blockDim.x + threadIdx.x;
-  if (bi >= nb) return;
+__global__ void __launch_bounds__(BIN_THREADS)
+k_bin_fill(const ProbDev *__restrict__ probs, const int *__restrict__ brick_prob,
+           const int *__restrict__ bb, const double *__restrict__ sbox, int nb,
+           const int *__restrict__ off, int *__restrict__ list) {
+  const int lane = threadIdx.x & 63;
+  const int bi = blockIdx.x * (BIN_THREADS / 64) + (threadIdx.x >> 6);
+  if (bi >= nb) return;  // uniform over the wavefront
   const ProbDev pr = probs[brick_prob[bi]];
   const int local = bi - pr.brick_base;
   const int bx = local % pr.nbx, by = (local / pr.nbx) % pr.nby, bz = local / (pr.nbx * pr.nby);
+  const unsigned long long below = (1ull << lane) - 1ull;
   int c = off[bi];
-  for (int s = pr.patch_begin; s < pr.patch_end; ++s)
-    if (brick_meets_patch(bb + 6 * s, sbox + 18 * s, bx, by, bz)) list[c++] = s;
+  for (int s0 = pr.patch_begin; s0 < pr.patch_end; s0 += 64) {
+    const int s = s0 + lane;
+    const bool m = s < pr.patch_end && brick_meets_patch(bb + 6 * s, sbox + 18 * s, bx, by, bz);
+    const unsigned long long bal = __ballot(m);
+    if (m) list[c + __popcll(bal & below)] = s;
+    c += __popcll(bal);
+  }
 }
 
 // Largest voxel box over the forward tiles (sizes the staged LDS).
@@ -531,7 +551,8 @@ extern "C" pvr_status pvr_plan_set_tiles(pvr_plan *p, int32_t tile_w, int32_t ti
 pvr_status pvr::plan_build_index(pvr_plan *p, hipStream_t stream) {
   const int T = 256;
   const int nb = p->n_bricks;
-  hipLaunchKernelGGL(k_bin_count, dim3((nb + T - 1) / T), dim3(T), 0, stream, p->d_prob,
+  const int nbw = (nb + BIN_THREADS / 64 - 1) / (BIN_THREADS / 64);
+  hipLaunchKernelGGL(k_bin_count, dim3(nbw), dim3(BIN_THREADS), 0, stream, p->d_prob,
                      p->d_brick_prob, p->d_bb, p->d_sbox, nb, p->d_bin_count);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, stream, p->d_bin_count, nb, p->d_bin_off,
@@ -549,7 +570,7 @@ pvr_status pvr::plan_build_index(pvr_plan *p, hipStream_t stream) {
     p->bin_cap = cap;
   }
   p->n_pairs = pairs;
-  hipLaunchKernelGGL(k_bin_fill, dim3((nb + T - 1) / T), dim3(T), 0, stream, p->d_prob,
+  hipLaunchKernelGGL(k_bin_fill, dim3(nbw), dim3(BIN_THREADS), 0, stream, p->d_prob,
                      p->d_brick_prob, p->d_bb, p->d_sbox, nb, p->d_bin_off, p->d_bin_patch);
   HIP_TRY(hipGetLastError());
   const int nsb = nb * 8;
