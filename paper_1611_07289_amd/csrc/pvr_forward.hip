@@ -23,9 +23,9 @@ template <typename T>
 __global__ void __launch_bounds__(SIM_THREADS)
 k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patches,
            const BlockWork *__restrict__ work, const typename GeoOf<T>::type *__restrict__ geo,
-           const T *__restrict__ invz, const T *__restrict__ X, const T *__restrict__ y_obs,
-           T *__restrict__ y_sim, T *__restrict__ resid, double *__restrict__ chunk_stats,
-           int n_work) {
+           const T *__restrict__ invz, const T *__restrict__ X, const T *__restrict__ XT,
+           const T *__restrict__ y_obs, T *__restrict__ y_sim, T *__restrict__ resid,
+           double *__restrict__ chunk_stats, int n_work) {
   const int wi = xcd_work(blockIdx.x, SIM_XCD_GRANULE);
   if (wi >= n_work) return;
   const BlockWork wk = work[wi];
@@ -33,7 +33,10 @@ k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patch
   const ProbDev pr = probs[pt.problem];
   const typename GeoOf<T>::type &g = geo[wk.patch];
   const unsigned nbytes = (unsigned)(pr.nx * pr.ny * pr.nz) * (unsigned)sizeof(T);
-  const __amdgpu_buffer_rsrc_t xr = raw_buffer(X + pr.vol_off, nbytes);
+  // patches whose rows run along y read the y-fastest copy, so that the lanes
+  // of a wave (consecutive pixels of a row) read consecutive addresses
+  const bool xt = XT != nullptr && pt.layout == 1;
+  const __amdgpu_buffer_rsrc_t xr = raw_buffer((xt ? XT : X) + pr.vol_off, nbytes);
   const int n = pt.w * pt.h;
   const int l1 = min(n, wk.l0 + SIM_CHUNK);
   double st[5] = {INFINITY, -INFINITY, 0.0, 0.0, 0.0};  // min e, max e, max|y|, sum e^2, count
@@ -46,11 +49,15 @@ k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patch
       int b[3];
       T f[3];
       sample_centre(g, pr, u, v, pt.slice, b, f);
-      // the patch's rows run along x or not for all its samples: one branch
-      // per chunk picks the matching walk
+      // the layout, and whether the walk's inner axis is the layout's fastest
+      // one, are uniform over the chunk: one branch per chunk picks the walk
       using G = typename GeoOf<T>::type;
-      yh = (g.perm[2] == 0 ? psf_walk_fwd<T, G, false, 1>(g, pr, b, f, xr, nbytes)
-                           : psf_walk_fwd<T, G, false, 2>(g, pr, b, f, xr, nbytes)) * iz;
+      if (xt)
+        yh = (g.perm[2] == 1 ? psf_walk_fwd<T, G, false, 1, true>(g, pr, b, f, xr, nbytes)
+                             : psf_walk_fwd<T, G, false, 2, true>(g, pr, b, f, xr, nbytes)) * iz;
+      else
+        yh = (g.perm[2] == 0 ? psf_walk_fwd<T, G, false, 1>(g, pr, b, f, xr, nbytes)
+                             : psf_walk_fwd<T, G, false, 2>(g, pr, b, f, xr, nbytes)) * iz;
     }
     if (y_sim) y_sim[j] = yh;
     if (resid) {
@@ -153,6 +160,40 @@ k_simulate_tiles(const ProbDev *__restrict__ probs, const PatchDev *__restrict__
   if (resid) resid[j] = iz > 0.f ? y_obs[j] - yh : 0.f;
 }
 
+// y-fastest copy of every problem's volume: XT[(z nx + x) ny + y] =
+// X[(z ny + y) nx + x], by 64 x 64 tiles through LDS (rows of both arrays
+// read and written whole).
+constexpr int XT_TILE = 64;
+__global__ void __launch_bounds__(256) k_transpose_xy(const float *__restrict__ X,
+                                                      float *__restrict__ XT, int nx, int ny) {
+  __shared__ float t[XT_TILE][XT_TILE + 1];
+  const int x0 = blockIdx.x * XT_TILE, y0 = blockIdx.y * XT_TILE;
+  const long long zo = (long long)blockIdx.z * nx * ny;
+  const int c = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+  for (int r = r0; r < XT_TILE; r += 4) {
+    const int x = x0 + c, y = y0 + r;
+    if (x < nx && y < ny) t[r][c] = X[zo + (long long)y * nx + x];
+  }
+  __syncthreads();
+  for (int r = r0; r < XT_TILE; r += 4) {
+    const int y = y0 + c, x = x0 + r;
+    if (x < nx && y < ny) XT[zo + (long long)x * ny + y] = t[c][r];
+  }
+}
+
+// Fills p->d_xt from X when the plan has patches that read it; returns the
+// copy (or nullptr).
+static const float *volume_xt(const pvr_plan *p, const float *X, hipStream_t stream) {
+  if (!p->any_xt) return nullptr;
+  for (int b = 0; b < p->P; ++b) {
+    const ProbDev &pr = p->h_prob[b];
+    const dim3 grid((pr.nx + XT_TILE - 1) / XT_TILE, (pr.ny + XT_TILE - 1) / XT_TILE, pr.nz);
+    hipLaunchKernelGGL(k_transpose_xy, grid, dim3(256), 0, stream, X + pr.vol_off,
+                       p->d_xt + pr.vol_off, pr.nx, pr.ny);
+  }
+  return p->d_xt;
+}
+
 template <typename T>
 static pvr_status simulate_impl(const pvr_plan *p, const T *X, const T *y_obs, T *y_sim, T *resid,
                                 const T *invz, hipStream_t stream) {
@@ -175,12 +216,17 @@ static pvr_status simulate_impl(const pvr_plan *p, const T *X, const T *y_obs, T
   double *stats = (sizeof(T) == 4 && resid) ? p->d_chunk_stats : nullptr;
   hipEvent_t *ev = timing_slot(p, PVR_KERNEL_SIMULATE);
   if (ev) HIP_TRY(hipEventRecord(ev[0], stream));
+  const T *XT = nullptr;
+  if constexpr (sizeof(T) == 4) {
+    XT = volume_xt(p, X, stream);
+    HIP_TRY(hipGetLastError());
+  }
   hipLaunchKernelGGL(k_simulate<T>, dim3(xcd_blocks(p->n_sim_blocks, SIM_XCD_GRANULE)),
                      dim3(SIM_THREADS), 0, stream, p->d_prob,
                      p->d_patch, p->d_sim_blocks,
                      (const typename GeoOf<T>::type *)(sizeof(T) == 4 ? (const void *)p->d_geof
                                                                       : (const void *)p->d_geod),
-                     invz, X, y_obs, y_sim, resid, stats, p->n_sim_blocks);
+                     invz, X, XT, y_obs, y_sim, resid, stats, p->n_sim_blocks);
   HIP_TRY(hipGetLastError());
   if (ev) HIP_TRY(hipEventRecord(ev[1], stream));
   // the residual statistics describe these buffers until the next build
@@ -266,6 +312,7 @@ struct RegShared {
 
 // NCC of the patch against its simulation at sh.th (valid samples only);
 // every lane returns the same value.
+template <bool XT>
 __device__ double reg_eval(RegShared &sh, const ProbDev &pr, const StackDev &st, const PatchDev &pt,
                            double k, __amdgpu_buffer_rsrc_t xr, unsigned nbytes,
                            const float *__restrict__ y,
@@ -287,8 +334,9 @@ __device__ double reg_eval(RegShared &sh, const ProbDev &pr, const StackDev &st,
     float f[3];
     if (!sample_centre(g, pr, u, v, pt.slice, b, f)) continue;
     float z = 0.f;
-    const float a = g.perm[2] == 0 ? psf_walk_fwd<float, GeoF, true, 1>(g, pr, b, f, xr, nbytes, &z)
-                                   : psf_walk_fwd<float, GeoF, true, 2>(g, pr, b, f, xr, nbytes, &z);
+    const float a = g.perm[2] == (XT ? 1 : 0)
+                        ? psf_walk_fwd<float, GeoF, true, 1, XT>(g, pr, b, f, xr, nbytes, &z)
+                        : psf_walk_fwd<float, GeoF, true, 2, XT>(g, pr, b, f, xr, nbytes, &z);
     if (!(z > 0.f)) continue;
     const double yh = (double)(a / z), yo = (double)y[j];
     acc6[0] += 1.0;
@@ -317,6 +365,7 @@ __device__ double reg_eval(RegShared &sh, const ProbDev &pr, const StackDev &st,
 //                            - NCC (y_hat_j - mean y_hat) / S_b] d y_hat_j,
 // which needs only the per-patch sums of d y_hat, y d y_hat and
 // y_hat d y_hat beside the six NCC sums.  Every lane returns the same values.
+template <bool XT>
 __device__ double reg_eval_exact(RegShared &sh, const ProbDev &pr, const StackDev &st,
                                  const PatchDev &pt, double k, __amdgpu_buffer_rsrc_t xr,
                                  unsigned nbytes, const float *__restrict__ y,
@@ -342,10 +391,10 @@ __device__ double reg_eval_exact(RegShared &sh, const ProbDev &pr, const StackDe
     float f[3];
     if (!sample_centre(g, pr, u, v, pt.slice, b, f)) continue;
     float xb, a, z, mx[9], me[9];
-    if (g.perm[2] == 0)
-      psf_walk_grad<1>(g, pr, b, f, xr, nbytes, xb, a, z, mx, me);
+    if (g.perm[2] == (XT ? 1 : 0))
+      psf_walk_grad<1, XT>(g, pr, b, f, xr, nbytes, xb, a, z, mx, me);
     else
-      psf_walk_grad<2>(g, pr, b, f, xr, nbytes, xb, a, z, mx, me);
+      psf_walk_grad<2, XT>(g, pr, b, f, xr, nbytes, xb, a, z, mx, me);
     if (!(z > 0.f)) continue;
     const float iz = 1.f / z;
     const float dl = a * iz;  // y_hat - X_b
@@ -401,21 +450,20 @@ __device__ double reg_eval_exact(RegShared &sh, const ProbDev &pr, const StackDe
 // One workgroup per patch; the optimiser's control flow is uniform (every
 // lane sees the same reduced NCC values), its state lives in LDS.  EXACT
 // selects the exact gradient (one reg_eval_exact) over central differences
-// (twelve reg_eval).
-template <bool EXACT>
-__global__ void __launch_bounds__(REG_THREADS)
-k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stacks,
-           const PatchDev *__restrict__ patches, const float *__restrict__ X,
-           const float *__restrict__ y, const uint8_t *__restrict__ mask, float *__restrict__ theta,
-           float *__restrict__ ncc_out, const uint8_t *__restrict__ reg, pvr_reg_params prm,
-           double k) {
-  __shared__ RegShared sh;
+// (twelve reg_eval); XT the y-fastest volume copy (patches of layout 1).
+template <bool EXACT, bool XT>
+__device__ __forceinline__ void register_patch(
+    RegShared &sh, const ProbDev *__restrict__ probs, const StackDev *__restrict__ stacks,
+    const PatchDev *__restrict__ patches, const float *__restrict__ Xv,
+    const float *__restrict__ y, const uint8_t *__restrict__ mask, float *__restrict__ theta,
+    float *__restrict__ ncc_out, const uint8_t *__restrict__ reg, const pvr_reg_params &prm,
+    double k) {
   const int s = blockIdx.x;
   const PatchDev pt = patches[s];
   const ProbDev pr = probs[pt.problem];
   const StackDev st = stacks[pt.stack];
   const unsigned nbytes = (unsigned)(pr.nx * pr.ny * pr.nz) * (unsigned)sizeof(float);
-  const __amdgpu_buffer_rsrc_t xr = raw_buffer(X + pr.vol_off, nbytes);
+  const __amdgpu_buffer_rsrc_t xr = raw_buffer(Xv + pr.vol_off, nbytes);
   // observed standard deviation over unmasked samples
   double sy[6] = {0, 0, 0, 0, 0, 0};
   const int n = pt.w * pt.h;
@@ -444,7 +492,7 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
     }
   }
   __syncthreads();
-  double f0 = reg_eval(sh, pr, st, pt, k, xr, nbytes, y, mask);
+  double f0 = reg_eval<XT>(sh, pr, st, pt, k, xr, nbytes, y, mask);
   const bool do_reg = (reg ? reg[s] != 0 : true) && sd >= prm.min_std && prm.max_iter > 0;
   if (do_reg) {
     double delta = prm.step0;
@@ -456,7 +504,7 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
         if (threadIdx.x == 0)
           for (int b = 0; b < 6; ++b) sh.th[b] = sh.q[b] / sh.sc[b];
         double gth[6];
-        reg_eval_exact(sh, pr, st, pt, k, xr, nbytes, y, mask, gth);
+        reg_eval_exact<XT>(sh, pr, st, pt, k, xr, nbytes, y, mask, gth);
         if (threadIdx.x == 0)
           for (int a = 0; a < 6; ++a) sh.grad[a] = gth[a] / sh.sc[a];
         have_grad = true;
@@ -468,10 +516,10 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
             for (int b = 0; b < 6; ++b) sh.th[b] = sh.q[b] / sh.sc[b];
             sh.th[a] = (sh.q[a] + prm.fd_h) / sh.sc[a];
           }
-          fp = reg_eval(sh, pr, st, pt, k, xr, nbytes, y, mask);
+          fp = reg_eval<XT>(sh, pr, st, pt, k, xr, nbytes, y, mask);
           __syncthreads();
           if (threadIdx.x == 0) sh.th[a] = (sh.q[a] - prm.fd_h) / sh.sc[a];
-          fm = reg_eval(sh, pr, st, pt, k, xr, nbytes, y, mask);
+          fm = reg_eval<XT>(sh, pr, st, pt, k, xr, nbytes, y, mask);
           if (threadIdx.x == 0) sh.grad[a] = (fp - fm) / (2.0 * prm.fd_h);
         }
         have_grad = true;
@@ -484,7 +532,7 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
       __syncthreads();
       if (threadIdx.x == 0)
         for (int a = 0; a < 6; ++a) sh.th[a] = (sh.q[a] + delta * sh.grad[a] / gn) / sh.sc[a];
-      const double ft = reg_eval(sh, pr, st, pt, k, xr, nbytes, y, mask);
+      const double ft = reg_eval<XT>(sh, pr, st, pt, k, xr, nbytes, y, mask);
       if (ft > f0) {
         __syncthreads();
         if (threadIdx.x == 0)
@@ -505,6 +553,21 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
   if (ncc_out && threadIdx.x == 0) ncc_out[s] = (float)f0;
 }
 
+// The optimiser of register_patch for the patches of one volume layout (the
+// others return at once): one launch per layout keeps the register use of a
+// single optimiser.
+template <bool EXACT, bool XT>
+__global__ void __launch_bounds__(REG_THREADS)
+k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stacks,
+           const PatchDev *__restrict__ patches, const float *__restrict__ Xv, int any_xt,
+           const float *__restrict__ y, const uint8_t *__restrict__ mask,
+           float *__restrict__ theta, float *__restrict__ ncc_out,
+           const uint8_t *__restrict__ reg, pvr_reg_params prm, double k) {
+  __shared__ RegShared sh;
+  if ((any_xt && patches[blockIdx.x].layout == 1) != XT) return;
+  register_patch<EXACT, XT>(sh, probs, stacks, patches, Xv, y, mask, theta, ncc_out, reg, prm, k);
+}
+
 extern "C" pvr_status pvr_register_patches(const pvr_plan *p, const float *X, const float *y_obs,
                                            float *theta, float *ncc, const uint8_t *reg,
                                            const pvr_reg_params *prm, hipStream_t stream) {
@@ -515,12 +578,21 @@ extern "C" pvr_status pvr_register_patches(const pvr_plan *p, const float *X, co
     return fail(PVR_EINVAL, "pvr_register_patches: invalid optimiser parameters");
   if (prm->gradient != PVR_REG_GRAD_FD && prm->gradient != PVR_REG_GRAD_EXACT)
     return fail(PVR_EINVAL, "pvr_register_patches: gradient must be PVR_REG_GRAD_FD or PVR_REG_GRAD_EXACT");
-  if (prm->gradient == PVR_REG_GRAD_EXACT)
-    hipLaunchKernelGGL(k_register<true>, dim3(p->M), dim3(REG_THREADS), 0, stream, p->d_prob,
-                       p->d_stack, p->d_patch, X, y_obs, p->d_mask, theta, ncc, reg, *prm, p->k);
-  else
-    hipLaunchKernelGGL(k_register<false>, dim3(p->M), dim3(REG_THREADS), 0, stream, p->d_prob,
-                       p->d_stack, p->d_patch, X, y_obs, p->d_mask, theta, ncc, reg, *prm, p->k);
+  const float *XT = volume_xt(p, X, stream);
+  HIP_TRY(hipGetLastError());
+  const int any = XT != nullptr;
+#define REG_LAUNCH(E, L, V)                                                                    \
+  hipLaunchKernelGGL((k_register<E, L>), dim3(p->M), dim3(REG_THREADS), 0, stream, p->d_prob, \
+                     p->d_stack, p->d_patch, V, any, y_obs, p->d_mask, theta, ncc, reg, *prm,  \
+                     p->k)
+  if (prm->gradient == PVR_REG_GRAD_EXACT) {
+    REG_LAUNCH(true, false, X);
+    if (any) REG_LAUNCH(true, true, XT);
+  } else {
+    REG_LAUNCH(false, false, X);
+    if (any) REG_LAUNCH(false, true, XT);
+  }
+#undef REG_LAUNCH
   HIP_TRY(hipGetLastError());
   return PVR_OK;
   PVR_API_END();

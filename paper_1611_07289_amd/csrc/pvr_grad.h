@@ -166,20 +166,21 @@ __device__ inline void make_grad_mom(const GradConst &gc, const int perm[3], Gra
   for (int q = 0; q < 9; ++q) gm.om[q] = (float)gc.om[q];
 }
 
-// One walk over the support of a sample (as psf_walk_fwd, FP32): the PSF sums
+// One walk over the support of a sample (as psf_walk_fwd, FP32, with its ROW
+// and XT): the PSF sums
 // relative to the centre voxel's value X_b (A' = sum g_hat (X - X_b),
 // Z = sum g_hat, so y_hat = X_b + A'/Z) and the nine offset moments of
 // e^{-Q/2} (X - X_b) and of e^{-Q/2} (first moments a, b, c, then the second
 // moments aa, ab, ac, bb, bc, cc).  The moments of the weights w_i follow as
 // mx - (y_hat - X_b) me; the reference X_b keeps that difference accurate.
-template <int ROW>
+template <int ROW, bool XT>
 __device__ __forceinline__ void psf_walk_grad(const GeoF &g, const ProbDev &p, const int b[3],
                                               const float f[3], __amdgpu_buffer_rsrc_t xr,
                                               unsigned nbytes, float &xb_out, float &a_out,
                                               float &z_out, float mx[9], float me[9]) {
-  const int sy = p.nx, sz = p.nx * p.ny;
+  const int sx = XT ? p.ny : 1, sy = XT ? 1 : p.nx, sz = p.nx * p.ny;
   const int ia = g.perm[0], ib = g.perm[1], ic = g.perm[2];
-  const int st_a = sel3(ia, 1, sy, sz), st_b = sel3(ib, 1, sy, sz), st_c = sel3(ic, 1, sy, sz);
+  const int st_a = sel3(ia, sx, sy, sz), st_b = sel3(ib, sx, sy, sz), st_c = sel3(ic, sx, sy, sz);
   const int b_a = sel3(ia, b[0], b[1], b[2]), b_b = sel3(ib, b[0], b[1], b[2]),
             b_c = sel3(ic, b[0], b[1], b[2]);
   const int n_a = sel3(ia, p.nx, p.ny, p.nz), n_b = sel3(ib, p.nx, p.ny, p.nz),
@@ -192,7 +193,7 @@ __device__ __forceinline__ void psf_walk_grad(const GeoF &g, const ProbDev &p, c
   const int lo_a = max((int)ceil(f_a - ha), -b_a);
   const int hi_a = min((int)floor(f_a + ha), n_a - 1 - b_a);
   const int cl_b = -b_b, ch_b = n_b - 1 - b_b, cl_c = -b_c, ch_c = n_c - 1 - b_c;
-  const int vb = (b[2] * p.ny + b[1]) * p.nx + b[0];
+  const int vb = b[0] * sx + b[1] * sy + b[2] * sz;
   const unsigned step = (unsigned)st_c * 4u;
   const float xb = load_vox<float>(xr, (unsigned)vb * 4u);
   float acc = 0.f, z = 0.f;

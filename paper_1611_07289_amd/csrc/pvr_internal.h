@@ -52,7 +52,8 @@ struct StackDev {
 };
 
 struct PatchDev {
-  int stack, slice, x0, y0, w, h, problem, pad;
+  int stack, slice, x0, y0, w, h, problem;
+  int layout;  // volume copy the forward walks read: 0 = X (x fastest), 1 = y fastest
   long long off;
 };
 
@@ -292,15 +293,16 @@ template <> __device__ __forceinline__ float clamp01<float>(float x) {
 template <> __device__ __forceinline__ double clamp01<double>(double x) { return fmax(x, 0.0); }
 
 // WITH_Z also sums the weights (the normaliser Z over in-volume voxels).
-// xr views the problem's volume (nbytes bytes).  ROW as for load_group (the
-// inner axis is x exactly when g.perm[2] == 0).
-template <typename T, typename GEO, bool WITH_Z = false, int ROW = 0>
+// xr views the problem's volume (nbytes bytes), x fastest, or with XT its
+// y-fastest copy ((z nx + x) ny + y).  ROW as for load_group: 1 when the inner
+// axis is the fastest one of the layout (g.perm[2] == 0, or 1 with XT).
+template <typename T, typename GEO, bool WITH_Z = false, int ROW = 0, bool XT = false>
 __device__ __forceinline__ T psf_walk_fwd(const GEO &g, const ProbDev &p, const int b[3],
                                           const T f[3], __amdgpu_buffer_rsrc_t xr,
                                           unsigned nbytes, T *z_out = nullptr) {
-  const int sy = p.nx, sz = p.nx * p.ny;
+  const int sx = XT ? p.ny : 1, sy = XT ? 1 : p.nx, sz = p.nx * p.ny;
   const int ia = g.perm[0], ib = g.perm[1], ic = g.perm[2];
-  const int st_a = sel3(ia, 1, sy, sz), st_b = sel3(ib, 1, sy, sz), st_c = sel3(ic, 1, sy, sz);
+  const int st_a = sel3(ia, sx, sy, sz), st_b = sel3(ib, sx, sy, sz), st_c = sel3(ic, sx, sy, sz);
   const int b_a = sel3(ia, b[0], b[1], b[2]), b_b = sel3(ib, b[0], b[1], b[2]),
             b_c = sel3(ic, b[0], b[1], b[2]);
   const int n_a = sel3(ia, p.nx, p.ny, p.nz), n_b = sel3(ib, p.nx, p.ny, p.nz),
@@ -314,7 +316,7 @@ __device__ __forceinline__ T psf_walk_fwd(const GEO &g, const ProbDev &p, const 
   const int lo_a = max((int)ceil(f_a - ha), -b_a);
   const int hi_a = min((int)floor(f_a + ha), n_a - 1 - b_a);
   const int cl_b = -b_b, ch_b = n_b - 1 - b_b, cl_c = -b_c, ch_c = n_c - 1 - b_c;
-  const int vb = (b[2] * p.ny + b[1]) * p.nx + b[0];
+  const int vb = b[0] * sx + b[1] * sy + b[2] * sz;
   const unsigned step = (unsigned)st_c * (unsigned)sizeof(T);
   T acc = (T)0, z = (T)0;
   for (int oa = lo_a; oa <= hi_a; ++oa) {
@@ -477,6 +479,8 @@ struct pvr_plan {
   float *d_pbar;             // [M] potentials when the caller passes none
   float *d_pval;             // [M] classification scratch (problems beyond the LDS copy)
   double *d_chunk_stats;     // [n_sim_blocks][5] residual statistics of the last simulate
+  float *d_xt;               // [V] y-fastest copy of the volume (plans with layout-1 patches)
+  bool any_xt;
   const void *stats_resid, *stats_y;  // ... and the buffers they describe
   bool stats_valid;
   int *d_total;              // [1] pinned readback target (device side)

@@ -350,6 +350,15 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
     PatchDev &d = p->h_patch[s];
     d.stack = q.stack; d.slice = q.slice; d.x0 = q.x0; d.y0 = q.y0; d.w = q.w; d.h = q.h;
     d.problem = prob; d.off = so;
+    {
+      // rows of the patch run along the stack's u axis: when that is closer
+      // to voxel y than to voxel x, the forward walks read the y-fastest copy
+      const double *W = p->h_prob[prob].w2v, *A = st.p2w;
+      double du[3];
+      for (int r = 0; r < 3; ++r) du[r] = W[4 * r] * A[0] + W[4 * r + 1] * A[4] + W[4 * r + 2] * A[8];
+      d.layout = fabs(du[1]) > fabs(du[0]) ? 1 : 0;
+      if (d.layout) p->any_xt = true;
+    }
     p->h_sample_off[s] = so;
     const int n = q.w * q.h;
     for (int l0 = 0; l0 < n; l0 += SIM_CHUNK) blocks.push_back(BlockWork{s, l0});
@@ -442,6 +451,7 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
   DEV_ALLOC(p, p->d_pbar, n_patches);
   DEV_ALLOC(p, p->d_pval, n_patches);
   DEV_ALLOC(p, p->d_chunk_stats, 5 * (size_t)p->n_sim_blocks);
+  if (p->any_xt) DEV_ALLOC(p, p->d_xt, p->V);
   DEV_ALLOC(p, p->d_total, 4);
   HIP_TRY(hipHostMalloc((void **)&p->h_total, sizeof(int) * 4, hipHostMallocDefault));
   HIP_TRY(hipMemcpy(p->d_prob, p->h_prob, sizeof(ProbDev) * n_problems, hipMemcpyHostToDevice));
