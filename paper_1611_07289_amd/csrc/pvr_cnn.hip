@@ -56,323 +56,427 @@ constexpr int CT = 256;  // threads per conv workgroup (4 waves)
 
 // ---------------------------------------------------------------------------
 // forward: out = relu(conv3x3(in, W, stride S, pad 1) + bias)
-// one wave = 32 output pixels x COUT channels
+//
+// Implicit GEMM, M = output pixels, N = COUT, K = 9 CIN.  The layer's weights
+// (B operand) are staged once per workgroup into LDS, rows of K padded by 8
+// elements; the workgroup (16 waves, so that two workgroups fill a CU even
+// with the largest weights) then loops over tiles of 256 output pixels, one
+// 16-row MFMA tile per wave, so each weight is read from memory once per
+// workgroup.  The A operand is gathered from global memory, 8 channels
+// (16 bytes) of one input pixel per lane per tap, zero outside the image; all
+// taps are loaded before the first MFMA so that their latencies overlap.
 // ---------------------------------------------------------------------------
+constexpr int FW_THREADS = 1024;                       // 16 waves share the staged weights
+constexpr int FW_TILE = (FW_THREADS / 64) * 16;       // one 16-pixel MFMA tile per wave
+
+template <int CIN, int COUT>
+struct FwdShape {
+  static constexpr int K = 9 * CIN;
+  static constexpr int KP = K < 32 ? 32 : K;  // K padded to one MFMA step when CIN < 32
+  static constexpr int LS = KP + 8;           // LDS row stride (elements), 16-byte rows
+  static constexpr int LDS_BYTES = COUT * LS * 2;
+};
+
 template <int CIN, int COUT, int S>
-__global__ void __launch_bounds__(CT)
+__global__ void __launch_bounds__(FW_THREADS)
 k_conv_fwd(const uint16_t *__restrict__ in, const uint16_t *__restrict__ W,
            const float *__restrict__ bias, uint16_t *__restrict__ out, int B, int H, int Wd,
            int relu) {
-  constexpr int NT = COUT / 16;
-  const int Ho = (H - 1) / S + 1, Wo = (Wd - 1) / S + 1;
-  const long long P = (long long)B * Ho * Wo;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long long pbase = ((long long)blockIdx.x * 4 + wave) * 32;
-  if (pbase >= P) return;
-  int pb[2], py[2], px[2];
-  bool pv[2];
-#pragma unroll
-  for (int mt = 0; mt < 2; ++mt) {
-    const long long p = pbase + mt * 16 + (lane & 15);
-    pv[mt] = p < P;
-    const long long pp = pv[mt] ? p : 0;
-    pb[mt] = (int)(pp / (Ho * Wo));
-    const int r = (int)(pp % (Ho * Wo));
-    py[mt] = r / Wo;
-    px[mt] = r % Wo;
-  }
-  f32x4 acc[2][NT];
-#pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  const int kq = lane >> 4;  // which 8-wide k group
-  if (CIN >= 32) {
-    constexpr int CB = CIN / 32;
-    for (int t = 0; t < 9 * CB; ++t) {
-      const int tap = t / CB, cb = t % CB;
-      const int ky = tap / 3, kx = tap % 3;
-      const int ci0 = cb * 32 + 8 * kq;
-      bf16x8 a[2];
-#pragma unroll
-      for (int mt = 0; mt < 2; ++mt) {
-        const int iy = py[mt] * S + ky - 1, ix = px[mt] * S + kx - 1;
-        if (pv[mt] && iy >= 0 && iy < H && ix >= 0 && ix < Wd)
-          a[mt] = load8(in + (((long long)pb[mt] * H + iy) * Wd + ix) * CIN + ci0);
-        else
-          a[mt] = zero8();
-      }
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const int co = nt * 16 + (lane & 15);
-        const bf16x8 b = load8(W + (long long)co * 9 * CIN + tap * CIN + ci0);
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b, acc[mt][nt], 0, 0, 0);
-      }
+  using SH = FwdShape<CIN, COUT>;
+  constexpr int NT = COUT / 16, K = SH::K, KP = SH::KP, LS = SH::LS;
+  __shared__ __attribute__((aligned(16))) uint16_t Wl[COUT * LS];
+  if constexpr (K % 8 == 0) {
+    for (int e = threadIdx.x; e < COUT * (K / 8); e += FW_THREADS) {
+      const int co = e / (K / 8), k8 = e % (K / 8);
+      *reinterpret_cast<uint4 *>(&Wl[co * LS + 8 * k8]) =
+          *reinterpret_cast<const uint4 *>(W + (long long)co * K + 8 * k8);
     }
   } else {
-    // CIN < 32: the whole K = 9*CIN (<= 32) in one step, zero padded
-    constexpr int K = 9 * CIN;
-    bf16x8 a[2];
+    for (int e = threadIdx.x; e < COUT * KP; e += FW_THREADS) {
+      const int co = e / KP, k = e % KP;
+      Wl[co * LS + k] = k < K ? W[co * K + k] : (uint16_t)0;
+    }
+  }
+  __syncthreads();
+  const int Ho = (H - 1) / S + 1, Wo = (Wd - 1) / S + 1;
+  const long long P = (long long)B * Ho * Wo;
+  const long long n_tiles = (P + FW_TILE - 1) / FW_TILE;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kq = lane >> 4, r16 = lane & 15;
+  for (long long tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const long long pbase = tile * FW_TILE + wave * 16;
+    if (pbase >= P) continue;
+    const long long p = pbase + r16;
+    const bool pv = p < P;
+    const long long pp = pv ? p : 0;
+    const int pb = (int)(pp / (Ho * Wo));
+    const int rr = (int)(pp % (Ho * Wo));
+    const int py = rr / Wo, px = rr % Wo;
+    f32x4 acc[NT];
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
-      V8 t;
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    if constexpr (CIN >= 32) {
+      constexpr int CB = CIN / 32, T = 9 * CB;
+      bf16x8 a[T];
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int tap = t / CB, cb = t % CB;
+        const int iy = py * S + tap / 3 - 1, ix = px * S + tap % 3 - 1;
+        if (pv && iy >= 0 && iy < H && ix >= 0 && ix < Wd)
+          a[t] = load8(in + (((long long)pb * H + iy) * Wd + ix) * CIN + cb * 32 + 8 * kq);
+        else
+          a[t] = zero8();
+      }
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int tap = t / CB, cb = t % CB;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const bf16x8 b = *reinterpret_cast<const bf16x8 *>(
+              &Wl[(nt * 16 + r16) * LS + tap * CIN + cb * 32 + 8 * kq]);
+          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], b, acc[nt], 0, 0, 0);
+        }
+      }
+    } else {
+      // K = 9 CIN <= 32: the whole K in one step, zero padded
+      V8 ta;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int k = 8 * kq + i;
         uint16_t v = 0;
-        if (k < K && pv[mt]) {
+        if (k < K && pv) {
           const int tap = k / CIN, ci = k % CIN;
-          const int iy = py[mt] * S + tap / 3 - 1, ix = px[mt] * S + tap % 3 - 1;
+          const int iy = py * S + tap / 3 - 1, ix = px * S + tap % 3 - 1;
           if (iy >= 0 && iy < H && ix >= 0 && ix < Wd)
-            v = in[(((long long)pb[mt] * H + iy) * Wd + ix) * CIN + ci];
+            v = in[(((long long)pb * H + iy) * Wd + ix) * CIN + ci];
         }
-        t.h[i] = v;
+        ta.h[i] = v;
       }
-      a[mt] = t.v;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Wl[(nt * 16 + r16) * LS + 8 * kq]);
+        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ta.v, b, acc[nt], 0, 0, 0);
+      }
     }
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-      const int co = nt * 16 + (lane & 15);
-      V8 t;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int k = 8 * kq + i;
-        t.h[i] = k < K ? W[co * K + k] : (uint16_t)0;
-      }
-#pragma unroll
-      for (int mt = 0; mt < 2; ++mt)
-        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], t.v, acc[mt][nt], 0, 0, 0);
-    }
-  }
-#pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const int co = nt * 16 + (lane & 15);
+      const int co = nt * 16 + r16;
       const float bb = bias[co];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const long long p = pbase + mt * 16 + 4 * kq + i;
-        if (p < P) {
-          float v = acc[mt][nt][i] + bb;
+        const long long q = pbase + 4 * kq + i;
+        if (q < P) {
+          float v = acc[nt][i] + bb;
           if (relu) v = v > 0.f ? v : 0.f;
-          out[p * COUT + co] = f2bf(v);
+          out[q * COUT + co] = f2bf(v);
         }
       }
     }
+  }
+}
+
+// Persistent grid: as many workgroups as fit on the chip at once with the
+// layer's LDS, at most one per tile.
+static unsigned persistent_grid(long long n_tiles, int lds_bytes) {
+  int per_cu = (150 * 1024) / (lds_bytes > 0 ? lds_bytes : 1);
+  per_cu = per_cu < 1 ? 1 : (per_cu > 2 ? 2 : per_cu);  // 1024-thread workgroups
+  const long long cap = 256LL * per_cu;
+  return (unsigned)(n_tiles < cap ? n_tiles : cap);
 }
 
 // ---------------------------------------------------------------------------
 // data gradient: gin = conv^T(gpre), gpre = gout * [out > 0]
-// M = input pixels, N = CIN, K = 9 * COUT; Wt = [3][3][CIN][COUT]
+// M = input pixels, N = CIN, K = 9 * COUT; Wt = [3][3][CIN][COUT], staged
+// into LDS as rows of K per input channel; tiles and persistence as the
+// forward pass.
 // ---------------------------------------------------------------------------
+template <int CIN, int COUT>
+struct DgradShape {
+  static constexpr int K = 9 * COUT;
+  static constexpr int LS = K + 8;
+  static constexpr int LDS_BYTES = CIN * LS * 2;
+};
+
 template <int CIN, int COUT, int S>
-__global__ void __launch_bounds__(CT)
+__global__ void __launch_bounds__(FW_THREADS)
 k_conv_dgrad(const uint16_t *__restrict__ gout, const uint16_t *__restrict__ out,
              const uint16_t *__restrict__ Wt, uint16_t *__restrict__ gin, int B, int H, int Wd) {
+  using SH = DgradShape<CIN, COUT>;
   constexpr int NT = CIN / 16;
-  constexpr int CB = COUT / 32;
+  constexpr int CB = COUT / 32, T = 9 * CB;
+  constexpr int LS = SH::LS;
+  __shared__ __attribute__((aligned(16))) uint16_t Wl[CIN * LS];
+  for (int e = threadIdx.x; e < 9 * CIN * (COUT / 8); e += FW_THREADS) {
+    const int co8 = e % (COUT / 8), r = e / (COUT / 8);  // r = tap * CIN + ci
+    const int tap = r / CIN, ci = r % CIN;
+    *reinterpret_cast<uint4 *>(&Wl[ci * LS + tap * COUT + 8 * co8]) =
+        *reinterpret_cast<const uint4 *>(Wt + (long long)r * COUT + 8 * co8);
+  }
+  __syncthreads();
   const int Ho = (H - 1) / S + 1, Wo = (Wd - 1) / S + 1;
   const long long P = (long long)B * H * Wd;
+  const long long n_tiles = (P + FW_TILE - 1) / FW_TILE;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long long pbase = ((long long)blockIdx.x * 4 + wave) * 32;
-  if (pbase >= P) return;
-  int pb[2], py[2], px[2];
-  bool pv[2];
+  const int kq = lane >> 4, r16 = lane & 15;
+  for (long long tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const long long pbase = tile * FW_TILE + wave * 16;
+    if (pbase >= P) continue;
+    const long long p = pbase + r16;
+    const bool pv = p < P;
+    const long long pp = pv ? p : 0;
+    const int pb = (int)(pp / (H * Wd));
+    const int rr = (int)(pp % (H * Wd));
+    const int py = rr / Wd, px = rr % Wd;
+    f32x4 acc[NT];
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt) {
-    const long long p = pbase + mt * 16 + (lane & 15);
-    pv[mt] = p < P;
-    const long long pp = pv[mt] ? p : 0;
-    pb[mt] = (int)(pp / (H * Wd));
-    const int r = (int)(pp % (H * Wd));
-    py[mt] = r / Wd;
-    px[mt] = r % Wd;
-  }
-  f32x4 acc[2][NT];
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    bf16x8 a[T];
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  const int kq = lane >> 4;
-  for (int t = 0; t < 9 * CB; ++t) {
-    const int tap = t / CB, cb = t % CB;
-    const int ky = tap / 3, kx = tap % 3;
-    const int co0 = cb * 32 + 8 * kq;
-    bf16x8 a[2];
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
-      const int ny = py[mt] + 1 - ky, nx = px[mt] + 1 - kx;  // = oy * S
-      bool ok = pv[mt] && ny >= 0 && nx >= 0 && (ny % S) == 0 && (nx % S) == 0;
+    for (int t = 0; t < T; ++t) {
+      const int tap = t / CB, cb = t % CB;
+      const int ny = py + 1 - tap / 3, nx = px + 1 - tap % 3;  // = oy * S
+      bool ok = pv && ny >= 0 && nx >= 0 && (ny % S) == 0 && (nx % S) == 0;
       const int oy = ny / S, ox = nx / S;
       ok = ok && oy < Ho && ox < Wo;
       if (ok) {
-        const long long o = (((long long)pb[mt] * Ho + oy) * Wo + ox) * COUT + co0;
+        const long long o = (((long long)pb * Ho + oy) * Wo + ox) * COUT + cb * 32 + 8 * kq;
         V8 g, y;
         g.u = *reinterpret_cast<const uint4 *>(gout + o);
         y.u = *reinterpret_cast<const uint4 *>(out + o);
 #pragma unroll
         for (int i = 0; i < 8; ++i)
           if (!(bf2f(y.h[i]) > 0.f)) g.h[i] = 0;
-        a[mt] = g.v;
+        a[t] = g.v;
       } else {
-        a[mt] = zero8();
+        a[t] = zero8();
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int tap = t / CB, cb = t % CB;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const bf16x8 b = *reinterpret_cast<const bf16x8 *>(
+            &Wl[(nt * 16 + r16) * LS + tap * COUT + cb * 32 + 8 * kq]);
+        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], b, acc[nt], 0, 0, 0);
       }
     }
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-      const int ci = nt * 16 + (lane & 15);
-      const bf16x8 b = load8(Wt + ((long long)tap * CIN + ci) * COUT + co0);
-#pragma unroll
-      for (int mt = 0; mt < 2; ++mt)
-        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b, acc[mt][nt], 0, 0, 0);
-    }
-  }
-#pragma unroll
-  for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const int ci = nt * 16 + (lane & 15);
+      const int ci = nt * 16 + r16;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const long long p = pbase + mt * 16 + 4 * kq + i;
-        if (p < P) gin[p * CIN + ci] = f2bf(acc[mt][nt][i]);
+        const long long q = pbase + 4 * kq + i;
+        if (q < P) gin[q * CIN + ci] = f2bf(acc[nt][i]);
       }
     }
+  }
 }
 
 // ---------------------------------------------------------------------------
 // weight gradient: dW[co][tap][ci] = sum_p gpre[p][co] in[p @ tap][ci]
-// One workgroup = one chunk of WCH output pixels and one tap (all taps when
-// CIN < 32: K columns = (tap, ci) flattened, padded to a multiple of 16).
-// Partial sums per chunk go to part[chunk][...]; a second kernel adds the
-// chunks in order (deterministic).
+// GEMM with M = COUT, N = taps x NC columns (tap, input channel; when
+// CIN < 32 the columns are (tap, ci) flattened and padded to 32 with one
+// "tap"), K = output pixels.  One workgroup (16 waves) takes a chunk of
+// pixels and every (co, tap, ci) tile.  Per step, each of KSPLIT wave groups
+// stages 32 pixels into LDS, transposed so that both MFMA operands are
+// 16-byte reads of 8 consecutive pixels: G[co][px] (gpre, with the ReLU mask)
+// and I[tap][column][px] (the input at every tap, zero outside the image).
+// The waves of a group share the group's tiles; each group writes its own
+// partial block (row chunk * KSPLIT + group), which k_wgrad_reduce adds in
+// order (deterministic).
 // ---------------------------------------------------------------------------
-constexpr int WCH = 1024;
-
 template <int CIN>
 struct WCols {
   static constexpr int n = CIN >= 32 ? CIN : ((9 * CIN + 15) / 16) * 16;
 };
 
+template <int CIN, int COUT>
+struct WgradShape {
+  static constexpr int NC = WCols<CIN>::n;
+  static constexpr int TAPS = CIN >= 32 ? 9 : 1;
+  static constexpr int TM = COUT / 16, TN = TAPS * NC / 16, TILES = TM * TN;
+  static constexpr int KSPLIT = TILES >= 144 ? 1 : TILES >= 72 ? 2 : TILES >= 36 ? 4 : 16;
+  static constexpr int WPG = 16 / KSPLIT;                 // waves per group
+  static constexpr int TPW = (TILES + WPG - 1) / WPG;     // tiles per wave
+  static constexpr int PS = 40;                           // LDS row stride (32 pixels + 8)
+  static constexpr int G_ELEMS = COUT * PS, I_ELEMS = TAPS * NC * PS;
+  static constexpr long long REC = (long long)TAPS * COUT * NC;  // floats per partial block
+};
+
+// Pixels per chunk (a multiple of 32 KSPLIT), chosen for about 256 chunks.
+static long long wgrad_chunk(long long P, int ksplit) {
+  const long long step = 32LL * ksplit;
+  long long c = (P + 255) / 256;
+  c = (c + step - 1) / step * step;
+  return c < step ? step : c;
+}
+
 template <int CIN, int COUT, int S>
-__global__ void __launch_bounds__(CT)
+__global__ void __launch_bounds__(1024)
 k_conv_wgrad(const uint16_t *__restrict__ gout, const uint16_t *__restrict__ out,
              const uint16_t *__restrict__ in, float *__restrict__ part,
-             float *__restrict__ bpart, int B, int H, int Wd) {
-  constexpr int NC = WCols<CIN>::n;      // columns of this workgroup's dW block
-  constexpr int TM = COUT / 16, TN = NC / 16;
-  constexpr int TILES = TM * TN;
-  constexpr int TPW = (TILES + 3) / 4;   // tiles per wave
-  __shared__ uint16_t Lg[32][COUT + 8];  // gpre tile (pixel-major), padded rows
-  __shared__ uint16_t Li[32][NC + 8];    // input tile at this tap
+             float *__restrict__ bpart, int B, int H, int Wd, long long wch) {
+  using SH = WgradShape<CIN, COUT>;
+  constexpr int NC = SH::NC, TAPS = SH::TAPS, TN = SH::TN, TILES = SH::TILES;
+  constexpr int KSPLIT = SH::KSPLIT, WPG = SH::WPG, TPW = SH::TPW, PS = SH::PS;
+  __shared__ __attribute__((aligned(16))) uint16_t Gs[KSPLIT * SH::G_ELEMS];
+  __shared__ __attribute__((aligned(16))) uint16_t Is[KSPLIT * SH::I_ELEMS];
   const int Ho = (H - 1) / S + 1, Wo = (Wd - 1) / S + 1;
   const long long P = (long long)B * Ho * Wo;
-  const int chunk = blockIdx.x;
-  const int tap = CIN >= 32 ? blockIdx.y : 0;
-  const int ky = tap / 3, kx = tap % 3;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, kq = lane >> 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kq = lane >> 4, r16 = lane & 15;
+  const int kg = wave / WPG, wl = wave % WPG;
+  if (CIN < 32) {
+    // the padding columns (tap, ci) >= 9 CIN stay zero
+    for (int e = threadIdx.x; e < KSPLIT * SH::I_ELEMS; e += 1024) Is[e] = 0;
+    __syncthreads();
+  }
   f32x4 acc[TPW];
 #pragma unroll
   for (int q = 0; q < TPW; ++q) acc[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  float bsum = 0.f;  // bias gradient partial (thread < COUT), tap 0 only
-  const long long p0 = (long long)chunk * WCH;
-  for (int step = 0; step < WCH / 32; ++step) {
-    const long long ps = p0 + step * 32;
-    if (ps >= P) break;
-    // stage gpre: 32 pixels x COUT
-    for (int e = threadIdx.x; e < 32 * COUT; e += CT) {
-      const int r = e / COUT, c = e % COUT;
+  float bsum = 0.f;  // bias partial of (group kg, channel wl * 64 + lane) when < COUT
+  const long long p0 = (long long)blockIdx.x * wch;
+  const long long p1 = p0 + wch < P ? p0 + wch : P;
+  for (long long ps = p0; ps < p1; ps += 32 * KSPLIT) {
+    // stage gpre (masked by the ReLU) transposed: Gs[g][co][px]
+    for (int e = threadIdx.x; e < KSPLIT * 32 * (COUT / 8); e += 1024) {
+      const int c8 = e % (COUT / 8), r = e / (COUT / 8);  // r = g * 32 + px
+      const int g = r / 32, px = r % 32;
       const long long p = ps + r;
-      uint16_t v = 0;
-      if (p < P) {
-        const uint16_t y = out[p * COUT + c];
-        if (bf2f(y) > 0.f) v = gout[p * COUT + c];
+      V8 gv;
+      gv.u = make_uint4(0, 0, 0, 0);
+      if (p < p1) {
+        V8 y;
+        gv.u = *reinterpret_cast<const uint4 *>(gout + p * COUT + 8 * c8);
+        y.u = *reinterpret_cast<const uint4 *>(out + p * COUT + 8 * c8);
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (!(bf2f(y.h[i]) > 0.f)) gv.h[i] = 0;
       }
-      Lg[r][c] = v;
+      uint16_t *dst = Gs + g * SH::G_ELEMS + (8 * c8) * PS + px;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) dst[i * PS] = gv.h[i];
     }
-    // stage the input: 32 pixels x NC columns
-    for (int e = threadIdx.x; e < 32 * NC; e += CT) {
-      const int r = e / NC, c = e % NC;
-      const long long p = ps + r;
-      uint16_t v = 0;
-      if (p < P) {
-        const int b = (int)(p / (Ho * Wo));
-        const int rr = (int)(p % (Ho * Wo));
-        const int oy = rr / Wo, ox = rr % Wo;
-        int ci = c, tky = ky, tkx = kx;
-        bool okc = true;
-        if (CIN < 32) {
-          okc = c < 9 * CIN;
-          const int t2 = c / CIN;
-          ci = c % CIN;
-          tky = t2 / 3;
-          tkx = t2 % 3;
+    // stage the input at every tap transposed: Is[g][tap][col][px]
+    if constexpr (CIN >= 32) {
+      for (int e = threadIdx.x; e < KSPLIT * 9 * 32 * (CIN / 8); e += 1024) {
+        const int c8 = e % (CIN / 8), r = e / (CIN / 8);  // r = (g * 9 + tap) * 32 + px
+        const int px = r % 32, gt = r / 32;
+        const int tap = gt % 9, g = gt / 9;
+        const long long p = ps + g * 32 + px;
+        V8 iv;
+        iv.u = make_uint4(0, 0, 0, 0);
+        if (p < p1) {
+          const int b = (int)(p / (Ho * Wo));
+          const int rr = (int)(p % (Ho * Wo));
+          const int iy = (rr / Wo) * S + tap / 3 - 1, ix = (rr % Wo) * S + tap % 3 - 1;
+          if (iy >= 0 && iy < H && ix >= 0 && ix < Wd)
+            iv.u = *reinterpret_cast<const uint4 *>(in + (((long long)b * H + iy) * Wd + ix) * CIN + 8 * c8);
         }
-        const int iy = oy * S + tky - 1, ix = ox * S + tkx - 1;
-        if (okc && iy >= 0 && iy < H && ix >= 0 && ix < Wd)
-          v = in[(((long long)b * H + iy) * Wd + ix) * CIN + ci];
+        uint16_t *dst = Is + g * SH::I_ELEMS + (tap * NC + 8 * c8) * PS + px;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) dst[i * PS] = iv.h[i];
       }
-      Li[r][c] = v;
+    } else {
+      for (int e = threadIdx.x; e < KSPLIT * 32 * 9; e += 1024) {
+        const int tap = e % 9, r = e / 9;  // r = g * 32 + px
+        const int g = r / 32, px = r % 32;
+        const long long p = ps + r;
+        uint16_t v[CIN];
+#pragma unroll
+        for (int c = 0; c < CIN; ++c) v[c] = 0;
+        if (p < p1) {
+          const int b = (int)(p / (Ho * Wo));
+          const int rr = (int)(p % (Ho * Wo));
+          const int iy = (rr / Wo) * S + tap / 3 - 1, ix = (rr % Wo) * S + tap % 3 - 1;
+          if (iy >= 0 && iy < H && ix >= 0 && ix < Wd)
+#pragma unroll
+            for (int c = 0; c < CIN; ++c) v[c] = in[(((long long)b * H + iy) * Wd + ix) * CIN + c];
+        }
+#pragma unroll
+        for (int c = 0; c < CIN; ++c) Is[g * SH::I_ELEMS + (tap * CIN + c) * PS + px] = v[c];
+      }
     }
     __syncthreads();
-    if (tap == 0 && threadIdx.x < COUT) {
-      for (int r = 0; r < 32; ++r) bsum += bf2f(Lg[r][threadIdx.x]);
+    {
+      const int co = wl * 64 + lane;
+      if (co < COUT) {
+        const uint16_t *gr = Gs + kg * SH::G_ELEMS + co * PS;
+        for (int px = 0; px < 32; ++px) bsum += bf2f(gr[px]);
+      }
     }
 #pragma unroll
     for (int q = 0; q < TPW; ++q) {
-      const int tile = wave * TPW + q;
-      if (tile < TILES) {
-        const int tm = tile / TN, tn = tile % TN;
-        V8 a, b;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          a.h[i] = Lg[8 * kq + i][tm * 16 + (lane & 15)];
-          b.h[i] = Li[8 * kq + i][tn * 16 + (lane & 15)];
-        }
-        acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc[q], 0, 0, 0);
+      const int t = wl * TPW + q;
+      if (t < TILES) {
+        const int tm = t / TN, tn = t % TN;
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(
+            Gs + kg * SH::G_ELEMS + (tm * 16 + r16) * PS + 8 * kq);
+        const bf16x8 b = *reinterpret_cast<const bf16x8 *>(
+            Is + kg * SH::I_ELEMS + (tn * 16 + r16) * PS + 8 * kq);
+        acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[q], 0, 0, 0);
       }
     }
     __syncthreads();
   }
-  // partial block: part[chunk][tap][co][col]
-  const int taps = CIN >= 32 ? 9 : 1;
-  float *dst = part + ((long long)chunk * taps + tap) * COUT * NC;
+  // partial block of this group: part[row][tap][co][col], row = chunk * KSPLIT + group
+  const long long row = (long long)blockIdx.x * KSPLIT + kg;
+  float *dst = part + row * SH::REC;
 #pragma unroll
   for (int q = 0; q < TPW; ++q) {
-    const int tile = wave * TPW + q;
-    if (tile < TILES) {
-      const int tm = tile / TN, tn = tile % TN;
+    const int t = wl * TPW + q;
+    if (t < TILES) {
+      const int tm = t / TN, tn = t % TN;
+      const int tap = tn / (NC / 16), col = (tn % (NC / 16)) * 16 + r16;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) dst[(tm * 16 + 4 * kq + i) * NC + tn * 16 + (lane & 15)] = acc[q][i];
+      for (int i = 0; i < 4; ++i)
+        dst[((long long)tap * COUT + tm * 16 + 4 * kq + i) * NC + col] = acc[q][i];
     }
   }
-  if (tap == 0 && threadIdx.x < COUT) bpart[(long long)chunk * COUT + threadIdx.x] = bsum;
+  {
+    const int co = wl * 64 + lane;
+    if (co < COUT) bpart[row * COUT + co] = bsum;
+  }
 }
 
-// dW[co][tap][ci] (FP32, layout of the master weights) = sum over chunks.
+// dW[co][tap][ci] (FP32, layout of the master weights) and db[co] = sums over
+// the chunks' partial blocks.  A workgroup of 16 waves takes 64 consecutive
+// outputs (one per lane, coalesced loads); wave g sums chunks g, g + 16, ...
+// in order (FP64), and the 16 partial sums are added in wave order: the
+// result does not depend on the launch.  Outputs past COUT * 9 CIN are the
+// bias entries (partial record stride COUT).
+constexpr int RED_WAVES = 16;
+
 template <int CIN, int COUT>
-__global__ void k_wgrad_reduce(const float *__restrict__ part, const float *__restrict__ bpart,
-                               int n_chunks, float *__restrict__ dW, float *__restrict__ db) {
+__global__ void __launch_bounds__(RED_WAVES * 64)
+k_wgrad_reduce(const float *__restrict__ part, const float *__restrict__ bpart, int n_chunks,
+               float *__restrict__ dW, float *__restrict__ db) {
   constexpr int NC = WCols<CIN>::n;
   constexpr int taps = CIN >= 32 ? 9 : 1;
-  const int K = 9 * CIN;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int K = 9 * CIN;
+  constexpr long long REC = (long long)taps * COUT * NC;
+  __shared__ double red[RED_WAVES][64];
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int idx = blockIdx.x * 64 + lane;
+  double sum = 0;
   if (idx < COUT * K) {
     const int co = idx / K, k = idx % K;
     const int tap = CIN >= 32 ? k / CIN : 0;
     const int col = CIN >= 32 ? k % CIN : k;
-    double s = 0;
-    for (int c = 0; c < n_chunks; ++c)
-      s += part[(((long long)c * taps + tap) * COUT + co) * NC + col];
-    dW[idx] = (float)s;
+    const float *src = part + ((long long)tap * COUT + co) * NC + col;
+    for (int c = g; c < n_chunks; c += RED_WAVES) sum += src[c * REC];
+  } else if (idx < COUT * K + COUT) {
+    const float *src = bpart + (idx - COUT * K);
+    for (int c = g; c < n_chunks; c += RED_WAVES) sum += src[(long long)c * COUT];
   }
-  if (idx < COUT) {
-    double s = 0;
-    for (int c = 0; c < n_chunks; ++c) s += bpart[(long long)c * COUT + idx];
-    db[idx] = (float)s;
+  red[g][lane] = sum;
+  __syncthreads();
+  if (g == 0) {
+    double t = 0;
+    for (int w = 0; w < RED_WAVES; ++w) t += red[w][lane];
+    if (idx < COUT * K) dW[idx] = (float)t;
+    else if (idx < COUT * K + COUT) db[idx - COUT * K] = (float)t;
   }
 }
 
@@ -502,13 +606,20 @@ __global__ void k_head_wgrad(const uint16_t *__restrict__ act, const float *__re
 }
 
 // sum of per-sample partials (fixed order)
-__global__ void k_sum_rows(const float *__restrict__ part, int rows, int cols,
-                           float *__restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
+// out[0] = sum of x[0..n) by one workgroup: thread t sums t, t + 1024, ...
+// in order (FP64), then a fixed tree over the threads.
+__global__ void __launch_bounds__(1024) k_sum_all(const float *__restrict__ x, int n,
+                                                  float *__restrict__ out) {
+  __shared__ double red[1024];
   double s = 0;
-  for (int r = 0; r < rows; ++r) s += part[(long long)r * cols + c];
-  out[c] = (float)s;
+  for (int i = threadIdx.x; i < n; i += 1024) s += x[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = (float)red[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -571,11 +682,12 @@ extern "C" pvr_status pvr_cnn_conv_fwd(const uint16_t *in, const uint16_t *w, co
   if (!in || !w || !bias || !out || B <= 0 || H <= 0 || W <= 0)
     return fail(PVR_EINVAL, "pvr_cnn_conv_fwd: invalid argument");
   const long long P = (long long)B * out_size(H, stride) * out_size(W, stride);
-  const dim3 grid((unsigned)((P + 127) / 128));
+  const long long n_tiles = (P + FW_TILE - 1) / FW_TILE;
 #define LAUNCH(CI, CO, ST)                                                                     \
   if (cin == CI && cout == CO && stride == ST) {                                               \
-    hipLaunchKernelGGL((k_conv_fwd<CI, CO, ST>), grid, dim3(CT), 0, stream, in, w, bias, out, \
-                       B, H, W, relu);                                                         \
+    const dim3 grid(persistent_grid(n_tiles, FwdShape<CI, CO>::LDS_BYTES));                    \
+    hipLaunchKernelGGL((k_conv_fwd<CI, CO, ST>), grid, dim3(FW_THREADS), 0, stream, in, w,     \
+                       bias, out, B, H, W, relu);                                              \
     HIP_TRY(hipGetLastError());                                                                \
     return PVR_OK;                                                                             \
   }
@@ -593,10 +705,12 @@ extern "C" pvr_status pvr_cnn_conv_dgrad(const uint16_t *gout, const uint16_t *o
   PVR_API_BEGIN();
   if (!gout || !out || !wt || !gin || B <= 0) return fail(PVR_EINVAL, "pvr_cnn_conv_dgrad: invalid argument");
   const long long P = (long long)B * H * W;
-  const dim3 grid((unsigned)((P + 127) / 128));
+  const long long n_tiles = (P + FW_TILE - 1) / FW_TILE;
 #define LAUNCH(CI, CO, ST)                                                                       \
   if (cin == CI && cout == CO && stride == ST && CI >= 16) {                                     \
-    hipLaunchKernelGGL((k_conv_dgrad<(CI >= 16 ? CI : 16), CO, ST>), grid, dim3(CT), 0, stream, \
+    constexpr int CIX = CI >= 16 ? CI : 16;                                                      \
+    const dim3 grid(persistent_grid(n_tiles, DgradShape<CIX, CO>::LDS_BYTES));                   \
+    hipLaunchKernelGGL((k_conv_dgrad<CIX, CO, ST>), grid, dim3(FW_THREADS), 0, stream,           \
                        gout, out, wt, gin, B, H, W);                                             \
     HIP_TRY(hipGetLastError());                                                                  \
     return PVR_OK;                                                                               \
@@ -608,13 +722,26 @@ extern "C" pvr_status pvr_cnn_conv_dgrad(const uint16_t *gout, const uint16_t *o
   PVR_API_END();
 }
 
+// Rows (partial blocks) of the weight-gradient scratch for a layer shape.
+template <int CIN, int COUT>
+static long long wgrad_rows(long long P, long long *wch) {
+  using SH = WgradShape<CIN, COUT>;
+  const long long c = wgrad_chunk(P, SH::KSPLIT);
+  if (wch) *wch = c;
+  return (P + c - 1) / c * SH::KSPLIT;
+}
+
 extern "C" int64_t pvr_cnn_wgrad_scratch(int32_t B, int32_t H, int32_t W, int32_t cin,
                                          int32_t cout, int32_t stride) {
   const long long P = (long long)B * out_size(H, stride) * out_size(W, stride);
-  const long long chunks = (P + WCH - 1) / WCH;
-  const int nc = cin >= 32 ? cin : ((9 * cin + 15) / 16) * 16;
-  const int taps = cin >= 32 ? 9 : 1;
-  return (chunks * taps * cout * nc + chunks * cout) * (long long)sizeof(float);
+#define SCR(CI, CO, ST)                                                                  \
+  if (cin == CI && cout == CO) {                                                         \
+    using SH = WgradShape<CI, CO>;                                                       \
+    return wgrad_rows<CI, CO>(P, nullptr) * (SH::REC + CO) * (long long)sizeof(float);  \
+  }
+  CONV_CASES(SCR)
+#undef SCR
+  return 0;
 }
 
 extern "C" pvr_status pvr_cnn_conv_wgrad(const uint16_t *gout, const uint16_t *out,
@@ -625,19 +752,20 @@ extern "C" pvr_status pvr_cnn_conv_wgrad(const uint16_t *gout, const uint16_t *o
   if (!gout || !out || !in || !scratch || !dw || !db || B <= 0)
     return fail(PVR_EINVAL, "pvr_cnn_conv_wgrad: invalid argument");
   const long long P = (long long)B * out_size(H, stride) * out_size(W, stride);
-  const int chunks = (int)((P + WCH - 1) / WCH);
-  const int nc = cin >= 32 ? cin : ((9 * cin + 15) / 16) * 16;
-  const int taps = cin >= 32 ? 9 : 1;
-  float *part = scratch;
-  float *bpart = scratch + (long long)chunks * taps * cout * nc;
-  const int nred = cout * 9 * cin;
+  const int nred = cout * 9 * cin + cout;  // weights, then biases
 #define LAUNCH(CI, CO, ST)                                                                       \
   if (cin == CI && cout == CO && stride == ST) {                                                 \
-    hipLaunchKernelGGL((k_conv_wgrad<CI, CO, ST>), dim3(chunks, taps), dim3(CT), 0, stream, gout, \
-                       out, in, part, bpart, B, H, W);                                           \
+    using SH = WgradShape<CI, CO>;                                                               \
+    long long wch = 0;                                                                           \
+    const long long rows = wgrad_rows<CI, CO>(P, &wch);                                          \
+    const int chunks = (int)(rows / SH::KSPLIT);                                                 \
+    float *part = scratch;                                                                       \
+    float *bpart = scratch + rows * SH::REC;                                                     \
+    hipLaunchKernelGGL((k_conv_wgrad<CI, CO, ST>), dim3(chunks), dim3(1024), 0, stream, gout,    \
+                       out, in, part, bpart, B, H, W, wch);                                      \
     HIP_TRY(hipGetLastError());                                                                  \
-    hipLaunchKernelGGL((k_wgrad_reduce<CI, CO>), dim3((nred + 255) / 256), dim3(256), 0, stream, \
-                       part, bpart, chunks, dw, db);                                             \
+    hipLaunchKernelGGL((k_wgrad_reduce<CI, CO>), dim3((nred + 63) / 64), dim3(RED_WAVES * 64), 0, \
+                       stream, part, bpart, (int)rows, dw, db);                                  \
     HIP_TRY(hipGetLastError());                                                                  \
     return PVR_OK;                                                                               \
   }
@@ -681,7 +809,7 @@ extern "C" pvr_status pvr_cnn_head(const uint16_t *act, int32_t B, int32_t hw, c
                      loss_w, pred, lp, dp, gact, 1.0f / B);
   HIP_TRY(hipGetLastError());
   if (target) {
-    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(64), 0, stream, lp, B * 6, 1, loss);
+    hipLaunchKernelGGL(k_sum_all, dim3(1), dim3(1024), 0, stream, lp, B * 6, loss);
     hipLaunchKernelGGL(k_head_wgrad, dim3((n_in + 6 + 255) / 256), dim3(256), 0, stream, act, dp,
                        B, n_in, dwfc, dbfc);
     HIP_TRY(hipGetLastError());
