@@ -74,7 +74,7 @@ struct FwdShape {
   static constexpr int K = 9 * CIN;
   static constexpr int KP = K < 32 ? 32 : K;  // K padded to one MFMA step when CIN < 32
   static constexpr int LS = KP + 8;           // LDS row stride (elements), 16-byte rows
-  static constexpr int LDS_BYTES = COUT * LS * 2;
+  static constexpr int LDS_BYTES = COUT * LS * 2 + (FW_THREADS / 64) * 16 * (COUT + 8) * 2;
 };
 
 template <int CIN, int COUT, int S>
@@ -85,6 +85,7 @@ k_conv_fwd(const uint16_t *__restrict__ in, const uint16_t *__restrict__ W,
   using SH = FwdShape<CIN, COUT>;
   constexpr int NT = COUT / 16, K = SH::K, KP = SH::KP, LS = SH::LS;
   __shared__ __attribute__((aligned(16))) uint16_t Wl[COUT * LS];
+  __shared__ __attribute__((aligned(16))) uint16_t Os[(FW_THREADS / 64) * 16 * (COUT + 8)];
   if constexpr (K % 8 == 0) {
     for (int e = threadIdx.x; e < COUT * (K / 8); e += FW_THREADS) {
       const int co = e / (K / 8), k8 = e % (K / 8);
@@ -103,9 +104,11 @@ k_conv_fwd(const uint16_t *__restrict__ in, const uint16_t *__restrict__ W,
   const long long n_tiles = (P + FW_TILE - 1) / FW_TILE;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kq = lane >> 4, r16 = lane & 15;
+  uint16_t *Ow = Os + wave * 16 * (COUT + 8);  // this wave's 16 pixels x COUT
   for (long long tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const long long pbase = tile * FW_TILE + wave * 16;
-    if (pbase >= P) continue;
+    // every wave runs every tile (the barriers below are workgroup-wide)
+    const bool active = pbase < P;
     const long long p = pbase + r16;
     const bool pv = p < P;
     const long long pp = pv ? p : 0;
@@ -140,17 +143,31 @@ k_conv_fwd(const uint16_t *__restrict__ in, const uint16_t *__restrict__ W,
     } else {
       // K = 9 CIN <= 32: the whole K in one step, zero padded
       V8 ta;
+      if constexpr (CIN == 2) {
+        // lane group kq holds taps 4 kq .. 4 kq + 3, both channels (one dword each)
+        uint32_t d[4];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int k = 8 * kq + i;
-        uint16_t v = 0;
-        if (k < K && pv) {
-          const int tap = k / CIN, ci = k % CIN;
+        for (int j = 0; j < 4; ++j) {
+          const int tap = 4 * kq + j;
           const int iy = py * S + tap / 3 - 1, ix = px * S + tap % 3 - 1;
-          if (iy >= 0 && iy < H && ix >= 0 && ix < Wd)
-            v = in[(((long long)pb * H + iy) * Wd + ix) * CIN + ci];
+          d[j] = (pv && tap < 9 && iy >= 0 && iy < H && ix >= 0 && ix < Wd)
+                     ? *reinterpret_cast<const uint32_t *>(in + (((long long)pb * H + iy) * Wd + ix) * 2)
+                     : 0u;
         }
-        ta.h[i] = v;
+        ta.u = make_uint4(d[0], d[1], d[2], d[3]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int k = 8 * kq + i;
+          uint16_t v = 0;
+          if (k < K && pv) {
+            const int tap = k / CIN, ci = k % CIN;
+            const int iy = py * S + tap / 3 - 1, ix = px * S + tap % 3 - 1;
+            if (iy >= 0 && iy < H && ix >= 0 && ix < Wd)
+              v = in[(((long long)pb * H + iy) * Wd + ix) * CIN + ci];
+          }
+          ta.h[i] = v;
+        }
       }
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
@@ -158,20 +175,31 @@ k_conv_fwd(const uint16_t *__restrict__ in, const uint16_t *__restrict__ W,
         acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ta.v, b, acc[nt], 0, 0, 0);
       }
     }
+    // bias, ReLU, BF16 into the wave's LDS tile [pixel][channel], then whole
+    // 16-byte rows of 8 channels to memory
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const int co = nt * 16 + r16;
       const float bb = bias[co];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const long long q = pbase + 4 * kq + i;
-        if (q < P) {
-          float v = acc[nt][i] + bb;
-          if (relu) v = v > 0.f ? v : 0.f;
-          out[q * COUT + co] = f2bf(v);
-        }
+        float v = acc[nt][i] + bb;
+        if (relu) v = v > 0.f ? v : 0.f;
+        Ow[(4 * kq + i) * (COUT + 8) + co] = f2bf(v);
       }
     }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < (16 * COUT / 8 + 63) / 64; ++j) {
+        const int c = lane + 64 * j;
+        const int q = c / (COUT / 8), c8 = c % (COUT / 8);
+        if (c < 16 * COUT / 8 && pbase + q < P)
+          *reinterpret_cast<uint4 *>(out + (pbase + q) * COUT + 8 * c8) =
+              *reinterpret_cast<const uint4 *>(&Ow[q * (COUT + 8) + 8 * c8]);
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -441,43 +469,60 @@ k_conv_wgrad(const uint16_t *__restrict__ gout, const uint16_t *__restrict__ out
 }
 
 // dW[co][tap][ci] (FP32, layout of the master weights) and db[co] = sums over
-// the chunks' partial blocks.  A workgroup of 16 waves takes 64 consecutive
-// outputs (one per lane, coalesced loads); wave g sums chunks g, g + 16, ...
-// in order (FP64), and the 16 partial sums are added in wave order: the
-// result does not depend on the launch.  Outputs past COUT * 9 CIN are the
-// bias entries (partial record stride COUT).
+// the partial blocks (rows).  A workgroup of 16 waves takes 64 consecutive
+// outputs (one per lane, coalesced loads) and a range of up to RED_ROWS rows;
+// wave g sums rows g, g + 16, ... of the range in order (FP64) and the 16
+// partial sums are added in wave order.  With one range the result is
+// written directly; with several, each range's sums go to `partial` and
+// k_wgrad_finish adds them in range order: the result does not depend on the
+// launch.  Outputs past COUT * 9 CIN are the bias entries (row stride COUT).
 constexpr int RED_WAVES = 16;
+constexpr int RED_ROWS = 256;
 
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(RED_WAVES * 64)
-k_wgrad_reduce(const float *__restrict__ part, const float *__restrict__ bpart, int n_chunks,
-               float *__restrict__ dW, float *__restrict__ db) {
+k_wgrad_reduce(const float *__restrict__ part, const float *__restrict__ bpart, int n_rows,
+               float *__restrict__ dW, float *__restrict__ db, double *__restrict__ partial) {
   constexpr int NC = WCols<CIN>::n;
   constexpr int taps = CIN >= 32 ? 9 : 1;
   constexpr int K = 9 * CIN;
+  constexpr int NRED = COUT * K + COUT;
   constexpr long long REC = (long long)taps * COUT * NC;
   __shared__ double red[RED_WAVES][64];
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int idx = blockIdx.x * 64 + lane;
+  const int r0 = blockIdx.y * RED_ROWS;
+  const int r1 = n_rows < r0 + RED_ROWS ? n_rows : r0 + RED_ROWS;
   double sum = 0;
   if (idx < COUT * K) {
     const int co = idx / K, k = idx % K;
     const int tap = CIN >= 32 ? k / CIN : 0;
     const int col = CIN >= 32 ? k % CIN : k;
     const float *src = part + ((long long)tap * COUT + co) * NC + col;
-    for (int c = g; c < n_chunks; c += RED_WAVES) sum += src[c * REC];
-  } else if (idx < COUT * K + COUT) {
+    for (int c = r0 + g; c < r1; c += RED_WAVES) sum += src[c * REC];
+  } else if (idx < NRED) {
     const float *src = bpart + (idx - COUT * K);
-    for (int c = g; c < n_chunks; c += RED_WAVES) sum += src[(long long)c * COUT];
+    for (int c = r0 + g; c < r1; c += RED_WAVES) sum += src[(long long)c * COUT];
   }
   red[g][lane] = sum;
   __syncthreads();
-  if (g == 0) {
+  if (g == 0 && idx < NRED) {
     double t = 0;
     for (int w = 0; w < RED_WAVES; ++w) t += red[w][lane];
-    if (idx < COUT * K) dW[idx] = (float)t;
-    else if (idx < COUT * K + COUT) db[idx - COUT * K] = (float)t;
+    if (gridDim.y > 1) partial[(long long)blockIdx.y * NRED + idx] = t;
+    else if (idx < COUT * K) dW[idx] = (float)t;
+    else db[idx - COUT * K] = (float)t;
   }
+}
+
+__global__ void k_wgrad_finish(const double *__restrict__ partial, int ranges, int n_w, int nred,
+                               float *__restrict__ dW, float *__restrict__ db) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nred) return;
+  double t = 0;
+  for (int r = 0; r < ranges; ++r) t += partial[(long long)r * nred + idx];
+  if (idx < n_w) dW[idx] = (float)t;
+  else db[idx - n_w] = (float)t;
 }
 
 // ---------------------------------------------------------------------------
@@ -583,25 +628,41 @@ k_head(const uint16_t *__restrict__ act, int n_in, const float *__restrict__ Wfc
   }
 }
 
-// dL/dWfc[e][k] = sum_b act[b][e] dp[b][k] (samples in order), dL/dbfc[k] =
-// sum_b dp[b][k]; one lane per input e (lanes n_in.. n_in + 5 take the bias).
-__global__ void k_head_wgrad(const uint16_t *__restrict__ act, const float *__restrict__ dp,
-                             int B, int n_in, float *__restrict__ dW, float *__restrict__ db) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+// dL/dWfc[e][k] = sum_b act[b][e] dp[b][k], dL/dbfc[k] = sum_b dp[b][k].  A
+// workgroup of 16 waves takes 64 inputs e (one per lane; the last lanes past
+// n_in take the bias); wave g sums the samples b = g, g + 16, ... in order and
+// the 16 partial sums are added in wave order (fixed summation order).
+__global__ void __launch_bounds__(RED_WAVES * 64)
+k_head_wgrad(const uint16_t *__restrict__ act, const float *__restrict__ dp, int B, int n_in,
+             float *__restrict__ dW, float *__restrict__ db) {
+  __shared__ float red[RED_WAVES][64][6];
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
+  float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (e < n_in) {
-    float g[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int b = 0; b < B; ++b) {
+    for (int b = g; b < B; b += RED_WAVES) {
       const float x = bf2f(act[(long long)b * n_in + e]);
 #pragma unroll
-      for (int k = 0; k < 6; ++k) g[k] = fmaf(x, dp[b * 6 + k], g[k]);
+      for (int k = 0; k < 6; ++k) acc[k] = fmaf(x, dp[b * 6 + k], acc[k]);
     }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) dW[e * 6 + k] = g[k];
   } else if (e < n_in + 6) {
     const int k = e - n_in;
-    float g = 0.f;
-    for (int b = 0; b < B; ++b) g += dp[b * 6 + k];
-    db[k] = g;
+    for (int b = g; b < B; b += RED_WAVES) acc[0] += dp[b * 6 + k];
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) red[g][lane][k] = acc[k];
+  __syncthreads();
+  if (g == 0) {
+    float t[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int w = 0; w < RED_WAVES; ++w)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) t[k] += red[w][lane][k];
+    if (e < n_in) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) dW[e * 6 + k] = t[k];
+    } else if (e < n_in + 6) {
+      db[e - n_in] = t[0];
+    }
   }
 }
 
@@ -737,7 +798,10 @@ extern "C" int64_t pvr_cnn_wgrad_scratch(int32_t B, int32_t H, int32_t W, int32_
 #define SCR(CI, CO, ST)                                                                  \
   if (cin == CI && cout == CO) {                                                         \
     using SH = WgradShape<CI, CO>;                                                       \
-    return wgrad_rows<CI, CO>(P, nullptr) * (SH::REC + CO) * (long long)sizeof(float);  \
+    const long long rows = wgrad_rows<CI, CO>(P, nullptr);                               \
+    const long long ranges = (rows + RED_ROWS - 1) / RED_ROWS;                            \
+    return rows * (SH::REC + CO) * (long long)sizeof(float) +                            \
+           (ranges > 1 ? ranges * (9LL * CI * CO + CO) * (long long)sizeof(double) : 0); \
   }
   CONV_CASES(SCR)
 #undef SCR
@@ -764,9 +828,16 @@ extern "C" pvr_status pvr_cnn_conv_wgrad(const uint16_t *gout, const uint16_t *o
     hipLaunchKernelGGL((k_conv_wgrad<CI, CO, ST>), dim3(chunks), dim3(1024), 0, stream, gout,    \
                        out, in, part, bpart, B, H, W, wch);                                      \
     HIP_TRY(hipGetLastError());                                                                  \
-    hipLaunchKernelGGL((k_wgrad_reduce<CI, CO>), dim3((nred + 63) / 64), dim3(RED_WAVES * 64), 0, \
-                       stream, part, bpart, (int)rows, dw, db);                                  \
+    const int ranges = (int)((rows + RED_ROWS - 1) / RED_ROWS);                                  \
+    double *partial = ranges > 1 ? (double *)(bpart + rows * CO) : nullptr;                      \
+    hipLaunchKernelGGL((k_wgrad_reduce<CI, CO>), dim3((nred + 63) / 64, ranges),                 \
+                       dim3(RED_WAVES * 64), 0, stream, part, bpart, (int)rows, dw, db, partial); \
     HIP_TRY(hipGetLastError());                                                                  \
+    if (ranges > 1) {                                                                            \
+      hipLaunchKernelGGL(k_wgrad_finish, dim3((nred + 255) / 256), dim3(256), 0, stream, partial, \
+                         ranges, nred - CO, nred, dw, db);                                       \
+      HIP_TRY(hipGetLastError());                                                                \
+    }                                                                                            \
     return PVR_OK;                                                                               \
   }
   CONV_CASES(LAUNCH)
@@ -810,8 +881,8 @@ extern "C" pvr_status pvr_cnn_head(const uint16_t *act, int32_t B, int32_t hw, c
   HIP_TRY(hipGetLastError());
   if (target) {
     hipLaunchKernelGGL(k_sum_all, dim3(1), dim3(1024), 0, stream, lp, B * 6, loss);
-    hipLaunchKernelGGL(k_head_wgrad, dim3((n_in + 6 + 255) / 256), dim3(256), 0, stream, act, dp,
-                       B, n_in, dwfc, dbfc);
+    hipLaunchKernelGGL(k_head_wgrad, dim3((n_in + 6 + 63) / 64), dim3(RED_WAVES * 64), 0, stream,
+                       act, dp, B, n_in, dwfc, dbfc);
     HIP_TRY(hipGetLastError());
   }
   return PVR_OK;
