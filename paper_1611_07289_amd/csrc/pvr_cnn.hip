@@ -222,7 +222,7 @@ template <int CIN, int COUT>
 struct DgradShape {
   static constexpr int K = 9 * COUT;
   static constexpr int LS = K + 8;
-  static constexpr int LDS_BYTES = CIN * LS * 2;
+  static constexpr int LDS_BYTES = CIN * LS * 2 + (FW_THREADS / 64) * 16 * (CIN + 8) * 2;
 };
 
 template <int CIN, int COUT, int S>
@@ -234,6 +234,7 @@ k_conv_dgrad(const uint16_t *__restrict__ gout, const uint16_t *__restrict__ out
   constexpr int CB = COUT / 32, T = 9 * CB;
   constexpr int LS = SH::LS;
   __shared__ __attribute__((aligned(16))) uint16_t Wl[CIN * LS];
+  __shared__ __attribute__((aligned(16))) uint16_t Os[(FW_THREADS / 64) * 16 * (CIN + 8)];
   for (int e = threadIdx.x; e < 9 * CIN * (COUT / 8); e += FW_THREADS) {
     const int co8 = e % (COUT / 8), r = e / (COUT / 8);  // r = tap * CIN + ci
     const int tap = r / CIN, ci = r % CIN;
@@ -246,9 +247,11 @@ k_conv_dgrad(const uint16_t *__restrict__ gout, const uint16_t *__restrict__ out
   const long long n_tiles = (P + FW_TILE - 1) / FW_TILE;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kq = lane >> 4, r16 = lane & 15;
+  uint16_t *Ow = Os + wave * 16 * (CIN + 8);  // this wave's 16 pixels x CIN
   for (long long tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const long long pbase = tile * FW_TILE + wave * 16;
-    if (pbase >= P) continue;
+    // every wave runs every tile (the barriers below are workgroup-wide)
+    const bool active = pbase < P;
     const long long p = pbase + r16;
     const bool pv = p < P;
     const long long pp = pv ? p : 0;
@@ -293,11 +296,20 @@ k_conv_dgrad(const uint16_t *__restrict__ gout, const uint16_t *__restrict__ out
     for (int nt = 0; nt < NT; ++nt) {
       const int ci = nt * 16 + r16;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const long long q = pbase + 4 * kq + i;
-        if (q < P) gin[q * CIN + ci] = f2bf(acc[nt][i]);
+      for (int i = 0; i < 4; ++i) Ow[(4 * kq + i) * (CIN + 8) + ci] = f2bf(acc[nt][i]);
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < (16 * CIN / 8 + 63) / 64; ++j) {
+        const int c = lane + 64 * j;
+        const int q = c / (CIN / 8), c8 = c % (CIN / 8);
+        if (c < 16 * CIN / 8 && pbase + q < P)
+          *reinterpret_cast<uint4 *>(gin + (pbase + q) * CIN + 8 * c8) =
+              *reinterpret_cast<const uint4 *>(&Ow[q * (CIN + 8) + 8 * c8]);
       }
     }
+    __syncthreads();
   }
 }
 

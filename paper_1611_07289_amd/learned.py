@@ -48,6 +48,17 @@ def macs_per_pair() -> int:
 N_FC = HW * 64 * 6        # head weights [HW][64][6]
 
 
+def activation_bytes_per_pair() -> int:
+    """Algorithmic memory traffic of one inference pass (BF16): the packed
+    input read once, every layer's output written once and read once by the
+    next layer (the last one by the head)."""
+    h, total = SIDE, 2 * SIDE * SIDE * 2
+    for _, cout, s in LAYERS:
+        h = (h - 1) // s + 1
+        total += 2 * h * h * cout * 2
+    return total
+
+
 def _p(t):
     return None if t is None else t.data_ptr()
 
