@@ -13,6 +13,9 @@ of libpvr.so with inputs resident in HBM.  Reported value: valid patch
 samples processed per second (whole job).
 
 Extra objects on the JSON line:
+  hbm_equivalent  the iteration time against the HBM floor of a stored-weight
+                implementation of the same iteration (bytes it would move /
+                8 TB/s);
   roofline      dominant kernel (k_simulate or k_backproject): algorithmic
                 work per launch / its average duration from the event pairs
                 the library records around each launch on its stream, against
@@ -117,6 +120,20 @@ def nnz_estimate(probs, n_valid):
     vox = abs(np.linalg.det(P.grid.vox2world[:, :3]))
     sig = np.asarray(P.stacks[0].fwhm_mm) / (2 * math.sqrt(2 * math.log(2)))
     return 4.0 / 3.0 * math.pi * 27.0 * float(np.prod(sig)) / vox * n_valid
+
+
+def hbm_equivalent(nnz, n_valid, V, ms_step):
+    """The SR iteration against the memory floor of a stored-weight design:
+    the bytes such an implementation moves per iteration (the PSF weight
+    lists read in both directions at 6 B per nonzero -- FP32 weight and
+    16-bit local index --, 16 B per valid sample for y, e and its re-reads,
+    32 B per voxel for X, num, den and X') over the chip's 8 TB/s, as a
+    fraction of the measured iteration time.  This path stores no weights,
+    so the figure is a like-for-like time budget, not a count of its own
+    traffic (see roofline.traffic for that)."""
+    b = 2.0 * nnz * 6 + n_valid * 16 + V * 32
+    floor_ms = b / (HBM_PEAK_GBS * 1e9) * 1e3
+    return {"bytes_per_iteration": b, "floor_ms": floor_ms, "frac": floor_ms / ms_step}
 
 
 def cpu_baseline(P, n_patch_sample: int = 192):
@@ -337,6 +354,7 @@ def main():
         "hot_kernels_ms": kern,
         "build_ms": t_build * 1e3,
         "roofline": roofline,
+        "hbm_equivalent": hbm_equivalent(nnz, n_valid, plan.V, ms_step),
         "em": {"sigma2": st[0].sigma2, "c": st[0].c, "excluded": st[0].n_excluded},
     }
 
