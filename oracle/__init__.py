@@ -66,6 +66,9 @@ def lib():
                                    ctypes.c_double, ctypes.c_double,
                                    ctypes.c_int, ctypes.c_double, ctypes.c_int, P]
         L.ora_ncc_grad.argtypes = [P, P, P, P, P, P, P]
+        L.ora_set_psf.argtypes = [P, ctypes.c_int]
+        L.ora_sinc_taylor.restype = ctypes.c_double
+        L.ora_sinc_taylor.argtypes = [ctypes.c_double]
         L.ora_ncc_patch.restype = ctypes.c_double
         L.ora_ncc_patch.argtypes = [P, ctypes.c_int, P, P, P, P]
         L.ora_num_threads.restype = ctypes.c_int
@@ -93,6 +96,11 @@ def rotation(th) -> np.ndarray:
     return R.reshape(3, 3)
 
 
+def sinc_taylor(R: float) -> float:
+    """sin(R)/R by the oracle's Taylor series (|R| <= pi)."""
+    return float(lib().ora_sinc_taylor(float(R)))
+
+
 def num_threads() -> int:
     return int(lib().ora_num_threads())
 
@@ -105,8 +113,10 @@ class Ctx:
     (M, 6) int rows (stack, slice, x0, y0, w, h) with stack indices local to
     this problem."""
 
+    PSF_KINDS = {"gaussian": 0, "sinc": 1}
+
     def __init__(self, grid, stacks, patches, k: float = 3.0,
-                 stack_base: int = 0):
+                 stack_base: int = 0, psf: str = "gaussian"):
         self.dims = np.array([grid.nx, grid.ny, grid.nz], dtype=np.int32)
         self.v2w = _f64(grid.vox2world).reshape(12).copy()
         self.sdims = np.array([[s.nx, s.ny, s.nslices] for s in stacks],
@@ -129,6 +139,10 @@ class Ctx:
                                        self.k)
         self.N = int(lib().ora_n_samples(self._h))
         self.patch_of_sample = np.repeat(np.arange(self.M), n)
+        if psf not in self.PSF_KINDS:
+            raise ValueError(f"psf must be one of {sorted(self.PSF_KINDS)}, not {psf!r}")
+        self.psf = psf
+        lib().ora_set_psf(self._h, self.PSF_KINDS[psf])
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -199,6 +213,8 @@ class Ctx:
     def ncc_grad(self, X, y, theta, mask=None):
         """Per-patch NCC and its exact gradient with respect to the six
         motion parameters: (ncc (M,), grad (M, 6))."""
+        if self.psf != "gaussian":
+            raise NotImplementedError("the exact NCC gradient is written for the Gaussian PSF")
         X = _f64(X).reshape(-1); y = _f64(y).reshape(-1)
         th = _f64(theta).reshape(-1)
         out = np.zeros(self.M)
@@ -213,6 +229,8 @@ class Ctx:
         gradient: "fd" (central differences with step fd_h) or "analytic"."""
         if gradient not in ("fd", "analytic"):
             raise ValueError(f"gradient must be 'fd' or 'analytic', not {gradient!r}")
+        if gradient == "analytic" and self.psf != "gaussian":
+            raise NotImplementedError("the exact NCC gradient is written for the Gaussian PSF")
         X = _f64(X).reshape(-1); y = _f64(y).reshape(-1)
         th = _f64(theta).reshape(-1).copy()
         out = np.zeros(self.M)

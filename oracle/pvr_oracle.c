@@ -54,6 +54,7 @@ typedef struct {
   int64_t *off;         /* [M+1] */
   int64_t N;
   double k;             /* support radius in standard deviations */
+  int psf;              /* 0: Gaussian, 1: sinc in-plane x slice profile */
 } ora_ctx;
 
 typedef struct {
@@ -65,7 +66,9 @@ typedef struct {
   double E[9];          /* [e1 e2 n]: unit stack axes as columns */
   double F[9];          /* R * [e1 e2 n] : columns are the moved PSF axes */
   double sig[3];        /* PSF standard deviations (mm) */
+  double wz[2];         /* sinc PSF: in-plane first zeros (mm) = in-plane FWHM */
   double ext[3];        /* support half-extent along voxel axes (voxels) */
+  double reach;         /* radius (mm) of a ball around the centre holding the support */
   int st, slice, x0, y0, w, h;
 } pgeo;
 
@@ -189,6 +192,24 @@ static void patch_geometry(const ora_ctx *C, int s, const double *th,
     }
   for (int a = 0; a < 3; ++a)
     g->sig[a] = C->fwhm[3 * g->st + a] / (2.0 * sqrt(2.0 * log(2.0)));
+  for (int a = 0; a < 2; ++a) g->wz[a] = C->fwhm[3 * g->st + a];
+  if (C->psf == 1) {
+    /* support box x + F (t_u w_u, t_v w_v, t_n sig_n), |t_u|, |t_v| < 1,
+     * |t_n| <= k: half extent along voxel axis b is the sum of the box's
+     * half widths times |W2V_lin F|_{b,a} */
+    const double hw[3] = {g->wz[0], g->wz[1], C->k * g->sig[2]};
+    for (int b = 0; b < 3; ++b) {
+      double acc = 0;
+      for (int a = 0; a < 3; ++a) {
+        double m = 0;
+        for (int q = 0; q < 3; ++q) m += C->w2v[4 * b + q] * g->F[3 * q + a];
+        acc += fabs(m) * hw[a];
+      }
+      g->ext[b] = acc;
+    }
+    g->reach = sqrt(hw[0] * hw[0] + hw[1] * hw[1] + hw[2] * hw[2]);
+    return;
+  }
   /* support ellipsoid x + F diag(sig) u, |u| <= k, in voxel coordinates:
    * half extent along voxel axis b is k * |row_b(W2V_lin F diag(sig))| */
   for (int b = 0; b < 3; ++b) {
@@ -201,7 +222,26 @@ static void patch_geometry(const ora_ctx *C, int s, const double *th,
     }
     g->ext[b] = C->k * sqrt(acc);
   }
+  g->reach = C->k * fmax(g->sig[0], fmax(g->sig[1], g->sig[2]));
 }
+
+/* sin(R) / R by its Taylor series 1 - R^2/3! + R^4/5! - ... (Sec. II, the
+ * PSF paragraph), summed until the next term is below 1e-15 of the partial
+ * sum (an alternating series with decreasing terms errs by less than its
+ * first omitted term) or after 40 terms; |R| <= pi here. */
+static double sinc_taylor(double R) {
+  const double r2 = R * R;
+  double term = 1.0, sum = 1.0;
+  for (int m = 1; m < 40; ++m) {
+    term *= -r2 / ((2.0 * m) * (2.0 * m + 1.0));
+    sum += term;
+    if (fabs(term) < 1e-15 * fabs(sum)) break;
+  }
+  return sum;
+}
+
+void ora_set_psf(ora_ctx *C, int kind) { C->psf = kind; }
+double ora_sinc_taylor(double R) { return sinc_taylor(R); }
 
 /* World centre of sample (u, v) of the patch after motion. */
 static void sample_centre(const pgeo *g, int u, int v, double x[3]) {
@@ -222,6 +262,16 @@ static double psf_hat(const ora_ctx *C, const pgeo *g, const double x[3],
   double ip[3] = {(double)i, (double)j, (double)kk}, v[3], dv[3];
   apply_affine(C->v2w, ip, v);
   for (int r = 0; r < 3; ++r) dv[r] = v[r] - x[r];
+  if (C->psf == 1) {
+    /* sinc in-plane (first zero at the in-plane FWHM) x the slice profile (a
+     * Gaussian of the through-plane FWHM, cut at k sigma and shifted to 0) */
+    double d[3];
+    for (int a = 0; a < 3; ++a) d[a] = g->F[a] * dv[0] + g->F[3 + a] * dv[1] + g->F[6 + a] * dv[2];
+    const double tu = d[0] / g->wz[0], tv = d[1] / g->wz[1], qn = (d[2] / g->sig[2]) * (d[2] / g->sig[2]);
+    if (!(fabs(tu) < 1.0) || !(fabs(tv) < 1.0) || qn > C->k * C->k) return -1.0;
+    return sinc_taylor(M_PI * tu) * sinc_taylor(M_PI * tv) *
+           (exp(-0.5 * qn) - exp(-0.5 * C->k * C->k));
+  }
   double Q = 0;
   for (int a = 0; a < 3; ++a) {
     double d = g->F[a] * dv[0] + g->F[3 + a] * dv[1] + g->F[6 + a] * dv[2];
@@ -454,10 +504,9 @@ static void backproject_voxels_impl(const ora_ctx *C, const double *theta,
       double sv = sqrt(g.A[1] * g.A[1] + g.A[4] * g.A[4] + g.A[7] * g.A[7]);
       double half = 0.5 * sqrt((g.w - 1) * (g.w - 1) * su * su +
                                (g.h - 1) * (g.h - 1) * sv * sv);
-      double smax = fmax(g.sig[0], fmax(g.sig[1], g.sig[2]));
       double dd = 0;
       for (int a = 0; a < 3; ++a) dd += (vw[a] - cen[a]) * (vw[a] - cen[a]);
-      double lim = half + C->k * smax + 1e-9;
+      double lim = half + g.reach + 1e-9;
       if (dd > lim * lim) continue;
       for (int64_t l = 0; l < (int64_t)g.w * g.h; ++l) {
         int64_t j = C->off[s] + l;
