@@ -213,6 +213,28 @@ pvr_status pvr_plan_build_f64(pvr_plan *plan, const double *theta,
                               const uint8_t *active, const uint8_t *sample_mask,
                               hipStream_t stream);
 
+/* PSF of the plan's forward model (Sec. II, "Patch to Volume Registration").
+ *   PVR_PSF_GAUSSIAN (default): a 3D Gaussian along the moved stack axes with
+ *     the stacks' FWHMs, truncated at k standard deviations and shifted to 0
+ *     there (the approximation of the method the paper builds on).
+ *   PVR_PSF_SINC: the paper's own PSF, a sinc in-plane times the slice
+ *     profile through-plane.  In the moved patch frame (offsets d_u, d_v, d_n
+ *     in mm) the weight is s(d_u / w_u) s(d_v / w_v) (exp(-d_n^2 / 2 sigma_n^2)
+ *     - exp(-k^2 / 2)) on |d_u| < w_u, |d_v| < w_v, |d_n| <= k sigma_n, where
+ *     s(t) = sin(pi t) / (pi t) is summed as its Taylor series in (pi t)^2
+ *     (terms through (pi t)^16 in FP32, remainder below 1.1e-8; through
+ *     (pi t)^22 in FP64), w = the in-plane FWHMs (the sinc's first zero;
+ *     main lobe only) and sigma_n the slice profile's deviation from the
+ *     through-plane FWHM.  Normalised over in-volume voxels like the Gaussian.
+ *     Registration and the theta-derivatives (pvr_register_patches,
+ *     pvr_simulate_grad_theta*) return PVR_EUNSUPPORTED for this PSF; the
+ *     LDS-tiled forward pass is not used with it.
+ * Takes effect at the next pvr_plan_build (the plan counts as unbuilt until
+ * then).  (host) */
+#define PVR_PSF_GAUSSIAN 0
+#define PVR_PSF_SINC 1
+pvr_status pvr_plan_set_psf(pvr_plan *plan, int32_t kind);
+
 /* Forward tile shape.  By default the simulation walks every sample's PSF
  * support in global memory (one workgroup per 1024-sample chunk of a patch).
  * With tile_w x tile_h > 0 it instead splits every patch into tile_w x tile_h

@@ -150,11 +150,44 @@ __device__ __forceinline__ void adj_patch_rt(const GEO &g, const PatchDev &pt, d
   }
 }
 
+// The sinc PSF (PVR_PSF_SINC): the weight factorises over the patch frame as
+// s(t_u) s(t_v) g(t_n) with t = pixel offset * (spacing / first zero) in-plane
+// and g = 2^-qk - 2^-K2 (clamped at 0) through-plane; candidates outside the
+// main lobe (|t| >= 1) or the patch get the factor 0.  HU, HV > 0: the
+// candidate half-widths every patch fits; 0 reads them per patch.
+template <typename T, typename GEO, typename V2, int HU, int HV, bool DEN>
+__device__ __forceinline__ void adj_patch_sinc(const GEO &g, const PatchDev &pt, double pu,
+                                               double pv, T qk, const V2 *__restrict__ rq, T &sn,
+                                               T &sd) {
+  const int hu = HU > 0 ? HU : g.hu, hv = HV > 0 ? HV : g.hv;
+  const double rud = rint(pu), rvd = rint(pv);
+  const int ru = (int)rud - pt.x0, rv = (int)rvd - pt.y0;
+  const T fu = (T)(pu - rud), fv = (T)(pv - rvd);
+  const T cu = (T)g.cu, cv = (T)g.cv, cut = (T)g.cut;
+  T gz = fast_exp2<T>(-qk) - cut;
+  gz = gz > (T)0 ? gz : (T)0;
+  const __amdgpu_buffer_rsrc_t r = patch_rsrc(rq + pt.off, pt.w * pt.h);
+  for (int b = -hv; b <= hv; ++b) {
+    const T tv = ((T)b - fv) * cv;
+    const bool inb = ((unsigned)(rv + b) < (unsigned)pt.h) & (fabs(tv) < (T)1);
+    const T e = inb ? sinc_poly<T>(tv) * gz : (T)0;
+    const int row = (rv + b) * pt.w;
+    for (int a = -hu; a <= hu; ++a) {
+      const T tu = ((T)a - fu) * cu;
+      const bool ina = ((unsigned)(ru + a) < (unsigned)pt.w) & (fabs(tu) < (T)1);
+      const T gh = ina ? sinc_poly<T>(tu) * e : (T)0;
+      const V2 q = load_rq<V2>(r, (row + ru + a + 1) * (int)sizeof(V2));
+      sn = fma(gh, q.x, sn);
+      if (DEN) sd = fma(gh, q.y, sd);
+    }
+  }
+}
+
 // One workgroup = one 8^3 brick; each wavefront owns one 4^3 sub-brick and
 // walks that sub-brick's patch list (wave-uniform), one voxel per lane.
 // HW: the candidate half-width every patch of the plan fits (1 or 2, fixed
 // at compile time), or 0 to read it per patch.
-template <typename T, bool DEN, int HW>
+template <typename T, bool DEN, int HW, bool SINC>
 __global__ void __launch_bounds__(BP_THREADS)
 k_backproject(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patches,
               const typename GeoOf<T>::type *__restrict__ geo, const int *__restrict__ brick_prob,
@@ -190,7 +223,9 @@ k_backproject(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ pa
     if (!(qk <= (T)g.K2)) continue;
     const double pu = fma(g.G[0], fi, fma(g.G[1], fj, fma(g.G[2], fk, g.G[3])));
     const double pv = fma(g.G[4], fi, fma(g.G[5], fj, fma(g.G[6], fk, g.G[7])));
-    if (HW == 1)
+    if (SINC)
+      adj_patch_sinc<T, GEO, V2, HW, HW, DEN>(g, pt, pu, pv, qk, rq, sn, sd);
+    else if (HW == 1)
       adj_patch<T, GEO, V2, 1, 1, DEN>(g, pt, pu, pv, qk, rq, sn, sd);
     else if (HW == 2)
       adj_patch<T, GEO, V2, 2, 2, DEN>(g, pt, pu, pv, qk, rq, sn, sd);
@@ -222,19 +257,23 @@ static pvr_status backproject_impl(const pvr_plan *p, const T *e, const T *pp, c
   if (ev) HIP_TRY(hipEventRecord(ev[0], stream));
   const int hw = (p->max_hu <= 1 && p->max_hv <= 1) ? 1 : (p->max_hu <= 2 && p->max_hv <= 2) ? 2 : 0;
   const auto *geot = (const typename GeoOf<T>::type *)geo;
-#define BP_LAUNCH(D, H)                                                                         \
-  hipLaunchKernelGGL((k_backproject<T, D, H>), grid, dim3(BP_THREADS), 0, stream, p->d_prob,    \
-                     p->d_patch, geot, p->d_brick_prob, p->d_sub_off, p->d_sub_patch, rq,        \
+#define BP_LAUNCH(D, H, SC)                                                                     \
+  hipLaunchKernelGGL((k_backproject<T, D, H, SC>), grid, dim3(BP_THREADS), 0, stream, p->d_prob, \
+                     p->d_patch, geot, p->d_brick_prob, p->d_sub_off, p->d_sub_patch, rq,         \
                      patch_w, num, den, p->n_bricks)
+#define BP_LAUNCH_HW(D, SC)            \
+  if (hw == 1) BP_LAUNCH(D, 1, SC);    \
+  else if (hw == 2) BP_LAUNCH(D, 2, SC); \
+  else BP_LAUNCH(D, 0, SC)
+  const bool sinc = p->psf == PVR_PSF_SINC;
   if (den) {
-    if (hw == 1) BP_LAUNCH(true, 1);
-    else if (hw == 2) BP_LAUNCH(true, 2);
-    else BP_LAUNCH(true, 0);
+    if (sinc) { BP_LAUNCH_HW(true, true); }
+    else { BP_LAUNCH_HW(true, false); }
   } else {
-    if (hw == 1) BP_LAUNCH(false, 1);
-    else if (hw == 2) BP_LAUNCH(false, 2);
-    else BP_LAUNCH(false, 0);
+    if (sinc) { BP_LAUNCH_HW(false, true); }
+    else { BP_LAUNCH_HW(false, false); }
   }
+#undef BP_LAUNCH_HW
 #undef BP_LAUNCH
   HIP_TRY(hipGetLastError());
   if (ev) HIP_TRY(hipEventRecord(ev[1], stream));

@@ -35,7 +35,8 @@ k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patch
   const unsigned nbytes = (unsigned)(pr.nx * pr.ny * pr.nz) * (unsigned)sizeof(T);
   // patches whose rows run along y read the y-fastest copy, so that the lanes
   // of a wave (consecutive pixels of a row) read consecutive addresses
-  const bool xt = XT != nullptr && pt.layout == 1;
+  const bool sinc = g.psf == PVR_PSF_SINC;
+  const bool xt = XT != nullptr && pt.layout == 1 && !sinc;
   const __amdgpu_buffer_rsrc_t xr = raw_buffer((xt ? XT : X) + pr.vol_off, nbytes);
   const int n = pt.w * pt.h;
   const int l1 = min(n, wk.l0 + SIM_CHUNK);
@@ -52,7 +53,10 @@ k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patch
       // the layout, and whether the walk's inner axis is the layout's fastest
       // one, are uniform over the chunk: one branch per chunk picks the walk
       using G = typename GeoOf<T>::type;
-      if (xt)
+      if (sinc) {
+        T z;
+        yh = psf_walk_sinc<T, G, true>(g, pr, b, f, xr, &z) * iz;
+      } else if (xt)
         yh = (g.perm[2] == 1 ? psf_walk_fwd<T, G, false, 1, true>(g, pr, b, f, xr, nbytes)
                              : psf_walk_fwd<T, G, false, 2, true>(g, pr, b, f, xr, nbytes)) * iz;
       else
@@ -184,7 +188,7 @@ __global__ void __launch_bounds__(256) k_transpose_xy(const float *__restrict__ 
 // Fills p->d_xt from X when the plan has patches that read it; returns the
 // copy (or nullptr).
 static const float *volume_xt(const pvr_plan *p, const float *X, hipStream_t stream) {
-  if (!p->any_xt) return nullptr;
+  if (!p->any_xt || p->psf != PVR_PSF_GAUSSIAN) return nullptr;
   for (int b = 0; b < p->P; ++b) {
     const ProbDev &pr = p->h_prob[b];
     const dim3 grid((pr.nx + XT_TILE - 1) / XT_TILE, (pr.ny + XT_TILE - 1) / XT_TILE, pr.nz);
@@ -200,7 +204,7 @@ static pvr_status simulate_impl(const pvr_plan *p, const T *X, const T *y_obs, T
   if (!X) return fail(PVR_EINVAL, "pvr_simulate: X is NULL");
   if (resid && !y_obs) return fail(PVR_EINVAL, "pvr_simulate: resid requires y_obs");
   if (!y_sim && !resid) return PVR_OK;
-  if (sizeof(T) == 4 && p->use_tiles && p->lds_box > 0) {
+  if (sizeof(T) == 4 && p->use_tiles && p->lds_box > 0 && p->psf == PVR_PSF_GAUSSIAN) {
     hipEvent_t *ev = timing_slot(p, PVR_KERNEL_SIMULATE);
     if (ev) HIP_TRY(hipEventRecord(ev[0], stream));
     hipLaunchKernelGGL(k_simulate_tiles, dim3(xcd_blocks(p->n_tiles, SIM_XCD_GRANULE)), dim3(SIM_THREADS),
@@ -576,6 +580,8 @@ extern "C" pvr_status pvr_register_patches(const pvr_plan *p, const float *X, co
   if (!p->built) return fail(PVR_EINVAL, "pvr_register_patches: plan has not been built");
   if (prm->max_iter < 0 || !(prm->step0 > 0) || !(prm->step_min > 0) || !(prm->fd_h > 0))
     return fail(PVR_EINVAL, "pvr_register_patches: invalid optimiser parameters");
+  if (p->psf != PVR_PSF_GAUSSIAN)
+    return fail(PVR_EUNSUPPORTED, "pvr_register_patches: registration is implemented for the Gaussian PSF");
   if (prm->gradient != PVR_REG_GRAD_FD && prm->gradient != PVR_REG_GRAD_EXACT)
     return fail(PVR_EINVAL, "pvr_register_patches: gradient must be PVR_REG_GRAD_FD or PVR_REG_GRAD_EXACT");
   const float *XT = volume_xt(p, X, stream);

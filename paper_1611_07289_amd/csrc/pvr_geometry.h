@@ -63,6 +63,11 @@ __host__ __device__ static inline int cand_halfwidth(double K2, double c) {
   return (int)floor(sqrt(K2) / c + 0.5);
 }
 
+// The same for the sinc PSF's main lobe |t| < 1 with t = pixel offset * c.
+__host__ __device__ static inline int sinc_halfwidth(double c) {
+  return (int)floor(1.0 / c + 0.5);
+}
+
 // R = Rz(rz) Ry(ry) Rx(rx)
 __host__ __device__ static inline void rot_zyx(const double *th, double *R) {
   double cx = cos(th[0]), sx = sin(th[0]), cy = cos(th[1]), sy = sin(th[1]);
@@ -74,7 +79,8 @@ __host__ __device__ static inline void rot_zyx(const double *th, double *R) {
 
 // Per-patch motion geometry (see pvr_internal.h).  One thread per patch.
 __device__ inline void make_geometry(const ProbDev &pr, const StackDev &st, const PatchDev &pt,
-                              const double *th, double k, GeoD &g, GeoF &gf, int *bb) {
+                              const double *th, double k, GeoD &g, GeoF &gf, int *bb,
+                              int psf = PVR_PSF_GAUSSIAN) {
   double R[9];
   rot_zyx(th, R);
   double A[9], o[3];
@@ -113,6 +119,24 @@ __device__ inline void make_geometry(const ProbDev &pr, const StackDev &st, cons
   const double K2 = KAPPA * k * k;
   double ext[3];
   for (int b = 0; b < 3; ++b) ext[b] = sqrt(K2 * Ai[4 * b]);
+  if (psf == PVR_PSF_SINC) {
+    // support box |t_u| < 1, |t_v| < 1, |t_n| <= k with t = diag(1/w_u, 1/w_v,
+    // 1/sigma_n) F^T Vl (voxel offset): its half extent along voxel axis b is
+    // sum_a |(Wl F)_{b a}| h_a, h = (w_u, w_v, k sigma_n)
+    const double hw[3] = {st.wz[0], st.wz[1], k * st.sigma[2]};
+    const double sc[3] = {1.0 / st.wz[0], 1.0 / st.wz[1], 1.0 / st.sigma[2]};
+    for (int a = 0; a < 3; ++a)
+      for (int j = 0; j < 3; ++j)
+        g.L[3 * a + j] = (F[a] * Vl[j] + F[3 + a] * Vl[3 + j] + F[6 + a] * Vl[6 + j]) * sc[a];
+    double WF[9];
+    for (int b = 0; b < 3; ++b)
+      for (int a = 0; a < 3; ++a)
+        WF[3 * b + a] = Wl[3 * b] * F[a] + Wl[3 * b + 1] * F[3 + a] + Wl[3 * b + 2] * F[6 + a];
+    for (int b = 0; b < 3; ++b)
+      ext[b] = fabs(WF[3 * b]) * hw[0] + fabs(WF[3 * b + 1]) * hw[1] + fabs(WF[3 * b + 2]) * hw[2];
+  }
+  g.psf = psf;
+  g.kcut = k;
   for (int b = 0; b < 3; ++b) { g.ext[b] = ext[b]; gf.ext[b] = (float)ext[b]; }
   int ic = 0;
   if (ext[1] > ext[ic]) ic = 1;
@@ -137,10 +161,17 @@ __device__ inline void make_geometry(const ProbDev &pr, const StackDev &st, cons
   g.cu = sk * st.spacing[0] / st.sigma[0];
   g.cv = sk * st.spacing[1] / st.sigma[1];
   g.ck = sk * st.spacing[2] / st.sigma[2];
+  if (psf == PVR_PSF_SINC) {
+    // in-plane: pixel offset -> t (the sinc's argument over pi)
+    g.cu = st.spacing[0] / st.wz[0];
+    g.cv = st.spacing[1] / st.wz[1];
+  }
   // brick range of the union of the patch's supports: the pixel box grown by
-  // k sigma along every stack axis, mapped by H
+  // the support's half widths along every stack axis, mapped by H
   double r3[3];
   for (int a = 0; a < 3; ++a) r3[a] = k * st.sigma[a] / st.spacing[a];
+  if (psf == PVR_PSF_SINC)
+    for (int a = 0; a < 2; ++a) r3[a] = st.wz[a] / st.spacing[a];
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
   for (int q = 0; q < 8; ++q) {
     double cu = (q & 1) ? pt.x0 + pt.w - 1 + r3[0] : pt.x0 - r3[0];
@@ -172,9 +203,12 @@ __device__ inline void make_geometry(const ProbDev &pr, const StackDev &st, cons
   g.inv_cu = 1.0 / g.cu; g.inv_cv = 1.0 / g.cv;
   // integer pixels within the in-plane support radius R of a point p are
   // among rint(p) + [-h, h] with h = floor(R + 1/2)
-  g.hu = cand_halfwidth(K2, g.cu);
-  g.hv = cand_halfwidth(K2, g.cv);
+  g.hu = psf == PVR_PSF_SINC ? sinc_halfwidth(g.cu) : cand_halfwidth(K2, g.cu);
+  g.hv = psf == PVR_PSF_SINC ? sinc_halfwidth(g.cv) : cand_halfwidth(K2, g.cv);
   gf.hu = g.hu; gf.hv = g.hv;
+  gf.psf = g.psf;
+  gf.kcut = (float)g.kcut;
+  for (int q = 0; q < 9; ++q) gf.L[q] = (float)g.L[q];
   gf.inv_cu = (float)g.inv_cu; gf.inv_cv = (float)g.inv_cv;
   for (int q = 0; q < 3; ++q) gf.perm[q] = g.perm[q];
 }

@@ -84,6 +84,8 @@ template <typename T>
 static pvr_status grad_impl(const pvr_plan *p, const T *X, const T *gy, T *grad, const T *invz,
                             hipStream_t stream) {
   if (!X || !gy || !grad) return fail(PVR_EINVAL, "pvr_simulate_grad_theta: NULL argument");
+  if (p->psf != PVR_PSF_GAUSSIAN)
+    return fail(PVR_EUNSUPPORTED, "pvr_simulate_grad_theta: the theta-derivative is implemented for the Gaussian PSF");
   const void *geo = sizeof(T) == 4 ? (const void *)p->d_geof : (const void *)p->d_geod;
   hipLaunchKernelGGL(k_grad_theta<T>, dim3(p->M), dim3(GR_THREADS), 0, stream, p->d_prob,
                      p->d_stack, p->d_patch, (const typename GeoOf<T>::type *)geo, p->d_theta,

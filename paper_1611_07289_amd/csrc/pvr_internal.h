@@ -49,6 +49,7 @@ struct StackDev {
   double E[9];        // unit axes as columns (row-major 3x3)
   double spacing[3];  // column norms of the linear part
   double sigma[3];    // PSF standard deviations (mm)
+  double wz[2];       // sinc PSF: in-plane first zeros (mm) = in-plane FWHM
 };
 
 struct PatchDev {
@@ -72,6 +73,9 @@ struct GeoD {
   int perm[3];
   int bb_lo[3], bb_hi[3];   // brick range (inclusive); empty if lo > hi
   int hu, hv;               // adjoint candidate half-widths (pixels)
+  int psf;                  // PVR_PSF_GAUSSIAN or PVR_PSF_SINC
+  double L[9];              // sinc PSF: voxel offset -> (t_u, t_v, t_n), row-major
+  double kcut;              // k (the slice profile's cut in standard deviations)
 };
 
 // The same constants in single precision for the float kernels (G stays in
@@ -87,6 +91,9 @@ struct GeoF {
   float ext[3];             // support half-extent along voxel axes (voxels)
   int perm[3];
   int hu, hv;               // adjoint candidate half-widths (pixels)
+  int psf;                  // PVR_PSF_GAUSSIAN or PVR_PSF_SINC
+  float L[9];               // sinc PSF: voxel offset -> (t_u, t_v, t_n), row-major
+  float kcut;               // k
 };
 
 template <typename T> struct GeoOf;
@@ -360,6 +367,115 @@ __device__ __forceinline__ T psf_walk_fwd(const GEO &g, const ProbDev &p, const 
   return acc;
 }
 
+// s(t) = sin(pi t) / (pi t) by its Taylor series in y = (pi t)^2,
+// sum_m (-1)^m y^m / (2m + 1)!, in Horner form: terms through y^8 in FP32
+// (for |t| <= 1 the first omitted term, pi^18 / 19!, is below 1.1e-8) and
+// through y^11 in FP64 (pi^24 / 25! < 6e-14).
+template <typename T> __device__ __forceinline__ T sinc_poly(T t);
+template <> __device__ __forceinline__ float sinc_poly<float>(float t) {
+  const float y = (3.14159265358979f * t) * (3.14159265358979f * t);
+  float s = 2.8114572543455208e-15f;              //  1 / 17!
+  s = fmaf(s, y, -7.6471637318198164e-13f);       // -1 / 15!
+  s = fmaf(s, y, 1.6059043836821613e-10f);        //  1 / 13!
+  s = fmaf(s, y, -2.5052108385441720e-08f);       // -1 / 11!
+  s = fmaf(s, y, 2.7557319223985893e-06f);        //  1 / 9!
+  s = fmaf(s, y, -1.9841269841269841e-04f);       // -1 / 7!
+  s = fmaf(s, y, 8.3333333333333333e-03f);        //  1 / 5!
+  s = fmaf(s, y, -1.6666666666666667e-01f);       // -1 / 3!
+  return fmaf(s, y, 1.0f);
+}
+template <> __device__ __forceinline__ double sinc_poly<double>(double t) {
+  const double y = (3.141592653589793 * t) * (3.141592653589793 * t);
+  double s = -3.8681701706306841e-23;             // -1 / 23!
+  s = fma(s, y, 1.9572941063391263e-20);          //  1 / 21!
+  s = fma(s, y, -8.2206352466243295e-18);         // -1 / 19!
+  s = fma(s, y, 2.8114572543455208e-15);          //  1 / 17!
+  s = fma(s, y, -7.6471637318198164e-13);         // -1 / 15!
+  s = fma(s, y, 1.6059043836821613e-10);          //  1 / 13!
+  s = fma(s, y, -2.5052108385441720e-08);         // -1 / 11!
+  s = fma(s, y, 2.7557319223985893e-06);          //  1 / 9!
+  s = fma(s, y, -1.9841269841269841e-04);         // -1 / 7!
+  s = fma(s, y, 8.3333333333333333e-03);          //  1 / 5!
+  s = fma(s, y, -1.6666666666666667e-01);         // -1 / 3!
+  return fma(s, y, 1.0);
+}
+
+// Walk the support box of one sample for the sinc PSF (PVR_PSF_SINC): with
+// t = L (voxel - centre), the support is |t_u| < 1, |t_v| < 1, |t_n| <= k.
+// The outer axes a, b run over the box's voxel extents; along the inner axis
+// c each row's range is the intersection of the three slabs (exact, then
+// widened by 1e-4 voxel; the weight decides membership voxel by voxel).
+// Returns sum g_hat X (WITH_X) and sum g_hat in *z_out, over in-grid voxels.
+template <typename T, typename GEO, bool WITH_X>
+__device__ __forceinline__ T psf_walk_sinc(const GEO &g, const ProbDev &p, const int b[3],
+                                           const T f[3], __amdgpu_buffer_rsrc_t xr, T *z_out) {
+  const int sy = p.nx, sz = p.nx * p.ny;
+  const int ia = g.perm[0], ib = g.perm[1], ic = g.perm[2];
+  const int st_a = sel3(ia, 1, sy, sz), st_b = sel3(ib, 1, sy, sz), st_c = sel3(ic, 1, sy, sz);
+  const int b_a = sel3(ia, b[0], b[1], b[2]), b_b = sel3(ib, b[0], b[1], b[2]),
+            b_c = sel3(ic, b[0], b[1], b[2]);
+  const int n_a = sel3(ia, p.nx, p.ny, p.nz), n_b = sel3(ib, p.nx, p.ny, p.nz),
+            n_c = sel3(ic, p.nx, p.ny, p.nz);
+  const T f_a = sel3f<T>(ia, f[0], f[1], f[2]), f_b = sel3f<T>(ib, f[0], f[1], f[2]),
+          f_c = sel3f<T>(ic, f[0], f[1], f[2]);
+  T La[3], Lb[3], Lc[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    La[i] = (T)g.L[3 * i + ia];
+    Lb[i] = (T)g.L[3 * i + ib];
+    Lc[i] = (T)g.L[3 * i + ic];
+  }
+  const T Bd[3] = {(T)1, (T)1, (T)g.kcut};
+  const T cut = (T)g.cut, kap = (T)KAPPA;
+  const T ea = (T)g.ext[ia], eb = (T)g.ext[ib];
+  const int lo_a = max((int)ceil(f_a - ea), -b_a);
+  const int hi_a = min((int)floor(f_a + ea), n_a - 1 - b_a);
+  const int lo_b = max((int)ceil(f_b - eb), -b_b);
+  const int hi_b = min((int)floor(f_b + eb), n_b - 1 - b_b);
+  const int vb = (b[2] * p.ny + b[1]) * p.nx + b[0];
+  T acc = (T)0, z = (T)0;
+  for (int oa = lo_a; oa <= hi_a; ++oa) {
+    const T wa = (T)oa - f_a;
+    for (int ob = lo_b; ob <= hi_b; ++ob) {
+      const T wb = (T)ob - f_b;
+      T r[3];
+      T lo = (T)-1e30, hi = (T)1e30;
+      bool empty = false;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        r[i] = La[i] * wa + Lb[i] * wb;
+        if (fabs(Lc[i]) > (T)1e-20) {
+          const T t1 = (-Bd[i] - r[i]) / Lc[i], t2 = (Bd[i] - r[i]) / Lc[i];
+          lo = fmax(lo, fmin(t1, t2));
+          hi = fmin(hi, fmax(t1, t2));
+        } else if (fabs(r[i]) > Bd[i]) {
+          empty = true;
+        }
+      }
+      if (empty || !(lo <= hi)) continue;
+      const int lo_c = max((int)ceil(f_c + lo - (T)1e-4), -b_c);
+      const int hi_c = min((int)floor(f_c + hi + (T)1e-4), n_c - 1 - b_c);
+      const T wc0 = (T)lo_c - f_c;
+      T t0 = fma(Lc[0], wc0, r[0]), t1 = fma(Lc[1], wc0, r[1]), t2 = fma(Lc[2], wc0, r[2]);
+      unsigned off = (unsigned)(vb + oa * st_a + ob * st_b + lo_c * st_c) * (unsigned)sizeof(T);
+      for (int oc = lo_c; oc <= hi_c; ++oc) {
+        T gz = fast_exp2<T>(-kap * t2 * t2) - cut;
+        gz = gz > (T)0 ? gz : (T)0;
+        const bool in = fabs(t0) < (T)1 && fabs(t1) < (T)1;
+        const T gh = in ? sinc_poly<T>(t0) * sinc_poly<T>(t1) * gz : (T)0;
+        if (WITH_X) acc = fma(gh, load_vox<T>(xr, off), acc);
+        z += gh;
+        t0 += Lc[0];
+        t1 += Lc[1];
+        t2 += Lc[2];
+        off += (unsigned)st_c * (unsigned)sizeof(T);
+      }
+    }
+  }
+  *z_out = z;
+  return acc;
+}
+
 // Voxel box (inclusive, clipped to the grid, padded by one voxel) that holds
 // the PSF supports of every sample of a tile: the tile's corner centres
 // bound all its centres (the pixel -> voxel map is affine), and a support
@@ -481,6 +597,7 @@ struct pvr_plan {
   double *d_chunk_stats;     // [n_sim_blocks][5] residual statistics of the last simulate
   float *d_xt;               // [V] y-fastest copy of the volume (plans with layout-1 patches)
   bool any_xt;
+  int psf;                   // PVR_PSF_GAUSSIAN (default) or PVR_PSF_SINC
   const void *stats_resid, *stats_y;  // ... and the buffers they describe
   bool stats_valid;
   int *d_total;              // [1] pinned readback target (device side)

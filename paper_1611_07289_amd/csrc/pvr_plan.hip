@@ -29,7 +29,7 @@ __global__ void k_copy_theta(const double *__restrict__ th, double *__restrict__
 
 __global__ void k_geometry(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stacks,
                            const PatchDev *__restrict__ patches, const double *__restrict__ theta,
-                           int M, double k, GeoD *__restrict__ gd, GeoF *__restrict__ gf,
+                           int M, double k, int psf, GeoD *__restrict__ gd, GeoF *__restrict__ gf,
                            int *__restrict__ bb, double *__restrict__ sbox) {
   int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= M) return;
@@ -37,13 +37,15 @@ __global__ void k_geometry(const ProbDev *__restrict__ probs, const StackDev *__
   const StackDev st = stacks[pt.stack];
   GeoD g;
   GeoF f;
-  make_geometry(probs[pt.problem], st, pt, theta + 6 * s, k, g, f, bb + 6 * s);
+  make_geometry(probs[pt.problem], st, pt, theta + 6 * s, k, g, f, bb + 6 * s, psf);
   gd[s] = g;
   gf[s] = f;
   // voxel -> pixel map and the pixel-frame support box of the patch
   double *o = sbox + 18 * s;
   for (int q = 0; q < 12; ++q) o[q] = g.G[q];
-  const double ru = k * st.sigma[0] / st.spacing[0], rv = k * st.sigma[1] / st.spacing[1],
+  const bool sinc = psf == PVR_PSF_SINC;
+  const double ru = sinc ? st.wz[0] / st.spacing[0] : k * st.sigma[0] / st.spacing[0],
+               rv = sinc ? st.wz[1] / st.spacing[1] : k * st.sigma[1] / st.spacing[1],
                rk = k * st.sigma[2] / st.spacing[2];
   o[12] = pt.x0 - ru; o[13] = pt.x0 + pt.w - 1 + ru;
   o[14] = pt.y0 - rv; o[15] = pt.y0 + pt.h - 1 + rv;
@@ -71,7 +73,12 @@ k_normalisers(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ pa
     T f[3];
     bool ok = sample_centre(g, pr, u, v, pt.slice, b, f) && act && (!mask || mask[j]);
     T z = 0, acc = 0;
-    if (ok) psf_walk<T, typename GeoOf<T>::type, false>(g, pr, b, f, nullptr, z, acc);
+    if (ok && g.psf == PVR_PSF_SINC) {
+      const __amdgpu_buffer_rsrc_t none = raw_buffer((const T *)nullptr, 0u);
+      psf_walk_sinc<T, typename GeoOf<T>::type, false>(g, pr, b, f, none, &z);
+    } else if (ok) {
+      psf_walk<T, typename GeoOf<T>::type, false>(g, pr, b, f, nullptr, z, acc);
+    }
     ok = ok && z > (T)0;
     const T iz = ok ? (T)1 / z : (T)0;
     invz[j] = (float)iz;
@@ -313,6 +320,7 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
       for (int r = 0; r < 3; ++r) d.E[3 * r + a] = L[3 * r + a] / n;
       if (!(st.fwhm_mm[a] > 0)) return fail(PVR_EINVAL, "pvr_plan_create: stack %d fwhm[%d] <= 0", s, a);
       d.sigma[a] = st.fwhm_mm[a] / (2.0 * sqrt(2.0 * log(2.0)));
+      if (a < 2) d.wz[a] = st.fwhm_mm[a];
     }
     for (int a = 0; a < 3; ++a)
       for (int c = a + 1; c < 3; ++c) {
@@ -526,6 +534,31 @@ static pvr_status update_lds_box(pvr_plan *p, hipStream_t stream) {
   return PVR_OK;
 }
 
+extern "C" pvr_status pvr_plan_set_psf(pvr_plan *p, int32_t kind) {
+  PVR_API_BEGIN();
+  if (!p) return fail(PVR_EINVAL, "pvr_plan_set_psf: plan is NULL");
+  if (kind != PVR_PSF_GAUSSIAN && kind != PVR_PSF_SINC)
+    return fail(PVR_EINVAL, "pvr_plan_set_psf: kind must be PVR_PSF_GAUSSIAN or PVR_PSF_SINC");
+  p->psf = kind;
+  // the adjoint's candidate grid follows the PSF's in-plane reach
+  const double sk = sqrt(KAPPA), K2 = KAPPA * p->k * p->k;
+  p->max_hu = p->max_hv = 0;
+  for (int s = 0; s < p->S; ++s) {
+    const StackDev &d = p->h_stack[s];
+    const int hu = kind == PVR_PSF_SINC ? sinc_halfwidth(d.spacing[0] / d.wz[0])
+                                        : cand_halfwidth(K2, sk * d.spacing[0] / d.sigma[0]);
+    const int hv = kind == PVR_PSF_SINC ? sinc_halfwidth(d.spacing[1] / d.wz[1])
+                                        : cand_halfwidth(K2, sk * d.spacing[1] / d.sigma[1]);
+    p->max_hu = std::max(p->max_hu, hu);
+    p->max_hv = std::max(p->max_hv, hv);
+  }
+  p->built = p->built64 = false;
+  p->index_valid = false;
+  p->stats_valid = false;
+  return PVR_OK;
+  PVR_API_END();
+}
+
 extern "C" pvr_status pvr_plan_set_tiles(pvr_plan *p, int32_t tile_w, int32_t tile_h,
                                          hipStream_t stream) {
   PVR_API_BEGIN();
@@ -625,7 +658,8 @@ static pvr_status plan_build_common(pvr_plan *p, const uint8_t *active, const ui
     launch_fill_u8(p->d_mask, 1, p->N, stream);
   }
   hipLaunchKernelGGL(k_geometry, dim3((M + T - 1) / T), dim3(T), 0, stream, p->d_prob, p->d_stack,
-                     p->d_patch, p->d_theta, M, p->k, p->d_geod, p->d_geof, p->d_bb, p->d_sbox);
+                     p->d_patch, p->d_theta, M, p->k, p->psf, p->d_geod, p->d_geof, p->d_bb,
+                     p->d_sbox);
   HIP_TRY(hipGetLastError());
   if (f64) {
     if (!p->d_invz64) DEV_ALLOC(p, p->d_invz64, p->N);

@@ -23,6 +23,8 @@ PVR_EM_FIX_W = 2
 PVR_EM_RESID_FRESH = 4
 PVR_REG_GRAD_FD = 0
 PVR_REG_GRAD_EXACT = 1
+PVR_PSF_GAUSSIAN = 0
+PVR_PSF_SINC = 1
 
 _STATUS = {0: "PVR_OK", 1: "PVR_EINVAL", 2: "PVR_ESHAPE", 3: "PVR_ENOMEM",
            4: "PVR_EHIP", 5: "PVR_ENUMERIC", 6: "PVR_EUNSUPPORTED"}
@@ -93,6 +95,7 @@ EXPORTS = ["pvr_last_error", "pvr_version", "pvr_plan_create", "pvr_plan_destroy
            "pvr_backproject_f64", "pvr_robust_weights", "pvr_sr_update",
            "pvr_register_patches", "pvr_simulate_grad_theta", "pvr_simulate_grad_theta_f64",
            "pvr_ncc_grad", "pvr_plan_set_tiles", "pvr_plan_set_timing", "pvr_plan_kernel_time",
+           "pvr_plan_set_psf",
            "pvr_cnn_conv_fwd", "pvr_cnn_conv_dgrad",
            "pvr_cnn_wgrad_scratch", "pvr_cnn_conv_wgrad", "pvr_cnn_pack_pairs",
            "pvr_cnn_head_scratch", "pvr_cnn_head", "pvr_cnn_adam"]
@@ -132,6 +135,7 @@ def load(path: str = LIB_PATH):
     L.pvr_simulate_grad_theta_f64.argtypes = [P, P, P, P, P]
     L.pvr_ncc_grad.argtypes = [P, P, P, P, P, P]
     L.pvr_plan_set_tiles.argtypes = [P, i32, i32, P]
+    L.pvr_plan_set_psf.argtypes = [P, i32]
     L.pvr_plan_set_timing.argtypes = [P, i32]
     L.pvr_plan_kernel_time.argtypes = [P, i32, P, P]
     L.pvr_cnn_conv_fwd.argtypes = [P, P, P, P, i32, i32, i32, i32, i32, i32, i32, P]
@@ -259,6 +263,11 @@ class Plan:
         ms, n = ctypes.c_double(), ctypes.c_int32()
         _check(load().pvr_plan_kernel_time(self.h, int(kernel), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def set_psf(self, kind: int):
+        """PVR_PSF_GAUSSIAN or PVR_PSF_SINC; takes effect at the next build."""
+        _check(load().pvr_plan_set_psf(self.h, int(kind)))
+        self.psf = int(kind)
 
     def set_tiles(self, tile_w: int, tile_h: int):
         _check(load().pvr_plan_set_tiles(self.h, int(tile_w), int(tile_h), _stream()))

@@ -1,0 +1,121 @@
+"""The sinc PSF (PVR_PSF_SINC: Taylor-series sinc in-plane, main lobe, times
+the truncated Gaussian slice profile) through the C ABI against the FP64
+oracle with the same PSF, on the tiny 32^3 case: normalisers and validity,
+per-sample simulation (1e-5 relative), the adjoint (bar of
+tests/_tolerance.py), the FP32 adjoint identity, 10 SR iterations (relative L2
+1e-4), the FP64 entry points (1e-12), and the unsupported calls."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import torch  # noqa: E402
+
+import oracle
+from oracle import recon
+from paper_1611_07289_amd import pvr, synth
+from tests._tolerance import adjoint_bar
+from tests.test_gpu_parity import _gpu_sr_loop, dev, host, sample_close
+
+
+@pytest.fixture(scope="module")
+def sinc():
+    print("[gpu] tiny32 problem, sinc PSF: building plan", flush=True)
+    P = synth.tiny_problem()
+    ctx = oracle.Ctx(P.grid, P.stacks, P.patches, psf="sinc")
+    plan = pvr.Plan.from_problems([P])
+    plan.set_psf(pvr.PVR_PSF_SINC)
+    plan.build(dev(P.theta_true, torch.float32))
+    torch.cuda.synchronize()
+    th32 = np.asarray(P.theta_true, np.float32).astype(np.float64)
+    yc, Z, val = ctx.simulate(P.x_true, th32)
+    y = synth.corrupt(yc, P.patches, P.outlier_patch, 0.01, P.seed_base + 3, P.seed_base + 5)
+    return dict(P=P, ctx=ctx, plan=plan, th32=th32, y=y, val=val)
+
+
+def test_sinc_normalisers_validity_and_simulate(sinc):
+    P, ctx, plan, th32, val = sinc["P"], sinc["ctx"], sinc["plan"], sinc["th32"], sinc["val"]
+    one = torch.ones(plan.V, dtype=torch.float32, device="cuda")
+    ys = torch.empty(plan.N, dtype=torch.float32, device="cuda")
+    plan.simulate(one, y_sim=ys)
+    g1 = host(ys)
+    assert np.array_equal(g1 > 0.5, val), "validity differs from the oracle"
+    assert np.allclose(g1[val], 1.0, atol=2e-6) and np.all(g1[~val] == 0)
+    plan.simulate(dev(P.x_true), y_sim=ys)
+    yo, _, _ = ctx.simulate(P.x_true, th32)
+    worst, _ = sample_close(host(ys), yo)
+    print(f"[gpu] sinc simulate worst per-sample rel err {worst:.2e}")
+    assert worst <= 1e-5
+    # the sinc model differs from the Gaussian one on the same data
+    yg, _, _ = oracle.Ctx(P.grid, P.stacks, P.patches).simulate(P.x_true, th32)
+    assert np.abs(yg - yo)[val].max() > 1.0
+
+
+def test_sinc_backproject_and_adjoint_identity(sinc):
+    P, ctx, plan, th32 = sinc["P"], sinc["ctx"], sinc["plan"], sinc["th32"]
+    rng = np.random.default_rng(21)
+    r = rng.normal(size=plan.N).astype(np.float32)
+    num = torch.empty(plan.V, dtype=torch.float32, device="cuda")
+    plan.backproject(dev(r), num=num)
+    ro = ctx.backproject(th32, r.astype(np.float64)).reshape(-1)
+    bar = adjoint_bar(ctx, th32, r.astype(np.float64))
+    err = float((np.abs(host(num) - ro) / (bar + 1e-30)).max())
+    print(f"[gpu] sinc backproject worst error / bar {err:.2e}")
+    assert err <= 1.0
+    x = torch.rand(plan.V, device="cuda")
+    Ax = torch.empty(plan.N, dtype=torch.float32, device="cuda")
+    plan.simulate(x, y_sim=Ax)
+    rd = dev(r)
+    lhs = float(torch.dot(Ax.double(), rd.double()))
+    rhs = float(torch.dot(x.double(), num.double()))
+    scale = float(torch.dot(Ax.double().abs(), rd.double().abs()))
+    assert abs(lhs - rhs) <= 1e-5 * scale
+
+
+def test_sinc_ten_sr_iterations_match_oracle(sinc):
+    P, ctx, plan, th32, y = sinc["P"], sinc["ctx"], sinc["plan"], sinc["th32"], sinc["y"]
+    X0 = recon.initial_volume(ctx, y, th32)
+    X = X0.copy()
+    state = recon.EMState()
+    Ws, pis = [], []
+    for it in range(10):
+        X, state, diag = recon.sr_iteration(ctx, X, y, th32, state, recon.SRParams())
+        Ws.append(diag["W"]); pis.append(diag["pi"])
+    near = sum(int(np.sum(np.abs(pi - 0.5) < 1e-3)) for pi in pis)
+    Xg, Wg = _gpu_sr_loop(plan, X0, y, 10, pvr.SRParams.make(), fix_w_list=Ws if near else None)
+    rel = np.linalg.norm(Xg.reshape(-1) - X.reshape(-1)) / np.linalg.norm(X)
+    print(f"[gpu] sinc 10 SR iterations rel-L2 {rel:.2e}; near-threshold {near}")
+    assert rel <= 1e-4
+    assert recon.psnr(Xg.reshape(X.shape), P.x_true) > recon.psnr(X0, P.x_true) + 10
+
+
+def test_sinc_f64_path_matches_oracle(sinc):
+    P, ctx = sinc["P"], sinc["ctx"]
+    plan = pvr.Plan.from_problems([P])
+    plan.set_psf(pvr.PVR_PSF_SINC)
+    plan.build(dev(P.theta_true, torch.float64))
+    ys = torch.empty(plan.N, dtype=torch.float64, device="cuda")
+    plan.simulate(dev(P.x_true.astype(np.float64)), y_sim=ys)
+    yo, _, _ = ctx.simulate(P.x_true, P.theta_true)
+    worst, _ = sample_close(host(ys), yo)
+    assert worst <= 1e-12, worst
+    r = np.random.default_rng(3).normal(size=P.N)
+    num = torch.empty(plan.V, dtype=torch.float64, device="cuda")
+    plan.backproject(dev(r), num=num)
+    ro = ctx.backproject(P.theta_true, r).reshape(-1)
+    rabs = ctx.backproject(P.theta_true, np.abs(r)).reshape(-1)
+    err = np.abs(host(num) - ro) / (rabs + 1e-300)
+    assert err.max() <= 1e-12, err.max()
+
+
+def test_sinc_unsupported_calls_fail_cleanly(sinc):
+    P, plan = sinc["P"], sinc["plan"]
+    X = dev(P.x_true)
+    y = torch.zeros(plan.N, dtype=torch.float32, device="cuda")
+    th = dev(P.theta_true, torch.float32)
+    with pytest.raises(pvr.PvrError, match="Gaussian PSF"):
+        plan.register(X, y, th)
+    with pytest.raises(pvr.PvrError, match="Gaussian PSF"):
+        plan.grad_theta(X, y, torch.empty(plan.M, 6, device="cuda"))
+    with pytest.raises(pvr.PvrError):
+        plan.set_psf(7)
