@@ -1,6 +1,10 @@
 #!/usr/bin/env python3
 """Benchmark of the PVR super-resolution hot path on one MI355X.
 
+Workloads: uterus256 (default) below; sinc256 the same with the paper's sinc
+PSF (pvr_plan_set_psf); batched, diff48, learned and multiscale as their
+functions say.
+
 Workload (default): the 256^3 whole-uterus case -- 1 mm grid, 4 stacks of
 256x256x60 slices at 1x1x4 mm (3 orthogonal + 1 oblique at 30 deg), PSF FWHM
 (1, 1, 4) mm, 64x64 patches with stride 32 (11 760 patches, 48.2 M samples),
@@ -59,6 +63,11 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0  # dense
 # 1 + weighted value 2; adjoint: two weighted sums 4).
 FLOP_PER_NNZ_FWD = 16
 FLOP_PER_NNZ_ADJ = 17
+# The sinc PSF: offsets (3), scaling (3), two Taylor series in (pi t)^2 to the
+# 8th power (2 x 18), the slice profile (square, scale, exponential, cut-off:
+# 4), the product (2), accumulation (forward 3, adjoint 4).
+FLOP_PER_NNZ_SINC_FWD = 51
+FLOP_PER_NNZ_SINC_ADJ = 52
 # HBM-side bytes per launch of the hot kernels, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes scaled by a 1 GiB device copy; valid only for the library
 # sources they were taken on (their SHA-256 is stored beside the figures).
@@ -97,7 +106,7 @@ def log(msg):
 
 def make_workload(name: str):
     from paper_1611_07289_amd import synth
-    if name == "uterus256":
+    if name in ("uterus256", "sinc256"):
         return [synth.full_problem()]
     if name == "tiny32":
         return [synth.tiny_problem()]
@@ -112,13 +121,18 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def nnz_estimate(probs, n_valid):
+def nnz_estimate(probs, n_valid, sinc=False):
     """Expected PSF support size times the valid samples: a support is the
     lattice points inside the ellipsoid of semi-axes k sigma, on average its
-    volume 4/3 pi k^3 prod(sigma) over the voxel volume (k = 3)."""
+    volume 4/3 pi k^3 prod(sigma) over the voxel volume (k = 3); for the sinc
+    PSF inside the box of half widths (w_u, w_v, k sigma_n), w = in-plane
+    FWHM."""
     P = probs[0]
     vox = abs(np.linalg.det(P.grid.vox2world[:, :3]))
-    sig = np.asarray(P.stacks[0].fwhm_mm) / (2 * math.sqrt(2 * math.log(2)))
+    fw = np.asarray(P.stacks[0].fwhm_mm, float)
+    sig = fw / (2 * math.sqrt(2 * math.log(2)))
+    if sinc:
+        return 8.0 * fw[0] * fw[1] * 3.0 * sig[2] / vox * n_valid
     return 4.0 / 3.0 * math.pi * 27.0 * float(np.prod(sig)) / vox * n_valid
 
 
@@ -224,6 +238,9 @@ def main():
         multiscale_bench(args, *probs[0], dev)
         return
     plan = pvr.Plan.from_problems(probs)
+    sinc = args.workload == "sinc256"
+    if sinc:
+        plan.set_psf(pvr.PVR_PSF_SINC)
     log(f"[bench] plan: N={plan.N} M={plan.M} V={plan.V} problems={plan.P}")
 
     theta = torch.from_numpy(np.concatenate([P.theta_true for P in probs]).astype(np.float32)).to(dev)
@@ -322,9 +339,12 @@ def main():
         tot, n = plan.kernel_time(kid)
         kern[name] = tot / max(n, 1)
     plan.set_timing(False)
-    nnz = nnz_estimate(probs, n_valid)
+    nnz = nnz_estimate(probs, n_valid, sinc)
     dom = max(kern, key=kern.get)
-    fpn = FLOP_PER_NNZ_FWD if dom == "k_simulate" else FLOP_PER_NNZ_ADJ
+    if sinc:
+        fpn = FLOP_PER_NNZ_SINC_FWD if dom == "k_simulate" else FLOP_PER_NNZ_SINC_ADJ
+    else:
+        fpn = FLOP_PER_NNZ_FWD if dom == "k_simulate" else FLOP_PER_NNZ_ADJ
     achieved = nnz * fpn / (kern[dom] * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved,
                 "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -349,12 +369,13 @@ def main():
         "config": {"workload": args.workload, "problems": plan.P, "patches": plan.M,
                    "samples": plan.N, "valid_samples": n_valid, "voxels": plan.V,
                    "patch": "64x64 stride 32" if args.workload == "uterus256" else "mixed",
-                   "psf_fwhm_mm": [1, 1, 4], "parallelism": "single GPU"},
+                   "psf_fwhm_mm": [1, 1, 4], "psf": "sinc" if sinc else "gaussian",
+                   "parallelism": "single GPU"},
         "kernels_ms": per,
         "hot_kernels_ms": kern,
         "build_ms": t_build * 1e3,
         "roofline": roofline,
-        "hbm_equivalent": hbm_equivalent(nnz, n_valid, plan.V, ms_step),
+        "hbm_equivalent": hbm_equivalent(nnz, n_valid, plan.V, ms_step),  # same bytes per nonzero
         "em": {"sigma2": st[0].sigma2, "c": st[0].c, "excluded": st[0].n_excluded},
     }
 

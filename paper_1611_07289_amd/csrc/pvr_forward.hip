@@ -36,7 +36,7 @@ k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patch
   // patches whose rows run along y read the y-fastest copy, so that the lanes
   // of a wave (consecutive pixels of a row) read consecutive addresses
   const bool sinc = g.psf == PVR_PSF_SINC;
-  const bool xt = XT != nullptr && pt.layout == 1 && !sinc;
+  const bool xt = XT != nullptr && pt.layout == 1;
   const __amdgpu_buffer_rsrc_t xr = raw_buffer((xt ? XT : X) + pr.vol_off, nbytes);
   const int n = pt.w * pt.h;
   const int l1 = min(n, wk.l0 + SIM_CHUNK);
@@ -55,7 +55,12 @@ k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patch
       using G = typename GeoOf<T>::type;
       if (sinc) {
         T z;
-        yh = psf_walk_sinc<T, G, true>(g, pr, b, f, xr, &z) * iz;
+        if (xt)
+          yh = (g.perm[2] == 1 ? psf_walk_sinc<T, G, true, 1, true>(g, pr, b, f, xr, nbytes, &z)
+                               : psf_walk_sinc<T, G, true, 2, true>(g, pr, b, f, xr, nbytes, &z)) * iz;
+        else
+          yh = (g.perm[2] == 0 ? psf_walk_sinc<T, G, true, 1>(g, pr, b, f, xr, nbytes, &z)
+                               : psf_walk_sinc<T, G, true, 2>(g, pr, b, f, xr, nbytes, &z)) * iz;
       } else if (xt)
         yh = (g.perm[2] == 1 ? psf_walk_fwd<T, G, false, 1, true>(g, pr, b, f, xr, nbytes)
                              : psf_walk_fwd<T, G, false, 2, true>(g, pr, b, f, xr, nbytes)) * iz;
@@ -188,7 +193,7 @@ __global__ void __launch_bounds__(256) k_transpose_xy(const float *__restrict__ 
 // Fills p->d_xt from X when the plan has patches that read it; returns the
 // copy (or nullptr).
 static const float *volume_xt(const pvr_plan *p, const float *X, hipStream_t stream) {
-  if (!p->any_xt || p->psf != PVR_PSF_GAUSSIAN) return nullptr;
+  if (!p->any_xt) return nullptr;
   for (int b = 0; b < p->P; ++b) {
     const ProbDev &pr = p->h_prob[b];
     const dim3 grid((pr.nx + XT_TILE - 1) / XT_TILE, (pr.ny + XT_TILE - 1) / XT_TILE, pr.nz);

@@ -404,14 +404,17 @@ template <> __device__ __forceinline__ double sinc_poly<double>(double t) {
 // t = L (voxel - centre), the support is |t_u| < 1, |t_v| < 1, |t_n| <= k.
 // The outer axes a, b run over the box's voxel extents; along the inner axis
 // c each row's range is the intersection of the three slabs (exact, then
-// widened by 1e-4 voxel; the weight decides membership voxel by voxel).
-// Returns sum g_hat X (WITH_X) and sum g_hat in *z_out, over in-grid voxels.
-template <typename T, typename GEO, bool WITH_X>
+// widened by 1e-4 voxel; the weight decides membership voxel by voxel).  The
+// row's voxels are loaded four at a time (load_group; ROW and XT as for
+// psf_walk_fwd).  Returns sum g_hat X (WITH_X) and sum g_hat in *z_out, over
+// in-grid voxels.
+template <typename T, typename GEO, bool WITH_X, int ROW = 0, bool XT = false>
 __device__ __forceinline__ T psf_walk_sinc(const GEO &g, const ProbDev &p, const int b[3],
-                                           const T f[3], __amdgpu_buffer_rsrc_t xr, T *z_out) {
-  const int sy = p.nx, sz = p.nx * p.ny;
+                                           const T f[3], __amdgpu_buffer_rsrc_t xr,
+                                           unsigned nbytes, T *z_out) {
+  const int sx = XT ? p.ny : 1, sy = XT ? 1 : p.nx, sz = p.nx * p.ny;
   const int ia = g.perm[0], ib = g.perm[1], ic = g.perm[2];
-  const int st_a = sel3(ia, 1, sy, sz), st_b = sel3(ib, 1, sy, sz), st_c = sel3(ic, 1, sy, sz);
+  const int st_a = sel3(ia, sx, sy, sz), st_b = sel3(ib, sx, sy, sz), st_c = sel3(ic, sx, sy, sz);
   const int b_a = sel3(ia, b[0], b[1], b[2]), b_b = sel3(ib, b[0], b[1], b[2]),
             b_c = sel3(ic, b[0], b[1], b[2]);
   const int n_a = sel3(ia, p.nx, p.ny, p.nz), n_b = sel3(ib, p.nx, p.ny, p.nz),
@@ -432,7 +435,8 @@ __device__ __forceinline__ T psf_walk_sinc(const GEO &g, const ProbDev &p, const
   const int hi_a = min((int)floor(f_a + ea), n_a - 1 - b_a);
   const int lo_b = max((int)ceil(f_b - eb), -b_b);
   const int hi_b = min((int)floor(f_b + eb), n_b - 1 - b_b);
-  const int vb = (b[2] * p.ny + b[1]) * p.nx + b[0];
+  const int vb = b[0] * sx + b[1] * sy + b[2] * sz;
+  const unsigned step = (unsigned)st_c * (unsigned)sizeof(T);
   T acc = (T)0, z = (T)0;
   for (int oa = lo_a; oa <= hi_a; ++oa) {
     const T wa = (T)oa - f_a;
@@ -455,20 +459,26 @@ __device__ __forceinline__ T psf_walk_sinc(const GEO &g, const ProbDev &p, const
       if (empty || !(lo <= hi)) continue;
       const int lo_c = max((int)ceil(f_c + lo - (T)1e-4), -b_c);
       const int hi_c = min((int)floor(f_c + hi + (T)1e-4), n_c - 1 - b_c);
+      const int n = hi_c - lo_c + 1;
       const T wc0 = (T)lo_c - f_c;
       T t0 = fma(Lc[0], wc0, r[0]), t1 = fma(Lc[1], wc0, r[1]), t2 = fma(Lc[2], wc0, r[2]);
       unsigned off = (unsigned)(vb + oa * st_a + ob * st_b + lo_c * st_c) * (unsigned)sizeof(T);
-      for (int oc = lo_c; oc <= hi_c; ++oc) {
-        T gz = fast_exp2<T>(-kap * t2 * t2) - cut;
-        gz = gz > (T)0 ? gz : (T)0;
-        const bool in = fabs(t0) < (T)1 && fabs(t1) < (T)1;
-        const T gh = in ? sinc_poly<T>(t0) * sinc_poly<T>(t1) * gz : (T)0;
-        if (WITH_X) acc = fma(gh, load_vox<T>(xr, off), acc);
-        z += gh;
-        t0 += Lc[0];
-        t1 += Lc[1];
-        t2 += Lc[2];
-        off += (unsigned)st_c * (unsigned)sizeof(T);
+      for (int k0 = 0; k0 < n; k0 += 4) {
+        T x[4];
+        if (WITH_X) load_group<T, ROW>(xr, off, step, nbytes, x);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          T gz = fast_exp2<T>(-kap * t2 * t2) - cut;
+          gz = gz > (T)0 ? gz : (T)0;
+          const bool in = k0 + k < n && fabs(t0) < (T)1 && fabs(t1) < (T)1;
+          const T gh = in ? sinc_poly<T>(t0) * sinc_poly<T>(t1) * gz : (T)0;
+          if (WITH_X) acc = fma(gh, x[k], acc);
+          z += gh;
+          t0 += Lc[0];
+          t1 += Lc[1];
+          t2 += Lc[2];
+        }
+        off += 4 * step;
       }
     }
   }

@@ -75,7 +75,7 @@ k_normalisers(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ pa
     T z = 0, acc = 0;
     if (ok && g.psf == PVR_PSF_SINC) {
       const __amdgpu_buffer_rsrc_t none = raw_buffer((const T *)nullptr, 0u);
-      psf_walk_sinc<T, typename GeoOf<T>::type, false>(g, pr, b, f, none, &z);
+      psf_walk_sinc<T, typename GeoOf<T>::type, false>(g, pr, b, f, none, 0u, &z);
     } else if (ok) {
       psf_walk<T, typename GeoOf<T>::type, false>(g, pr, b, f, nullptr, z, acc);
     }
