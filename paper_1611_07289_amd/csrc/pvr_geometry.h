@@ -78,9 +78,12 @@ __host__ __device__ static inline void rot_zyx(const double *th, double *R) {
 }
 
 // Per-patch motion geometry (see pvr_internal.h).  One thread per patch.
+// PSF: PVR_PSF_GAUSSIAN or PVR_PSF_SINC, a template parameter so that code
+// which only ever uses one PSF (registration) carries no code for the other.
+template <int PSF = PVR_PSF_GAUSSIAN>
 __device__ inline void make_geometry(const ProbDev &pr, const StackDev &st, const PatchDev &pt,
-                              const double *th, double k, GeoD &g, GeoF &gf, int *bb,
-                              int psf = PVR_PSF_GAUSSIAN) {
+                              const double *th, double k, GeoD &g, GeoF &gf, int *bb) {
+  constexpr int psf = PSF;
   double R[9];
   rot_zyx(th, R);
   double A[9], o[3];
@@ -119,7 +122,7 @@ __device__ inline void make_geometry(const ProbDev &pr, const StackDev &st, cons
   const double K2 = KAPPA * k * k;
   double ext[3];
   for (int b = 0; b < 3; ++b) ext[b] = sqrt(K2 * Ai[4 * b]);
-  if (psf == PVR_PSF_SINC) {
+  if constexpr (psf == PVR_PSF_SINC) {
     // support box |t_u| < 1, |t_v| < 1, |t_n| <= k with t = diag(1/w_u, 1/w_v,
     // 1/sigma_n) F^T Vl (voxel offset): its half extent along voxel axis b is
     // sum_a |(Wl F)_{b a}| h_a, h = (w_u, w_v, k sigma_n)
@@ -136,7 +139,7 @@ __device__ inline void make_geometry(const ProbDev &pr, const StackDev &st, cons
       ext[b] = fabs(WF[3 * b]) * hw[0] + fabs(WF[3 * b + 1]) * hw[1] + fabs(WF[3 * b + 2]) * hw[2];
   }
   g.psf = psf;
-  g.kcut = k;
+  g.kcut = k;  // (L is set for the sinc PSF only)
   for (int b = 0; b < 3; ++b) { g.ext[b] = ext[b]; gf.ext[b] = (float)ext[b]; }
   int ic = 0;
   if (ext[1] > ext[ic]) ic = 1;
@@ -161,7 +164,7 @@ __device__ inline void make_geometry(const ProbDev &pr, const StackDev &st, cons
   g.cu = sk * st.spacing[0] / st.sigma[0];
   g.cv = sk * st.spacing[1] / st.sigma[1];
   g.ck = sk * st.spacing[2] / st.sigma[2];
-  if (psf == PVR_PSF_SINC) {
+  if constexpr (psf == PVR_PSF_SINC) {
     // in-plane: pixel offset -> t (the sinc's argument over pi)
     g.cu = st.spacing[0] / st.wz[0];
     g.cv = st.spacing[1] / st.wz[1];
@@ -170,7 +173,7 @@ __device__ inline void make_geometry(const ProbDev &pr, const StackDev &st, cons
   // the support's half widths along every stack axis, mapped by H
   double r3[3];
   for (int a = 0; a < 3; ++a) r3[a] = k * st.sigma[a] / st.spacing[a];
-  if (psf == PVR_PSF_SINC)
+  if constexpr (psf == PVR_PSF_SINC)
     for (int a = 0; a < 2; ++a) r3[a] = st.wz[a] / st.spacing[a];
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
   for (int q = 0; q < 8; ++q) {
@@ -207,8 +210,10 @@ __device__ inline void make_geometry(const ProbDev &pr, const StackDev &st, cons
   g.hv = psf == PVR_PSF_SINC ? sinc_halfwidth(g.cv) : cand_halfwidth(K2, g.cv);
   gf.hu = g.hu; gf.hv = g.hv;
   gf.psf = g.psf;
-  gf.kcut = (float)g.kcut;
-  for (int q = 0; q < 9; ++q) gf.L[q] = (float)g.L[q];
+  if constexpr (psf == PVR_PSF_SINC) {
+    gf.kcut = (float)g.kcut;
+    for (int q = 0; q < 9; ++q) gf.L[q] = (float)g.L[q];
+  }
   gf.inv_cu = (float)g.inv_cu; gf.inv_cv = (float)g.inv_cv;
   for (int q = 0; q < 3; ++q) gf.perm[q] = g.perm[q];
 }

@@ -37,7 +37,10 @@ __global__ void k_geometry(const ProbDev *__restrict__ probs, const StackDev *__
   const StackDev st = stacks[pt.stack];
   GeoD g;
   GeoF f;
-  make_geometry(probs[pt.problem], st, pt, theta + 6 * s, k, g, f, bb + 6 * s, psf);
+  if (psf == PVR_PSF_SINC)
+    make_geometry<PVR_PSF_SINC>(probs[pt.problem], st, pt, theta + 6 * s, k, g, f, bb + 6 * s);
+  else
+    make_geometry<PVR_PSF_GAUSSIAN>(probs[pt.problem], st, pt, theta + 6 * s, k, g, f, bb + 6 * s);
   gd[s] = g;
   gf[s] = f;
   // voxel -> pixel map and the pixel-frame support box of the patch
