@@ -35,7 +35,13 @@ Extra objects on the JSON line:
                 registration and with the learned initialiser (trained first
                 on --learned-pairs forward-model pairs of another phantom;
                 training time reported apart), each with the registration
-                gradient by central differences and exact ("_exact").
+                gradient by central differences and exact ("_exact");
+  superpixel_pvr  (uterus256, unless --no-superpixel) whole slices observed
+                under per-slice motion, reconstructed (exact registration,
+                same schedule) from 64x64 stride-32 square patches and from
+                SLIC superpixel patches (a = 32 and a = 64, dilation 60 % of
+                a) of the same slices: patch and sample counts, extraction
+                time, seconds and PSNR of each.
 """
 from __future__ import annotations
 
@@ -209,6 +215,8 @@ def main():
     ap.add_argument("--learned-pairs", type=int, default=1_000_000,
                     help="training pairs of the learned initialiser for the full-PVR "
                          "comparison (0: plain reconstruction only)")
+    ap.add_argument("--no-superpixel", action="store_true",
+                    help="skip the superpixel-versus-square-patch reconstruction")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (for counter scaling)")
     args = ap.parse_args()
@@ -381,6 +389,8 @@ def main():
 
     if not args.no_full_pvr and args.workload == "uterus256":
         out["full_pvr"] = full_pvr(plan, probs, y, Xtrue, dev, learned_pairs=args.learned_pairs)
+    if not args.no_superpixel and args.workload == "uterus256":
+        out["superpixel_pvr"] = superpixel_pvr(probs[0], Xtrue, dev)
 
     if args.copy_calibration:
         a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev)
@@ -671,6 +681,88 @@ def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10, learned_pairs=0):
     res["cycles"] = cycles
     res["sr_iterations"] = n_sr
     res["paper_runtime_s"] = "2000-4000 (whole PVR, unspecified NVIDIA GPU machines; Sec. V)"
+    return res
+
+
+def superpixel_pvr(P, Xtrue, dev, sizes=((32, 19), (64, 38)), cycles=3, n_sr=10,
+                   max_rot_deg=4.0, max_trans_mm=4.0, square=True):
+    """Square versus superpixel patches on the same observed slices (paper
+    Sec. II "Patch Extraction").  Every slice of the four stacks is simulated
+    whole under its own rigid motion about the slice centre (<= max_rot_deg,
+    <= max_trans_mm), with 1 % noise; square patches (64x64, stride 32) and
+    SLIC superpixels (step a, dilation gamma = 60 % of a, compactness t0 = 40
+    adapting per superpixel, t_min = 5, 10 iterations) for every (a, gamma) in
+    `sizes` are cut from these slices, and each set is reconstructed from zero
+    motion with exact registration.  Overlapping patches share their pixels'
+    noise here (unlike the per-patch observations of the main workload), so
+    the PSNR ceiling is lower."""
+    import torch
+    from paper_1611_07289_amd import driver, pvr, superpixel, synth
+    ns = sum(s.nslices for s in P.stacks)
+    h, w = P.stacks[0].ny, P.stacks[0].nx
+    whole = synth.square_patches(P.stacks, max(h, w), max(h, w))
+    assert whole.M == ns and int(whole.w[0]) == w and int(whole.h[0]) == h
+    plan_sl = pvr.Plan([P.grid], [P.stacks], [whole])
+    th_sl = synth.random_motion(ns, max_rot_deg, max_trans_mm, P.seed_base + 40)
+    plan_sl.build(torch.from_numpy(th_sl.astype(np.float32)).to(dev))
+    ysl = torch.empty(plan_sl.N, dtype=torch.float32, device=dev)
+    plan_sl.simulate(Xtrue, y_sim=ysl)
+    ych = synth.corrupt(ysl.cpu().numpy(), whole, np.zeros(ns, bool), 0.01, P.seed_base + 41,
+                        P.seed_base + 42)
+    img = torch.from_numpy(ych).to(dev).reshape(ns, h, w)
+    del plan_sl, ysl, ych
+    image_of = np.zeros(len(P.stacks) + 1, np.int64)
+    image_of[1:] = np.cumsum([s.nslices for s in P.stacks])
+    iss = np.array([(si, k) for si, s in enumerate(P.stacks) for k in range(s.nslices)], np.int32)
+    res = {"slices": ns,
+           "slice_motion": f"<= {max_rot_deg:g} deg, <= {max_trans_mm:g} mm per slice"}
+
+    def recon(key, patches, y, mask):
+        plan = pvr.Plan([P.grid], [P.stacks], [patches])
+        ymax = float(y.abs().max())
+        th0 = torch.zeros(plan.M, 6, dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X, th, hist = driver.reconstruct(plan, y, th0, cycles=cycles, n_sr=n_sr,
+                                         reg_params=pvr.RegParams.make(min_std=0.01 * ymax,
+                                                                       exact=True),
+                                         sample_mask=mask)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        n_in = plan.N if mask is None else int(mask.sum())
+        res[key] = {"patches": plan.M, "samples": plan.N, "samples_in_patches": n_in,
+                    "seconds": sec, "psnr_db": driver.psnr(X, Xtrue, plan),
+                    "timings": hist["timings"]}
+        log(f"superpixel_pvr {key}: M={plan.M} N={plan.N} {sec:.3f} s, "
+            f"PSNR {res[key]['psnr_db']:.2f} dB")
+        del plan
+
+    if square:
+        # square patches: the pack call with one label covering every slice
+        sq = synth.square_patches(P.stacks, 64, 32)
+        tab = np.column_stack([image_of[sq.stack] + sq.slice, np.zeros(sq.M, np.int32), sq.x0,
+                               sq.y0, sq.w, sq.h]).astype(np.int32)
+        zero = torch.zeros(ns, h, w, dtype=torch.int32, device=dev)
+        y_sq, _ = superpixel.pack(img, zero, 0, tab)
+        del zero
+        recon("square", sq, y_sq, None)
+        del y_sq
+    for a, gamma in sizes:
+        key = f"superpixel_a{a}"
+        superpixel.superpixel_patches(img[:4], a, gamma, 40.0, 5.0, 10, iss[:4])  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cols, y_sp, m_sp, tab, lab, C = superpixel.superpixel_patches(img, a, gamma, 40.0, 5.0,
+                                                                      10, iss)
+        torch.cuda.synchronize()
+        ext = (time.perf_counter() - t0) * 1e3
+        recon(key, synth.Patches(**{k: np.asarray(v, np.int32) for k, v in cols.items()}),
+              y_sp, m_sp)
+        res[key].update({"a": a, "gamma": gamma, "extraction_ms": ext})
+        if square:
+            res[key]["delta_psnr_db"] = res[key]["psnr_db"] - res["square"]["psnr_db"]
+            res[key]["speedup"] = res["square"]["seconds"] / res[key]["seconds"]
+        del y_sp, m_sp, lab, C
     return res
 
 

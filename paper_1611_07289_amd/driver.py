@@ -82,13 +82,16 @@ def sr_iterations(plan, X, y, buf: Buffers, n_sr: int, params: Optional[pvr.SRPa
 def reconstruct(plan, y, theta0, cycles: int = 3, n_sr: int = 10,
                 reg_params: Optional[pvr.RegParams] = None,
                 sr_params: Optional[pvr.SRParams] = None, register: bool = True,
-                init_fn=None, active_schedule=None):
+                init_fn=None, active_schedule=None, sample_mask=None):
     """Full reconstruction; theta0 is [M, 6] float32 on the device and is
     updated in place.  ``init_fn(plan, X, y, theta)``, when given, runs before
     each registration (a learned initialiser).  ``active_schedule``, when
     given, is a list of per-patch uint8 device masks used cycle by cycle (in
     turn): multi-scale patches (paper Sec. II, eq. Y_i), where cycle c
     registers and reconstructs from the patches of one scale only.
+    ``sample_mask`` (uint8 [N] on the device), when given, applies at every
+    build: the samples of arbitrarily shaped patches (superpixels) inside
+    their rectangular boxes.
     Returns (X, theta, history)."""
     import torch
     buf = Buffers(plan, y.device)
@@ -103,7 +106,7 @@ def reconstruct(plan, y, theta0, cycles: int = 3, n_sr: int = 10,
         return time.perf_counter()
 
     t = tick()
-    plan.build(theta, active=active(0))
+    plan.build(theta, active=active(0), mask=sample_mask)
     X = initial_volume(plan, y, buf)
     t1 = tick(); timings["build"] += t1 - t
     hist = {"ncc": [], "excluded": []}
@@ -120,10 +123,10 @@ def reconstruct(plan, y, theta0, cycles: int = 3, n_sr: int = 10,
             t1 = tick(); timings["register"] += t1 - t
             hist["ncc"].append(float(buf.ncc.mean()))
             t = tick()
-            plan.build(theta, active=active(c))
+            plan.build(theta, active=active(c), mask=sample_mask)
             timings["build"] += tick() - t
         elif active_schedule:
-            plan.build(theta, active=active(c))
+            plan.build(theta, active=active(c), mask=sample_mask)
         t = tick()
         sr_iterations(plan, X, y, buf, n_sr, sr_params)
         timings["sr"] += tick() - t

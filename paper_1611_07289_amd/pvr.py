@@ -98,7 +98,9 @@ EXPORTS = ["pvr_last_error", "pvr_version", "pvr_plan_create", "pvr_plan_destroy
            "pvr_plan_set_psf",
            "pvr_cnn_conv_fwd", "pvr_cnn_conv_dgrad",
            "pvr_cnn_wgrad_scratch", "pvr_cnn_conv_wgrad", "pvr_cnn_pack_pairs",
-           "pvr_cnn_head_scratch", "pvr_cnn_head", "pvr_cnn_adam"]
+           "pvr_cnn_head_scratch", "pvr_cnn_head", "pvr_cnn_adam",
+           "pvr_slic_centres", "pvr_slic_init", "pvr_slic_assign", "pvr_slic_update", "pvr_slic",
+           "pvr_slic_boxes", "pvr_slic_pack"]
 
 _lib = None
 
@@ -149,9 +151,18 @@ def load(path: str = LIB_PATH):
     L.pvr_cnn_head.argtypes = [P, i32, i32, P, P, P, P, P, P, P, P, P, P, P]
     L.pvr_cnn_adam.argtypes = [P, P, P, P, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                ctypes.c_float, i32, P, P, i32, i32, P]
+    f32 = ctypes.c_float
+    L.pvr_slic_centres.argtypes = [i32, i32, i32]
+    L.pvr_slic_centres.restype = i64
+    L.pvr_slic_init.argtypes = [P, i32, i32, i32, i32, f32, P, P]
+    L.pvr_slic_assign.argtypes = [P, i32, i32, i32, i32, P, P, P, P]
+    L.pvr_slic_update.argtypes = [P, i32, i32, i32, i32, P, f32, P, P]
+    L.pvr_slic.argtypes = [P, i32, i32, i32, i32, f32, f32, i32, P, P, P, P]
+    L.pvr_slic_boxes.argtypes = [P, i32, i32, i32, i32, P, i32, P, P]
+    L.pvr_slic_pack.argtypes = [P, P, i32, i32, i32, i32, i32, P, P, P, P]
     for name in EXPORTS:
         if name not in ("pvr_last_error", "pvr_version", "pvr_plan_destroy", "pvr_plan_inv_z",
-                        "pvr_cnn_wgrad_scratch", "pvr_cnn_head_scratch"):
+                        "pvr_cnn_wgrad_scratch", "pvr_cnn_head_scratch", "pvr_slic_centres"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -515,3 +515,19 @@ def residual_mixture(n: int, seed: int, sigma: float = 10.0, frac_in: float = 0.
     inl = rng.random(n) < frac_in
     e = np.where(inl, rng.normal(0.0, sigma, size=n), rng.uniform(lo, hi, size=n))
     return e
+
+
+def slice_images(n_img: int, h: int, w: int, seed: int, n: int = 64,
+                 noise: float = 0.01) -> np.ndarray:
+    """float32 [n_img][h][w] test images for superpixel clustering: axial
+    slices of a uterus phantom of n^3 voxels (evenly spaced through its middle
+    half, cropped or zero-padded to h x w) plus Gaussian noise of `noise`
+    times the phantom maximum."""
+    V = phantom_uterus(n, seed, seed + 1)
+    rng = np.random.default_rng(seed + 2)
+    zs = np.linspace(n // 4, 3 * n // 4, n_img).astype(int)
+    out = np.zeros((n_img, h, w), np.float32)
+    hh, ww = min(h, n), min(w, n)
+    out[:, :hh, :ww] = V[zs, :hh, :ww]
+    out += rng.normal(0.0, noise * float(V.max()), out.shape).astype(np.float32)
+    return out

@@ -1,5 +1,5 @@
 """C-ABI checks that need no GPU: the library loads, exports every function
-declared in include/pvr.h, its struct layouts match the header, and invalid
+declared in include/*.h, its struct layouts match the header, and invalid
 descriptors are rejected on the host before any device call."""
 import ctypes
 import os
@@ -16,7 +16,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     names = set()
-    for h in ("pvr.h", "pvr_cnn.h"):
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
         txt = open(os.path.join(ROOT, "include", h)).read()
         names |= set(re.findall(r"^(?:pvr_status|const char|const float|void|int64_t)[\s*]+"
                                 r"(pvr_[a-z0-9_]+)\s*\(", txt, re.M))
