@@ -81,10 +81,16 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_uterus256.json")
 
 
 def library_source_sha() -> str:
+    """Hash of the sources the two PSF kernels are compiled from (their
+    translation units, the plan that lays out their inputs, every header)."""
     import glob
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1611_07289_amd", "csrc", "*"))):
+    csrc = os.path.join(ROOT, "paper_1611_07289_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(csrc, "*.h")) +
+                   [os.path.join(csrc, f) for f in ("pvr_forward.hip", "pvr_adjoint.hip",
+                                                    "pvr_plan.hip")])
+    for f in files:
         with open(f, "rb") as fh:
             h.update(os.path.basename(f).encode() + b"\0" + fh.read())
     return h.hexdigest()

@@ -7,11 +7,12 @@
  * step, t a compactness that adapts per superpixel).
  *
  * Images: FP32 [n_img][h][w] row-major, device.  Centres: FP32
- * [n_img][K][4] = (x, y, intensity, t), K = ceil(h / a) * ceil(w / a) per
- * image, one per a x a grid cell in row-major cell order.  Labels: int32
- * [n_img][h][w], the centre index within the image, -1 where no centre's
- * window reaches.  Scratch: uint64 [n_img][h][w] (packed distance and
- * index).  The caller owns all memory; calls are asynchronous on `stream`.
+ * [n_img][K][4] = (x, y, intensity, t), 16-byte aligned, K = ceil(h / a) *
+ * ceil(w / a) per image, one per a x a grid cell in row-major cell order.
+ * Labels: int32 [n_img][h][w], the centre index within the image, -1 where
+ * no centre's window reaches.  Scratch: at least n_img uint64 elements of
+ * device workspace.  The caller owns all memory; calls are asynchronous on
+ * `stream`.
  *
  *  init:   centres at their cell's middle pixel position (the cell clipped to
  *          the image), intensity of the nearest pixel, t = t0;

@@ -1,11 +1,11 @@
 // Superpixel patch extraction: SLIC on every observed slice (see
-// include/pvr_slic.h for the definition).  Assignment is a scatter from the
-// centres: one workgroup per (image, centre) walks the centre's 2a x 2a window
-// and takes, per pixel, the atomic minimum of (D^2 as FP32 bits) << 32 |
-// index.  D^2 >= 0, so the bit patterns order like the values and the packed
-// minimum is the least distance, ties to the lower index, whatever the order
-// the workgroups run in.  The update gathers: one workgroup per centre sums
-// the pixels of its window that carry its label.
+// include/pvr_slic.h for the definition).  Assignment is a gather over pixel
+// tiles: the centres that can reach a tile are listed in LDS, and every pixel
+// keeps the least (D^2 as FP32 bits) << 32 | index over the list.  D^2 >= 0,
+// so the bit patterns order like the values and the packed minimum is the
+// least distance, ties to the lower index, whatever the order of the list.
+// The update gathers too: one workgroup per centre sums the pixels of its
+// window that carry its label.
 #include <limits.h>
 #include <math.h>
 #include <stdint.h>
@@ -55,110 +55,165 @@ __global__ void k_slic_init(const float *__restrict__ img, int n_img, int h, int
   c[3] = t0;
 }
 
-__global__ void k_slic_fill(uint64_t *__restrict__ s, long long n) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) s[i] = ~0ull;
-}
-
+// Largest distance of a centre from its grid cell's middle, per image: a
+// centre whose window covers a pixel sits in a cell at most a + drift away.
 __global__ void __launch_bounds__(SLIC_T)
-k_slic_scatter(const float *__restrict__ img, int h, int w, int a, int K,
-               const float *__restrict__ C, uint64_t *__restrict__ best) {
-  const int im = blockIdx.y, k = blockIdx.x;
-  const float *c = C + 4 * ((long long)im * K + k);
-  const float cx = c[0], cy = c[1], ci = c[2], tt = c[3];
-  const float s = tt * tt / (float)(a * a);
-  int x0, x1, y0, y1;
-  window(cx, cy, a, h, w, x0, x1, y0, y1);
-  const int ww = x1 - x0 + 1, n = ww * (y1 - y0 + 1);
-  if (ww <= 0 || y1 < y0) return;
-  const long long base = (long long)im * h * w;
-  for (int q = threadIdx.x; q < n; q += SLIC_T) {
-    const int x = x0 + q % ww, y = y0 + q / ww;
-    const float dx = (float)x - cx, dy = (float)y - cy;
-    if (!(fabsf(dx) <= (float)a && fabsf(dy) <= (float)a)) continue;
-    const long long p = base + (long long)y * w + x;
-    const float dc = img[p] - ci;
-    const float d2 = fmaf(dc, dc, (dx * dx + dy * dy) * s);
-    const uint64_t packed = ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)k;
-    atomicMin((unsigned long long *)(best + p), (unsigned long long)packed);
+k_slic_drift(const float *__restrict__ C, int h, int w, int a, int kx, int K,
+             float *__restrict__ drift) {
+  __shared__ float red[SLIC_T / 64];
+  const int im = blockIdx.x;
+  float d = 0.0f;
+  for (int k = threadIdx.x; k < K; k += SLIC_T) {
+    const float *c = C + 4 * ((long long)im * K + k);
+    float gx, gy;
+    cell_of(k, kx, a, h, w, gx, gy);
+    const float e = fmaxf(fabsf(c[0] - gx), fabsf(c[1] - gy));
+    d = (e == e) ? fmaxf(d, e) : INFINITY;  // a NaN centre widens the search to all cells
   }
-}
-
-__global__ void k_slic_labels(const uint64_t *__restrict__ best, long long n,
-                              int32_t *__restrict__ labels) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) labels[i] = best[i] == ~0ull ? -1 : (int32_t)(best[i] & 0xffffffffu);
-}
-
-// sum of RED values over the workgroup in a fixed order
-template <int RED>
-__device__ __forceinline__ void block_sum_d(double v[RED], double (*lds)[SLIC_T / 64]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int r = 0; r < RED; ++r) {
-    double x = v[r];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    if (lane == 0) lds[r][wave] = x;
-  }
+  for (int o = 32; o > 0; o >>= 1) d = fmaxf(d, __shfl_xor(d, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = d;
   __syncthreads();
-#pragma unroll
-  for (int r = 0; r < RED; ++r) {
-    double x = 0;
-#pragma unroll
-    for (int q = 0; q < SLIC_T / 64; ++q) x += lds[r][q];
-    v[r] = x;
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < SLIC_T / 64; ++q) d = fmaxf(d, red[q]);
+    drift[im] = fmaxf(d, red[0]);
   }
-  __syncthreads();
 }
 
+constexpr int TILE_X = 32, TILE_Y = SLIC_T / TILE_X;
+
+struct Cand {
+  float cx, cy, ci, s;
+  int k;
+};
+
+// Assignment as a gather: one workgroup per TILE_X x TILE_Y pixel tile.  The
+// centres whose window can reach the tile are found among the cells within
+// a + drift of it and listed in LDS (a chunk of SLIC_T cells at a time), then
+// every pixel takes the least packed (D^2 bits, index) over the list -- the
+// same key and the same FP32 arithmetic for every (pixel, centre) pair
+// whatever the order of the list.
+__global__ void __launch_bounds__(SLIC_T)
+k_slic_gather(const float *__restrict__ img, int h, int w, int a, int kx, int ky, int K,
+              const float *__restrict__ C, const float *__restrict__ drift,
+              int32_t *__restrict__ labels) {
+  __shared__ Cand list[SLIC_T];
+  __shared__ int n_list;
+  const int im = blockIdx.y;
+  const int tiles_x = (w + TILE_X - 1) / TILE_X;
+  const int tx0 = (blockIdx.x % tiles_x) * TILE_X, ty0 = (blockIdx.x / tiles_x) * TILE_Y;
+  const int tx1 = min(w, tx0 + TILE_X) - 1, ty1 = min(h, ty0 + TILE_Y) - 1;
+  const int x = tx0 + (threadIdx.x % TILE_X), y = ty0 + (threadIdx.x / TILE_X);
+  const bool inside = x <= tx1 && y <= ty1;
+  const long long p = ((long long)im * h + y) * w + x;
+  const float I = inside ? img[p] : 0.0f;
+  // cells i whose middle (in [i a, i a + (a-1)/2]) lies within a + drift of the tile
+  const float D = drift[im];
+  int i0 = 0, i1 = kx - 1, j0 = 0, j1 = ky - 1;
+  if (D <= 4.0f * (float)(h + w)) {
+    const float r = (float)a + D + 1.0f;
+    i0 = max(0, (int)floorf(((float)tx0 - r - 0.5f * (float)(a - 1)) / (float)a));
+    i1 = min(kx - 1, (int)floorf(((float)tx1 + r) / (float)a));
+    j0 = max(0, (int)floorf(((float)ty0 - r - 0.5f * (float)(a - 1)) / (float)a));
+    j1 = min(ky - 1, (int)floorf(((float)ty1 + r) / (float)a));
+  }
+  const int ni = i1 - i0 + 1, ncand = (ni > 0 && j1 >= j0) ? ni * (j1 - j0 + 1) : 0;
+  uint64_t best = ~0ull;
+  for (int c0 = 0; c0 < ncand; c0 += SLIC_T) {
+    if (threadIdx.x == 0) n_list = 0;
+    __syncthreads();
+    const int c = c0 + threadIdx.x;
+    if (c < ncand) {
+      const int k = (j0 + c / ni) * kx + i0 + c % ni;
+      const float4 cc = *(const float4 *)(C + 4 * ((long long)im * K + k));
+      // the window |x - cx| <= a meets the tile (one pixel of slack for rounding)
+      if (cc.x - (float)a <= (float)(tx1 + 1) && cc.x + (float)a >= (float)(tx0 - 1) &&
+          cc.y - (float)a <= (float)(ty1 + 1) && cc.y + (float)a >= (float)(ty0 - 1)) {
+        const int slot = atomicAdd(&n_list, 1);
+        list[slot] = Cand{cc.x, cc.y, cc.z, cc.w * cc.w / (float)(a * a), k};
+      }
+    }
+    __syncthreads();
+    const int n = n_list;
+    for (int e = 0; e < n; ++e) {
+      const Cand cd = list[e];
+      const float dx = (float)x - cd.cx, dy = (float)y - cd.cy;
+      if (!(fabsf(dx) <= (float)a && fabsf(dy) <= (float)a)) continue;
+      const float dc = I - cd.ci;
+      const float d2 = fmaf(dc, dc, (dx * dx + dy * dy) * cd.s);
+      const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)cd.k;
+      best = key < best ? key : best;
+    }
+    __syncthreads();
+  }
+  if (inside) labels[p] = best == ~0ull ? -1 : (int32_t)(best & 0xffffffffu);
+}
+
+// Update: one workgroup per centre over its window, one pass: count, FP64
+// sums of x, y and I, and the extreme intensities (max |I - mean| is reached
+// at one of them).  Waves take rows, lanes consecutive pixels of a row.
 __global__ void __launch_bounds__(SLIC_T)
 k_slic_update(const float *__restrict__ img, int h, int w, int a, int K,
               const int32_t *__restrict__ labels, float t_min, float *__restrict__ C) {
   __shared__ double lds[4][SLIC_T / 64];
+  __shared__ float lim[2][SLIC_T / 64];
   const int im = blockIdx.y, k = blockIdx.x;
   float *c = C + 4 * ((long long)im * K + k);
-  const float cx = c[0], cy = c[1];
   int x0, x1, y0, y1;
-  window(cx, cy, a, h, w, x0, x1, y0, y1);
-  const int ww = x1 - x0 + 1, n = (ww > 0 && y1 >= y0) ? ww * (y1 - y0 + 1) : 0;
+  window(c[0], c[1], a, h, w, x0, x1, y0, y1);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long base = (long long)im * h * w;
   double s[4] = {0, 0, 0, 0};  // count, sum x, sum y, sum I
-  for (int q = threadIdx.x; q < n; q += SLIC_T) {
-    const int x = x0 + q % ww, y = y0 + q / ww;
-    const long long p = base + (long long)y * w + x;
-    if (labels[p] == k) {
-      s[0] += 1.0;
-      s[1] += (double)x;
-      s[2] += (double)y;
-      s[3] += (double)img[p];
+  float imax = -INFINITY, imin = INFINITY;
+  for (int y = y0 + wave; y <= y1; y += SLIC_T / 64) {
+    const long long row = base + (long long)y * w;
+    for (int x = x0 + lane; x <= x1; x += 64) {
+      if (labels[row + x] == k) {
+        const float I = img[row + x];
+        s[0] += 1.0;
+        s[1] += (double)x;
+        s[2] += (double)y;
+        s[3] += (double)I;
+        imax = fmaxf(imax, I);
+        imin = fminf(imin, I);
+      }
     }
   }
-  block_sum_d<4>(s, lds);
-  if (!(s[0] > 0)) return;  // uniform: every lane holds the same sums
-  const double mi = s[3] / s[0];
-  double m[1] = {0.0};
-  for (int q = threadIdx.x; q < n; q += SLIC_T) {
-    const int x = x0 + q % ww, y = y0 + q / ww;
-    const long long p = base + (long long)y * w + x;
-    if (labels[p] == k) m[0] = fmax(m[0], fabs((double)img[p] - mi));
-  }
-  // maximum over the workgroup (order-independent)
-  {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double x = m[0];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
-    if (lane == 0) lds[0][wave] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = lds[0][0];
-      for (int q = 1; q < SLIC_T / 64; ++q) t = fmax(t, lds[0][q]);
-      c[0] = (float)(s[1] / s[0]);
-      c[1] = (float)(s[2] / s[0]);
-      c[2] = (float)mi;
-      c[3] = (float)fmax(t, (double)t_min);
+  for (int r = 0; r < 4; ++r) {
+    double v = s[r];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) lds[r][wave] = v;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    imax = fmaxf(imax, __shfl_xor(imax, o, 64));
+    imin = fminf(imin, __shfl_xor(imin, o, 64));
+  }
+  if (lane == 0) {
+    lim[0][wave] = imax;
+    lim[1][wave] = imin;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      t[r] = 0.0;
+      for (int q = 0; q < SLIC_T / 64; ++q) t[r] += lds[r][q];
     }
+    if (!(t[0] > 0)) return;  // no pixels: the centre stays
+    for (int q = 0; q < SLIC_T / 64; ++q) {
+      imax = fmaxf(imax, lim[0][q]);
+      imin = fminf(imin, lim[1][q]);
+    }
+    const double mi = t[3] / t[0];
+    const double dev = fmax((double)imax - mi, mi - (double)imin);
+    c[0] = (float)(t[1] / t[0]);
+    c[1] = (float)(t[2] / t[0]);
+    c[2] = (float)mi;
+    c[3] = (float)fmax(dev, (double)t_min);
   }
 }
 
@@ -201,13 +256,13 @@ extern "C" pvr_status pvr_slic_assign(const float *img, int32_t n_img, int32_t h
   if (a <= 0) return fail(PVR_EINVAL, "pvr_slic_assign: a must be positive");
   pvr_status st = check_sizes("pvr_slic_assign", n_img, h, w, a);
   if (st != PVR_OK) return st;
-  const int K = ((w + a - 1) / a) * ((h + a - 1) / a);
-  const long long n = (long long)n_img * h * w;
-  const unsigned g = (unsigned)((n + 255) / 256);
-  hipLaunchKernelGGL(k_slic_fill, dim3(g), dim3(256), 0, stream, scratch, n);
-  hipLaunchKernelGGL(k_slic_scatter, dim3(K, n_img), dim3(SLIC_T), 0, stream, img, h, w, a, K,
-                     centres, scratch);
-  hipLaunchKernelGGL(k_slic_labels, dim3(g), dim3(256), 0, stream, scratch, n, labels);
+  const int kx = (w + a - 1) / a, ky = (h + a - 1) / a, K = kx * ky;
+  float *drift = (float *)scratch;  // n_img floats
+  hipLaunchKernelGGL(k_slic_drift, dim3(n_img), dim3(SLIC_T), 0, stream, centres, h, w, a, kx, K,
+                     drift);
+  const long long tiles = (long long)((w + TILE_X - 1) / TILE_X) * ((h + TILE_Y - 1) / TILE_Y);
+  hipLaunchKernelGGL(k_slic_gather, dim3((unsigned)tiles, n_img), dim3(SLIC_T), 0, stream, img, h,
+                     w, a, kx, ky, K, centres, drift, labels);
   HIP_TRY(hipGetLastError());
   return PVR_OK;
   PVR_API_END();

@@ -42,7 +42,7 @@ def assign(img, C, a: int, scratch=None):
     n, h, w = img.shape
     lab = torch.empty(n, h, w, dtype=torch.int32, device=img.device)
     if scratch is None:
-        scratch = torch.empty(n * h * w, dtype=torch.int64, device=img.device)
+        scratch = torch.empty(n, dtype=torch.int64, device=img.device)
     pvr._check(pvr.load().pvr_slic_assign(img.data_ptr(), n, h, w, int(a), C.data_ptr(),
                                           scratch.data_ptr(), lab.data_ptr(), pvr._stream()))
     return lab
@@ -64,7 +64,7 @@ def slic(img, a: int, t0: float, t_min: float, iters: int = 10):
     n, h, w = img.shape
     C = torch.empty(n, n_centres(h, w, a), 4, dtype=torch.float32, device=img.device)
     lab = torch.empty(n, h, w, dtype=torch.int32, device=img.device)
-    scratch = torch.empty(n * h * w, dtype=torch.int64, device=img.device)
+    scratch = torch.empty(n, dtype=torch.int64, device=img.device)
     pvr._check(pvr.load().pvr_slic(img.data_ptr(), n, h, w, int(a), float(t0), float(t_min),
                                    int(iters), scratch.data_ptr(), C.data_ptr(), lab.data_ptr(),
                                    pvr._stream()))

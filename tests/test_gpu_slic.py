@@ -153,3 +153,20 @@ def test_constant_image_is_the_voronoi_of_the_grid_with_exact_ties():
         assert np.array_equal(lab[i], ref)
     C1 = sp.update(Ig, torch.from_numpy(lab).cuda(), C0.clone(), 8, TMIN).cpu().numpy()
     assert np.all(C1[..., 3] == TMIN) and np.all(C1[..., 2] == 300.0)
+
+
+def test_assignment_with_centres_far_from_their_cells(imgs):
+    # centres scattered anywhere over the image (several cells from their
+    # own): the gather widens its search by the largest such distance
+    I, Ig = imgs
+    rng = np.random.default_rng(17)
+    K = sp.n_centres(61, 53, A)
+    Cs = np.zeros((I.shape[0], K, 4), np.float32)
+    Cs[..., 0] = rng.uniform(0, 52, (I.shape[0], K))
+    Cs[..., 1] = rng.uniform(0, 60, (I.shape[0], K))
+    Cs[..., 2] = rng.uniform(0, 1000, (I.shape[0], K))
+    Cs[..., 3] = rng.uniform(5, 300, (I.shape[0], K))
+    Cs[0, :3, :2] = [[52.0, 60.0], [0.0, 0.0], [26.5, 30.25]]
+    lab = sp.assign(Ig, torch.from_numpy(Cs).cuda(), A).cpu().numpy()
+    for i in range(I.shape[0]):
+        _check_assignment(I[i].astype(np.float64), Cs[i].astype(np.float64), lab[i], A)
