@@ -359,6 +359,42 @@ pvr_status pvr_ncc_grad(const pvr_plan *plan, const float *y_obs,
                         const float *y_sim, float *grad_y, float *ncc,
                         hipStream_t stream);
 
+/* Numeric faults.  The SR update raises PVR_FAULT_VOLUME when a voxel of the
+ * new volume is not finite before the clamp (which would otherwise hide a
+ * NaN); the robust weights raise PVR_FAULT_RESIDUAL when a problem's residual
+ * statistics (sum of e^2, range of e, max |y|) are not finite -- a NaN or an
+ * infinity in X, y or on the way.  The flags accumulate on the device over
+ * calls; pvr_check synchronises `stream`, reads and clears them, and returns
+ * PVR_ENUMERIC with the raised flags named in pvr_last_error(), PVR_OK when
+ * none was raised. */
+#define PVR_FAULT_VOLUME 1u
+#define PVR_FAULT_RESIDUAL 2u
+pvr_status pvr_check(pvr_plan *plan, hipStream_t stream);
+
+/* Captured SR iterations (the batched form of Sec. III level II: every
+ * problem of the plan in each launch).  Records `iters` SR iterations into a
+ * HIP graph: iteration i simulates from the current volume (X for even i,
+ * X_alt for odd i) with residuals into resid, runs the robust weights with
+ * PVR_EM_RESID_FRESH (EM continues from em's state: start a cycle with an
+ * eager call with PVR_EM_INIT first), back-projects into num / den and writes
+ * the update into the other volume; after a launch the volume is in X when
+ * iters is even, else in X_alt.  All buffers are device memory of the sizes
+ * of the corresponding calls and must stay allocated while the graph lives;
+ * params is read at capture.  Before capturing, the call prepares the
+ * adjoint's brick index and synchronises `stream`; kernel timing must be off.
+ * A graph records the plan as it is: after pvr_plan_build*, pvr_plan_set_psf,
+ * pvr_plan_set_tiles or an index rebuild pvr_sr_graph_launch returns
+ * PVR_EINVAL (capture again).  Destroy graphs before their plan.  Launches
+ * are asynchronous on `stream`. */
+typedef struct pvr_sr_graph pvr_sr_graph;
+pvr_status pvr_sr_graph_create(pvr_plan *plan, float *X, float *X_alt, const float *y_obs,
+                               float *resid, float *p, float *pbar, float *patch_w,
+                               float *num, float *den, pvr_em_state *em,
+                               const pvr_sr_params *params, int32_t iters,
+                               hipStream_t stream, pvr_sr_graph **out);
+pvr_status pvr_sr_graph_launch(const pvr_sr_graph *graph, hipStream_t stream);
+void pvr_sr_graph_destroy(pvr_sr_graph *graph); /* NULL is a no-op */
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,5 +1,6 @@
 """Several independent reconstructions in one plan, with the SR iteration
-captured once in a HIP graph and replayed.
+captured once in a HIP graph by the library (pvr_sr_graph_create) and
+replayed.
 
 All problems of the plan share every launch (one simulate, one set of EM
 kernels with one workgroup per problem for the per-problem statistics, one
@@ -48,22 +49,14 @@ class GraphedSR:
         self.X.copy_(self.Xn)
 
     def capture(self):
-        import torch
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            # one eager pair on the capture stream first (allocator warm-up)
-            self._iter(self.X, self.Xn)
-            self._iter(self.Xn, self.X)
-        torch.cuda.current_stream().wait_stream(side)
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            self._iter(self.X, self.Xn)
-            self._iter(self.Xn, self.X)
-        self.graph = g
-        return g
+        """Two SR iterations (X -> Xn -> X) recorded in one graph."""
+        if self.graph is not None:
+            self.graph.close()
+        self.graph = pvr.SRGraph(self.plan, self.X, self.Xn, self.y, self.e, self.p, self.pbar,
+                                 self.W, self.num, self.den, self.em, self.prm, iters=2)
+        return self.graph
 
     def replay_pairs(self, n_pairs: int):
         """2 * n_pairs SR iterations; the volume ends in X."""
         for _ in range(n_pairs):
-            self.graph.replay()
+            self.graph.launch()

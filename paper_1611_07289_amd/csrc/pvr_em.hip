@@ -114,7 +114,8 @@ k_em_patch_stats(const PatchDev *__restrict__ patches, const float *__restrict__
 // per-chunk records (stride 5) over the problem's chunk range.
 __global__ void __launch_bounds__(EMP_T)
 k_em_problem(const ProbDev *__restrict__ probs, const double *__restrict__ pstat,
-             const double *__restrict__ chunk_stats, pvr_em_state *__restrict__ em, int init) {
+             const double *__restrict__ chunk_stats, pvr_em_state *__restrict__ em, int init,
+             unsigned *__restrict__ status) {
   __shared__ double lds[8 * (EMP_T / 64)];
   const ProbDev pr = probs[blockIdx.x];
   double mn = INFINITY, mx = -INFINITY, ym = 0, se2 = 0, cnt = 0;
@@ -134,6 +135,8 @@ k_em_problem(const ProbDev *__restrict__ probs, const double *__restrict__ pstat
   se2 = bsum<EMP_T>(se2, lds);
   cnt = bsum<EMP_T>(cnt, lds);
   if (threadIdx.x == 0) {
+    // min / max skip NaN residuals, their squares' sum does not
+    if (!isfinite(se2) || !isfinite(mx - mn) || !isfinite(ym)) atomicOr(status, PVR_FAULT_RESIDUAL);
     pvr_em_state &st = em[blockIdx.x];
     const double eps = 1e-6 * ym;
     const double range = cnt > 0 ? fmax(mx - mn, eps) : 0.0;
@@ -462,7 +465,7 @@ extern "C" pvr_status pvr_robust_weights(pvr_plan *p, const float *resid, const 
     HIP_TRY(hipGetLastError());
   }
   hipLaunchKernelGGL(k_em_problem, dim3(p->P), dim3(EMP_T), 0, stream, p->d_prob, p->d_pstat,
-                     fresh ? (const double *)p->d_chunk_stats : nullptr, em, init);
+                     fresh ? (const double *)p->d_chunk_stats : nullptr, em, init, p->d_status);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_em_estep, dim3(p->M), dim3(EM_T), 0, stream, p->d_patch, p->d_invz, resid,
                      em, pp, pb, p->d_pstat);

@@ -610,6 +610,8 @@ struct pvr_plan {
   int psf;                   // PVR_PSF_GAUSSIAN (default) or PVR_PSF_SINC
   const void *stats_resid, *stats_y;  // ... and the buffers they describe
   bool stats_valid;
+  unsigned *d_status;        // [1] numeric fault flags (PVR_FAULT_*), read by pvr_check
+  long long generation;      // bumped whenever launches recorded earlier would go stale
   int *d_total;              // [1] pinned readback target (device side)
   int *h_total;              // pinned host
   long long device_bytes;

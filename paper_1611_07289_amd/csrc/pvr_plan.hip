@@ -464,6 +464,8 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
   DEV_ALLOC(p, p->d_chunk_stats, 5 * (size_t)p->n_sim_blocks);
   if (p->any_xt) DEV_ALLOC(p, p->d_xt, p->V);
   DEV_ALLOC(p, p->d_total, 4);
+  DEV_ALLOC(p, p->d_status, 1);
+  HIP_TRY(hipMemset(p->d_status, 0, sizeof(unsigned)));
   HIP_TRY(hipHostMalloc((void **)&p->h_total, sizeof(int) * 4, hipHostMallocDefault));
   HIP_TRY(hipMemcpy(p->d_prob, p->h_prob, sizeof(ProbDev) * n_problems, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(p->d_stack, p->h_stack, sizeof(StackDev) * n_stacks, hipMemcpyHostToDevice));
@@ -558,6 +560,7 @@ extern "C" pvr_status pvr_plan_set_psf(pvr_plan *p, int32_t kind) {
   p->built = p->built64 = false;
   p->index_valid = false;
   p->stats_valid = false;
+  ++p->generation;
   return PVR_OK;
   PVR_API_END();
 }
@@ -566,6 +569,7 @@ extern "C" pvr_status pvr_plan_set_tiles(pvr_plan *p, int32_t tile_w, int32_t ti
                                          hipStream_t stream) {
   PVR_API_BEGIN();
   if (!p) return fail(PVR_EINVAL, "pvr_plan_set_tiles: plan is NULL");
+  ++p->generation;
   if (tile_w == 0 && tile_h == 0) {
     p->use_tiles = false;
     return PVR_OK;
@@ -643,6 +647,7 @@ pvr_status pvr::plan_build_index(pvr_plan *p, hipStream_t stream) {
                      p->d_sub_patch);
   HIP_TRY(hipGetLastError());
   p->index_valid = true;
+  ++p->generation;
   return PVR_OK;
 }
 
@@ -684,6 +689,7 @@ static pvr_status plan_build_common(pvr_plan *p, const uint8_t *active, const ui
   p->stats_valid = false;
   p->built = true;
   p->built64 = f64;
+  ++p->generation;
   return PVR_OK;
 }
 

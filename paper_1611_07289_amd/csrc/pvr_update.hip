@@ -17,7 +17,8 @@ using namespace pvr;
 __global__ void __launch_bounds__(256)
 k_sr_update(const ProbDev *__restrict__ probs, const int *__restrict__ plane_prob,
             const float *__restrict__ X, const float *__restrict__ num,
-            const float *__restrict__ den, pvr_sr_params prm, float *__restrict__ Xo) {
+            const float *__restrict__ den, pvr_sr_params prm, float *__restrict__ Xo,
+            unsigned *__restrict__ status) {
   const int zg = blockIdx.z;
   const ProbDev pr = probs[plane_prob[zg]];
   const int k = zg - plane_prob[gridDim.z + plane_prob[zg]];
@@ -60,6 +61,10 @@ k_sr_update(const ProbDev *__restrict__ probs, const int *__restrict__ plane_pro
   }
   float out = fmaf(prm.alpha, step, x);
   out = fmaf(prm.alpha * prm.lambda, R, out);
+  // a non-finite value before the clamp (which would hide a NaN) raises the
+  // volume flag once per wave
+  const unsigned long long bad = __ballot(!__builtin_isfinite(out));
+  if (bad && (threadIdx.x & 63) == (unsigned)__builtin_ctzll(bad)) atomicOr(status, PVR_FAULT_VOLUME);
   if (prm.use_clamp) out = fmaxf(out, prm.clamp_min);
   Xo[pr.vol_off + c] = out;
 }
@@ -72,7 +77,8 @@ extern "C" pvr_status pvr_sr_update(const pvr_plan *p, const float *X, const flo
   if (X_out == X) return fail(PVR_EINVAL, "pvr_sr_update: X_out must not alias X");
   if (!(prm->delta > 0)) return fail(PVR_EINVAL, "pvr_sr_update: delta must be > 0");
   hipLaunchKernelGGL(k_sr_update, dim3((p->max_nx + 63) / 64, (p->max_ny + 3) / 4, p->n_planes),
-                     dim3(256), 0, stream, p->d_prob, p->d_plane_prob, X, num, den, *prm, X_out);
+                     dim3(256), 0, stream, p->d_prob, p->d_plane_prob, X, num, den, *prm, X_out,
+                     p->d_status);
   HIP_TRY(hipGetLastError());
   return PVR_OK;
   PVR_API_END();

@@ -46,7 +46,8 @@ void plan_free(pvr_plan *p) {
   void *dev[] = {p->d_prob, p->d_stack, p->d_patch, p->d_sim_blocks, p->d_tiles, p->d_box_max, p->d_brick_prob, p->d_plane_prob,
                  p->d_theta, p->d_geod, p->d_geof, p->d_bb, p->d_sbox, p->d_invz, p->d_invz64,
                  p->d_mask, p->d_active, p->d_bin_count, p->d_bin_off, p->d_bin_patch, p->d_sub_count, p->d_sub_off, p->d_sub_patch,
-                 p->d_rq, p->d_rq64, p->d_pstat, p->d_pbar, p->d_pval, p->d_chunk_stats, p->d_xt, p->d_total};
+                 p->d_rq, p->d_rq64, p->d_pstat, p->d_pbar, p->d_pval, p->d_chunk_stats, p->d_xt, p->d_total,
+                 p->d_status};
   for (void *q : dev)
     if (q) (void)hipFree(q);
   if (p->h_total) (void)hipHostFree(p->h_total);

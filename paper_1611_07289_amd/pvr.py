@@ -100,7 +100,8 @@ EXPORTS = ["pvr_last_error", "pvr_version", "pvr_plan_create", "pvr_plan_destroy
            "pvr_cnn_wgrad_scratch", "pvr_cnn_conv_wgrad", "pvr_cnn_pack_pairs",
            "pvr_cnn_head_scratch", "pvr_cnn_head", "pvr_cnn_adam",
            "pvr_slic_centres", "pvr_slic_init", "pvr_slic_assign", "pvr_slic_update", "pvr_slic",
-           "pvr_slic_boxes", "pvr_slic_pack"]
+           "pvr_slic_boxes", "pvr_slic_pack", "pvr_check", "pvr_sr_graph_create",
+           "pvr_sr_graph_launch", "pvr_sr_graph_destroy"]
 
 _lib = None
 
@@ -160,9 +161,15 @@ def load(path: str = LIB_PATH):
     L.pvr_slic.argtypes = [P, i32, i32, i32, i32, f32, f32, i32, P, P, P, P]
     L.pvr_slic_boxes.argtypes = [P, i32, i32, i32, i32, P, i32, P, P]
     L.pvr_slic_pack.argtypes = [P, P, i32, i32, i32, i32, i32, P, P, P, P]
+    L.pvr_check.argtypes = [P, P]
+    L.pvr_sr_graph_create.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, i32, P, P]
+    L.pvr_sr_graph_launch.argtypes = [P, P]
+    L.pvr_sr_graph_destroy.argtypes = [P]
+    L.pvr_sr_graph_destroy.restype = None
     for name in EXPORTS:
         if name not in ("pvr_last_error", "pvr_version", "pvr_plan_destroy", "pvr_plan_inv_z",
-                        "pvr_cnn_wgrad_scratch", "pvr_cnn_head_scratch", "pvr_slic_centres"):
+                        "pvr_cnn_wgrad_scratch", "pvr_cnn_head_scratch", "pvr_slic_centres",
+                        "pvr_sr_graph_destroy"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -265,6 +272,11 @@ class Plan:
         _check(f(self.h, _ptr(theta), _ptr(active), _ptr(mask), _stream()))
         self.build_id = getattr(self, "build_id", 0) + 1
 
+    def check(self):
+        """Raises PvrError(PVR_ENUMERIC) when a kernel has flagged non-finite
+        values since the last check (synchronises the current stream)."""
+        _check(load().pvr_check(self.h, _stream()))
+
     def set_timing(self, on: bool = True):
         _check(load().pvr_plan_set_timing(self.h, 1 if on else 0))
 
@@ -332,3 +344,36 @@ class Plan:
         raw = em.detach().cpu().numpy().tobytes()
         n = len(raw) // ctypes.sizeof(EMState)
         return [EMState.from_buffer_copy(raw, i * ctypes.sizeof(EMState)) for i in range(n)]
+
+
+class SRGraph:
+    """`iters` SR iterations recorded once in a HIP graph by the library
+    (pvr_sr_graph_create); launch() replays them on the current stream.  The
+    tensors passed in are kept referenced for the graph's lifetime."""
+
+    def __init__(self, plan: Plan, X, X_alt, y, resid, p, pbar, W, num, den, em,
+                 params: Optional[SRParams] = None, iters: int = 2):
+        self.plan = plan
+        self.prm = params or SRParams.make()
+        self._keep = (X, X_alt, y, resid, p, pbar, W, num, den, em)
+        h = ctypes.c_void_p()
+        _check(load().pvr_sr_graph_create(plan.h, _ptr(X), _ptr(X_alt), _ptr(y), _ptr(resid),
+                                          _ptr(p), _ptr(pbar), _ptr(W), _ptr(num), _ptr(den),
+                                          _ptr(em), ctypes.byref(self.prm), int(iters),
+                                          _stream(), ctypes.byref(h)))
+        self.h = h
+        self.iters = int(iters)
+
+    def launch(self):
+        _check(load().pvr_sr_graph_launch(self.h, _stream()))
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            load().pvr_sr_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -112,4 +112,12 @@ def test_destroy_null_is_noop_and_null_plan_calls_fail():
     assert L.pvr_sr_update(None, None, None, None, None, None, None) == 1
     assert L.pvr_register_patches(None, None, None, None, None, None, None, None) == 1
     assert L.pvr_robust_weights(None, None, None, None, None, None, None, 0, None) == 1
+    assert L.pvr_check(None, None) == 1
+    out = ctypes.c_void_p()
+    assert L.pvr_sr_graph_create(None, None, None, None, None, None, None, None, None, None,
+                                 None, None, 2, None, ctypes.byref(out)) == 1 and not out.value
+    assert L.pvr_sr_graph_create(None, None, None, None, None, None, None, None, None, None,
+                                 None, None, 2, None, None) == 1
+    assert L.pvr_sr_graph_launch(None, None) == 1
+    L.pvr_sr_graph_destroy(None)
     assert "NULL" in L.pvr_last_error().decode()

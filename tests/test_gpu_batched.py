@@ -122,8 +122,6 @@ def test_graph_replays_equal_eager(batch):
     X0 = torch.from_numpy(np.concatenate([P.x_true.reshape(-1) for P in probs]) * 0.9).cuda()
     ref = Eager(plan, X0.clone(), y)
     ref.step(init=True)
-    ref.step()
-    ref.step()
     snaps = []
     for k in range(3):
         ref.step()
