@@ -148,16 +148,17 @@ def nnz_estimate(probs, n_valid, sinc=False):
     return 4.0 / 3.0 * math.pi * 27.0 * float(np.prod(sig)) / vox * n_valid
 
 
-def hbm_equivalent(nnz, n_valid, V, ms_step):
+def hbm_equivalent(nnz, nnz_adj, n_valid, V, ms_step):
     """The SR iteration against the memory floor of a stored-weight design:
     the bytes such an implementation moves per iteration (the PSF weight
-    lists read in both directions at 6 B per nonzero -- FP32 weight and
-    16-bit local index --, 16 B per valid sample for y, e and its re-reads,
+    lists read at 6 B per nonzero -- FP32 weight and 16-bit local index --
+    forward for every valid sample and backward for those of the patches the
+    EM keeps, 16 B per valid sample for y, e and its re-reads,
     32 B per voxel for X, num, den and X') over the chip's 8 TB/s, as a
     fraction of the measured iteration time.  This path stores no weights,
     so the figure is a like-for-like time budget, not a count of its own
     traffic (see roofline.traffic for that)."""
-    b = 2.0 * nnz * 6 + n_valid * 16 + V * 32
+    b = (nnz + nnz_adj) * 6 + n_valid * 16 + V * 32
     floor_ms = b / (HBM_PEAK_GBS * 1e9) * 1e3
     return {"bytes_per_iteration": b, "floor_ms": floor_ms, "frac": floor_ms / ms_step}
 
@@ -283,7 +284,8 @@ def main():
     ones = torch.ones(plan.V, dtype=torch.float32, device=dev)
     ysim1 = torch.empty(plan.N, dtype=torch.float32, device=dev)
     plan.simulate(ones, y_sim=ysim1)
-    n_valid = int((ysim1 > 0.5).sum().item())
+    valid = ysim1 > 0.5
+    n_valid = int(valid.sum().item())
     del ysim1, ones
 
     e = torch.empty(plan.N, dtype=torch.float32, device=dev)
@@ -354,17 +356,26 @@ def main():
         kern[name] = tot / max(n, 1)
     plan.set_timing(False)
     nnz = nnz_estimate(probs, n_valid, sinc)
+    # the adjoint skips patches the EM excludes (W = 0): its work is the
+    # nonzeros of the valid samples of the kept patches
+    counts = torch.from_numpy(np.diff(plan.sample_off)).to(dev)
+    kept = torch.repeat_interleave(W > 0, counts)
+    n_kept = int((valid & kept).sum().item())
+    del valid, kept, counts
+    nnz_adj = nnz * n_kept / max(n_valid, 1)
     dom = max(kern, key=kern.get)
     if sinc:
         fpn = FLOP_PER_NNZ_SINC_FWD if dom == "k_simulate" else FLOP_PER_NNZ_SINC_ADJ
     else:
         fpn = FLOP_PER_NNZ_FWD if dom == "k_simulate" else FLOP_PER_NNZ_ADJ
-    achieved = nnz * fpn / (kern[dom] * 1e-3) / 1e12
+    nnz_dom = nnz if dom == "k_simulate" else nnz_adj
+    achieved = nnz_dom * fpn / (kern[dom] * 1e-3) / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved,
                 "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / FP32_VALU_PEAK_TFLOPS,
                 "traffic": measured_traffic(dom, args.workload),
-                "kernel_ms": kern[dom], "nnz_per_launch": nnz, "flop_per_nnz": fpn}
+                "kernel_ms": kern[dom], "nnz_per_launch": nnz_dom, "flop_per_nnz": fpn,
+                "valid_samples_kept": n_kept}
 
     st = pvr.Plan.read_em(em)
     out = {
@@ -389,7 +400,7 @@ def main():
         "hot_kernels_ms": kern,
         "build_ms": t_build * 1e3,
         "roofline": roofline,
-        "hbm_equivalent": hbm_equivalent(nnz, n_valid, plan.V, ms_step),  # same bytes per nonzero
+        "hbm_equivalent": hbm_equivalent(nnz, nnz_adj, n_valid, plan.V, ms_step),  # same bytes per nonzero
         "em": {"sigma2": st[0].sigma2, "c": st[0].c, "excluded": st[0].n_excluded},
     }
 
