@@ -702,7 +702,7 @@ def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10, learned_pairs=0):
 
 
 def superpixel_pvr(P, Xtrue, dev, sizes=((32, 19), (64, 38)), cycles=3, n_sr=10,
-                   max_rot_deg=4.0, max_trans_mm=4.0, square=True):
+                   max_rot_deg=4.0, max_trans_mm=4.0, square=True, ms_schedule=(32, 64, 32)):
     """Square versus superpixel patches on the same observed slices (paper
     Sec. II "Patch Extraction").  Every slice of the four stacks is simulated
     whole under its own rigid motion about the slice centre (<= max_rot_deg,
@@ -710,7 +710,8 @@ def superpixel_pvr(P, Xtrue, dev, sizes=((32, 19), (64, 38)), cycles=3, n_sr=10,
     SLIC superpixels (step a, dilation gamma = 60 % of a, compactness t0 = 40
     adapting per superpixel, t_min = 5, 10 iterations) for every (a, gamma) in
     `sizes` are cut from these slices, and each set is reconstructed from zero
-    motion with exact registration.  Overlapping patches share their pixels'
+    motion with exact registration; then all sizes together in one plan as
+    multi-scale superpixels, cycle c using the size ms_schedule[c].  Overlapping patches share their pixels'
     noise here (unlike the per-patch observations of the main workload), so
     the PSNR ceiling is lower."""
     import torch
@@ -734,7 +735,7 @@ def superpixel_pvr(P, Xtrue, dev, sizes=((32, 19), (64, 38)), cycles=3, n_sr=10,
     res = {"slices": ns,
            "slice_motion": f"<= {max_rot_deg:g} deg, <= {max_trans_mm:g} mm per slice"}
 
-    def recon(key, patches, y, mask):
+    def recon(key, patches, y, mask, schedule=None):
         plan = pvr.Plan([P.grid], [P.stacks], [patches])
         ymax = float(y.abs().max())
         th0 = torch.zeros(plan.M, 6, dtype=torch.float32, device=dev)
@@ -743,7 +744,7 @@ def superpixel_pvr(P, Xtrue, dev, sizes=((32, 19), (64, 38)), cycles=3, n_sr=10,
         X, th, hist = driver.reconstruct(plan, y, th0, cycles=cycles, n_sr=n_sr,
                                          reg_params=pvr.RegParams.make(min_std=0.01 * ymax,
                                                                        exact=True),
-                                         sample_mask=mask)
+                                         sample_mask=mask, active_schedule=schedule)
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         n_in = plan.N if mask is None else int(mask.sum())
@@ -764,6 +765,7 @@ def superpixel_pvr(P, Xtrue, dev, sizes=((32, 19), (64, 38)), cycles=3, n_sr=10,
         del zero
         recon("square", sq, y_sq, None)
         del y_sq
+    extracted = {}
     for a, gamma in sizes:
         key = f"superpixel_a{a}"
         superpixel.superpixel_patches(img[:4], a, gamma, 40.0, 5.0, 10, iss[:4])  # warm-up
@@ -779,7 +781,28 @@ def superpixel_pvr(P, Xtrue, dev, sizes=((32, 19), (64, 38)), cycles=3, n_sr=10,
         if square:
             res[key]["delta_psnr_db"] = res[key]["psnr_db"] - res["square"]["psnr_db"]
             res[key]["speedup"] = res["square"]["seconds"] / res[key]["seconds"]
-        del y_sp, m_sp, lab, C
+        extracted[a] = (cols, y_sp, m_sp)
+        del lab, C
+    # multi-scale superpixels (paper Sec. II, eq. Y_i over superpixel sizes):
+    # every size's patches in one plan, each cycle registering and
+    # reconstructing from one size (schedule `ms_schedule`, sizes in order)
+    if ms_schedule and all(a in extracted for a in ms_schedule):
+        sizes_ms = sorted(set(ms_schedule))
+        cols = {k: np.concatenate([np.asarray(extracted[a][0][k], np.int32) for a in sizes_ms])
+                for k in ("stack", "slice", "x0", "y0", "w", "h")}
+        y_ms = torch.cat([extracted[a][1] for a in sizes_ms])
+        m_ms = torch.cat([extracted[a][2] for a in sizes_ms])
+        scale = np.concatenate([np.full(len(extracted[a][0]["x0"]), i, np.uint8)
+                                for i, a in enumerate(sizes_ms)])
+        act = {a: torch.from_numpy((scale == i).astype(np.uint8)).to(dev)
+               for i, a in enumerate(sizes_ms)}
+        key = "superpixel_ms"
+        recon(key, synth.Patches(**cols), y_ms, m_ms,
+              schedule=[act[a] for a in ms_schedule])
+        res[key]["schedule_a"] = list(ms_schedule)
+        if square:
+            res[key]["delta_psnr_db"] = res[key]["psnr_db"] - res["square"]["psnr_db"]
+            res[key]["speedup"] = res["square"]["seconds"] / res[key]["seconds"]
     return res
 
 
