@@ -711,7 +711,8 @@ def superpixel_pvr(P, Xtrue, dev, sizes=((32, 19), (64, 38)), cycles=3, n_sr=10,
     adapting per superpixel, t_min = 5, 10 iterations) for every (a, gamma) in
     `sizes` are cut from these slices, and each set is reconstructed from zero
     motion with exact registration; then all sizes together in one plan as
-    multi-scale superpixels, cycle c using the size ms_schedule[c].  Overlapping patches share their pixels'
+    multi-scale superpixels, cycle c using the size ms_schedule[c], and the
+    square patches of the same sizes (stride a/2) on the same schedule.  Overlapping patches share their pixels'
     noise here (unlike the per-patch observations of the main workload), so
     the PSNR ceiling is lower."""
     import torch
@@ -757,14 +758,27 @@ def superpixel_pvr(P, Xtrue, dev, sizes=((32, 19), (64, 38)), cycles=3, n_sr=10,
 
     if square:
         # square patches: the pack call with one label covering every slice
-        sq = synth.square_patches(P.stacks, 64, 32)
-        tab = np.column_stack([image_of[sq.stack] + sq.slice, np.zeros(sq.M, np.int32), sq.x0,
-                               sq.y0, sq.w, sq.h]).astype(np.int32)
         zero = torch.zeros(ns, h, w, dtype=torch.int32, device=dev)
-        y_sq, _ = superpixel.pack(img, zero, 0, tab)
+
+        def cut(sq):
+            tab = np.column_stack([image_of[sq.stack] + sq.slice, np.zeros(sq.M, np.int32),
+                                   sq.x0, sq.y0, sq.w, sq.h]).astype(np.int32)
+            return superpixel.pack(img, zero, 0, tab)[0]
+
+        sq = synth.square_patches(P.stacks, 64, 32)
+        recon("square", sq, cut(sq), None)
+        if ms_schedule:
+            # multi-scale squares of the same two scales (a, stride a/2),
+            # the same schedule
+            sizes_sq = sorted(set(ms_schedule))
+            parts = [synth.square_patches(P.stacks, a, a // 2) for a in sizes_sq]
+            both = synth.concat_patches(parts)
+            scale = np.concatenate([np.full(q.M, i, np.uint8) for i, q in enumerate(parts)])
+            act = {a: torch.from_numpy((scale == i).astype(np.uint8)).to(dev)
+                   for i, a in enumerate(sizes_sq)}
+            recon("square_ms", both, cut(both), None, schedule=[act[a] for a in ms_schedule])
+            res["square_ms"]["schedule_a"] = list(ms_schedule)
         del zero
-        recon("square", sq, y_sq, None)
-        del y_sq
     extracted = {}
     for a, gamma in sizes:
         key = f"superpixel_a{a}"
@@ -801,8 +815,9 @@ def superpixel_pvr(P, Xtrue, dev, sizes=((32, 19), (64, 38)), cycles=3, n_sr=10,
               schedule=[act[a] for a in ms_schedule])
         res[key]["schedule_a"] = list(ms_schedule)
         if square:
-            res[key]["delta_psnr_db"] = res[key]["psnr_db"] - res["square"]["psnr_db"]
-            res[key]["speedup"] = res["square"]["seconds"] / res[key]["seconds"]
+            ref = "square_ms" if "square_ms" in res else "square"
+            res[key]["delta_psnr_db_vs_" + ref] = res[key]["psnr_db"] - res[ref]["psnr_db"]
+            res[key]["speedup_vs_" + ref] = res[ref]["seconds"] / res[key]["seconds"]
     return res
 
 

@@ -66,9 +66,10 @@
 extern "C" {
 #endif
 
-/* Largest number of patches of one problem (the patch classification keeps
- * a problem's patch potentials in one workgroup's registers). */
-#define PVR_MAX_PROBLEM_PATCHES 65536
+/* Largest number of patches of one problem (the patch classification of a
+ * problem runs in one workgroup: its potentials sit in LDS up to 12288
+ * patches, beyond that in the plan's scratch array). */
+#define PVR_MAX_PROBLEM_PATCHES (1 << 20)
 
 typedef enum {
   PVR_OK = 0,
