@@ -395,6 +395,7 @@ def main():
                    "samples": plan.N, "valid_samples": n_valid, "voxels": plan.V,
                    "patch": "64x64 stride 32" if args.workload == "uterus256" else "mixed",
                    "psf_fwhm_mm": [1, 1, 4], "psf": "sinc" if sinc else "gaussian",
+                   "plan_device_bytes": int(plan.info().device_bytes),
                    "parallelism": "single GPU"},
         "kernels_ms": per,
         "hot_kernels_ms": kern,
