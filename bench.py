@@ -29,13 +29,14 @@ Extra objects on the JSON line:
                 the library's stream);
   hot_kernels_ms  the two PSF kernels alone;
   cpu_baseline  the FP64 oracle timed on the host on a bounded sample;
-  full_pvr      (uterus256, unless --no-full-pvr) seconds and PSNR of a whole
-                reconstruction from zero motion -- initial volume, then 3
-                cycles of [registration, 10 SR iterations] -- with plain
-                registration and with the learned initialiser (trained first
-                on --learned-pairs forward-model pairs of another phantom;
-                training time reported apart), each with the registration
-                gradient by central differences and exact ("_exact");
+  full_pvr      (uterus256 and sinc256, unless --no-full-pvr) seconds and
+                PSNR of a whole reconstruction from zero motion -- initial
+                volume, then 3 cycles of [registration, 10 SR iterations] --
+                with plain registration and (uterus256) with the learned
+                initialiser (trained first on --learned-pairs forward-model
+                pairs of another phantom; training time reported apart), each
+                with the registration gradient by central differences and
+                (uterus256) exact ("_exact");
   superpixel_pvr  (uterus256, unless --no-superpixel) whole slices observed
                 under per-slice motion, reconstructed (exact registration,
                 same schedule) from 64x64 stride-32 square patches and from
@@ -407,6 +408,9 @@ def main():
 
     if not args.no_full_pvr and args.workload == "uterus256":
         out["full_pvr"] = full_pvr(plan, probs, y, Xtrue, dev, learned_pairs=args.learned_pairs)
+    if not args.no_full_pvr and args.workload == "sinc256":
+        # the sinc PSF registers with the central-difference gradient only
+        out["full_pvr"] = full_pvr(plan, probs, y, Xtrue, dev, exact=False)
     if not args.no_superpixel and args.workload == "uterus256":
         out["superpixel_pvr"] = superpixel_pvr(probs[0], Xtrue, dev)
 
@@ -654,7 +658,7 @@ def plan_patch_begin(plan, probs, b):
     return int(sum(P.M for P in probs[:b]))
 
 
-def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10, learned_pairs=0):
+def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10, learned_pairs=0, exact=True):
     """Seconds and PSNR of a whole reconstruction from the motion-corrupted
     start (zero motion): plain registration, and with learned_pairs > 0 also
     the learned initialiser (trained first, on a phantom of another seed)."""
@@ -677,8 +681,9 @@ def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10, learned_pairs=0):
     # plain registration: central-difference gradient (12 NCC evaluations per
     # gradient), then the exact gradient (one evaluation)
     run("plain", pvr.RegParams.make(min_std=0.01 * ymax))
-    run("plain_exact", pvr.RegParams.make(min_std=0.01 * ymax, exact=True))
-    if learned_pairs > 0:
+    if exact:
+        run("plain_exact", pvr.RegParams.make(min_std=0.01 * ymax, exact=True))
+    if learned_pairs > 0 and exact:
         P = probs[0]
         Xtr = torch.from_numpy(synth.phantom_uterus(P.grid.nx, 7700, 7701).reshape(-1)).to(dev)
         net = learned.Net(seed=5005)

@@ -321,7 +321,7 @@ struct RegShared {
 
 // NCC of the patch against its simulation at sh.th (valid samples only);
 // every lane returns the same value.
-template <bool XT>
+template <bool XT, int PSF = PVR_PSF_GAUSSIAN>
 __device__ double reg_eval(RegShared &sh, const ProbDev &pr, const StackDev &st, const PatchDev &pt,
                            double k, __amdgpu_buffer_rsrc_t xr, unsigned nbytes,
                            const float *__restrict__ y,
@@ -329,7 +329,7 @@ __device__ double reg_eval(RegShared &sh, const ProbDev &pr, const StackDev &st,
   if (threadIdx.x == 0) {
     GeoD gd;
     int bb[6];
-    make_geometry(pr, st, pt, sh.th, k, gd, sh.g, bb);
+    make_geometry<PSF>(pr, st, pt, sh.th, k, gd, sh.g, bb);
   }
   __syncthreads();
   const GeoF g = wave_uniform(sh.g);
@@ -343,9 +343,15 @@ __device__ double reg_eval(RegShared &sh, const ProbDev &pr, const StackDev &st,
     float f[3];
     if (!sample_centre(g, pr, u, v, pt.slice, b, f)) continue;
     float z = 0.f;
-    const float a = g.perm[2] == (XT ? 1 : 0)
-                        ? psf_walk_fwd<float, GeoF, true, 1, XT>(g, pr, b, f, xr, nbytes, &z)
-                        : psf_walk_fwd<float, GeoF, true, 2, XT>(g, pr, b, f, xr, nbytes, &z);
+    float a;
+    if constexpr (PSF == PVR_PSF_SINC)
+      a = g.perm[2] == (XT ? 1 : 0)
+              ? psf_walk_sinc<float, GeoF, true, 1, XT>(g, pr, b, f, xr, nbytes, &z)
+              : psf_walk_sinc<float, GeoF, true, 2, XT>(g, pr, b, f, xr, nbytes, &z);
+    else
+      a = g.perm[2] == (XT ? 1 : 0)
+              ? psf_walk_fwd<float, GeoF, true, 1, XT>(g, pr, b, f, xr, nbytes, &z)
+              : psf_walk_fwd<float, GeoF, true, 2, XT>(g, pr, b, f, xr, nbytes, &z);
     if (!(z > 0.f)) continue;
     const double yh = (double)(a / z), yo = (double)y[j];
     acc6[0] += 1.0;
@@ -459,8 +465,9 @@ __device__ double reg_eval_exact(RegShared &sh, const ProbDev &pr, const StackDe
 // One workgroup per patch; the optimiser's control flow is uniform (every
 // lane sees the same reduced NCC values), its state lives in LDS.  EXACT
 // selects the exact gradient (one reg_eval_exact) over central differences
-// (twelve reg_eval); XT the y-fastest volume copy (patches of layout 1).
-template <bool EXACT, bool XT>
+// (twelve reg_eval); XT the y-fastest volume copy (patches of layout 1); PSF
+// the plan's PSF (the exact gradient is written for the Gaussian only).
+template <bool EXACT, bool XT, int PSF>
 __device__ __forceinline__ void register_patch(
     RegShared &sh, const ProbDev *__restrict__ probs, const StackDev *__restrict__ stacks,
     const PatchDev *__restrict__ patches, const float *__restrict__ Xv,
@@ -501,13 +508,14 @@ __device__ __forceinline__ void register_patch(
     }
   }
   __syncthreads();
-  double f0 = reg_eval<XT>(sh, pr, st, pt, k, xr, nbytes, y, mask);
+  double f0 = reg_eval<XT, PSF>(sh, pr, st, pt, k, xr, nbytes, y, mask);
   const bool do_reg = (reg ? reg[s] != 0 : true) && sd >= prm.min_std && prm.max_iter > 0;
   if (do_reg) {
     double delta = prm.step0;
     bool have_grad = false, moved = false;
     for (int it = 0; it < prm.max_iter; ++it) {
       if (delta < prm.step_min) break;
+      if constexpr (EXACT) static_assert(PSF == PVR_PSF_GAUSSIAN, "exact gradient: Gaussian PSF only");
       if (!have_grad && EXACT) {
         __syncthreads();
         if (threadIdx.x == 0)
@@ -525,10 +533,10 @@ __device__ __forceinline__ void register_patch(
             for (int b = 0; b < 6; ++b) sh.th[b] = sh.q[b] / sh.sc[b];
             sh.th[a] = (sh.q[a] + prm.fd_h) / sh.sc[a];
           }
-          fp = reg_eval<XT>(sh, pr, st, pt, k, xr, nbytes, y, mask);
+          fp = reg_eval<XT, PSF>(sh, pr, st, pt, k, xr, nbytes, y, mask);
           __syncthreads();
           if (threadIdx.x == 0) sh.th[a] = (sh.q[a] - prm.fd_h) / sh.sc[a];
-          fm = reg_eval<XT>(sh, pr, st, pt, k, xr, nbytes, y, mask);
+          fm = reg_eval<XT, PSF>(sh, pr, st, pt, k, xr, nbytes, y, mask);
           if (threadIdx.x == 0) sh.grad[a] = (fp - fm) / (2.0 * prm.fd_h);
         }
         have_grad = true;
@@ -541,7 +549,7 @@ __device__ __forceinline__ void register_patch(
       __syncthreads();
       if (threadIdx.x == 0)
         for (int a = 0; a < 6; ++a) sh.th[a] = (sh.q[a] + delta * sh.grad[a] / gn) / sh.sc[a];
-      const double ft = reg_eval<XT>(sh, pr, st, pt, k, xr, nbytes, y, mask);
+      const double ft = reg_eval<XT, PSF>(sh, pr, st, pt, k, xr, nbytes, y, mask);
       if (ft > f0) {
         __syncthreads();
         if (threadIdx.x == 0)
@@ -565,7 +573,7 @@ __device__ __forceinline__ void register_patch(
 // The optimiser of register_patch for the patches of one volume layout (the
 // others return at once): one launch per layout keeps the register use of a
 // single optimiser.
-template <bool EXACT, bool XT>
+template <bool EXACT, bool XT, int PSF>
 __global__ void __launch_bounds__(REG_THREADS)
 k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stacks,
            const PatchDev *__restrict__ patches, const float *__restrict__ Xv, int any_xt,
@@ -574,7 +582,8 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
            const uint8_t *__restrict__ reg, pvr_reg_params prm, double k) {
   __shared__ RegShared sh;
   if ((any_xt && patches[blockIdx.x].layout == 1) != XT) return;
-  register_patch<EXACT, XT>(sh, probs, stacks, patches, Xv, y, mask, theta, ncc_out, reg, prm, k);
+  register_patch<EXACT, XT, PSF>(sh, probs, stacks, patches, Xv, y, mask, theta, ncc_out, reg, prm,
+                                 k);
 }
 
 extern "C" pvr_status pvr_register_patches(const pvr_plan *p, const float *X, const float *y_obs,
@@ -585,23 +594,29 @@ extern "C" pvr_status pvr_register_patches(const pvr_plan *p, const float *X, co
   if (!p->built) return fail(PVR_EINVAL, "pvr_register_patches: plan has not been built");
   if (prm->max_iter < 0 || !(prm->step0 > 0) || !(prm->step_min > 0) || !(prm->fd_h > 0))
     return fail(PVR_EINVAL, "pvr_register_patches: invalid optimiser parameters");
-  if (p->psf != PVR_PSF_GAUSSIAN)
-    return fail(PVR_EUNSUPPORTED, "pvr_register_patches: registration is implemented for the Gaussian PSF");
   if (prm->gradient != PVR_REG_GRAD_FD && prm->gradient != PVR_REG_GRAD_EXACT)
     return fail(PVR_EINVAL, "pvr_register_patches: gradient must be PVR_REG_GRAD_FD or PVR_REG_GRAD_EXACT");
+  const bool sinc = p->psf == PVR_PSF_SINC;
+  if (sinc && prm->gradient == PVR_REG_GRAD_EXACT)
+    return fail(PVR_EUNSUPPORTED,
+                "pvr_register_patches: the exact gradient is implemented for the Gaussian PSF "
+                "(use PVR_REG_GRAD_FD with the sinc PSF)");
   const float *XT = volume_xt(p, X, stream);
   HIP_TRY(hipGetLastError());
   const int any = XT != nullptr;
-#define REG_LAUNCH(E, L, V)                                                                    \
-  hipLaunchKernelGGL((k_register<E, L>), dim3(p->M), dim3(REG_THREADS), 0, stream, p->d_prob, \
-                     p->d_stack, p->d_patch, V, any, y_obs, p->d_mask, theta, ncc, reg, *prm,  \
+#define REG_LAUNCH(E, L, S, V)                                                                   \
+  hipLaunchKernelGGL((k_register<E, L, S>), dim3(p->M), dim3(REG_THREADS), 0, stream, p->d_prob, \
+                     p->d_stack, p->d_patch, V, any, y_obs, p->d_mask, theta, ncc, reg, *prm,     \
                      p->k)
-  if (prm->gradient == PVR_REG_GRAD_EXACT) {
-    REG_LAUNCH(true, false, X);
-    if (any) REG_LAUNCH(true, true, XT);
+  if (sinc) {
+    REG_LAUNCH(false, false, PVR_PSF_SINC, X);
+    if (any) REG_LAUNCH(false, true, PVR_PSF_SINC, XT);
+  } else if (prm->gradient == PVR_REG_GRAD_EXACT) {
+    REG_LAUNCH(true, false, PVR_PSF_GAUSSIAN, X);
+    if (any) REG_LAUNCH(true, true, PVR_PSF_GAUSSIAN, XT);
   } else {
-    REG_LAUNCH(false, false, X);
-    if (any) REG_LAUNCH(false, true, XT);
+    REG_LAUNCH(false, false, PVR_PSF_GAUSSIAN, X);
+    if (any) REG_LAUNCH(false, true, PVR_PSF_GAUSSIAN, XT);
   }
 #undef REG_LAUNCH
   HIP_TRY(hipGetLastError());

@@ -114,8 +114,42 @@ def test_sinc_unsupported_calls_fail_cleanly(sinc):
     y = torch.zeros(plan.N, dtype=torch.float32, device="cuda")
     th = dev(P.theta_true, torch.float32)
     with pytest.raises(pvr.PvrError, match="Gaussian PSF"):
-        plan.register(X, y, th)
+        plan.register(X, y, th, params=pvr.RegParams.make(exact=True))
     with pytest.raises(pvr.PvrError, match="Gaussian PSF"):
         plan.grad_theta(X, y, torch.empty(plan.M, 6, device="cuda"))
     with pytest.raises(pvr.PvrError):
         plan.set_psf(7)
+
+
+def test_sinc_registration_matches_oracle():
+    """Registration with the sinc PSF (central-difference gradient): NCC at a
+    fixed motion to 1e-5, and the optimiser's outcome of the same quality as
+    the oracle's on the textured 32^3 case."""
+    import math
+    from tests.test_gpu_parity import _textured_registration_case
+    P, _, X, _, th_true = _textured_registration_case()
+    ctx = oracle.Ctx(P.grid, P.stacks, P.patches, psf="sinc")
+    y = ctx.simulate(X, th_true)[0].astype(np.float32)
+    th0 = (P.theta_true + synth.random_motion(P.M, 3.0, 1.0, 99)).astype(np.float32)
+    plan = pvr.Plan.from_problems([P])
+    plan.set_psf(pvr.PVR_PSF_SINC)
+    plan.build(dev(th0))
+    ncc = torch.empty(plan.M, dtype=torch.float32, device="cuda")
+    tt = dev(th0)
+    plan.register(dev(X), dev(y), tt, ncc, params=pvr.RegParams.make(max_iter=0))
+    n0 = ctx.ncc(X, y, th0.astype(np.float64))
+    assert np.abs(host(ncc) - n0).max() <= 1e-5
+    tho, nco = ctx.register(X, y, th0.astype(np.float64))
+    plan.register(dev(X), dev(y), tt, ncc, params=pvr.RegParams.make())
+    thg, ncg = host(tt).astype(np.float64), host(ncc)
+    assert np.all(ncg >= n0 - 1e-5)
+    drot_g = np.degrees(np.abs(thg[:, :3] - th_true[:, :3])).max(1)
+    drot_o = np.degrees(np.abs(tho[:, :3] - th_true[:, :3])).max(1)
+    dtr_g = np.abs(thg[:, 3:] - th_true[:, 3:]).max(1)
+    dtr_o = np.abs(tho[:, 3:] - th_true[:, 3:]).max(1)
+    same = (np.abs(thg - tho)[:, :3].max(1) < math.radians(0.25)) & (np.abs(thg - tho)[:, 3:].max(1) < 0.1)
+    print(f"[gpu] sinc reg median rot err gpu {np.median(drot_g):.3f} ora {np.median(drot_o):.3f}; "
+          f"trans gpu {np.median(dtr_g):.4f} ora {np.median(dtr_o):.4f}; agreement {same.mean():.3f}")
+    assert np.median(drot_g) <= max(0.35, 1.25 * np.median(drot_o))
+    assert np.median(dtr_g) <= max(0.03, 1.25 * np.median(dtr_o))
+    assert np.mean(ncg > 0.999) >= np.mean(nco > 0.999) - 0.05

@@ -16,9 +16,10 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLOORS = {
     "pvr_forward.hip": {
         "_Z10k_simulateIfE": 7,
-        "_Z10k_registerILb1ELb0E": 2,   # exact gradient, x-fastest volume
-        "_Z10k_registerILb1ELb1E": 2,   # exact gradient, y-fastest copy
-        "_Z10k_registerILb0ELb0E": 3,   # central differences
+        "_Z10k_registerILb1ELb0ELi0E": 2,   # exact gradient, x-fastest volume
+        "_Z10k_registerILb1ELb1ELi0E": 2,   # exact gradient, y-fastest copy
+        "_Z10k_registerILb0ELb0ELi0E": 3,   # central differences
+        "_Z10k_registerILb0ELb0ELi1E": 2,   # central differences, sinc PSF
     },
     "pvr_adjoint.hip": {
         "_Z13k_backprojectIfLb1ELi1ELb0E": 8,
