@@ -227,8 +227,9 @@ pvr_status pvr_plan_build_f64(pvr_plan *plan, const double *theta,
  *     (pi t)^22 in FP64), w = the in-plane FWHMs (the sinc's first zero;
  *     main lobe only) and sigma_n the slice profile's deviation from the
  *     through-plane FWHM.  Normalised over in-volume voxels like the Gaussian.
- *     Registration and the theta-derivatives (pvr_register_patches,
- *     pvr_simulate_grad_theta*) return PVR_EUNSUPPORTED for this PSF; the
+ *     Registration runs with the central-difference gradient only: the
+ *     exact gradient (PVR_REG_GRAD_EXACT) and the theta-derivatives
+ *     (pvr_simulate_grad_theta*) return PVR_EUNSUPPORTED for this PSF; the
  *     LDS-tiled forward pass is not used with it.
  * Takes effect at the next pvr_plan_build (the plan counts as unbuilt until
  * then).  (host) */
