@@ -321,7 +321,8 @@ pvr_status pvr_sr_update(const pvr_plan *plan, const float *X,
  * uses the full PSF forward model and NCC runs over samples valid at theta.
  * Optimiser: variables (rho * angles, translations) with rho the patch
  * half-diagonal in mm; gradient by central differences with step fd_h or
- * exact (params->gradient, PVR_REG_GRAD_*); a normalised
+ * exact (params->gradient, PVR_REG_GRAD_*; exact needs the Gaussian PSF,
+ * PVR_EUNSUPPORTED otherwise); a normalised
  * step of length delta is accepted on strict improvement (delta doubles,
  * capped at step0) or delta halves; stop below step_min or after max_iter
  * trial steps.  Patches with std(y_s) < min_std keep theta.
