@@ -223,6 +223,8 @@ def main():
     ap.add_argument("--learned-pairs", type=int, default=1_000_000,
                     help="training pairs of the learned initialiser for the full-PVR "
                          "comparison (0: plain reconstruction only)")
+    ap.add_argument("--no-training", action="store_true",
+                    help="learned workload: time inference only")
     ap.add_argument("--no-superpixel", action="store_true",
                     help="skip the superpixel-versus-square-patch reconstruction")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -576,6 +578,9 @@ def learned_bench(args, P, dev):
     gbs_inf = learned.activation_bytes_per_pair() * plan.M / t_inf / 1e9
     # training steps
     Bt = 256
+    if args.no_training:
+        log(f"[bench] learned: inference {plan.M / t_inf:.0f} pairs/s ({tf_inf:.1f} TFLOP/s)")
+        return
     tgt = torch.zeros(Bt * 6, device=dev)
     bf = net.buffers(Bt)
     bf["ids"].copy_(ids[:Bt])
