@@ -41,9 +41,11 @@
  *          (for a box from pvr_slic_boxes: the dilated superpixel), else 0.
  *          Boxes must lie in the image and hold at most 65536 pixels.
  *          Synchronises `stream` once (the table is staged to the device).
- * Errors: PVR_EINVAL for NULL pointers, non-positive sizes or gamma < 0,
- * PVR_ESHAPE when n_img * h * w exceeds 2^31, K exceeds 2^20, n_img exceeds
- * 65535 or a packed box leaves its image or holds more than 65536 pixels.
+ * Errors: PVR_EINVAL for NULL pointers, non-positive sizes, a beyond 2^20 or
+ * gamma < 0, PVR_ESHAPE when n_img * h * w exceeds 2^31, h or w exceeds
+ * 2^20, K exceeds 2^20, n_img exceeds 65535 or a packed box leaves its image
+ * or holds more than 65536 pixels.  Centres of any value (NaN included) are
+ * safe: a centre whose window misses the image takes no pixel.
  */
 #ifndef PVR_SLIC_H
 #define PVR_SLIC_H

@@ -29,13 +29,19 @@ __device__ __forceinline__ void cell_of(int k, int kx, int a, int h, int w, floa
   y = 0.5f * (float)(j * a + min(h, (j + 1) * a) - 1);
 }
 
-// window of a centre: integer pixel ranges with |x - cx| <= a, clipped
+// window of a centre: integer pixel ranges with |x - cx| <= a, clipped to the
+// image (empty when x0 > x1 or y0 > y1).  The centre is first clamped to a
+// band around the image that leaves every window inside the image unchanged,
+// so that any input (NaN, infinities, far-off centres) gives small integers.
 __device__ __forceinline__ void window(float cx, float cy, int a, int h, int w, int &x0, int &x1,
                                        int &y0, int &y1) {
-  x0 = max(0, (int)ceilf(cx - (float)a));
-  x1 = min(w - 1, (int)floorf(cx + (float)a));
-  y0 = max(0, (int)ceilf(cy - (float)a));
-  y1 = min(h - 1, (int)floorf(cy + (float)a));
+  const float fa = (float)a;
+  cx = fminf(fmaxf(cx, -2.f * fa - 1.f), (float)w + 2.f * fa);
+  cy = fminf(fmaxf(cy, -2.f * fa - 1.f), (float)h + 2.f * fa);
+  x0 = max(0, (int)ceilf(cx - fa));
+  x1 = min(w - 1, (int)floorf(cx + fa));
+  y0 = max(0, (int)ceilf(cy - fa));
+  y1 = min(h - 1, (int)floorf(cy + fa));
 }
 
 }  // namespace
@@ -221,6 +227,7 @@ static pvr_status check_sizes(const char *fn, int n_img, int h, int w, int a) {
   // a = 0: no centre grid to check (pack)
   if (n_img <= 0 || h <= 0 || w <= 0 || a < 0) return fail(PVR_EINVAL, "%s: sizes must be positive", fn);
   if ((long long)n_img * h * w > (1LL << 31)) return fail(PVR_ESHAPE, "%s: more than 2^31 pixels", fn);
+  if (h > (1 << 20) || w > (1 << 20)) return fail(PVR_ESHAPE, "%s: a side beyond 2^20 pixels", fn);
   const long long K = a > 0 ? (long long)((h + a - 1) / a) * ((w + a - 1) / a) : 0;
   if (K > (1 << 20)) return fail(PVR_ESHAPE, "%s: more than 2^20 centres per image", fn);
   if ((long long)n_img > 65535) return fail(PVR_ESHAPE, "%s: more than 65535 images", fn);
@@ -236,7 +243,7 @@ extern "C" pvr_status pvr_slic_init(const float *img, int32_t n_img, int32_t h, 
                                     int32_t a, float t0, float *centres, hipStream_t stream) {
   PVR_API_BEGIN();
   if (!img || !centres) return fail(PVR_EINVAL, "pvr_slic_init: NULL argument");
-  if (a <= 0) return fail(PVR_EINVAL, "pvr_slic_init: a must be positive");
+  if (a <= 0 || a > (1 << 20)) return fail(PVR_EINVAL, "pvr_slic_init: a must be in [1, 2^20]");
   pvr_status st = check_sizes("pvr_slic_init", n_img, h, w, a);
   if (st != PVR_OK) return st;
   const int kx = (w + a - 1) / a, K = kx * ((h + a - 1) / a);
@@ -253,7 +260,7 @@ extern "C" pvr_status pvr_slic_assign(const float *img, int32_t n_img, int32_t h
                                       int32_t *labels, hipStream_t stream) {
   PVR_API_BEGIN();
   if (!img || !centres || !scratch || !labels) return fail(PVR_EINVAL, "pvr_slic_assign: NULL argument");
-  if (a <= 0) return fail(PVR_EINVAL, "pvr_slic_assign: a must be positive");
+  if (a <= 0 || a > (1 << 20)) return fail(PVR_EINVAL, "pvr_slic_assign: a must be in [1, 2^20]");
   pvr_status st = check_sizes("pvr_slic_assign", n_img, h, w, a);
   if (st != PVR_OK) return st;
   const int kx = (w + a - 1) / a, ky = (h + a - 1) / a, K = kx * ky;
@@ -273,7 +280,7 @@ extern "C" pvr_status pvr_slic_update(const float *img, int32_t n_img, int32_t h
                                       float *centres, hipStream_t stream) {
   PVR_API_BEGIN();
   if (!img || !labels || !centres) return fail(PVR_EINVAL, "pvr_slic_update: NULL argument");
-  if (a <= 0) return fail(PVR_EINVAL, "pvr_slic_update: a must be positive");
+  if (a <= 0 || a > (1 << 20)) return fail(PVR_EINVAL, "pvr_slic_update: a must be in [1, 2^20]");
   pvr_status st = check_sizes("pvr_slic_update", n_img, h, w, a);
   if (st != PVR_OK) return st;
   const int K = ((w + a - 1) / a) * ((h + a - 1) / a);
@@ -408,7 +415,7 @@ extern "C" pvr_status pvr_slic_boxes(const int32_t *labels, int32_t n_img, int32
   PVR_API_BEGIN();
   if (!labels || !centres || !boxes) return fail(PVR_EINVAL, "pvr_slic_boxes: NULL argument");
   if (gamma < 0) return fail(PVR_EINVAL, "pvr_slic_boxes: gamma < 0");
-  if (a <= 0) return fail(PVR_EINVAL, "pvr_slic_boxes: a must be positive");
+  if (a <= 0 || a > (1 << 20)) return fail(PVR_EINVAL, "pvr_slic_boxes: a must be in [1, 2^20]");
   pvr_status st = check_sizes("pvr_slic_boxes", n_img, h, w, a);
   if (st != PVR_OK) return st;
   const int K = ((w + a - 1) / a) * ((h + a - 1) / a);

@@ -170,3 +170,25 @@ def test_assignment_with_centres_far_from_their_cells(imgs):
     lab = sp.assign(Ig, torch.from_numpy(Cs).cuda(), A).cpu().numpy()
     for i in range(I.shape[0]):
         _check_assignment(I[i].astype(np.float64), Cs[i].astype(np.float64), lab[i], A)
+
+
+def test_centres_off_the_image_take_no_pixels(imgs):
+    # centres at NaN, at +-1e30 and far outside the image: their windows miss
+    # every pixel, so they take none and the update leaves them as they were;
+    # the remaining centres assign as usual
+    I, Ig = imgs
+    C = sp.init(Ig, A, T0)
+    bad = torch.tensor([[float("nan"), 3.0, 100.0, 40.0], [1e30, -1e30, 100.0, 40.0],
+                        [-500.0, 700.0, 100.0, 40.0]], device="cuda")
+    C[:, :3] = bad
+    lab = sp.assign(Ig, C, A)
+    ln = lab.cpu().numpy()
+    assert not np.isin(ln, [0, 1, 2]).any()
+    C2 = sp.update(Ig, lab, C.clone(), A, TMIN).cpu().numpy()
+    Cn = C.cpu().numpy()
+    assert np.array_equal(C2[:, :3], Cn[:, :3], equal_nan=True)
+    Cg = Cn.astype(np.float64)
+    for i in range(I.shape[0]):
+        _check_assignment(I[i].astype(np.float64), np.where(np.isnan(Cg[i]), 1e9, Cg[i]), ln[i], A)
+    B = sp.boxes(lab, C, A, 3).cpu().numpy()
+    assert np.all(B[:, :3] == 0)

@@ -22,6 +22,8 @@ def test_invalid_arguments_rejected_on_host():
     fake = ctypes.c_void_p(64)  # never dereferenced: every case fails first
     assert L.pvr_slic_init(None, 1, 8, 8, 4, 1.0, fake, None) == 1
     assert L.pvr_slic_init(fake, 1, 8, 8, 0, 1.0, fake, None) == 1
+    assert L.pvr_slic_assign(fake, 1, 8, 8, (1 << 20) + 1, fake, fake, fake, None) == 1
+    assert L.pvr_slic_update(fake, 1, 1, (1 << 21), 4, fake, 0.0, fake, None) == 2
     assert L.pvr_slic_assign(fake, 0, 8, 8, 4, fake, fake, fake, None) == 1
     assert L.pvr_slic_assign(fake, 70000, 8, 8, 4, fake, fake, fake, None) == 2
     assert L.pvr_slic_assign(fake, 40000, 256, 256, 4, fake, fake, fake, None) == 2
