@@ -188,7 +188,11 @@ __device__ inline void make_geometry(const ProbDev &pr, const StackDev &st, cons
   }
   const int nb[3] = {pr.nbx, pr.nby, pr.nbz};
   for (int r = 0; r < 3; ++r) {
-    double l = floor(lo[r]) - 1.0, h = ceil(hi[r]) + 1.0;
+    // clamped before the conversion, so that a non-finite motion gives an
+    // empty range instead of an out-of-range integer
+    const double span = (double)BRICK * (nb[r] + 2);
+    double l = fmin(fmax(floor(lo[r]) - 1.0, -span), span);
+    double h = fmin(fmax(ceil(hi[r]) + 1.0, -span), span);
     int bl = (int)floor(l / BRICK), bh = (int)floor(h / BRICK);
     bl = bl < 0 ? 0 : bl;
     bh = bh > nb[r] - 1 ? nb[r] - 1 : bh;

@@ -145,3 +145,40 @@ def test_edge_all_patches_inactive(edge):
     assert torch.equal(Xn, Xd)
     plan.build(dev(th32.astype(np.float32)))
     plan.check()
+
+
+def test_non_finite_motion_makes_a_patch_invalid(edge):
+    """A patch whose motion is NaN or infinite has no valid sample: it
+    simulates to 0, takes no part in the adjoint, and the other patches are
+    unaffected (compared with the same build where that patch is inactive)."""
+    plan, th32, X, pat = edge["plan"], edge["th32"], edge["X"], edge["pat"]
+    rng = np.random.default_rng(9)
+    r = dev(rng.normal(size=plan.N).astype(np.float32))
+    off = pat.sample_off
+    outs = []
+    for bad in (float("nan"), float("inf")):
+        th = th32.astype(np.float32).copy()
+        th[2, 1] = bad
+        th[4, 4] = -bad if bad == bad else bad
+        plan.build(dev(th))
+        ys = torch.empty(plan.N, dtype=torch.float32, device="cuda")
+        plan.simulate(dev(X.reshape(-1)), y_sim=ys)
+        num = torch.empty(plan.V, dtype=torch.float32, device="cuda")
+        den = torch.empty_like(num)
+        plan.backproject(r, None, None, num, den)
+        outs.append((host(ys).copy(), host(num).copy(), host(den).copy()))
+    act = np.ones(pat.M, np.uint8)
+    act[[2, 4]] = 0
+    plan.build(dev(th32.astype(np.float32)), active=dev(act))
+    ys = torch.empty(plan.N, dtype=torch.float32, device="cuda")
+    plan.simulate(dev(X.reshape(-1)), y_sim=ys)
+    num = torch.empty(plan.V, dtype=torch.float32, device="cuda")
+    den = torch.empty_like(num)
+    plan.backproject(r, None, None, num, den)
+    ref = (host(ys), host(num), host(den))
+    for y_b, n_b, d_b in outs:
+        assert np.all(y_b[off[2]:off[3]] == 0) and np.all(y_b[off[4]:off[5]] == 0)
+        assert np.array_equal(y_b, ref[0])
+        assert np.array_equal(n_b, ref[1]) and np.array_equal(d_b, ref[2])
+    plan.build(dev(th32.astype(np.float32)))
+    plan.check()
