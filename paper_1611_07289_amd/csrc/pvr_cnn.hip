@@ -57,25 +57,49 @@ constexpr int CT = 256;  // threads per conv workgroup (4 waves)
 // ---------------------------------------------------------------------------
 // forward: out = relu(conv3x3(in, W, stride S, pad 1) + bias)
 //
-// Implicit GEMM, M = output pixels, N = COUT, K = 9 CIN.  The layer's weights
-// (B operand) are staged once per workgroup into LDS, rows of K padded by 8
-// elements; the workgroup (16 waves, so that two workgroups fill a CU even
-// with the largest weights) then loops over tiles of 256 output pixels, one
-// 16-row MFMA tile per wave, so each weight is read from memory once per
-// workgroup.  The A operand is gathered from global memory, 8 channels
-// (16 bytes) of one input pixel per lane per tap, zero outside the image; all
-// taps are loaded before the first MFMA so that their latencies overlap.
+// Implicit GEMM with the weights as the A operand (M = COUT) and the
+// gathered input as B (N = output pixels), K = 9 CIN, so that each lane ends
+// with four consecutive channels of one pixel and stores them as one 8-byte
+// word: no LDS staging of the output and no barrier inside the tile loop.
+// The layer's weights are staged once per workgroup into LDS, rows of K padded
+// by 8 elements; the workgroup (16 waves) then loops over tiles of 256 output
+// pixels, one 16-pixel MFMA column block per wave, so each weight is read from
+// memory once per workgroup.  The B operand is gathered from global memory, 8
+// channels (16 bytes) of one input pixel per lane per tap, zero outside the
+// image; all taps are loaded before the first MFMA so that their latencies
+// overlap.
 // ---------------------------------------------------------------------------
 constexpr int FW_THREADS = 1024;                       // 16 waves share the staged weights
-constexpr int FW_TILE = (FW_THREADS / 64) * 16;       // one 16-pixel MFMA tile per wave
+constexpr int FW_TILE = (FW_THREADS / 64) * 16;       // 16 output pixels per wave
 
 template <int CIN, int COUT>
 struct FwdShape {
   static constexpr int K = 9 * CIN;
   static constexpr int KP = K < 32 ? 32 : K;  // K padded to one MFMA step when CIN < 32
   static constexpr int LS = KP + 8;           // LDS row stride (elements), 16-byte rows
-  static constexpr int LDS_BYTES = COUT * LS * 2 + (FW_THREADS / 64) * 16 * (COUT + 8) * 2;
+  static constexpr int LDS_BYTES = COUT * LS * 2;
 };
+
+// bias, ReLU, BF16: lane (kq, r16) holds channels nt*16 + 4kq .. +3 of
+// pixel p, one 8-byte store per 16-channel block
+template <int COUT, int NT>
+__device__ __forceinline__ void conv_store(uint16_t *__restrict__ out, long long p, int kq,
+                                           const f32x4 (&acc)[NT], const float (&bb)[NT][4],
+                                           int relu) {
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    uint16_t h4[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float v = acc[nt][i] + bb[nt][i];
+      if (relu) v = v > 0.f ? v : 0.f;
+      h4[i] = f2bf(v);
+    }
+    const uint2 wv = make_uint2((uint32_t)h4[0] | ((uint32_t)h4[1] << 16),
+                                (uint32_t)h4[2] | ((uint32_t)h4[3] << 16));
+    *reinterpret_cast<uint2 *>(out + p * COUT + nt * 16 + 4 * kq) = wv;
+  }
+}
 
 template <int CIN, int COUT, int S>
 __global__ void __launch_bounds__(FW_THREADS)
@@ -85,7 +109,6 @@ k_conv_fwd(const uint16_t *__restrict__ in, const uint16_t *__restrict__ W,
   using SH = FwdShape<CIN, COUT>;
   constexpr int NT = COUT / 16, K = SH::K, KP = SH::KP, LS = SH::LS;
   __shared__ __attribute__((aligned(16))) uint16_t Wl[COUT * LS];
-  __shared__ __attribute__((aligned(16))) uint16_t Os[(FW_THREADS / 64) * 16 * (COUT + 8)];
   if constexpr (K % 8 == 0) {
     for (int e = threadIdx.x; e < COUT * (K / 8); e += FW_THREADS) {
       const int co = e / (K / 8), k8 = e % (K / 8);
@@ -104,102 +127,111 @@ k_conv_fwd(const uint16_t *__restrict__ in, const uint16_t *__restrict__ W,
   const long long n_tiles = (P + FW_TILE - 1) / FW_TILE;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kq = lane >> 4, r16 = lane & 15;
-  uint16_t *Ow = Os + wave * 16 * (COUT + 8);  // this wave's 16 pixels x COUT
-  for (long long tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    const long long pbase = tile * FW_TILE + wave * 16;
-    // every wave runs every tile (the barriers below are workgroup-wide)
-    const bool active = pbase < P;
-    const long long p = pbase + r16;
-    const bool pv = p < P;
-    const long long pp = pv ? p : 0;
-    const int pb = (int)(pp / (Ho * Wo));
-    const int rr = (int)(pp % (Ho * Wo));
-    const int py = rr / Wo, px = rr % Wo;
-    f32x4 acc[NT];
+  float bb[NT][4];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bb[nt][i] = bias[nt * 16 + 4 * kq + i];
+  // U tiles per wave and pass, their loads all issued before the first MFMA
+  // (2 and 4 were measured no faster than 1 on the 64x64 layers)
+  constexpr int U = 1;
+  for (long long t0 = blockIdx.x; t0 < n_tiles; t0 += (long long)U * gridDim.x) {
+    long long pu[U];
+    bool act[U], pv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long tile = t0 + (long long)u * gridDim.x;
+      const long long pbase = tile * FW_TILE + wave * 16;
+      act[u] = tile < n_tiles && pbase < P;  // wave-uniform
+      pu[u] = pbase + r16;
+      pv[u] = act[u] && pu[u] < P;
+    }
     if constexpr (CIN >= 32) {
       constexpr int CB = CIN / 32, T = 9 * CB;
-      bf16x8 a[T];
+      bf16x8 a[U][T];
 #pragma unroll
-      for (int t = 0; t < T; ++t) {
-        const int tap = t / CB, cb = t % CB;
-        const int iy = py * S + tap / 3 - 1, ix = px * S + tap % 3 - 1;
-        if (pv && iy >= 0 && iy < H && ix >= 0 && ix < Wd)
-          a[t] = load8(in + (((long long)pb * H + iy) * Wd + ix) * CIN + cb * 32 + 8 * kq);
-        else
-          a[t] = zero8();
+      for (int u = 0; u < U; ++u) {
+        const long long pp = pv[u] ? pu[u] : 0;
+        const int pb = (int)(pp / (Ho * Wo));
+        const int rr = (int)(pp % (Ho * Wo));
+        const int py = rr / Wo, px = rr % Wo;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          const int tap = t / CB, cb = t % CB;
+          const int iy = py * S + tap / 3 - 1, ix = px * S + tap % 3 - 1;
+          if (pv[u] && iy >= 0 && iy < H && ix >= 0 && ix < Wd)
+            a[u][t] = load8(in + (((long long)pb * H + iy) * Wd + ix) * CIN + cb * 32 + 8 * kq);
+          else
+            a[u][t] = zero8();
+        }
       }
 #pragma unroll
-      for (int t = 0; t < T; ++t) {
-        const int tap = t / CB, cb = t % CB;
+      for (int u = 0; u < U; ++u) {
+        if (!act[u]) continue;
+        f32x4 acc[NT];
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const bf16x8 b = *reinterpret_cast<const bf16x8 *>(
-              &Wl[(nt * 16 + r16) * LS + tap * CIN + cb * 32 + 8 * kq]);
-          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], b, acc[nt], 0, 0, 0);
+        for (int nt = 0; nt < NT; ++nt) acc[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          const int tap = t / CB, cb = t % CB;
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            const bf16x8 w = *reinterpret_cast<const bf16x8 *>(
+                &Wl[(nt * 16 + r16) * LS + tap * CIN + cb * 32 + 8 * kq]);
+            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, a[u][t], acc[nt], 0, 0, 0);
+          }
         }
+        if (pv[u]) conv_store<COUT, NT>(out, pu[u], kq, acc, bb, relu);
       }
     } else {
       // K = 9 CIN <= 32: the whole K in one step, zero padded
-      V8 ta;
-      if constexpr (CIN == 2) {
-        // lane group kq holds taps 4 kq .. 4 kq + 3, both channels (one dword each)
-        uint32_t d[4];
+      V8 ta[U];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int tap = 4 * kq + j;
-          const int iy = py * S + tap / 3 - 1, ix = px * S + tap % 3 - 1;
-          d[j] = (pv && tap < 9 && iy >= 0 && iy < H && ix >= 0 && ix < Wd)
-                     ? *reinterpret_cast<const uint32_t *>(in + (((long long)pb * H + iy) * Wd + ix) * 2)
-                     : 0u;
-        }
-        ta.u = make_uint4(d[0], d[1], d[2], d[3]);
-      } else {
+      for (int u = 0; u < U; ++u) {
+        const long long pp = pv[u] ? pu[u] : 0;
+        const int pb = (int)(pp / (Ho * Wo));
+        const int rr = (int)(pp % (Ho * Wo));
+        const int py = rr / Wo, px = rr % Wo;
+        if constexpr (CIN == 2) {
+          // lane group kq holds taps 4 kq .. 4 kq + 3, both channels (one dword each)
+          uint32_t d[4];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int k = 8 * kq + i;
-          uint16_t v = 0;
-          if (k < K && pv) {
-            const int tap = k / CIN, ci = k % CIN;
+          for (int j = 0; j < 4; ++j) {
+            const int tap = 4 * kq + j;
             const int iy = py * S + tap / 3 - 1, ix = px * S + tap % 3 - 1;
-            if (iy >= 0 && iy < H && ix >= 0 && ix < Wd)
-              v = in[(((long long)pb * H + iy) * Wd + ix) * CIN + ci];
+            d[j] = (pv[u] && tap < 9 && iy >= 0 && iy < H && ix >= 0 && ix < Wd)
+                       ? *reinterpret_cast<const uint32_t *>(in + (((long long)pb * H + iy) * Wd + ix) * 2)
+                       : 0u;
           }
-          ta.h[i] = v;
+          ta[u].u = make_uint4(d[0], d[1], d[2], d[3]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int k = 8 * kq + i;
+            uint16_t v = 0;
+            if (k < K && pv[u]) {
+              const int tap = k / CIN, ci = k % CIN;
+              const int iy = py * S + tap / 3 - 1, ix = px * S + tap % 3 - 1;
+              if (iy >= 0 && iy < H && ix >= 0 && ix < Wd)
+                v = in[(((long long)pb * H + iy) * Wd + ix) * CIN + ci];
+            }
+            ta[u].h[i] = v;
+          }
         }
       }
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Wl[(nt * 16 + r16) * LS + 8 * kq]);
-        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ta.v, b, acc[nt], 0, 0, 0);
+      for (int u = 0; u < U; ++u) {
+        if (!act[u]) continue;
+        f32x4 acc[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const bf16x8 w = *reinterpret_cast<const bf16x8 *>(&Wl[(nt * 16 + r16) * LS + 8 * kq]);
+          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, ta[u].v, (f32x4){0.f, 0.f, 0.f, 0.f},
+                                                            0, 0, 0);
+        }
+        if (pv[u]) conv_store<COUT, NT>(out, pu[u], kq, acc, bb, relu);
       }
     }
-    // bias, ReLU, BF16 into the wave's LDS tile [pixel][channel], then whole
-    // 16-byte rows of 8 channels to memory
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const int co = nt * 16 + r16;
-      const float bb = bias[co];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        float v = acc[nt][i] + bb;
-        if (relu) v = v > 0.f ? v : 0.f;
-        Ow[(4 * kq + i) * (COUT + 8) + co] = f2bf(v);
-      }
-    }
-    __syncthreads();
-    if (active) {
-#pragma unroll
-      for (int j = 0; j < (16 * COUT / 8 + 63) / 64; ++j) {
-        const int c = lane + 64 * j;
-        const int q = c / (COUT / 8), c8 = c % (COUT / 8);
-        if (c < 16 * COUT / 8 && pbase + q < P)
-          *reinterpret_cast<uint4 *>(out + (pbase + q) * COUT + 8 * c8) =
-              *reinterpret_cast<const uint4 *>(&Ow[q * (COUT + 8) + 8 * c8]);
-      }
-    }
-    __syncthreads();
   }
 }
 
