@@ -254,7 +254,7 @@ template <int CIN, int COUT>
 struct DgradShape {
   static constexpr int K = 9 * COUT;
   static constexpr int LS = K + 8;
-  static constexpr int LDS_BYTES = CIN * LS * 2 + (FW_THREADS / 64) * 16 * (CIN + 8) * 2;
+  static constexpr int LDS_BYTES = CIN * LS * 2;
 };
 
 template <int CIN, int COUT, int S>
@@ -266,7 +266,6 @@ k_conv_dgrad(const uint16_t *__restrict__ gout, const uint16_t *__restrict__ out
   constexpr int CB = COUT / 32, T = 9 * CB;
   constexpr int LS = SH::LS;
   __shared__ __attribute__((aligned(16))) uint16_t Wl[CIN * LS];
-  __shared__ __attribute__((aligned(16))) uint16_t Os[(FW_THREADS / 64) * 16 * (CIN + 8)];
   for (int e = threadIdx.x; e < 9 * CIN * (COUT / 8); e += FW_THREADS) {
     const int co8 = e % (COUT / 8), r = e / (COUT / 8);  // r = tap * CIN + ci
     const int tap = r / CIN, ci = r % CIN;
@@ -279,11 +278,9 @@ k_conv_dgrad(const uint16_t *__restrict__ gout, const uint16_t *__restrict__ out
   const long long n_tiles = (P + FW_TILE - 1) / FW_TILE;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kq = lane >> 4, r16 = lane & 15;
-  uint16_t *Ow = Os + wave * 16 * (CIN + 8);  // this wave's 16 pixels x CIN
   for (long long tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const long long pbase = tile * FW_TILE + wave * 16;
-    // every wave runs every tile (the barriers below are workgroup-wide)
-    const bool active = pbase < P;
+    if (pbase >= P) continue;  // wave-uniform; no barrier below
     const long long p = pbase + r16;
     const bool pv = p < P;
     const long long pp = pv ? p : 0;
@@ -321,27 +318,19 @@ k_conv_dgrad(const uint16_t *__restrict__ gout, const uint16_t *__restrict__ out
       for (int nt = 0; nt < NT; ++nt) {
         const bf16x8 b = *reinterpret_cast<const bf16x8 *>(
             &Wl[(nt * 16 + r16) * LS + tap * COUT + cb * 32 + 8 * kq]);
-        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], b, acc[nt], 0, 0, 0);
+        // weights as the A operand (M = CIN): lane (kq, r16) ends with input
+        // channels nt*16 + 4kq .. +3 of pixel p
+        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, a[t], acc[nt], 0, 0, 0);
       }
     }
+    if (pv) {
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const int ci = nt * 16 + r16;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) Ow[(4 * kq + i) * (CIN + 8) + ci] = f2bf(acc[nt][i]);
-    }
-    __syncthreads();
-    if (active) {
-#pragma unroll
-      for (int j = 0; j < (16 * CIN / 8 + 63) / 64; ++j) {
-        const int c = lane + 64 * j;
-        const int q = c / (CIN / 8), c8 = c % (CIN / 8);
-        if (c < 16 * CIN / 8 && pbase + q < P)
-          *reinterpret_cast<uint4 *>(gin + (pbase + q) * CIN + 8 * c8) =
-              *reinterpret_cast<const uint4 *>(&Ow[q * (CIN + 8) + 8 * c8]);
+      for (int nt = 0; nt < NT; ++nt) {
+        const uint2 wv = make_uint2((uint32_t)f2bf(acc[nt][0]) | ((uint32_t)f2bf(acc[nt][1]) << 16),
+                                    (uint32_t)f2bf(acc[nt][2]) | ((uint32_t)f2bf(acc[nt][3]) << 16));
+        *reinterpret_cast<uint2 *>(gin + p * CIN + nt * 16 + 4 * kq) = wv;
       }
     }
-    __syncthreads();
   }
 }
 
@@ -605,16 +594,16 @@ k_pack_pairs(const PatchDev *__restrict__ patches, const int *__restrict__ ids,
   const double m0 = a[1] / c, m1 = a[3] / c;
   const double s0 = sqrt(fmax(a[2] / c - m0 * m0, 0.0)) + 1e-3;
   const double s1 = sqrt(fmax(a[4] / c - m1 * m1, 0.0)) + 1e-3;
+  const double r0 = 1.0 / s0, r1 = 1.0 / s1;
+  uint32_t *o32 = reinterpret_cast<uint32_t *>(outp) + (long long)bi * n;
   for (int l = threadIdx.x; l < n; l += 256) {
     const long long j = pt.off + l;
     float u = 0.f, v = 0.f;
     if (invz[j] > 0.f) {
-      u = (float)((y[j] - m0) / s0);
-      v = (float)((ys[j] - m1) / s1);
+      u = (float)((y[j] - m0) * r0);
+      v = (float)((ys[j] - m1) * r1);
     }
-    const long long o = ((long long)bi * n + l) * 2;
-    outp[o] = f2bf(u);
-    outp[o + 1] = f2bf(v);
+    o32[l] = (uint32_t)f2bf(u) | ((uint32_t)f2bf(v) << 16);  // both channels of pixel l
   }
 }
 
