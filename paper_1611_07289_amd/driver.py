@@ -82,7 +82,8 @@ def sr_iterations(plan, X, y, buf: Buffers, n_sr: int, params: Optional[pvr.SRPa
 def reconstruct(plan, y, theta0, cycles: int = 3, n_sr: int = 10,
                 reg_params: Optional[pvr.RegParams] = None,
                 sr_params: Optional[pvr.SRParams] = None, register: bool = True,
-                init_fn=None, active_schedule=None, sample_mask=None):
+                init_fn=None, active_schedule=None, sample_mask=None, X0=None,
+                first_cycle: int = 0, on_cycle=None):
     """Full reconstruction; theta0 is [M, 6] float32 on the device and is
     updated in place.  ``init_fn(plan, X, y, theta)``, when given, runs before
     each registration (a learned initialiser).  ``active_schedule``, when
@@ -92,6 +93,13 @@ def reconstruct(plan, y, theta0, cycles: int = 3, n_sr: int = 10,
     ``sample_mask`` (uint8 [N] on the device), when given, applies at every
     build: the samples of arbitrarily shaped patches (superpixels) inside
     their rectangular boxes.
+    Resuming: ``X0`` (a volume [V] on the device) replaces the initial volume
+    and the cycles are numbered from ``first_cycle`` (the active schedule
+    follows the numbering); EM restarts every cycle, so (X, theta, cycle) is
+    the whole state between cycles (see save_checkpoint / load_checkpoint).
+    ``on_cycle(record)``, when given, receives after every cycle a dict of
+    its statistics: cycle, mean NCC after registration, EM sigma^2, c, m and
+    excluded patches, and the cumulative timings.
     Returns (X, theta, history)."""
     import torch
     buf = Buffers(plan, y.device)
@@ -106,13 +114,13 @@ def reconstruct(plan, y, theta0, cycles: int = 3, n_sr: int = 10,
         return time.perf_counter()
 
     t = tick()
-    plan.build(theta, active=active(0), mask=sample_mask)
-    X = initial_volume(plan, y, buf)
+    plan.build(theta, active=active(first_cycle), mask=sample_mask)
+    X = initial_volume(plan, y, buf) if X0 is None else X0.clone()
     t1 = tick(); timings["build"] += t1 - t
     hist = {"ncc": [], "excluded": []}
     ymax = float(y.abs().max())
     rp = reg_params or pvr.RegParams.make(min_std=0.01 * ymax)
-    for c in range(cycles):
+    for c in range(first_cycle, first_cycle + cycles):
         if register:
             if init_fn is not None:
                 t = tick()
@@ -130,9 +138,40 @@ def reconstruct(plan, y, theta0, cycles: int = 3, n_sr: int = 10,
         t = tick()
         sr_iterations(plan, X, y, buf, n_sr, sr_params)
         timings["sr"] += tick() - t
-        hist["excluded"].append(pvr.Plan.read_em(buf.em)[0].n_excluded)
+        em = pvr.Plan.read_em(buf.em)
+        hist["excluded"].append(em[0].n_excluded)
+        if on_cycle is not None:
+            on_cycle({"cycle": c, "mean_ncc": hist["ncc"][-1] if register else None,
+                      "sigma2": [e.sigma2 for e in em], "c": [e.c for e in em],
+                      "m": [e.m for e in em], "excluded": [e.n_excluded for e in em],
+                      "timings": dict(timings)})
     hist["timings"] = timings
     return X, theta, hist
+
+
+def save_checkpoint(path: str, X, theta, cycle: int) -> None:
+    """The state between two cycles (EM restarts every cycle): the volume,
+    the motion and the index of the next cycle, as an .npz file."""
+    np.savez(path, X=X.detach().cpu().numpy(), theta=theta.detach().cpu().numpy(),
+             next_cycle=np.int64(cycle))
+
+
+def load_checkpoint(path: str, device="cuda"):
+    """(X, theta, next_cycle) of save_checkpoint, tensors on ``device``."""
+    import torch
+    with np.load(path, allow_pickle=False) as d:
+        return (torch.from_numpy(d["X"]).to(device), torch.from_numpy(d["theta"]).to(device),
+                int(d["next_cycle"]))
+
+
+def json_lines(stream):
+    """An on_cycle callback writing one JSON line per cycle to ``stream``."""
+    import json
+
+    def write(record):
+        stream.write(json.dumps(record) + "\n")
+        stream.flush()
+    return write
 
 
 def psnr(X, X_true, plan, dilate_vox: int = 5) -> float:
