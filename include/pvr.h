@@ -33,7 +33,9 @@
  * Conventions
  *  - Pointers are DEVICE pointers unless marked (host).  The caller owns every
  *    buffer passed in; the plan owns its own device buffers (allocated by
- *    pvr_plan_create / pvr_plan_build, freed by pvr_plan_destroy).
+ *    pvr_plan_create / pvr_plan_build, freed by pvr_plan_destroy).  Device
+ *    arrays are aligned to their element size (FP32 and int32 4 bytes, FP64
+ *    and pvr_em_state 8); a misaligned pointer gives PVR_EINVAL.
  *  - Calls are asynchronous on `stream` except where noted.  A plan is used on
  *    one stream at a time (thread-compatible, not thread-safe).
  *  - Every function returns a pvr_status; no exception crosses the ABI.  On

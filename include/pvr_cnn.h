@@ -18,7 +18,10 @@
  * Conventions: device pointers; BF16 values are stored as uint16_t (upper
  * half of the FP32 bit pattern, round to nearest even); activations NHWC
  * ([B][H][W][C]); conv weights [Cout][3][3][Cin] (forward and FP32 master)
- * and [3][3][Cin][Cout] (data gradient).  All calls are asynchronous on
+ * and [3][3][Cin][Cout] (data gradient).  BF16 activations, weights,
+ * activation gradients and the FP32 scratch arrays are 16-byte aligned (they
+ * are read 16 bytes at a time), other FP32 and int32 arrays 4-byte aligned;
+ * a misaligned pointer gives PVR_EINVAL.  All calls are asynchronous on
  * `stream` and return pvr_status (pvr_last_error() explains failures).
  * Supported (cin, cout, stride): (2,32,1) (32,32,2) (32,64,1) (64,64,2)
  * (64,64,1) (32,32,1) (64,32,1); the data gradient needs cin >= 16.

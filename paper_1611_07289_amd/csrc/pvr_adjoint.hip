@@ -284,6 +284,11 @@ extern "C" pvr_status pvr_backproject(const pvr_plan *p, const float *e, const f
                                       const float *patch_w, float *num, float *den,
                                       hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_backproject", e, 4);
+  PVR_ALIGNED("pvr_backproject", pp, 4);
+  PVR_ALIGNED("pvr_backproject", patch_w, 4);
+  PVR_ALIGNED("pvr_backproject", num, 4);
+  PVR_ALIGNED("pvr_backproject", den, 4);
   if (!p) return fail(PVR_EINVAL, "pvr_backproject: plan is NULL");
   if (!p->built) return fail(PVR_EINVAL, "pvr_backproject: plan has not been built");
   return backproject_impl<float>(p, e, pp, patch_w, num, den, p->d_invz, p->d_rq + 1, stream);
@@ -294,6 +299,11 @@ extern "C" pvr_status pvr_backproject_f64(const pvr_plan *p, const double *e, co
                                           const double *patch_w, double *num, double *den,
                                           hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_backproject_f64", e, 8);
+  PVR_ALIGNED("pvr_backproject_f64", pp, 8);
+  PVR_ALIGNED("pvr_backproject_f64", patch_w, 8);
+  PVR_ALIGNED("pvr_backproject_f64", num, 8);
+  PVR_ALIGNED("pvr_backproject_f64", den, 8);
   if (!p) return fail(PVR_EINVAL, "pvr_backproject_f64: plan is NULL");
   if (!p->built || !p->built64) return fail(PVR_EINVAL, "pvr_backproject_f64: plan needs pvr_plan_build_f64");
   pvr_plan *mp = const_cast<pvr_plan *>(p);

@@ -773,6 +773,10 @@ extern "C" pvr_status pvr_cnn_conv_fwd(const uint16_t *in, const uint16_t *w, co
                                        int32_t cin, int32_t cout, int32_t stride, int32_t relu,
                                        hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_cnn_conv_fwd", in, 16);
+  PVR_ALIGNED("pvr_cnn_conv_fwd", w, 16);
+  PVR_ALIGNED("pvr_cnn_conv_fwd", bias, 4);
+  PVR_ALIGNED("pvr_cnn_conv_fwd", out, 16);
   if (!in || !w || !bias || !out || B <= 0 || H <= 0 || W <= 0)
     return fail(PVR_EINVAL, "pvr_cnn_conv_fwd: invalid argument");
   const long long P = (long long)B * out_size(H, stride) * out_size(W, stride);
@@ -797,6 +801,10 @@ extern "C" pvr_status pvr_cnn_conv_dgrad(const uint16_t *gout, const uint16_t *o
                                          int32_t W, int32_t cin, int32_t cout, int32_t stride,
                                          hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_cnn_conv_dgrad", gout, 16);
+  PVR_ALIGNED("pvr_cnn_conv_dgrad", out, 16);
+  PVR_ALIGNED("pvr_cnn_conv_dgrad", wt, 16);
+  PVR_ALIGNED("pvr_cnn_conv_dgrad", gin, 16);
   if (!gout || !out || !wt || !gin || B <= 0) return fail(PVR_EINVAL, "pvr_cnn_conv_dgrad: invalid argument");
   const long long P = (long long)B * H * W;
   const long long n_tiles = (P + FW_TILE - 1) / FW_TILE;
@@ -846,6 +854,12 @@ extern "C" pvr_status pvr_cnn_conv_wgrad(const uint16_t *gout, const uint16_t *o
                                          int32_t B, int32_t H, int32_t W, int32_t cin,
                                          int32_t cout, int32_t stride, hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_cnn_conv_wgrad", gout, 16);
+  PVR_ALIGNED("pvr_cnn_conv_wgrad", out, 16);
+  PVR_ALIGNED("pvr_cnn_conv_wgrad", in, 16);
+  PVR_ALIGNED("pvr_cnn_conv_wgrad", scratch, 16);
+  PVR_ALIGNED("pvr_cnn_conv_wgrad", dw, 4);
+  PVR_ALIGNED("pvr_cnn_conv_wgrad", db, 4);
   if (!gout || !out || !in || !scratch || !dw || !db || B <= 0)
     return fail(PVR_EINVAL, "pvr_cnn_conv_wgrad: invalid argument");
   const long long P = (long long)B * out_size(H, stride) * out_size(W, stride);
@@ -884,6 +898,10 @@ extern "C" pvr_status pvr_cnn_pack_pairs(const pvr_plan *p, const int32_t *patch
                                          const float *y_obs, const float *y_sim, uint16_t *out,
                                          hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_cnn_pack_pairs", patch_ids, 4);
+  PVR_ALIGNED("pvr_cnn_pack_pairs", y_obs, 4);
+  PVR_ALIGNED("pvr_cnn_pack_pairs", y_sim, 4);
+  PVR_ALIGNED("pvr_cnn_pack_pairs", out, 4);
   if (!p || !patch_ids || !y_obs || !y_sim || !out || B <= 0)
     return fail(PVR_EINVAL, "pvr_cnn_pack_pairs: invalid argument");
   if (!p->built) return fail(PVR_EINVAL, "pvr_cnn_pack_pairs: plan has not been built");
@@ -903,6 +921,17 @@ extern "C" pvr_status pvr_cnn_head(const uint16_t *act, int32_t B, int32_t hw, c
                                    float *pred, float *loss, uint16_t *gact, float *dwfc,
                                    float *dbfc, float *scratch, hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_cnn_head", act, 16);
+  PVR_ALIGNED("pvr_cnn_head", wfc, 4);
+  PVR_ALIGNED("pvr_cnn_head", bfc, 4);
+  PVR_ALIGNED("pvr_cnn_head", target, 4);
+  PVR_ALIGNED("pvr_cnn_head", loss_w, 4);
+  PVR_ALIGNED("pvr_cnn_head", pred, 4);
+  PVR_ALIGNED("pvr_cnn_head", loss, 4);
+  PVR_ALIGNED("pvr_cnn_head", gact, 16);
+  PVR_ALIGNED("pvr_cnn_head", dwfc, 4);
+  PVR_ALIGNED("pvr_cnn_head", dbfc, 4);
+  PVR_ALIGNED("pvr_cnn_head", scratch, 16);
   if (!act || !wfc || !bfc || !pred || B <= 0 || hw <= 0) return fail(PVR_EINVAL, "pvr_cnn_head: invalid argument");
   if ((long long)hw * 64 > (1 << 24)) return fail(PVR_ESHAPE, "pvr_cnn_head: hw too large");
   if (target && (!loss_w || !loss || !gact || !dwfc || !dbfc || !scratch))
@@ -931,6 +960,12 @@ extern "C" pvr_status pvr_cnn_adam(float *w, const float *g, float *m, float *v,
                                    uint16_t *w_bf16, uint16_t *wt_bf16, int32_t cout, int32_t cin,
                                    hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_cnn_adam", w, 4);
+  PVR_ALIGNED("pvr_cnn_adam", g, 4);
+  PVR_ALIGNED("pvr_cnn_adam", m, 4);
+  PVR_ALIGNED("pvr_cnn_adam", v, 4);
+  PVR_ALIGNED("pvr_cnn_adam", w_bf16, 16);
+  PVR_ALIGNED("pvr_cnn_adam", wt_bf16, 16);
   if (!w || !m || !v || n <= 0 || step < 0) return fail(PVR_EINVAL, "pvr_cnn_adam: invalid argument");
   if (wt_bf16 && (cout <= 0 || cin <= 0 || cout * 9 * cin != n))
     return fail(PVR_EINVAL, "pvr_cnn_adam: transposed copy needs n = cout * 9 * cin");

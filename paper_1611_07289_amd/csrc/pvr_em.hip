@@ -449,6 +449,12 @@ extern "C" pvr_status pvr_robust_weights(pvr_plan *p, const float *resid, const 
                                          pvr_em_state *em, float *pp, float *pbar,
                                          float *patch_w, int32_t flags, hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_robust_weights", resid, 4);
+  PVR_ALIGNED("pvr_robust_weights", y_obs, 4);
+  PVR_ALIGNED("pvr_robust_weights", em, 8);
+  PVR_ALIGNED("pvr_robust_weights", pp, 4);
+  PVR_ALIGNED("pvr_robust_weights", pbar, 4);
+  PVR_ALIGNED("pvr_robust_weights", patch_w, 4);
   if (!p || !resid || !y_obs || !em || !patch_w) return fail(PVR_EINVAL, "pvr_robust_weights: NULL argument");
   if (!p->built) return fail(PVR_EINVAL, "pvr_robust_weights: plan has not been built");
   const int init = (flags & PVR_EM_INIT) != 0;

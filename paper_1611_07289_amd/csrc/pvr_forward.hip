@@ -249,6 +249,10 @@ static pvr_status simulate_impl(const pvr_plan *p, const T *X, const T *y_obs, T
 extern "C" pvr_status pvr_simulate(const pvr_plan *p, const float *X, const float *y_obs,
                                    float *y_sim, float *resid, hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_simulate", X, 4);
+  PVR_ALIGNED("pvr_simulate", y_obs, 4);
+  PVR_ALIGNED("pvr_simulate", y_sim, 4);
+  PVR_ALIGNED("pvr_simulate", resid, 4);
   if (!p) return fail(PVR_EINVAL, "pvr_simulate: plan is NULL");
   if (!p->built) return fail(PVR_EINVAL, "pvr_simulate: plan has not been built");
   return simulate_impl<float>(p, X, y_obs, y_sim, resid, p->d_invz, stream);
@@ -258,6 +262,10 @@ extern "C" pvr_status pvr_simulate(const pvr_plan *p, const float *X, const floa
 extern "C" pvr_status pvr_simulate_f64(const pvr_plan *p, const double *X, const double *y_obs,
                                        double *y_sim, double *resid, hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_simulate_f64", X, 8);
+  PVR_ALIGNED("pvr_simulate_f64", y_obs, 8);
+  PVR_ALIGNED("pvr_simulate_f64", y_sim, 8);
+  PVR_ALIGNED("pvr_simulate_f64", resid, 8);
   if (!p) return fail(PVR_EINVAL, "pvr_simulate_f64: plan is NULL");
   if (!p->built || !p->built64) return fail(PVR_EINVAL, "pvr_simulate_f64: plan needs pvr_plan_build_f64");
   return simulate_impl<double>(p, X, y_obs, y_sim, resid, p->d_invz64, stream);
@@ -590,6 +598,10 @@ extern "C" pvr_status pvr_register_patches(const pvr_plan *p, const float *X, co
                                            float *theta, float *ncc, const uint8_t *reg,
                                            const pvr_reg_params *prm, hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_register_patches", X, 4);
+  PVR_ALIGNED("pvr_register_patches", y_obs, 4);
+  PVR_ALIGNED("pvr_register_patches", theta, 4);
+  PVR_ALIGNED("pvr_register_patches", ncc, 4);
   if (!p || !X || !y_obs || !theta || !prm) return fail(PVR_EINVAL, "pvr_register_patches: NULL argument");
   if (!p->built) return fail(PVR_EINVAL, "pvr_register_patches: plan has not been built");
   if (prm->max_iter < 0 || !(prm->step0 > 0) || !(prm->step_min > 0) || !(prm->fd_h > 0))

@@ -97,6 +97,9 @@ static pvr_status grad_impl(const pvr_plan *p, const T *X, const T *gy, T *grad,
 extern "C" pvr_status pvr_simulate_grad_theta(const pvr_plan *p, const float *X, const float *gy,
                                               float *grad_theta, hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_simulate_grad_theta", X, 4);
+  PVR_ALIGNED("pvr_simulate_grad_theta", gy, 4);
+  PVR_ALIGNED("pvr_simulate_grad_theta", grad_theta, 4);
   if (!p) return fail(PVR_EINVAL, "pvr_simulate_grad_theta: plan is NULL");
   if (!p->built) return fail(PVR_EINVAL, "pvr_simulate_grad_theta: plan has not been built");
   return grad_impl<float>(p, X, gy, grad_theta, p->d_invz, stream);
@@ -107,6 +110,9 @@ extern "C" pvr_status pvr_simulate_grad_theta_f64(const pvr_plan *p, const doubl
                                                   const double *gy, double *grad_theta,
                                                   hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_simulate_grad_theta_f64", X, 8);
+  PVR_ALIGNED("pvr_simulate_grad_theta_f64", gy, 8);
+  PVR_ALIGNED("pvr_simulate_grad_theta_f64", grad_theta, 8);
   if (!p) return fail(PVR_EINVAL, "pvr_simulate_grad_theta_f64: plan is NULL");
   if (!p->built || !p->built64)
     return fail(PVR_EINVAL, "pvr_simulate_grad_theta_f64: plan needs pvr_plan_build_f64");
@@ -182,6 +188,10 @@ k_ncc_grad(const PatchDev *__restrict__ patches, const float *__restrict__ invz,
 extern "C" pvr_status pvr_ncc_grad(const pvr_plan *p, const float *y_obs, const float *y_sim,
                                    float *grad_y, float *ncc, hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_ncc_grad", y_obs, 4);
+  PVR_ALIGNED("pvr_ncc_grad", y_sim, 4);
+  PVR_ALIGNED("pvr_ncc_grad", grad_y, 4);
+  PVR_ALIGNED("pvr_ncc_grad", ncc, 4);
   if (!p || !y_obs || !y_sim) return fail(PVR_EINVAL, "pvr_ncc_grad: NULL argument");
   if (!p->built) return fail(PVR_EINVAL, "pvr_ncc_grad: plan has not been built");
   hipLaunchKernelGGL(k_ncc_grad, dim3(p->M), dim3(GR_THREADS), 0, stream, p->d_patch, p->d_invz,

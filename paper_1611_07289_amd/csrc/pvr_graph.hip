@@ -46,6 +46,16 @@ extern "C" pvr_status pvr_sr_graph_create(pvr_plan *plan, float *X, float *X_alt
                                           int32_t iters, hipStream_t stream,
                                           pvr_sr_graph **out) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_sr_graph_create", X, 4);
+  PVR_ALIGNED("pvr_sr_graph_create", X_alt, 4);
+  PVR_ALIGNED("pvr_sr_graph_create", y_obs, 4);
+  PVR_ALIGNED("pvr_sr_graph_create", resid, 4);
+  PVR_ALIGNED("pvr_sr_graph_create", p, 4);
+  PVR_ALIGNED("pvr_sr_graph_create", pbar, 4);
+  PVR_ALIGNED("pvr_sr_graph_create", patch_w, 4);
+  PVR_ALIGNED("pvr_sr_graph_create", num, 4);
+  PVR_ALIGNED("pvr_sr_graph_create", den, 4);
+  PVR_ALIGNED("pvr_sr_graph_create", em, 8);
   if (!out) return fail(PVR_EINVAL, "pvr_sr_graph_create: out is NULL");
   *out = nullptr;
   if (!plan || !X || !X_alt || !y_obs || !resid || !p || !pbar || !patch_w || !num || !den ||

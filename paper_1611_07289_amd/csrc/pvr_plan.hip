@@ -696,6 +696,7 @@ static pvr_status plan_build_common(pvr_plan *p, const uint8_t *active, const ui
 extern "C" pvr_status pvr_plan_build(pvr_plan *p, const float *theta, const uint8_t *active,
                                      const uint8_t *sample_mask, hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_plan_build", theta, 4);
   if (!p || !theta) return fail(PVR_EINVAL, "pvr_plan_build: NULL plan or theta");
   const int n = 6 * p->M;
   hipLaunchKernelGGL(k_theta_to_f64, dim3((n + 255) / 256), dim3(256), 0, stream, theta, p->d_theta, n);
@@ -707,6 +708,7 @@ extern "C" pvr_status pvr_plan_build(pvr_plan *p, const float *theta, const uint
 extern "C" pvr_status pvr_plan_build_f64(pvr_plan *p, const double *theta, const uint8_t *active,
                                          const uint8_t *sample_mask, hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_plan_build_f64", theta, 8);
   if (!p || !theta) return fail(PVR_EINVAL, "pvr_plan_build_f64: NULL plan or theta");
   const int n = 6 * p->M;
   hipLaunchKernelGGL(k_copy_theta, dim3((n + 255) / 256), dim3(256), 0, stream, theta, p->d_theta, n);

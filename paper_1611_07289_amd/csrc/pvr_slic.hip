@@ -242,6 +242,8 @@ extern "C" int64_t pvr_slic_centres(int32_t h, int32_t w, int32_t a) {
 extern "C" pvr_status pvr_slic_init(const float *img, int32_t n_img, int32_t h, int32_t w,
                                     int32_t a, float t0, float *centres, hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_slic_init", img, 4);
+  PVR_ALIGNED("pvr_slic_init", centres, 16);
   if (!img || !centres) return fail(PVR_EINVAL, "pvr_slic_init: NULL argument");
   if (a <= 0 || a > (1 << 20)) return fail(PVR_EINVAL, "pvr_slic_init: a must be in [1, 2^20]");
   pvr_status st = check_sizes("pvr_slic_init", n_img, h, w, a);
@@ -259,6 +261,10 @@ extern "C" pvr_status pvr_slic_assign(const float *img, int32_t n_img, int32_t h
                                       int32_t a, const float *centres, uint64_t *scratch,
                                       int32_t *labels, hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_slic_assign", img, 4);
+  PVR_ALIGNED("pvr_slic_assign", centres, 16);
+  PVR_ALIGNED("pvr_slic_assign", scratch, 8);
+  PVR_ALIGNED("pvr_slic_assign", labels, 4);
   if (!img || !centres || !scratch || !labels) return fail(PVR_EINVAL, "pvr_slic_assign: NULL argument");
   if (a <= 0 || a > (1 << 20)) return fail(PVR_EINVAL, "pvr_slic_assign: a must be in [1, 2^20]");
   pvr_status st = check_sizes("pvr_slic_assign", n_img, h, w, a);
@@ -279,6 +285,9 @@ extern "C" pvr_status pvr_slic_update(const float *img, int32_t n_img, int32_t h
                                       int32_t a, const int32_t *labels, float t_min,
                                       float *centres, hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_slic_update", img, 4);
+  PVR_ALIGNED("pvr_slic_update", labels, 4);
+  PVR_ALIGNED("pvr_slic_update", centres, 16);
   if (!img || !labels || !centres) return fail(PVR_EINVAL, "pvr_slic_update: NULL argument");
   if (a <= 0 || a > (1 << 20)) return fail(PVR_EINVAL, "pvr_slic_update: a must be in [1, 2^20]");
   pvr_status st = check_sizes("pvr_slic_update", n_img, h, w, a);
@@ -295,6 +304,10 @@ extern "C" pvr_status pvr_slic(const float *img, int32_t n_img, int32_t h, int32
                                float t0, float t_min, int32_t iters, uint64_t *scratch,
                                float *centres, int32_t *labels, hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_slic", img, 4);
+  PVR_ALIGNED("pvr_slic", centres, 16);
+  PVR_ALIGNED("pvr_slic", scratch, 8);
+  PVR_ALIGNED("pvr_slic", labels, 4);
   if (iters < 0) return fail(PVR_EINVAL, "pvr_slic: iters < 0");
   pvr_status st = pvr_slic_init(img, n_img, h, w, a, t0, centres, stream);
   for (int it = 0; st == PVR_OK && it < iters; ++it) {
@@ -413,6 +426,9 @@ extern "C" pvr_status pvr_slic_boxes(const int32_t *labels, int32_t n_img, int32
                                      int32_t a, const float *centres, int32_t gamma,
                                      int32_t *boxes, hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_slic_boxes", labels, 4);
+  PVR_ALIGNED("pvr_slic_boxes", centres, 16);
+  PVR_ALIGNED("pvr_slic_boxes", boxes, 4);
   if (!labels || !centres || !boxes) return fail(PVR_EINVAL, "pvr_slic_boxes: NULL argument");
   if (gamma < 0) return fail(PVR_EINVAL, "pvr_slic_boxes: gamma < 0");
   if (a <= 0 || a > (1 << 20)) return fail(PVR_EINVAL, "pvr_slic_boxes: a must be in [1, 2^20]");
@@ -431,6 +447,9 @@ extern "C" pvr_status pvr_slic_pack(const float *img, const int32_t *labels, int
                                     const int32_t *table, float *y, uint8_t *mask,
                                     hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_slic_pack", img, 4);
+  PVR_ALIGNED("pvr_slic_pack", labels, 4);
+  PVR_ALIGNED("pvr_slic_pack", y, 4);
   if (!img || !labels || !table || (M > 0 && (!y || !mask)))
     return fail(PVR_EINVAL, "pvr_slic_pack: NULL argument");
   if (gamma < 0 || M < 0) return fail(PVR_EINVAL, "pvr_slic_pack: gamma < 0 or M < 0");

@@ -73,6 +73,10 @@ extern "C" pvr_status pvr_sr_update(const pvr_plan *p, const float *X, const flo
                                     const float *den, const pvr_sr_params *prm, float *X_out,
                                     hipStream_t stream) {
   PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_sr_update", X, 4);
+  PVR_ALIGNED("pvr_sr_update", num, 4);
+  PVR_ALIGNED("pvr_sr_update", den, 4);
+  PVR_ALIGNED("pvr_sr_update", X_out, 4);
   if (!p || !X || !num || !den || !prm || !X_out) return fail(PVR_EINVAL, "pvr_sr_update: NULL argument");
   if (X_out == X) return fail(PVR_EINVAL, "pvr_sr_update: X_out must not alias X");
   if (!(prm->delta > 0)) return fail(PVR_EINVAL, "pvr_sr_update: delta must be > 0");

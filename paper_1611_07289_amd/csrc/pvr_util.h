@@ -52,6 +52,15 @@ struct PlanGuard {
                        hipGetErrorString(e_), __FILE__, __LINE__);             \
   } while (0)
 
+// Device arrays must be aligned to the width the kernels read them with; a
+// NULL pointer passes (whether it may be NULL is checked separately).
+#define PVR_ALIGNED(fn, ptr, a)                                                \
+  do {                                                                         \
+    if ((reinterpret_cast<uintptr_t>(ptr) & ((uintptr_t)(a) - 1)) != 0)        \
+      return pvr::fail(PVR_EINVAL, "%s: %s is not %d-byte aligned", fn, #ptr,  \
+                       (int)(a));                                              \
+  } while (0)
+
 #define DEV_ALLOC(plan, ptr, count)                                            \
   do {                                                                         \
     size_t n_ = (size_t)(count) * sizeof(*(ptr));                              \

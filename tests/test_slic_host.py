@@ -57,3 +57,16 @@ def test_pack_table_follows_the_oracle_patch_order():
             B[i, k] = (x0, y0, w, h)
             expect.append((i, k, x0, y0, w, h))
     assert np.array_equal(superpixel.patch_table(B), np.array(expect, np.int32))
+
+
+def test_misaligned_device_pointers_rejected_on_host():
+    L = pvr.load()
+    a, odd = ctypes.c_void_p(4096), ctypes.c_void_p(4096 + 2)
+    assert L.pvr_sr_update(None, odd, a, a, None, a, None) == 1
+    assert "4-byte aligned" in L.pvr_last_error().decode()
+    assert L.pvr_simulate_f64(None, ctypes.c_void_p(4096 + 4), None, None, None, None) == 1
+    assert "8-byte aligned" in L.pvr_last_error().decode()
+    assert L.pvr_slic_init(a, 1, 8, 8, 4, 1.0, ctypes.c_void_p(4096 + 8), None) == 1
+    assert "centres is not 16-byte aligned" in L.pvr_last_error().decode()
+    assert L.pvr_cnn_conv_fwd(ctypes.c_void_p(4096 + 8), a, a, a, 1, 8, 8, 32, 32, 1, 1, None) == 1
+    assert "16-byte aligned" in L.pvr_last_error().decode()
