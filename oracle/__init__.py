@@ -40,10 +40,14 @@ def build(force: bool = False) -> str:
 
 
 def lib():
+    """The oracle library: the in-tree build, or the file PVR_ORACLE_LIB names
+    (a sanitizer build of the same source, in the tests)."""
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(_LIB)
+        path = os.environ.get("PVR_ORACLE_LIB")
+        if not path:
+            path = build()
+        L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i64 = ctypes.c_int64
         L.ora_ctx_create.restype = P
