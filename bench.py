@@ -313,7 +313,8 @@ def main():
         if ev is not None:
             ev[1].record()
         plan.robust_weights(e, y, em, p, pbar, W,
-                            (pvr.PVR_EM_INIT if first else 0) | pvr.PVR_EM_RESID_FRESH)
+                            (pvr.PVR_EM_INIT if first else 0) | pvr.PVR_EM_RESID_FRESH
+                            | pvr.PVR_EM_PREP_ADJOINT)
         if ev is not None:
             ev[2].record()
         plan.backproject(e, p, W, num, den)

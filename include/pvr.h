@@ -144,6 +144,16 @@ typedef struct {
                                 library also checks the two pointers; with a
                                 mismatch, LDS-tiled simulation or a build in
                                 between it passes over resid as usual) */
+#define PVR_EM_PREP_ADJOINT 8 /* also prepare the adjoint's per-sample inputs
+                                 (p e / Z, p / Z) for a pvr_backproject(resid,
+                                 p, patch_w, ...) that follows with these same
+                                 resid and p buffers, unmodified: the
+                                 preparation runs on the plan's second stream
+                                 while the patch classification runs on
+                                 `stream` (joined before the call returns on
+                                 `stream`), and pvr_backproject skips its own
+                                 pass.  Needs p != NULL; a pvr_simulate or a
+                                 build in between cancels it */
 
 typedef struct {
   float alpha;              /* step length (default 1) */
@@ -380,7 +390,8 @@ pvr_status pvr_check(pvr_plan *plan, hipStream_t stream);
  * problem of the plan in each launch).  Records `iters` SR iterations into a
  * HIP graph: iteration i simulates from the current volume (X for even i,
  * X_alt for odd i) with residuals into resid, runs the robust weights with
- * PVR_EM_RESID_FRESH (EM continues from em's state: start a cycle with an
+ * PVR_EM_RESID_FRESH | PVR_EM_PREP_ADJOINT (the preparation branch of the
+ * adjoint is a second branch of the graph; EM continues from em's state: start a cycle with an
  * eager call with PVR_EM_INIT first), back-projects into num / den and writes
  * the update into the other volume; after a launch the volume is in X when
  * iters is even, else in X_alt.  All buffers are device memory of the sizes

@@ -39,7 +39,7 @@ class GraphedSR:
         pl = self.plan
         pl.simulate(src, y_obs=self.y, resid=self.e)
         pl.robust_weights(self.e, self.y, self.em, self.p, self.pbar, self.W,
-                          flags | pvr.PVR_EM_RESID_FRESH)
+                          flags | pvr.PVR_EM_RESID_FRESH | pvr.PVR_EM_PREP_ADJOINT)
         pl.backproject(self.e, self.p, self.W, self.num, self.den)
         pl.sr_update(src, self.num, self.den, dst, self.prm)
 

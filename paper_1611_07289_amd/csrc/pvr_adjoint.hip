@@ -20,23 +20,23 @@ template <typename T> struct Vec2Of;
 template <> struct Vec2Of<float> { using type = float2; };
 template <> struct Vec2Of<double> { using type = double2; };
 
-// rq_j = (W_s p_j e_j / Z_j, W_s p_j / Z_j) for valid samples, 0 otherwise.
+// rq_j = (p_j e_j / Z_j, p_j / Z_j) for valid samples, 0 otherwise (the
+// patch weight W_s is applied by the gather, per patch).
 template <typename T>
 __global__ void __launch_bounds__(SIM_THREADS)
 k_bp_prep(const PatchDev *__restrict__ patches, const BlockWork *__restrict__ work,
           const T *__restrict__ invz, const T *__restrict__ e, const T *__restrict__ p,
-          const T *__restrict__ patch_w, typename Vec2Of<T>::type *__restrict__ rq) {
+          typename Vec2Of<T>::type *__restrict__ rq) {
   const BlockWork wk = work[blockIdx.x];
   const PatchDev pt = patches[wk.patch];
-  const T w = patch_w ? patch_w[wk.patch] : (T)1;
   const int n = pt.w * pt.h;
   const int l1 = min(n, wk.l0 + SIM_CHUNK);
   for (int l = wk.l0 + threadIdx.x; l < l1; l += SIM_THREADS) {
     const long long j = pt.off + l;
     const T iz = invz[j];
     typename Vec2Of<T>::type o;
-    if (iz > (T)0 && w != (T)0) {
-      const T q = w * (p ? p[j] : (T)1) * iz;
+    if (iz > (T)0) {
+      const T q = (p ? p[j] : (T)1) * iz;
       o.x = q * e[j];
       o.y = q;
     } else {
@@ -213,8 +213,10 @@ k_backproject(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ pa
   const double fi = i, fj = jj, fk = kk;
   for (int q = q0; q < q1; ++q) {
     const int s = sub_patch[q];
-    // an excluded patch (weight 0) contributes exactly 0: its rq entries are 0
-    if (patch_w && patch_w[s] == (T)0) continue;
+    // the patch weight scales the patch's whole contribution; an excluded
+    // patch (weight 0) is skipped
+    const T ws = patch_w ? patch_w[s] : (T)1;
+    if (ws == (T)0) continue;
     const GEO &g = geo[s];
     const PatchDev pt = patches[s];
     const double pk = fma(g.G[8], fi, fma(g.G[9], fj, fma(g.G[10], fk, g.G[11])));
@@ -223,20 +225,32 @@ k_backproject(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ pa
     if (!(qk <= (T)g.K2)) continue;
     const double pu = fma(g.G[0], fi, fma(g.G[1], fj, fma(g.G[2], fk, g.G[3])));
     const double pv = fma(g.G[4], fi, fma(g.G[5], fj, fma(g.G[6], fk, g.G[7])));
+    T pn = 0, pd = 0;
     if (SINC)
-      adj_patch_sinc<T, GEO, V2, HW, HW, DEN>(g, pt, pu, pv, qk, rq, sn, sd);
+      adj_patch_sinc<T, GEO, V2, HW, HW, DEN>(g, pt, pu, pv, qk, rq, pn, pd);
     else if (HW == 1)
-      adj_patch<T, GEO, V2, 1, 1, DEN>(g, pt, pu, pv, qk, rq, sn, sd);
+      adj_patch<T, GEO, V2, 1, 1, DEN>(g, pt, pu, pv, qk, rq, pn, pd);
     else if (HW == 2)
-      adj_patch<T, GEO, V2, 2, 2, DEN>(g, pt, pu, pv, qk, rq, sn, sd);
+      adj_patch<T, GEO, V2, 2, 2, DEN>(g, pt, pu, pv, qk, rq, pn, pd);
     else
-      adj_patch_rt<T, GEO, V2, DEN>(g, pt, pu, pv, qk, rq, sn, sd);
+      adj_patch_rt<T, GEO, V2, DEN>(g, pt, pu, pv, qk, rq, pn, pd);
+    sn = fma(ws, pn, sn);
+    if (DEN) sd = fma(ws, pd, sd);
   }
   if (inside) {
     const long long idx = pr.vol_off + ((long long)kk * pr.ny + jj) * pr.nx + i;
     num[idx] = sn;
     if (DEN) den[idx] = sd;
   }
+}
+
+// The preparation pass on its own (FP32), for pvr_robust_weights.
+pvr_status pvr::launch_bp_prep(const pvr_plan *p, const float *e, const float *pp,
+                               hipStream_t stream) {
+  hipLaunchKernelGGL(k_bp_prep<float>, dim3(p->n_sim_blocks), dim3(SIM_THREADS), 0, stream,
+                     p->d_patch, p->d_sim_blocks, p->d_invz, e, pp, p->d_rq + 1);
+  HIP_TRY(hipGetLastError());
+  return PVR_OK;
 }
 
 template <typename T>
@@ -248,9 +262,15 @@ static pvr_status backproject_impl(const pvr_plan *p, const T *e, const T *pp, c
     const pvr_status st = plan_build_index(const_cast<pvr_plan *>(p), stream);
     if (st != PVR_OK) return st;
   }
-  hipLaunchKernelGGL(k_bp_prep<T>, dim3(p->n_sim_blocks), dim3(SIM_THREADS), 0, stream, p->d_patch,
-                     p->d_sim_blocks, invz, e, pp, patch_w, rq);
-  HIP_TRY(hipGetLastError());
+  // the preparation pass, unless pvr_robust_weights (PVR_EM_PREP_ADJOINT)
+  // already ran it for these residuals and posteriors
+  const bool prepared = sizeof(T) == 4 && p->rq_fresh && p->rq_e == (const void *)e &&
+                        p->rq_p == (const void *)pp;
+  if (!prepared) {
+    hipLaunchKernelGGL(k_bp_prep<T>, dim3(p->n_sim_blocks), dim3(SIM_THREADS), 0, stream,
+                       p->d_patch, p->d_sim_blocks, invz, e, pp, rq);
+    HIP_TRY(hipGetLastError());
+  }
   const void *geo = sizeof(T) == 4 ? (const void *)p->d_geof : (const void *)p->d_geod;
   const dim3 grid(xcd_blocks(p->n_bricks, BP_XCD_GRANULE));
   hipEvent_t *ev = timing_slot(p, PVR_KERNEL_BACKPROJECT);

@@ -476,11 +476,29 @@ extern "C" pvr_status pvr_robust_weights(pvr_plan *p, const float *resid, const 
   hipLaunchKernelGGL(k_em_estep, dim3(p->M), dim3(EM_T), 0, stream, p->d_patch, p->d_invz, resid,
                      em, pp, pb, p->d_pstat);
   HIP_TRY(hipGetLastError());
+  // the adjoint's inputs need the posteriors only, not the patch weights: on
+  // request they are prepared on the plan's second stream while the patch
+  // classification (one workgroup per problem) runs on this one
+  const bool prep = (flags & PVR_EM_PREP_ADJOINT) && pp != nullptr;
+  p->rq_fresh = false;
+  if (prep) {
+    HIP_TRY(hipEventRecord(p->ev_fork, stream));
+    HIP_TRY(hipStreamWaitEvent(p->side, p->ev_fork, 0));
+    const pvr_status st = launch_bp_prep(p, resid, pp, p->side);
+    if (st != PVR_OK) return st;
+    HIP_TRY(hipEventRecord(p->ev_join, p->side));
+  }
   const int use_lds = p->max_problem_patches <= EMP_LDS;
   hipLaunchKernelGGL(k_em_patches, dim3(p->P), dim3(EMP_T),
                      use_lds ? (size_t)p->max_problem_patches * sizeof(float) : 0, stream,
                      p->d_prob, pb, p->d_active, p->d_pstat, p->d_pval, patch_w, em, fix, use_lds);
   HIP_TRY(hipGetLastError());
+  if (prep) {
+    HIP_TRY(hipStreamWaitEvent(stream, p->ev_join, 0));
+    p->rq_fresh = true;
+    p->rq_e = resid;
+    p->rq_p = pp;
+  }
   return PVR_OK;
   PVR_API_END();
 }

@@ -240,6 +240,7 @@ static pvr_status simulate_impl(const pvr_plan *p, const T *X, const T *y_obs, T
   if (ev) HIP_TRY(hipEventRecord(ev[1], stream));
   // the residual statistics describe these buffers until the next build
   pvr_plan *mp = const_cast<pvr_plan *>(p);
+  mp->rq_fresh = false;  // the residuals may have changed
   mp->stats_valid = stats != nullptr;
   mp->stats_resid = resid;
   mp->stats_y = y_obs;

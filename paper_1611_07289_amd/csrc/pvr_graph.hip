@@ -83,7 +83,8 @@ extern "C" pvr_status pvr_sr_graph_create(pvr_plan *plan, float *X, float *X_alt
   for (int i = 0; i < iters && st == PVR_OK; ++i) {
     st = pvr_simulate(plan, cur, y_obs, nullptr, resid, cs);
     if (st == PVR_OK)
-      st = pvr_robust_weights(plan, resid, y_obs, em, p, pbar, patch_w, PVR_EM_RESID_FRESH, cs);
+      st = pvr_robust_weights(plan, resid, y_obs, em, p, pbar, patch_w,
+                              PVR_EM_RESID_FRESH | PVR_EM_PREP_ADJOINT, cs);
     if (st == PVR_OK) st = pvr_backproject(plan, resid, p, patch_w, num, den, cs);
     if (st == PVR_OK) st = pvr_sr_update(plan, cur, num, den, params, nxt, cs);
     std::swap(cur, nxt);

@@ -610,6 +610,13 @@ struct pvr_plan {
   int psf;                   // PVR_PSF_GAUSSIAN (default) or PVR_PSF_SINC
   const void *stats_resid, *stats_y;  // ... and the buffers they describe
   bool stats_valid;
+  // adjoint inputs prepared by pvr_robust_weights (PVR_EM_PREP_ADJOINT) for
+  // these residual / posterior buffers, on a second stream beside the
+  // patch classification
+  bool rq_fresh;
+  const void *rq_e, *rq_p;
+  hipStream_t side;
+  hipEvent_t ev_fork, ev_join;
   unsigned *d_status;        // [1] numeric fault flags (PVR_FAULT_*), read by pvr_check
   long long generation;      // bumped whenever launches recorded earlier would go stale
   int *d_total;              // [1] pinned readback target (device side)

@@ -465,6 +465,9 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
   if (p->any_xt) DEV_ALLOC(p, p->d_xt, p->V);
   DEV_ALLOC(p, p->d_total, 4);
   DEV_ALLOC(p, p->d_status, 1);
+  HIP_TRY(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
   HIP_TRY(hipMemset(p->d_status, 0, sizeof(unsigned)));
   HIP_TRY(hipHostMalloc((void **)&p->h_total, sizeof(int) * 4, hipHostMallocDefault));
   HIP_TRY(hipMemcpy(p->d_prob, p->h_prob, sizeof(ProbDev) * n_problems, hipMemcpyHostToDevice));
@@ -560,6 +563,7 @@ extern "C" pvr_status pvr_plan_set_psf(pvr_plan *p, int32_t kind) {
   p->built = p->built64 = false;
   p->index_valid = false;
   p->stats_valid = false;
+  p->rq_fresh = false;
   ++p->generation;
   return PVR_OK;
   PVR_API_END();
@@ -687,6 +691,7 @@ static pvr_status plan_build_common(pvr_plan *p, const uint8_t *active, const ui
   }
   p->index_valid = false;
   p->stats_valid = false;
+  p->rq_fresh = false;
   p->built = true;
   p->built64 = f64;
   ++p->generation;

@@ -15,6 +15,7 @@ pvr_status fail(pvr_status st, const char *fmt, ...) __attribute__((format(print
 void clear_error();
 void plan_free(pvr_plan *p);
 pvr_status plan_build_index(pvr_plan *p, hipStream_t stream);
+pvr_status launch_bp_prep(const pvr_plan *p, const float *e, const float *pp, hipStream_t stream);
 void launch_fill_u8(uint8_t *dst, uint8_t v, long long n, hipStream_t stream);
 void launch_fill_i32(int *dst, int v, long long n, hipStream_t stream);
 void launch_fill_f32(float *dst, float v, long long n, hipStream_t stream);

@@ -51,6 +51,9 @@ void plan_free(pvr_plan *p) {
   for (void *q : dev)
     if (q) (void)hipFree(q);
   if (p->h_total) (void)hipHostFree(p->h_total);
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+  if (p->side) (void)hipStreamDestroy(p->side);
   if (p->timers) {
     for (int k = 0; k < TIMING_KERNELS; ++k)
       for (int i = 0; i < TIMING_CAP; ++i)

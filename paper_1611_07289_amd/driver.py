@@ -69,7 +69,8 @@ def sr_iterations(plan, X, y, buf: Buffers, n_sr: int, params: Optional[pvr.SRPa
     cur, nxt = X, buf.Xn
     for it in range(n_sr):
         plan.simulate(cur, y_obs=y, resid=buf.e)
-        flags = (pvr.PVR_EM_INIT if (fresh_em and it == 0) else 0) | pvr.PVR_EM_RESID_FRESH
+        flags = ((pvr.PVR_EM_INIT if (fresh_em and it == 0) else 0) | pvr.PVR_EM_RESID_FRESH
+                 | pvr.PVR_EM_PREP_ADJOINT)
         plan.robust_weights(buf.e, y, buf.em, buf.p, buf.pbar, buf.W, flags)
         plan.backproject(buf.e, buf.p, buf.W, buf.num, buf.den)
         plan.sr_update(cur, buf.num, buf.den, nxt, prm)

@@ -21,6 +21,7 @@ PVR_KERNEL_BACKPROJECT = 1
 PVR_EM_INIT = 1
 PVR_EM_FIX_W = 2
 PVR_EM_RESID_FRESH = 4
+PVR_EM_PREP_ADJOINT = 8
 PVR_REG_GRAD_FD = 0
 PVR_REG_GRAD_EXACT = 1
 PVR_PSF_GAUSSIAN = 0

@@ -114,3 +114,31 @@ def test_check_reports_and_clears_non_finite_values(tiny):
         plan.check()
     assert "residual statistics" in str(ei.value)
     plan.check()
+
+
+def test_adjoint_preparation_beside_the_classification(tiny):
+    """PVR_EM_PREP_ADJOINT: the back-projection that follows gives the same
+    bits as without the flag; a simulation in between cancels the prepared
+    inputs (the back-projection then prepares them itself)."""
+    P, plan, th, Xt, y = tiny
+    plan.build(th)
+    X = Xt * 0.9
+
+    def run(flags, resimulate=False):
+        b = Bufs(plan)
+        plan.simulate(X, y_obs=y, resid=b.e)
+        plan.robust_weights(b.e, y, b.em, b.p, b.pbar, b.W, flags)
+        if resimulate:
+            plan.simulate(X * 1.05, y_obs=y, resid=b.e)
+        plan.backproject(b.e, b.p, b.W, b.num, b.den)
+        torch.cuda.synchronize()
+        return b.num.clone(), b.den.clone()
+
+    base = pvr.PVR_EM_INIT | pvr.PVR_EM_RESID_FRESH
+    n0, d0 = run(base)
+    n1, d1 = run(base | pvr.PVR_EM_PREP_ADJOINT)
+    assert torch.equal(n0, n1) and torch.equal(d0, d1)
+    n2, d2 = run(base, resimulate=True)
+    n3, d3 = run(base | pvr.PVR_EM_PREP_ADJOINT, resimulate=True)
+    assert torch.equal(n2, n3) and torch.equal(d2, d3)
+    assert not torch.equal(n2, n0)
