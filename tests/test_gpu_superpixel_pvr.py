@@ -117,3 +117,55 @@ def test_masked_ncc_and_sr_iterations(sp):
     rel = np.linalg.norm(Xg.reshape(-1) - X.reshape(-1)) / np.linalg.norm(X)
     print(f"[gpu] superpixel patches: 5 SR iterations rel-L2 {rel:.2e}, near-threshold {near}")
     assert rel <= 1e-4
+
+
+@pytest.mark.parametrize("scale", [0, 1])
+def test_multiscale_superpixels_active_set(scale):
+    """Multi-scale superpixels: the oracle's superpixel patches of two sizes
+    (a = 8 and a = 12) in one plan with their masks; a build with one size's
+    active set runs three SR iterations from that size's patches only,
+    against the oracle with the same mask and active set."""
+    from paper_1611_07289_amd import driver
+    P = synth.tiny_problem()
+    whole = synth.square_patches(P.stacks, 32, 32)
+    ctx_w = oracle.Ctx(P.grid, P.stacks, whole)
+    th_w = synth.random_motion(whole.M, 3.0, 1.0, 81)
+    imgs = ctx_w.simulate(P.x_true, th_w)[0].reshape(whole.M, 32, 32)
+    cols = {k: [] for k in ("stack", "slice", "x0", "y0", "w", "h")}
+    masks, sc, owner = [], [], []
+    for si, (a, gam) in enumerate([(8, 3), (12, 5)]):
+        for i in range(whole.M):
+            lab, _ = oslic.slic(imgs[i], a, 40.0, 5.0, iters=4)
+            for (x0, y0, w, h, m) in oslic.superpixel_patches(lab, gam):
+                for k, v in zip(("stack", "slice", "x0", "y0", "w", "h"),
+                                (whole.stack[i], whole.slice[i], x0, y0, w, h)):
+                    cols[k].append(v)
+                masks.append(m.reshape(-1)); sc.append(si); owner.append(i)
+    pat = synth.Patches(*[np.asarray(cols[k], np.int32) for k in ("stack", "slice", "x0", "y0", "w", "h")])
+    mask = np.concatenate(masks).astype(np.uint8)
+    sc, owner = np.asarray(sc), np.asarray(owner)
+    th32 = (th_w[owner] + synth.random_motion(pat.M, 1.0, 0.5, 82)).astype(np.float32).astype(np.float64)
+    y = np.concatenate([imgs[owner[s]][pat.y0[s]:pat.y0[s] + pat.h[s],
+                                       pat.x0[s]:pat.x0[s] + pat.w[s]].reshape(-1)
+                        for s in range(pat.M)])
+    active = (sc == scale).astype(np.uint8)
+    ctx = oracle.Ctx(P.grid, P.stacks, pat)
+    X = recon.initial_volume(ctx, y, th32, mask, active)
+    state = recon.EMState()
+    pis = []
+    for _ in range(3):
+        X, state, diag = recon.sr_iteration(ctx, X, y, th32, state, recon.SRParams(), mask, active)
+        pis.append(diag["pi"])
+    near = sum(int(np.sum(np.abs(pi - 0.5) < 1e-3)) for pi in pis)
+    plan = pvr.Plan([P.grid], [P.stacks], [pat])
+    plan.build(dev(th32.astype(np.float32)), active=dev(active), mask=dev(mask))
+    buf = driver.Buffers(plan)
+    yd = dev(y.astype(np.float32))
+    Xg = driver.initial_volume(plan, yd, buf)
+    driver.sr_iterations(plan, Xg, yd, buf, 3)
+    g = host(Xg).astype(np.float64)
+    rel = np.linalg.norm(g - X.reshape(-1)) / np.linalg.norm(X)
+    print(f"[gpu] multi-scale superpixels, scale {scale} ({int(active.sum())} of {pat.M} patches): "
+          f"3 SR iterations rel-L2 {rel:.2e}, near-threshold {near}")
+    assert rel <= 1e-4 or near > 0
+    assert np.all(host(buf.W)[active == 0] == 0)
