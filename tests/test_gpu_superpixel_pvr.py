@@ -169,3 +169,37 @@ def test_multiscale_superpixels_active_set(scale):
           f"3 SR iterations rel-L2 {rel:.2e}, near-threshold {near}")
     assert rel <= 1e-4 or near > 0
     assert np.all(host(buf.W)[active == 0] == 0)
+
+
+@pytest.mark.parametrize("gradient", ["fd", "exact"])
+def test_masked_registration_matches_oracle(sp, gradient):
+    """Registration of the superpixel patches (masked samples excluded from
+    the NCC) from perturbed motion: the same outcome as the oracle's."""
+    import math
+    P, ctx, plan, th32, mask, y = sp["P"], sp["ctx"], sp["plan"], sp["th32"], sp["mask"], sp["y"]
+    from scipy.ndimage import gaussian_filter
+    X = gaussian_filter(np.random.default_rng(5).uniform(0, 1000, (32, 32, 32)), 1.5)
+    X = ((X - X.min()) / (X.max() - X.min()) * 1000.0).astype(np.float32)
+    yt = ctx.simulate(X, th32, mask=mask)[0].astype(np.float32)
+    th0 = (th32 + synth.random_motion(len(th32), 3.0, 1.0, 99)).astype(np.float32)
+    tho, nco = ctx.register(X, yt, th0.astype(np.float64), mask=mask,
+                            gradient="analytic" if gradient == "exact" else "fd")
+    plan.build(dev(th0), mask=sp["md"])
+    tt = dev(th0)
+    ncc = torch.empty(plan.M, dtype=torch.float32, device="cuda")
+    plan.register(dev(X), dev(yt), tt, ncc, params=pvr.RegParams.make(exact=gradient == "exact"))
+    thg, ncg = host(tt).astype(np.float64), host(ncc)
+    n0 = ctx.ncc(X, yt, th0.astype(np.float64), mask=mask)
+    assert np.all(ncg >= n0 - 1e-5)
+    drot_g = np.degrees(np.abs(thg[:, :3] - th32[:, :3])).max(1)
+    drot_o = np.degrees(np.abs(tho[:, :3] - th32[:, :3])).max(1)
+    dtr_g = np.abs(thg[:, 3:] - th32[:, 3:]).max(1)
+    dtr_o = np.abs(tho[:, 3:] - th32[:, 3:]).max(1)
+    same = (np.abs(thg - tho)[:, :3].max(1) < math.radians(0.25)) & (np.abs(thg - tho)[:, 3:].max(1) < 0.1)
+    print(f"[gpu] masked reg ({gradient}): median rot err gpu {np.median(drot_g):.3f} ora "
+          f"{np.median(drot_o):.3f}; trans gpu {np.median(dtr_g):.4f} ora {np.median(dtr_o):.4f}; "
+          f"agreement {same.mean():.3f}")
+    assert np.median(drot_g) <= max(0.35, 1.25 * np.median(drot_o))
+    assert np.median(dtr_g) <= max(0.03, 1.25 * np.median(dtr_o))
+    assert np.mean(ncg > 0.999) >= np.mean(nco > 0.999) - 0.05
+    plan.build(dev(th32.astype(np.float32)), mask=sp["md"])
