@@ -231,7 +231,7 @@ def main():
                     help="also run one 1 GiB device copy (for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design, see the documentation)", file=sys.stderr)
         sys.exit(2)
 
