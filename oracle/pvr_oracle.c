@@ -440,7 +440,11 @@ static void backproject_impl(const ora_ctx *C, const double *theta, const uint8_
                              const uint8_t *active, const double *r, int indicator,
                              double *out) {
   const int64_t V = (int64_t)C->dims[0] * C->dims[1] * C->dims[2];
-  const int NCH = 8;
+  /* one private accumulator per thread (patch ranges in order), summed in
+     chunk order afterwards */
+  int NCH = omp_get_max_threads();
+  if (NCH < 1) NCH = 1;
+  if (NCH > 64) NCH = 64;
   double *buf = (double *)calloc((size_t)NCH * V, sizeof(double));
   const int nx = C->dims[0], ny = C->dims[1];
 #pragma omp parallel for schedule(static, 1)

@@ -89,13 +89,21 @@ def sr_iteration(ctx, X, y, theta, state: EMState, params: SRParams,
 
 
 def reconstruct(ctx, y, theta0, cycles=1, n_sr=10, params: SRParams = SRParams(),
-                register=True, mask=None, reg_kw=None, X0=None):
+                register=True, mask=None, reg_kw=None, X0=None, trace=None):
+    """C cycles of [register every patch against X -> restart EM -> n_sr SR
+    iterations] from X_0 = A^T y / A^T 1 at theta0.  Returns (X, theta,
+    per-iteration diagnostics).  ``trace``, when a list, receives one dict
+    per cycle: the volume the cycle's SR iterations start from (after its
+    registration), the motion they use and the NCC the registration reached."""
     theta = np.array(theta0, dtype=np.float64).reshape(-1, 6).copy()
     X = initial_volume(ctx, y, theta, mask) if X0 is None else np.asarray(X0, np.float64)
     hist = []
     for cyc in range(cycles):
+        ncc = None
         if register:
             theta, ncc = ctx.register(X, y, theta, mask=mask, **(reg_kw or {}))
+        if trace is not None:
+            trace.append(dict(X=np.array(X, copy=True), theta=theta.copy(), ncc=ncc))
         state = EMState()
         for it in range(n_sr):
             X, state, diag = sr_iteration(ctx, X, y, theta, state, params, mask)

@@ -1,0 +1,131 @@
+"""Whole reconstruction cycles against the FP64 oracle (paper Sec. II: every
+patch is registered to the current volume, then the volume is re-estimated
+by SR iterations with EM outlier removal; Fig. overview's loop).
+
+  * 32^3 with registration, either gradient: the textured volume observed by
+    the oracle's forward model with the tiny workload's corruption (1 %
+    noise, 5 % outlier patches), motion perturbed from the truth by <= 3 deg,
+    <= 1 mm; three cycles of [register -> rebuild -> EM restart -> five SR
+    iterations] through driver.reconstruct against recon.reconstruct with the
+    same registration parameters.  Registration is path-dependent in FP32, so
+    the run is pinned on its outcome: the final motion within (0.25 deg,
+    0.1 mm) of the oracle's on >= 95 % of the non-flat patches, and PSNR
+    within 0.1 dB of the oracle's.  The SR part is pinned exactly: from the
+    oracle's volume and motion at the start of the last cycle, with the
+    oracle's patch weights, the GPU's five SR iterations give the oracle's
+    final volume to relative L2 <= 1e-4.
+  * 256^3, one full SR iteration over all 11 760 patches of the four-stack
+    uterus workload (observations from the oracle's forward model with the
+    workload's corruption; motion fixed to the truth; the iteration starting
+    from the truth blurred by sigma = 2 voxels), in the launch configuration
+    the benchmark times (driver.sr_iterations): relative L2 <= 1e-4 against
+    recon.sr_iteration, patch exclusions identical except at posteriors
+    within 1e-3 of the 0.5 threshold (then the oracle's weights are fed).
+"""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import torch  # noqa: E402  (CPU import is fine; GPU use is gated by the marker)
+
+import oracle
+from oracle import recon
+from paper_1611_07289_amd import driver, pvr, synth
+from tests._gpu import dev, host, sr_loop
+
+
+def _textured_tiny():
+    from scipy.ndimage import gaussian_filter
+    P = synth.tiny_problem()
+    X = gaussian_filter(np.random.default_rng(5).uniform(0, 1000, (32, 32, 32)), 1.5)
+    X = (X - X.min()) / (X.max() - X.min()) * 1000.0
+    ctx = oracle.Ctx(P.grid, P.stacks, P.patches)
+    th_true = np.asarray(P.theta_true, np.float32).astype(np.float64)
+    yc, _, _ = ctx.simulate(X, th_true)
+    y = synth.corrupt(yc, P.patches, P.outlier_patch, 0.01, P.seed_base + 3, P.seed_base + 5)
+    return P, ctx, X, np.asarray(y, np.float32), th_true
+
+
+@pytest.mark.parametrize("gradient", ["fd", "exact"])
+def test_cycles_with_registration_match_oracle(gradient):
+    print(f"[gpu] cycle parity 32^3 ({gradient}): oracle run", flush=True)
+    P, ctx, X_true, y, th_true = _textured_tiny()
+    th0 = (th_true + synth.random_motion(P.M, 3.0, 1.0, 123)).astype(np.float32)
+    min_std = 0.01 * float(np.abs(y).max())
+    cycles, n_sr = 3, 5
+    trace = []
+    Xo, tho, hist = recon.reconstruct(
+        ctx, y.astype(np.float64), th0.astype(np.float64), cycles=cycles, n_sr=n_sr,
+        register=True, trace=trace,
+        reg_kw=dict(min_std=min_std, gradient="analytic" if gradient == "exact" else "fd"))
+    print(f"[gpu] cycle parity 32^3 ({gradient}): GPU run", flush=True)
+    plan = pvr.Plan.from_problems([P])
+    yd = dev(y)
+    tt = dev(th0)
+    Xg, _, ghist = driver.reconstruct(plan, yd, tt, cycles=cycles, n_sr=n_sr,
+                                      reg_params=pvr.RegParams.make(min_std=min_std,
+                                                                    exact=gradient == "exact"))
+    Xg, thg = host(Xg).astype(np.float64), host(tt).astype(np.float64)
+    # outcome of the registrations
+    off = P.patches.sample_off
+    nonflat = np.array([y[off[s]:off[s + 1]].std() >= min_std for s in range(P.M)])
+    d = np.abs(thg - tho)
+    same = (d[:, :3].max(1) < math.radians(0.25)) & (d[:, 3:].max(1) < 0.1)
+    ps_g = recon.psnr(Xg.reshape(P.x_true.shape), X_true)
+    ps_o = recon.psnr(Xo, X_true)
+    ps_0 = recon.psnr(trace[0]["X"], X_true)
+    print(f"[gpu] cycle parity 32^3 ({gradient}): motion agreement {same[nonflat].mean():.3f} "
+          f"over {int(nonflat.sum())} non-flat patches; PSNR gpu {ps_g:.3f} oracle {ps_o:.3f} "
+          f"(initial {ps_0:.3f}) dB", flush=True)
+    assert nonflat.sum() >= 0.5 * P.M
+    assert same[nonflat].mean() >= 0.95
+    assert abs(ps_g - ps_o) <= 0.1
+    assert ps_o > ps_0 + 3.0
+    # the last cycle's SR iterations from the oracle's state
+    last = trace[-1]
+    Ws = [h["W"] for h in hist[-n_sr:]]
+    plan.build(dev(last["theta"], torch.float64))
+    Xf, _ = sr_loop(plan, last["X"], y, n_sr, fix_w_list=Ws)
+    rel = np.linalg.norm(Xf.reshape(-1) - Xo.reshape(-1)) / np.linalg.norm(Xo)
+    print(f"[gpu] cycle parity 32^3 ({gradient}): last cycle from the oracle's state, "
+          f"rel-L2 {rel:.2e}", flush=True)
+    assert rel <= 1e-4
+
+
+def test_full_sr_iteration_matches_oracle():
+    from scipy.ndimage import gaussian_filter
+    print("[gpu] uterus256 full SR iteration: oracle observations", flush=True)
+    P = synth.full_problem()
+    ctx = oracle.Ctx(P.grid, P.stacks, P.patches)
+    th32 = np.asarray(P.theta_true, np.float32).astype(np.float64)
+    yc, _, _ = ctx.simulate(P.x_true, th32)
+    y = synth.corrupt(yc, P.patches, P.outlier_patch, P.noise_frac, P.seed_base + 3,
+                      P.seed_base + 5)
+    del yc
+    X0 = gaussian_filter(np.asarray(P.x_true, np.float64), 2.0)
+    print("[gpu] uterus256 full SR iteration: oracle iteration", flush=True)
+    Xo, _, diag = recon.sr_iteration(ctx, X0, y, th32, recon.EMState(), recon.SRParams())
+    near = int(np.sum(np.abs(diag["pi"] - 0.5) < 1e-3))
+    print("[gpu] uterus256 full SR iteration: GPU iteration", flush=True)
+    plan = pvr.Plan.from_problems([P])
+    plan.build(dev(th32.astype(np.float32)))
+    buf = driver.Buffers(plan)
+    yd = dev(np.asarray(y, np.float32))
+    Xg = dev(X0.astype(np.float32).reshape(-1))
+    driver.sr_iterations(plan, Xg, yd, buf, 1)
+    g = host(Xg).astype(np.float64)
+    Wg = host(buf.W)
+    flips = int(np.sum((Wg > 0) != (diag["W"] > 0)))
+    rel = np.linalg.norm(g - Xo.reshape(-1)) / np.linalg.norm(Xo)
+    print(f"[gpu] uterus256 full SR iteration: rel-L2 {rel:.2e}, W flips {flips}, "
+          f"near-threshold {near}, excluded {int(np.sum(diag['W'] == 0))}", flush=True)
+    if near:
+        Xf, _ = sr_loop(plan, X0, y, 1, fix_w_list=[diag["W"]])
+        rel = np.linalg.norm(Xf.reshape(-1) - Xo.reshape(-1)) / np.linalg.norm(Xo)
+        print(f"[gpu] uterus256 full SR iteration with the oracle's W: rel-L2 {rel:.2e}", flush=True)
+    else:
+        assert flips == 0
+    assert rel <= 1e-4

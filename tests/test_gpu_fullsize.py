@@ -17,7 +17,7 @@ properties that hold at any size.
     against the oracle, interior voxels of each crop;
   * registration (either gradient) of 24 sampled patches from perturbed
     motion, observations simulated by the oracle: the oracle's outcome on
-    >= 90 % of them, no NCC lowered, the other patches untouched.
+    >= 95 % of them, no NCC lowered, the other patches untouched.
 """
 import numpy as np
 import pytest
@@ -201,7 +201,7 @@ def test_full_registration_sampled(full, gradient):
     """Registration at full size on 24 sampled patches (the others are not
     registered): observations simulated by the oracle for those patches,
     motion perturbed by <= 3 deg, <= 1 mm; the GPU reaches the oracle's
-    outcome (within 0.25 deg and 0.1 mm) on >= 90 % of them and never lowers
+    outcome (within 0.25 deg and 0.1 mm) on >= 95 % of them and never lowers
     a patch's NCC."""
     import math
     P, ctx, plan, th32 = full["P"], full["ctx"], full["plan"], full["th32"]
@@ -240,5 +240,5 @@ def test_full_registration_sampled(full, gradient):
     err_o = np.abs(tho[pick, 3:] - th32[pick, 3:]).max(1)
     print(f"[gpu] full-size registration ({gradient}), 24 patches: agreement {same.mean():.3f}; "
           f"median translation error gpu {np.median(err_g):.4f} ora {np.median(err_o):.4f}")
-    assert same.mean() >= 0.9
+    assert same.mean() >= 0.95
     assert np.median(err_g) <= max(0.03, 1.25 * np.median(err_o))

@@ -150,6 +150,7 @@ def test_sinc_registration_matches_oracle():
     same = (np.abs(thg - tho)[:, :3].max(1) < math.radians(0.25)) & (np.abs(thg - tho)[:, 3:].max(1) < 0.1)
     print(f"[gpu] sinc reg median rot err gpu {np.median(drot_g):.3f} ora {np.median(drot_o):.3f}; "
           f"trans gpu {np.median(dtr_g):.4f} ora {np.median(dtr_o):.4f}; agreement {same.mean():.3f}")
+    assert same.mean() >= 0.95
     assert np.median(drot_g) <= max(0.35, 1.25 * np.median(drot_o))
     assert np.median(dtr_g) <= max(0.03, 1.25 * np.median(dtr_o))
     assert np.mean(ncg > 0.999) >= np.mean(nco > 0.999) - 0.05

@@ -150,12 +150,13 @@ def test_multiscale_superpixels_active_set(scale):
                         for s in range(pat.M)])
     active = (sc == scale).astype(np.uint8)
     ctx = oracle.Ctx(P.grid, P.stacks, pat)
-    X = recon.initial_volume(ctx, y, th32, mask, active)
+    X0 = recon.initial_volume(ctx, y, th32, mask, active)
+    X = X0
     state = recon.EMState()
-    pis = []
+    pis, Ws = [], []
     for _ in range(3):
         X, state, diag = recon.sr_iteration(ctx, X, y, th32, state, recon.SRParams(), mask, active)
-        pis.append(diag["pi"])
+        pis.append(diag["pi"]); Ws.append(diag["W"])
     near = sum(int(np.sum(np.abs(pi - 0.5) < 1e-3)) for pi in pis)
     plan = pvr.Plan([P.grid], [P.stacks], [pat])
     plan.build(dev(th32.astype(np.float32)), active=dev(active), mask=dev(mask))
@@ -167,7 +168,13 @@ def test_multiscale_superpixels_active_set(scale):
     rel = np.linalg.norm(g - X.reshape(-1)) / np.linalg.norm(X)
     print(f"[gpu] multi-scale superpixels, scale {scale} ({int(active.sum())} of {pat.M} patches): "
           f"3 SR iterations rel-L2 {rel:.2e}, near-threshold {near}")
-    assert rel <= 1e-4 or near > 0
+    if near:
+        # a posterior within rounding of the 0.5 threshold: the same three
+        # iterations from the oracle's X_0 with the oracle's patch weights
+        Xf, _ = _gpu_sr_loop(plan, X0, y, 3, pvr.SRParams.make(), fix_w_list=Ws)
+        rel = np.linalg.norm(Xf.reshape(-1) - X.reshape(-1)) / np.linalg.norm(X)
+        print(f"[gpu] multi-scale superpixels, scale {scale}: with the oracle's W, rel-L2 {rel:.2e}")
+    assert rel <= 1e-4
     assert np.all(host(buf.W)[active == 0] == 0)
 
 
@@ -199,6 +206,7 @@ def test_masked_registration_matches_oracle(sp, gradient):
     print(f"[gpu] masked reg ({gradient}): median rot err gpu {np.median(drot_g):.3f} ora "
           f"{np.median(drot_o):.3f}; trans gpu {np.median(dtr_g):.4f} ora {np.median(dtr_o):.4f}; "
           f"agreement {same.mean():.3f}")
+    assert same.mean() >= 0.95
     assert np.median(drot_g) <= max(0.35, 1.25 * np.median(drot_o))
     assert np.median(dtr_g) <= max(0.03, 1.25 * np.median(dtr_o))
     assert np.mean(ncg > 0.999) >= np.mean(nco > 0.999) - 0.05

@@ -105,3 +105,82 @@ def test_patch_weights_edge_cases():
     assert W[0] == 1.0
     W, pi = em.patch_weights(np.array([0.8, 0.0]), np.array([10.0, 0.0]))
     assert W[1] == 0.0 and W[0] == 1.0
+
+
+def _mixture_loglik(v, comps):
+    (mu1, sd1, w1), (mu0, sd0, w0) = comps
+    d1 = w1 * np.exp(-0.5 * ((v - mu1) / sd1) ** 2) / (sd1 * math.sqrt(2 * math.pi))
+    d0 = w0 * np.exp(-0.5 * ((v - mu0) / sd0) ** 2) / (sd0 * math.sqrt(2 * math.pi))
+    return float(np.sum(np.log(d1 + d0)))
+
+
+def test_patch_mixture_log_likelihood_never_decreases(monkeypatch):
+    """EM on the potentials' two-component mixture: the data log-likelihood
+    after k iterations is non-decreasing in k (the mixture is refitted with
+    k = 1 ... 20 iterations from the same start)."""
+    rng = np.random.default_rng(8)
+    v = np.concatenate([rng.normal(0.85, 0.05, 300), rng.normal(0.45, 0.12, 60),
+                        rng.uniform(0.0, 1.0, 20)])
+    rng.shuffle(v)
+    lls = []
+    for k in range(1, em.GMM_ITERS + 1):
+        monkeypatch.setattr(em, "GMM_ITERS", k)
+        _, comps = em.patch_mixture(v)
+        lls.append(_mixture_loglik(v, comps))
+    assert np.all(np.diff(lls) >= -1e-9 * np.abs(lls[:-1])), lls
+    assert lls[-1] > lls[0]
+
+
+def _weighted_case():
+    """Three patches of different sizes with patch weights != 1 and per-sample
+    posteriors, some samples invalid."""
+    rng = np.random.default_rng(31)
+    n = np.array([7, 5, 9])
+    pos = np.repeat(np.arange(3), n)
+    e = rng.normal(0, 12, pos.size)
+    p = rng.uniform(0.05, 1.0, pos.size)
+    valid = rng.uniform(size=pos.size) > 0.15
+    W = np.array([0.6, 0.9, 0.75])
+    n_s = np.bincount(pos, weights=valid.astype(float), minlength=3)
+    return e, p, valid, pos, n_s, W
+
+
+def test_mstep_is_the_weighted_complete_data_maximiser():
+    """The M-step maximises the expected complete-data log-likelihood with
+    every sample weighted by its patch weight,
+      Q(sigma^2, c) = sum_j W_j [p_j log(c G_sigma(e_j)) + (1 - p_j) log((1 - c) m)],
+    over several patches with W != 1 (checked by a numerical maximiser)."""
+    from scipy.optimize import minimize
+    e, p, valid, pos, n_s, W = _weighted_case()
+    Wj = W[pos]
+    s2, c = em.mstep(e, p, valid, Wj, n_s, W, 50.0, 0.5, 0.0)
+    m = 1e-3
+    ev, pv, wv = e[valid], p[valid], Wj[valid]
+
+    def negQ(x):
+        ls2, lc = x
+        sig2, cc = math.exp(ls2), 1 / (1 + math.exp(-lc))
+        logG = -ev * ev / (2 * sig2) - 0.5 * math.log(2 * math.pi * sig2)
+        return -float(np.sum(wv * (pv * (math.log(cc) + logG) + (1 - pv) * math.log((1 - cc) * m))))
+
+    res = minimize(negQ, x0=[math.log(100.0), 0.0], method="Nelder-Mead",
+                   options=dict(xatol=1e-10, fatol=1e-12, maxiter=20000))
+    s2_num, c_num = math.exp(res.x[0]), 1 / (1 + math.exp(-res.x[1]))
+    assert s2 == pytest.approx(s2_num, rel=1e-6)
+    assert c == pytest.approx(c_num, rel=1e-6)
+
+
+def test_mstep_integer_patch_weight_is_replication():
+    """A patch weight of 2 counts the patch twice: the M-step equals the one
+    over the same data with that patch duplicated at weight 1."""
+    e, p, valid, pos, n_s, _ = _weighted_case()
+    W = np.array([2.0, 1.0, 1.0])
+    s2a, ca = em.mstep(e, p, valid, W[pos], n_s, W, 50.0, 0.5, 0.0)
+    sel = pos == 0
+    e2 = np.concatenate([e, e[sel]]); p2 = np.concatenate([p, p[sel]])
+    v2 = np.concatenate([valid, valid[sel]]); pos2 = np.concatenate([pos, np.full(sel.sum(), 3)])
+    n2 = np.bincount(pos2, weights=v2.astype(float), minlength=4)
+    W2 = np.ones(4)
+    s2b, cb = em.mstep(e2, p2, v2, W2[pos2], n2, W2, 50.0, 0.5, 0.0)
+    assert s2a == pytest.approx(s2b, rel=1e-14)
+    assert ca == pytest.approx(cb, rel=1e-14)

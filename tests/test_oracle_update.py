@@ -85,3 +85,20 @@ def test_sirt_fixed_point_solves_least_squares():
     assert np.all(np.diff(res) <= 1e-9 * res[0])
     assert res[-1] >= res_ref * (1 - 1e-9)
     assert (res[-1] - res_ref) < 0.1 * (res[0] - res_ref)
+
+
+def test_psnr_hand_computed():
+    """PSNR = 10 log10(I_max^2 / MSE) (Sec. IV-A, base-10 logarithm read):
+    errors of +-10 on every voxel of a truth whose maximum is 1000 give
+    MSE = 100 and exactly 40 dB; a mask restricts the mean; zero error is
+    infinite."""
+    import math
+    from oracle import recon
+    T = np.array([[0.0, 1000.0], [500.0, 250.0]])
+    X = T + np.array([[10.0, -10.0], [10.0, -10.0]])
+    assert recon.psnr(X, T) == pytest.approx(40.0, abs=1e-12)
+    X2 = T + np.array([[0.0, 20.0], [0.0, 0.0]])
+    m = np.array([[False, True], [True, False]])
+    # masked MSE = (400 + 0) / 2 = 200
+    assert recon.psnr(X2, T, m) == pytest.approx(10 * math.log10(1e6 / 200), abs=1e-12)
+    assert recon.psnr(T, T) == float("inf")
