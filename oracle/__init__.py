@@ -150,7 +150,7 @@ class Ctx:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and lib is not None:  # the module may be torn down at exit
             lib().ora_ctx_free(h)
             self._h = None
 

@@ -7,13 +7,21 @@ by SR iterations with EM outlier removal; Fig. overview's loop).
     noise, 5 % outlier patches), motion perturbed from the truth by <= 3 deg,
     <= 1 mm; three cycles of [register -> rebuild -> EM restart -> five SR
     iterations] through driver.reconstruct against recon.reconstruct with the
-    same registration parameters.  Registration is path-dependent in FP32, so
-    the run is pinned on its outcome: the final motion within (0.25 deg,
-    0.1 mm) of the oracle's on >= 95 % of the non-flat patches, and PSNR
-    within 0.1 dB of the oracle's.  The SR part is pinned exactly: from the
-    oracle's volume and motion at the start of the last cycle, with the
-    oracle's patch weights, the GPU's five SR iterations give the oracle's
-    final volume to relative L2 <= 1e-4.
+    same registration parameters.
+    Registration is a sequence of accept / halve decisions on strict NCC
+    improvement, so an FP32 rounding can move one patch to a different stall
+    point; the SR iterations then see a slightly different motion and the
+    next cycle starts from a different volume (relative 1e-4 .. 1e-3 after
+    one cycle), which moves more patches there.  The run is therefore pinned
+    cycle by cycle from the oracle's state, and free-running on its outcome:
+      - every cycle's registration, started from the oracle's volume and
+        motion at that cycle, ends within (0.25 deg, 0.1 mm) of the oracle's
+        on >= 95 % of the non-flat patches;
+      - the free-running reconstruction's PSNR is within 0.1 dB of the
+        oracle's;
+      - from the oracle's volume and motion at the start of the last cycle,
+        with the oracle's patch weights, the GPU's five SR iterations give
+        the oracle's final volume to relative L2 <= 1e-4.
   * 256^3, one full SR iteration over all 11 760 patches of the four-stack
     uterus workload (observations from the oracle's forward model with the
     workload's corruption; motion fixed to the truth; the iteration starting
@@ -61,27 +69,34 @@ def test_cycles_with_registration_match_oracle(gradient):
         ctx, y.astype(np.float64), th0.astype(np.float64), cycles=cycles, n_sr=n_sr,
         register=True, trace=trace,
         reg_kw=dict(min_std=min_std, gradient="analytic" if gradient == "exact" else "fd"))
-    print(f"[gpu] cycle parity 32^3 ({gradient}): GPU run", flush=True)
-    plan = pvr.Plan.from_problems([P])
-    yd = dev(y)
-    tt = dev(th0)
-    Xg, _, ghist = driver.reconstruct(plan, yd, tt, cycles=cycles, n_sr=n_sr,
-                                      reg_params=pvr.RegParams.make(min_std=min_std,
-                                                                    exact=gradient == "exact"))
-    Xg, thg = host(Xg).astype(np.float64), host(tt).astype(np.float64)
-    # outcome of the registrations
     off = P.patches.sample_off
     nonflat = np.array([y[off[s]:off[s + 1]].std() >= min_std for s in range(P.M)])
-    d = np.abs(thg - tho)
-    same = (d[:, :3].max(1) < math.radians(0.25)) & (d[:, 3:].max(1) < 0.1)
+    assert nonflat.sum() >= 0.5 * P.M
+    plan = pvr.Plan.from_problems([P])
+    yd = dev(y)
+    rp = pvr.RegParams.make(min_std=min_std, exact=gradient == "exact")
+    # every cycle's registration from the oracle's state at that cycle
+    for c in range(cycles):
+        th_start = th0.astype(np.float64) if c == 0 else trace[c - 1]["theta"]
+        plan.build(dev(th_start, torch.float64))
+        tt = dev(th_start.astype(np.float32))
+        plan.register(dev(trace[c]["X"].astype(np.float32).reshape(-1)), yd, tt, None, params=rp)
+        d = np.abs(host(tt).astype(np.float64) - trace[c]["theta"])
+        same = (d[:, :3].max(1) < math.radians(0.25)) & (d[:, 3:].max(1) < 0.1)
+        print(f"[gpu] cycle parity 32^3 ({gradient}): cycle {c} registration from the oracle's "
+              f"state, agreement {same[nonflat].mean():.3f} over {int(nonflat.sum())} non-flat "
+              f"patches", flush=True)
+        assert same[nonflat].mean() >= 0.95
+    # the free-running reconstruction, on its outcome
+    print(f"[gpu] cycle parity 32^3 ({gradient}): GPU run", flush=True)
+    tt = dev(th0)
+    Xg, _, ghist = driver.reconstruct(plan, yd, tt, cycles=cycles, n_sr=n_sr, reg_params=rp)
+    Xg = host(Xg).astype(np.float64)
     ps_g = recon.psnr(Xg.reshape(P.x_true.shape), X_true)
     ps_o = recon.psnr(Xo, X_true)
     ps_0 = recon.psnr(trace[0]["X"], X_true)
-    print(f"[gpu] cycle parity 32^3 ({gradient}): motion agreement {same[nonflat].mean():.3f} "
-          f"over {int(nonflat.sum())} non-flat patches; PSNR gpu {ps_g:.3f} oracle {ps_o:.3f} "
+    print(f"[gpu] cycle parity 32^3 ({gradient}): PSNR gpu {ps_g:.3f} oracle {ps_o:.3f} "
           f"(initial {ps_0:.3f}) dB", flush=True)
-    assert nonflat.sum() >= 0.5 * P.M
-    assert same[nonflat].mean() >= 0.95
     assert abs(ps_g - ps_o) <= 0.1
     assert ps_o > ps_0 + 3.0
     # the last cycle's SR iterations from the oracle's state
