@@ -515,7 +515,7 @@ def diff_bench(args, P, dev):
     import torch
     from paper_1611_07289_amd import pvr
     from paper_1611_07289_amd.autograd import simulate
-    plan = pvr.Plan.from_problems([P])
+    plan = pvr.Plan.from_problems([P], f64=True)
     res = {}
     for name, dt in (("f64", torch.float64), ("f32", torch.float32)):
         X = torch.tensor(P.x_true.reshape(-1), dtype=dt, device=dev, requires_grad=True)

@@ -31,11 +31,14 @@
  *                         Sec. III parallelisation level I)
  *
  * Conventions
- *  - Pointers are DEVICE pointers unless marked (host).  The caller owns every
- *    buffer passed in; the plan owns its own device buffers (allocated by
- *    pvr_plan_create / pvr_plan_build, freed by pvr_plan_destroy).  Device
- *    arrays are aligned to their element size (FP32 and int32 4 bytes, FP64
- *    and pvr_em_state 8); a misaligned pointer gives PVR_EINVAL.
+ *  - Pointers are DEVICE pointers unless marked (host).  The caller owns all
+ *    device memory: every buffer passed in and the plan's workspace, which
+ *    the caller allocates at the size pvr_plan_workspace_size reports and
+ *    hands over with pvr_plan_attach.  The library allocates no device
+ *    memory; it keeps the host descriptors it is given (copied), a second
+ *    stream and two events per plan.  Device arrays are aligned to their
+ *    element size (FP32 and int32 4 bytes, FP64 and pvr_em_state 8); a
+ *    misaligned pointer gives PVR_EINVAL.
  *  - Calls are asynchronous on `stream` except where noted.  A plan is used on
  *    one stream at a time (thread-compatible, not thread-safe).
  *  - Every function returns a pvr_status; no exception crosses the ABI.  On
@@ -116,8 +119,11 @@ typedef struct {
   int32_t n_problems;
   int32_t n_stacks;
   int32_t n_bricks;         /* 8x8x8 voxel bricks over all problems */
-  int64_t n_bin_pairs;      /* brick/patch pairs after the last build */
-  int64_t device_bytes;     /* device memory owned by the plan */
+  int64_t n_bin_pairs;      /* sub-brick/patch pairs of the adjoint's index
+                               (0 until a back-projection built it) */
+  int64_t device_bytes;     /* bytes of the attached workspace (0 if none) */
+  int64_t bin_capacity;     /* brick/patch pairs the workspace holds */
+  int64_t sub_capacity;     /* sub-brick/patch pairs the workspace holds */
 } pvr_plan_sizes;
 
 /* EM state of one reconstruction, kept on the device so that an SR iteration
@@ -188,37 +194,70 @@ const char *pvr_last_error(void);
 /* Library version string. */
 const char *pvr_version(void);
 
-/* Create a plan.  All arrays are (host) and copied.  Patches must reference
- * valid stacks and lie inside their slice; every stack names a valid problem.
- * cutoff_k: PSF support radius in standard deviations (> 0, default 3).
+/* Create a plan (host work only: the problem, stack and patch tables of
+ * Sec. II "Patch Extraction", the forward work list and the capacity of the
+ * adjoint's index).  All arrays are (host) and copied.  Patches must
+ * reference valid stacks and lie inside their slice; every stack names a
+ * valid problem.  cutoff_k: PSF support radius in standard deviations (> 0,
+ * default 3).  No HIP call is made; the plan is usable once a workspace is
+ * attached.
  * Errors: PVR_EINVAL for null pointers or out-of-range indices, PVR_ESHAPE
  * for non-orthogonal stack axes, empty sizes, a grid beyond 2^28 voxels, a
  * problem with more than PVR_MAX_PROBLEM_PATCHES patches, or a patch beyond
- * 32767 pixels per side or 2^26 pixels, PVR_ENOMEM, PVR_EHIP. */
+ * 32767 pixels per side or 2^26 pixels. */
 pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
                            const pvr_stack *stacks, int32_t n_stacks,
                            const pvr_patch *patches, int32_t n_patches,
                            double cutoff_k, pvr_plan **out);
 
-/* Free a plan and its device buffers (NULL is a no-op).  Synchronises the
- * device first. */
+/* Workspace flags: PVR_WS_F64 adds room for the FP64 calls (the FP64
+ * normalisers of pvr_plan_build_f64 and the FP64 adjoint inputs; 24 bytes
+ * per sample). */
+#define PVR_WS_F64 1
+
+/* (host) Bytes of device workspace the plan needs with `flags`: its device
+ * tables, the per-build motion state, the adjoint's brick index at a
+ * capacity bounded over every motion (so no build reads a count back or
+ * grows a list), and per-sample / per-patch scratch. */
+pvr_status pvr_plan_workspace_size(const pvr_plan *plan, int32_t flags, size_t *bytes);
+
+/* Hand the plan its workspace: `bytes` >= pvr_plan_workspace_size(flags),
+ * 256-byte aligned, on the current device (the plan stays on the device of
+ * its first workspace; the first attach also creates the plan's second
+ * stream and its events).  The plan's tables are uploaded on `stream`,
+ * which is synchronised before the call returns.  The workspace must stay allocated until the plan is
+ * destroyed (or another workspace is attached, which synchronises `stream`
+ * first); the plan then counts as unbuilt.  Errors: PVR_EINVAL (NULL,
+ * misaligned, unknown flags, wrong device), PVR_ESHAPE (too small),
+ * PVR_EHIP. */
+pvr_status pvr_plan_attach(pvr_plan *plan, void *workspace, size_t bytes, int32_t flags,
+                           hipStream_t stream);
+
+/* Free a plan (NULL is a no-op).  Synchronises the device first when a
+ * workspace is attached; the caller may free the workspace afterwards. */
 void pvr_plan_destroy(pvr_plan *plan);
 
-/* (host) sizes. */
+/* (host) sizes.  Synchronises the device to read n_bin_pairs when the
+ * adjoint's index is built. */
 pvr_status pvr_plan_info(const pvr_plan *plan, pvr_plan_sizes *out);
 
 /* (host) sample_off[M+1] and vol_off[n_problems+1]; either may be NULL. */
 pvr_status pvr_plan_offsets(const pvr_plan *plan, int64_t *sample_off,
                             int64_t *vol_off);
 
-/* Build the motion-dependent state for theta (float [M][6] or double
- * [M][6]): per-patch geometry, per-sample inverse PSF normalisers (0 marks an
- * invalid sample) and the brick -> patch index of the adjoint.  active
- * ([M], nullable = all) and sample_mask ([N], nullable = all) are read here.
- * Synchronises `stream` once if LDS forward tiles are enabled
- * (pvr_plan_set_tiles), else not at all.  The adjoint's brick index is rebuilt lazily by
- * the first pvr_backproject after a build (synchronising `stream` twice), so
- * loops that only simulate (registration) do not pay for it. */
+/* Build the motion-dependent state of the observation model of Sec. I
+ * eq. (1), x_i = W_i y + n_i with W_i = D B T_i, for theta (float [M][6] or
+ * double [M][6]): per patch the rigid transform T_s and the PSF B moved
+ * with it, per sample the inverse PSF normaliser (0 marks an invalid
+ * sample).  active ([M], nullable = all) and sample_mask ([N], nullable =
+ * all) are read here.  The adjoint's brick -> patch index follows lazily
+ * with the first pvr_backproject after a build, so loops that only simulate
+ * (registration) do not pay for it; neither synchronises (the index lists
+ * have capacities bounded at plan creation).  With LDS forward tiles
+ * enabled (pvr_plan_set_tiles) the build synchronises `stream` once to size
+ * the staged boxes.  pvr_plan_build_f64 also writes FP64 normalisers when
+ * the workspace was attached with PVR_WS_F64 (needed by the _f64 calls).
+ * Errors: PVR_EINVAL (NULL, misaligned, no workspace), PVR_EHIP. */
 pvr_status pvr_plan_build(pvr_plan *plan, const float *theta,
                           const uint8_t *active, const uint8_t *sample_mask,
                           hipStream_t stream);
@@ -288,11 +327,15 @@ pvr_status pvr_simulate_f64(const pvr_plan *plan, const double *X,
                             const double *y_obs, double *y_sim, double *resid,
                             hipStream_t stream);
 
-/* Adjoint ("pixel-volume"), gather form: for every voxel i
+/* Adjoint ("pixel-volume", Sec. III level II) of the forward model, the
+ * reintegration step of the SR iterations (Sec. II, "EM-Based Outlier
+ * Removal": samples weighted by their posteriors and patch weights enter the
+ * volume update), in gather form: for every voxel i
  *   num_i = sum_j psi_ji W_s(j) p_j e_j,   den_i = sum_j psi_ji W_s(j) p_j
  * e [N] (required), p [N] (nullable = 1), patch_w [M] (nullable = 1),
  * num [V] (required), den [V] (nullable).  Deterministic: the summation order
- * is fixed (patch order, then pixel order). */
+ * is fixed (patch order, then pixel order).  The first call after a build
+ * also builds the adjoint's brick -> patch index on `stream`. */
 pvr_status pvr_backproject(const pvr_plan *plan, const float *e,
                            const float *p, const float *patch_w, float *num,
                            float *den, hipStream_t stream);
@@ -374,6 +417,47 @@ pvr_status pvr_ncc_grad(const pvr_plan *plan, const float *y_obs,
                         const float *y_sim, float *grad_y, float *ncc,
                         hipStream_t stream);
 
+/* Per-patch motion bookkeeping of the optimisers built on the forward model
+ * (one lane per patch; M = the plan's patches; theta-like arrays [M][6]).
+ * rho_s is the patch half-diagonal in mm (at least 1), the scale of the
+ * rotation variables of the registration (Sec. II, "Patch to Volume
+ * Registration": each patch's rigid parameters are optimised on its own).
+ *
+ * pvr_motion_frame: the motion in the patch's own frame, used as the
+ *   learned initialiser's target: out_s = base_s + A_s in_s (inverse = 0) or
+ *   base_s + A_s^-1 in_s (inverse != 0), A_s = diag(rho_s F_s^T, F_s^T) with
+ *   F_s the unit axes of the patch's stack (in-plane u, in-plane v, normal)
+ *   as columns.  base nullable (= 0); out may alias base, not in.
+ * pvr_motion_step: a normalised gradient-ascent trial in the variables
+ *   (rho angles, translations): trial_s = theta_s + delta_s g~_s / |g~_s|
+ *   mapped back (g~ = grad_theta with the angle part divided by rho_s) for
+ *   patches with delta_s >= step_min, else theta_s.
+ * pvr_motion_accept: where score_cand_s > score_s (and, when delta is given,
+ *   delta_s >= step_min): theta_s = cand_s and score_s = score_cand_s; with
+ *   delta, an accepted step doubles (capped at step0) and a rejected one
+ *   halves (patches below step_min are left alone); n_live (int32 [1],
+ *   nullable) is increased by the number of patches whose step is still
+ *   >= step_min afterwards (the caller zeroes it).
+ * pvr_motion_init_step: delta_s = step0 for patches whose observed samples
+ *   (those the last build's mask keeps) have a population standard
+ *   deviation >= min_std, else 0 (flat patches keep their motion).  Needs a
+ *   built plan.
+ * pvr_motion_fallback: where score_s < tau: theta_s = theta_ref_s and
+ *   flag_s = 1, else flag_s = 0 (uint8 [M]) -- the patches to register
+ *   again from their reference motion. */
+pvr_status pvr_motion_frame(const pvr_plan *plan, const float *in, int32_t inverse,
+                            const float *base, float *out, hipStream_t stream);
+pvr_status pvr_motion_step(const pvr_plan *plan, const float *theta, const float *grad_theta,
+                           const float *delta, float step_min, float *trial, hipStream_t stream);
+pvr_status pvr_motion_accept(const pvr_plan *plan, const float *cand, const float *score_cand,
+                             float *theta, float *score, float *delta, float step0,
+                             float step_min, int32_t *n_live, hipStream_t stream);
+pvr_status pvr_motion_init_step(const pvr_plan *plan, const float *y_obs, float step0,
+                                double min_std, float *delta, hipStream_t stream);
+pvr_status pvr_motion_fallback(const pvr_plan *plan, const float *score, float tau,
+                               const float *theta_ref, float *theta, uint8_t *flag,
+                               hipStream_t stream);
+
 /* Numeric faults.  The SR update raises PVR_FAULT_VOLUME when a voxel of the
  * new volume is not finite before the clamp (which would otherwise hide a
  * NaN); the robust weights raise PVR_FAULT_RESIDUAL when a problem's residual
@@ -384,6 +468,9 @@ pvr_status pvr_ncc_grad(const pvr_plan *plan, const float *y_obs,
  * none was raised. */
 #define PVR_FAULT_VOLUME 1u
 #define PVR_FAULT_RESIDUAL 2u
+#define PVR_FAULT_INDEX 4u  /* the adjoint's index outgrew its capacity (the
+                               host bound rules this out; pvr_check then
+                               returns PVR_ESHAPE) */
 pvr_status pvr_check(pvr_plan *plan, hipStream_t stream);
 
 /* Captured SR iterations (the batched form of Sec. III level II: every

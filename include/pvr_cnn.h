@@ -72,7 +72,8 @@ pvr_status pvr_cnn_conv_wgrad(const uint16_t *gout, const uint16_t *out,
 /* Network input for B patches of a built plan: out [B][64][64][2], channel 0
  * the observed patch, channel 1 the simulated one, each standardised over
  * the patch's valid samples (invalid samples 0).  patch_ids [B] (device);
- * every patch of the plan must be 64 x 64. */
+ * an id outside [0, M) gives an all-zero pair.  Every patch of the plan must
+ * be 64 x 64. */
 pvr_status pvr_cnn_pack_pairs(const pvr_plan *plan, const int32_t *patch_ids,
                               int32_t B, const float *y_obs, const float *y_sim,
                               uint16_t *out, hipStream_t stream);

@@ -40,11 +40,16 @@
  *          pixel lies in the dilation of the label's pixels inside the box
  *          (for a box from pvr_slic_boxes: the dilated superpixel), else 0.
  *          Boxes must lie in the image and hold at most 65536 pixels.
- *          Synchronises `stream` once (the table is staged to the device).
+ *          The table is staged into the caller's device workspace
+ *          (pvr_slic_pack_workspace(M) bytes, 16-byte aligned) through a
+ *          host array on the stack, synchronising `stream` once per 1024
+ *          patches before the packing kernel is launched; the workspace
+ *          must stay allocated until that kernel has run.  The library
+ *          allocates no memory.
  * Errors: PVR_EINVAL for NULL pointers, non-positive sizes, a beyond 2^20 or
  * gamma < 0, PVR_ESHAPE when n_img * h * w exceeds 2^31, h or w exceeds
- * 2^20, K exceeds 2^20, n_img exceeds 65535 or a packed box leaves its image
- * or holds more than 65536 pixels.  Centres of any value (NaN included) are
+ * 2^20, K exceeds 2^20, n_img exceeds 65535, a packed box leaves its image
+ * or holds more than 65536 pixels, or the pack workspace is too small.  Centres of any value (NaN included) are
  * safe: a centre whose window misses the image takes no pixel.
  */
 #ifndef PVR_SLIC_H
@@ -80,9 +85,13 @@ pvr_status pvr_slic_boxes(const int32_t *labels, int32_t n_img, int32_t h, int32
                           const float *centres, int32_t gamma, int32_t *boxes,
                           hipStream_t stream);
 
+/* Device workspace bytes of pvr_slic_pack for M patches (host; 0 for M <= 0). */
+size_t pvr_slic_pack_workspace(int32_t M);
+
 pvr_status pvr_slic_pack(const float *img, const int32_t *labels, int32_t n_img, int32_t h,
-                         int32_t w, int32_t gamma, int32_t M, const int32_t *table, float *y,
-                         uint8_t *mask, hipStream_t stream);
+                         int32_t w, int32_t gamma, int32_t M, const int32_t *table,
+                         void *workspace, size_t workspace_bytes, float *y, uint8_t *mask,
+                         hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -325,12 +325,9 @@ extern "C" pvr_status pvr_backproject_f64(const pvr_plan *p, const double *e, co
   PVR_ALIGNED("pvr_backproject_f64", num, 8);
   PVR_ALIGNED("pvr_backproject_f64", den, 8);
   if (!p) return fail(PVR_EINVAL, "pvr_backproject_f64: plan is NULL");
-  if (!p->built || !p->built64) return fail(PVR_EINVAL, "pvr_backproject_f64: plan needs pvr_plan_build_f64");
-  pvr_plan *mp = const_cast<pvr_plan *>(p);
-  if (!mp->d_rq64) {
-    DEV_ALLOC(mp, mp->d_rq64, mp->N + 2);  // guard entries as for d_rq
-    launch_fill_f64((double *)mp->d_rq64, 0.0, 2 * (mp->N + 2), stream);
-  }
-  return backproject_impl<double>(p, e, pp, patch_w, num, den, p->d_invz64, mp->d_rq64 + 1, stream);
+  if (!p->built || !p->built64)
+    return fail(PVR_EINVAL, "pvr_backproject_f64: plan needs pvr_plan_build_f64 on a workspace "
+                            "attached with PVR_WS_F64");
+  return backproject_impl<double>(p, e, pp, patch_w, num, den, p->d_invz64, p->d_rq64 + 1, stream);
   PVR_API_END();
 }

@@ -566,11 +566,17 @@ __global__ void k_wgrad_finish(const double *__restrict__ partial, int ranges, i
 __global__ void __launch_bounds__(256)
 k_pack_pairs(const PatchDev *__restrict__ patches, const int *__restrict__ ids,
              const float *__restrict__ invz, const float *__restrict__ y,
-             const float *__restrict__ ys, uint16_t *__restrict__ outp, int side) {
+             const float *__restrict__ ys, uint16_t *__restrict__ outp, int side, int M) {
   __shared__ double red[5][4];
   const int bi = blockIdx.x;
-  const PatchDev pt = patches[ids[bi]];
   const int n = side * side;
+  const int id = ids[bi];
+  if (id < 0 || id >= M) {  // not a patch of the plan: an all-zero pair (uniform per workgroup)
+    uint32_t *o32 = reinterpret_cast<uint32_t *>(outp) + (long long)bi * n;
+    for (int l = threadIdx.x; l < n; l += 256) o32[l] = 0u;
+    return;
+  }
+  const PatchDev pt = patches[id];
   double a[5] = {0, 0, 0, 0, 0};
   for (int l = threadIdx.x; l < n; l += 256) {
     const long long j = pt.off + l;
@@ -910,7 +916,7 @@ extern "C" pvr_status pvr_cnn_pack_pairs(const pvr_plan *p, const int32_t *patch
       return fail(PVR_ESHAPE, "pvr_cnn_pack_pairs: patch %d is not %dx%d", s, PVR_CNN_SIDE,
                   PVR_CNN_SIDE);
   hipLaunchKernelGGL(k_pack_pairs, dim3(B), dim3(256), 0, stream, p->d_patch, patch_ids, p->d_invz,
-                     y_obs, y_sim, out, PVR_CNN_SIDE);
+                     y_obs, y_sim, out, PVR_CNN_SIDE, p->M);
   HIP_TRY(hipGetLastError());
   return PVR_OK;
   PVR_API_END();

@@ -118,14 +118,14 @@ k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patch
 // tiles (xcd_work), keeping overlapping tiles in the same L2.
 __global__ void __launch_bounds__(SIM_THREADS)
 k_simulate_tiles(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patches,
-                 const TileWork *__restrict__ tiles, int n_tiles,
+                 const int *__restrict__ tile_off, int M, int tile_w, int tile_h, int n_tiles,
                  const GeoF *__restrict__ geo, const float *__restrict__ invz,
                  const float *__restrict__ X, const float *__restrict__ y_obs,
                  float *__restrict__ y_sim, float *__restrict__ resid, int lds_cap) {
   extern __shared__ float xs[];
   const int t = xcd_work(blockIdx.x, SIM_XCD_GRANULE);
   if (t >= n_tiles) return;
-  const TileWork tw = tiles[t];
+  const TileWork tw = tile_at(tile_off, M, patches, tile_w, tile_h, t);
   const PatchDev pt = patches[tw.patch];
   const ProbDev pr = probs[pt.problem];
   const GeoF &g = geo[tw.patch];
@@ -214,7 +214,8 @@ static pvr_status simulate_impl(const pvr_plan *p, const T *X, const T *y_obs, T
     if (ev) HIP_TRY(hipEventRecord(ev[0], stream));
     hipLaunchKernelGGL(k_simulate_tiles, dim3(xcd_blocks(p->n_tiles, SIM_XCD_GRANULE)), dim3(SIM_THREADS),
                        (size_t)p->lds_box * sizeof(float), stream, p->d_prob, p->d_patch,
-                       p->d_tiles, p->n_tiles, p->d_geof, (const float *)invz,
+                       p->d_tile_off, p->M, p->tile_w, p->tile_h, p->n_tiles, p->d_geof,
+                       (const float *)invz,
                        (const float *)X, (const float *)y_obs, (float *)y_sim, (float *)resid,
                        p->lds_box);
     HIP_TRY(hipGetLastError());
@@ -268,7 +269,9 @@ extern "C" pvr_status pvr_simulate_f64(const pvr_plan *p, const double *X, const
   PVR_ALIGNED("pvr_simulate_f64", y_sim, 8);
   PVR_ALIGNED("pvr_simulate_f64", resid, 8);
   if (!p) return fail(PVR_EINVAL, "pvr_simulate_f64: plan is NULL");
-  if (!p->built || !p->built64) return fail(PVR_EINVAL, "pvr_simulate_f64: plan needs pvr_plan_build_f64");
+  if (!p->built || !p->built64)
+    return fail(PVR_EINVAL, "pvr_simulate_f64: plan needs pvr_plan_build_f64 on a workspace "
+                            "attached with PVR_WS_F64");
   return simulate_impl<double>(p, X, y_obs, y_sim, resid, p->d_invz64, stream);
   PVR_API_END();
 }

@@ -115,7 +115,8 @@ extern "C" pvr_status pvr_simulate_grad_theta_f64(const pvr_plan *p, const doubl
   PVR_ALIGNED("pvr_simulate_grad_theta_f64", grad_theta, 8);
   if (!p) return fail(PVR_EINVAL, "pvr_simulate_grad_theta_f64: plan is NULL");
   if (!p->built || !p->built64)
-    return fail(PVR_EINVAL, "pvr_simulate_grad_theta_f64: plan needs pvr_plan_build_f64");
+    return fail(PVR_EINVAL, "pvr_simulate_grad_theta_f64: plan needs pvr_plan_build_f64 on a "
+                            "workspace attached with PVR_WS_F64");
   return grad_impl<double>(p, X, gy, grad_theta, p->d_invz64, stream);
   PVR_API_END();
 }

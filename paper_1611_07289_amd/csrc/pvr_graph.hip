@@ -27,12 +27,18 @@ struct pvr_sr_graph {
 extern "C" pvr_status pvr_check(pvr_plan *p, hipStream_t stream) {
   PVR_API_BEGIN();
   if (!p) return fail(PVR_EINVAL, "pvr_check: plan is NULL");
-  HIP_TRY(hipStreamSynchronize(stream));
+  if (!p->attached) return PVR_OK;  // nothing has run
   unsigned flags = 0;
-  HIP_TRY(hipMemcpy(&flags, p->d_status, sizeof(unsigned), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpyAsync(&flags, p->d_status, sizeof(unsigned), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
   if (!flags) return PVR_OK;
-  const unsigned zero = 0;
-  HIP_TRY(hipMemcpy(p->d_status, &zero, sizeof(unsigned), hipMemcpyHostToDevice));
+  launch_fill_i32((int *)p->d_status, 0, 1, stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (flags & PVR_FAULT_INDEX)
+    return fail(PVR_ESHAPE, "pvr_check: the adjoint's index outgrew its capacity%s%s",
+                (flags & PVR_FAULT_VOLUME) ? "; non-finite updated volume (pvr_sr_update)" : "",
+                (flags & PVR_FAULT_RESIDUAL) ? "; non-finite residual statistics" : "");
   return fail(PVR_ENUMERIC, "pvr_check: non-finite values:%s%s",
               (flags & PVR_FAULT_VOLUME) ? " updated volume (pvr_sr_update)" : "",
               (flags & PVR_FAULT_RESIDUAL) ? " residual statistics (pvr_robust_weights)" : "");

@@ -131,6 +131,25 @@ struct TileWork {    // one forward workgroup: a rectangle of one patch
   short u0, v0, tw, th;  // patch-local origin and size (tw * th <= 256)
 };
 
+// Tile t of the forward tiling (tile_w x tile_h rectangles, edge tiles
+// smaller, a patch's tiles row after row): its patch is the s with
+// tile_off[s] <= t < tile_off[s + 1] (binary search over the M + 1 offsets).
+__device__ __forceinline__ TileWork tile_at(const int *__restrict__ tile_off, int M,
+                                            const PatchDev *__restrict__ patches, int tile_w,
+                                            int tile_h, int t) {
+  int lo = 0, hi = M;  // tile_off[lo] <= t < tile_off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (tile_off[mid] <= t) lo = mid; else hi = mid;
+  }
+  const PatchDev pt = patches[lo];
+  const int tw = min(pt.w, tile_w), th = min(pt.h, tile_h);
+  const int ntx = (pt.w + tw - 1) / tw;
+  const int l = t - tile_off[lo];
+  const int u0 = (l % ntx) * tw, v0 = (l / ntx) * th;
+  return TileWork{lo, (short)u0, (short)v0, (short)min(tw, pt.w - u0), (short)min(th, pt.h - v0)};
+}
+
 template <typename T> __device__ __forceinline__ T fast_exp2(T x);
 template <> __device__ __forceinline__ float fast_exp2<float>(float x) {
   return __builtin_amdgcn_exp2f(x);
@@ -555,20 +574,30 @@ struct pvr_plan {
   long long N, V;
   int n_bricks;
   double k;
-  // host copies
+  // host copies (the device tables are uploaded from these by pvr_plan_attach)
   pvr::ProbDev *h_prob;
   pvr::StackDev *h_stack;
   pvr::PatchDev *h_patch;
   long long *h_sample_off;   // [M+1]
   long long *h_vol_off;      // [P+1]
+  pvr::BlockWork *h_sim_blocks;  // [n_sim_blocks]
+  int *h_brick_prob;         // [n_bricks]
+  int *h_plane_prob;         // [n_planes + P]
+  int *h_tile_off;           // [M+1] tiles before each patch (current tile shape)
   int n_sim_blocks;
+  // caller's device workspace (pvr_plan_attach); every d_ pointer below lies
+  // inside it.  The plan allocates no device memory.
+  void *ws;
+  size_t ws_bytes;
+  int ws_flags;              // PVR_WS_* it was sized for
+  bool attached;
   // device, static
   pvr::ProbDev *d_prob;
   pvr::StackDev *d_stack;
   pvr::PatchDev *d_patch;
   pvr::BlockWork *d_sim_blocks;
-  pvr::TileWork *d_tiles;
-  int n_tiles, tile_cap, tile_w, tile_h;
+  int *d_tile_off;           // [M+1]
+  int n_tiles, tile_w, tile_h;
   bool use_tiles;            // forward pass staged per tile in LDS (else global walk)
   bool timing;               // record event pairs around the hot kernels
   pvr::KernelTimer *timers;  // [TIMING_KERNELS] (created on first enable)
@@ -582,25 +611,23 @@ struct pvr_plan {
   pvr::GeoD *d_geod;
   pvr::GeoF *d_geof;
   float *d_invz;             // [N]
-  double *d_invz64;          // [N] (f64 builds)
+  double *d_invz64;          // [N] (workspaces with PVR_WS_F64)
   uint8_t *d_mask;           // [N]
   uint8_t *d_active;         // [M]
   int *d_bb;                 // [M][6] brick range per patch
   double *d_sbox;            // [M][18] voxel->pixel map and pixel support box
   int *d_bin_count;          // [n_bricks]
   int *d_bin_off;            // [n_bricks + 1]
-  int *d_bin_patch;          // [capacity]
-  long long bin_cap;
-  long long n_pairs;
+  int *d_bin_patch;          // [bin_cap]
+  long long bin_cap;         // host bound on brick/patch pairs over all motions
   int *d_sub_count;          // [8 n_bricks]
   int *d_sub_off;            // [8 n_bricks + 1]
   int *d_sub_patch;          // [sub_cap]
-  long long sub_cap;
-  long long n_sub_pairs;
+  long long sub_cap;         // host bound on sub-brick/patch pairs
   bool built, built64, index_valid;
   // scratch
   float2 *d_rq;              // [N + 2]: zero guard, N entries, zero guard
-  double2 *d_rq64;           // [N + 2] likewise (lazy)
+  double2 *d_rq64;           // [N + 2] likewise (workspaces with PVR_WS_F64)
   double *d_pstat;           // [M][10] per-patch EM partials
   float *d_pbar;             // [M] potentials when the caller passes none
   float *d_pval;             // [M] classification scratch (problems beyond the LDS copy)
@@ -617,9 +644,8 @@ struct pvr_plan {
   const void *rq_e, *rq_p;
   hipStream_t side;
   hipEvent_t ev_fork, ev_join;
-  unsigned *d_status;        // [1] numeric fault flags (PVR_FAULT_*), read by pvr_check
+  unsigned *d_status;        // [1] fault flags (PVR_FAULT_*), read by pvr_check
   long long generation;      // bumped whenever launches recorded earlier would go stale
-  int *d_total;              // [1] pinned readback target (device side)
-  int *h_total;              // pinned host
-  long long device_bytes;
+  int *d_total;              // [4] index totals: brick pairs, sub-brick pairs
+  int h_total[4];            // host readback
 };

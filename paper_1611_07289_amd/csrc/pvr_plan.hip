@@ -15,7 +15,61 @@
 
 using namespace pvr;
 
-static void make_tiles(const pvr_plan *p, std::vector<TileWork> &tiles);
+static pvr_status make_tiles(pvr_plan *p, int tile_w, int tile_h);
+
+// Largest capacity of an adjoint index list (its offsets are int32).
+constexpr long long INDEX_CAP_MAX = 0x7ffffff0LL;
+
+// Upper bound, over every motion and either PSF, on the number of bricks of
+// e^3 voxels (a lattice of step e voxels) that the separating-axis test of
+// the index kernels lists for one patch.  A brick is listed only if its
+// voxel-centre box meets each of the three slabs of the patch's pixel-frame
+// support box, so its centre lies in the support box widened on every side
+// by the box's largest projected half-width hb = (e - 1)/2 sum_c |V_c| (V_c
+// the voxel axes in mm).  That widened box K is a rotated box with sides
+// D_a (mm), and the cells of the centres inside it are disjoint and lie in K
+// grown by the cell's circumradius R, so the count is at most
+// (D0 D1 D2 + 2 (D0 D1 + D1 D2 + D2 D0) R + pi (D0 + D1 + D2) R^2 +
+// 4/3 pi R^3) / (e^3 |det V|), the Steiner volume of the grown box over the
+// cell volume.  At most `cap` (the grid's own count).
+static long long pair_bound(const ProbDev &pr, const StackDev &st, const PatchDev &q, double k,
+                            int e, long long cap) {
+  double V[3][3], sumn = 0;
+  for (int c = 0; c < 3; ++c) {
+    double n2 = 0;
+    for (int r = 0; r < 3; ++r) {
+      V[c][r] = pr.v2w[4 * r + c];
+      n2 += V[c][r] * V[c][r];
+    }
+    sumn += sqrt(n2);
+  }
+  double R = 0;
+  for (int sgn = 0; sgn < 8; ++sgn) {
+    double n2 = 0;
+    for (int r = 0; r < 3; ++r) {
+      double x = 0;
+      for (int c = 0; c < 3; ++c) x += ((sgn >> c) & 1 ? -1.0 : 1.0) * V[c][r];
+      n2 += x * x;
+    }
+    R = std::max(R, sqrt(n2));
+  }
+  R *= 0.5 * e;
+  const double det = fabs(V[0][0] * (V[1][1] * V[2][2] - V[1][2] * V[2][1]) -
+                          V[1][0] * (V[0][1] * V[2][2] - V[0][2] * V[2][1]) +
+                          V[2][0] * (V[0][1] * V[1][2] - V[0][2] * V[1][1]));
+  const double hb = 0.5 * (e - 1) * sumn;
+  const double reach_u = std::max(k * st.sigma[0], st.wz[0]);
+  const double reach_v = std::max(k * st.sigma[1], st.wz[1]);
+  const double reach_n = k * st.sigma[2];
+  double D[3] = {(q.w - 1) * st.spacing[0] + 2 * reach_u + 2 * hb,
+                 (q.h - 1) * st.spacing[1] + 2 * reach_v + 2 * hb, 2 * reach_n + 2 * hb};
+  for (double &d : D) d = d * (1 + 1e-6) + 1e-6;  // room for the test's rounding
+  const double pi = 3.14159265358979323846;
+  const double vol = D[0] * D[1] * D[2] + 2 * (D[0] * D[1] + D[1] * D[2] + D[2] * D[0]) * R +
+                     pi * (D[0] + D[1] + D[2]) * R * R + 4.0 / 3.0 * pi * R * R * R;
+  const double n = ceil(vol / (det * e * e * e)) + 1;
+  return n >= (double)cap ? cap : (long long)n;
+}
 
 __global__ void k_theta_to_f64(const float *__restrict__ th, double *__restrict__ out, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -157,7 +211,8 @@ __global__ void k_sub_fill(const ProbDev *__restrict__ probs, const int *__restr
   double lo[3], hi[3];
   sub_box(pr, sbi, lo, hi);
   int c = soff[sbi];
-  for (int q = off[sbi >> 3]; q < off[(sbi >> 3) + 1]; ++q) {
+  const int end = soff[sbi + 1];  // clamped to the capacity
+  for (int q = off[sbi >> 3]; q < off[(sbi >> 3) + 1] && c < end; ++q) {
     const int s = list[q];
     if (box_meets_patch(sbox + 18 * s, lo, hi)) slist[c++] = s;
   }
@@ -201,22 +256,24 @@ k_bin_fill(const ProbDev *__restrict__ probs, const int *__restrict__ brick_prob
   const int bx = local % pr.nbx, by = (local / pr.nbx) % pr.nby, bz = local / (pr.nbx * pr.nby);
   const unsigned long long below = (1ull << lane) - 1ull;
   int c = off[bi];
+  const int end = off[bi + 1];  // the list's end, clamped to its capacity
   for (int s0 = pr.patch_begin; s0 < pr.patch_end; s0 += 64) {
     const int s = s0 + lane;
     const bool m = s < pr.patch_end && brick_meets_patch(bb + 6 * s, sbox + 18 * s, bx, by, bz);
     const unsigned long long bal = __ballot(m);
-    if (m) list[c + __popcll(bal & below)] = s;
+    const int pos = c + __popcll(bal & below);
+    if (m && pos < end) list[pos] = s;
     c += __popcll(bal);
   }
 }
 
 // Largest voxel box over the forward tiles (sizes the staged LDS).
 __global__ void k_tile_boxmax(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patches,
-                              const TileWork *__restrict__ tiles, int n_tiles,
-                              const GeoF *__restrict__ geo, int *__restrict__ out) {
+                              const int *__restrict__ tile_off, int M, int tile_w, int tile_h,
+                              int n_tiles, const GeoF *__restrict__ geo, int *__restrict__ out) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_tiles) return;
-  const TileWork tw = tiles[t];
+  const TileWork tw = tile_at(tile_off, M, patches, tile_w, tile_h, t);
   const PatchDev pt = patches[tw.patch];
   int lo[3], hi[3];
   const int c = tile_box(geo[tw.patch], probs[pt.problem], pt, tw, lo, hi);
@@ -224,9 +281,13 @@ __global__ void k_tile_boxmax(const ProbDev *__restrict__ probs, const PatchDev 
 }
 
 // Exclusive scan of count[0..n) into off[0..n], off[n] = total, by one
-// workgroup of 1024 threads (each owns a contiguous run).
+// workgroup of 1024 threads (each owns a contiguous run).  The offsets are
+// clamped to the list's capacity `cap`; a total beyond it (which the host
+// bound on the pairs rules out) raises PVR_FAULT_INDEX, and the lists then
+// keep only what fits.
 __global__ void __launch_bounds__(1024) k_scan(const int *__restrict__ count, int n,
-                                               int *__restrict__ off, int *__restrict__ total) {
+                                               int *__restrict__ off, int *__restrict__ total,
+                                               long long cap, unsigned *__restrict__ status) {
   __shared__ long long lds[1024];
   const int tid = threadIdx.x;
   const int per = (n + 1023) / 1024;
@@ -243,12 +304,13 @@ __global__ void __launch_bounds__(1024) k_scan(const int *__restrict__ count, in
   }
   long long run = lds[tid] - s;
   for (int i = a; i < b; ++i) {
-    off[i] = (int)run;
+    off[i] = (int)min(run, cap);
     run += count[i];
   }
   if (tid == 1023) {
-    off[n] = (int)lds[1023];
-    total[0] = (int)min(lds[1023], (long long)0x7fffffff);
+    off[n] = (int)min(lds[1023], cap);
+    total[0] = (int)min(lds[1023], cap);
+    if (lds[1023] > cap) atomicOr(status, PVR_FAULT_INDEX);
   }
 }
 
@@ -345,7 +407,6 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
   long long so = 0;
   int prev_prob = 0;
   std::vector<BlockWork> blocks;
-  std::vector<TileWork> tiles;
   std::vector<int> pcount(n_problems, 0);
   std::vector<long long> scount(n_problems, 0);
   for (int s = 0; s < n_patches; ++s) {
@@ -412,8 +473,11 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
   p->tile_w = TILE;
   p->tile_h = TILE;
   p->use_tiles = false;
-  make_tiles(p, tiles);
-  p->n_tiles = (int)tiles.size();
+  p->h_tile_off = (int *)calloc(n_patches + 1, sizeof(int));
+  {
+    const pvr_status st = make_tiles(p, TILE, TILE);
+    if (st != PVR_OK) return st;
+  }
   std::vector<int> plane_prob;
   std::vector<int> plane_first(n_problems);
   p->max_nx = p->max_ny = 0;
@@ -426,61 +490,137 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
   p->n_planes = (int)plane_prob.size();
   if (p->n_planes > 65535) return fail(PVR_ESHAPE, "pvr_plan_create: more than 65535 z-planes in total");
   plane_prob.insert(plane_prob.end(), plane_first.begin(), plane_first.end());
-  std::vector<int> brick_prob(nbr);
+  p->h_plane_prob = (int *)malloc(sizeof(int) * plane_prob.size());
+  std::copy(plane_prob.begin(), plane_prob.end(), p->h_plane_prob);
+  p->h_brick_prob = (int *)malloc(sizeof(int) * (size_t)std::max(nbr, 1));
   for (int b = 0; b < n_problems; ++b)
-    for (int i = 0; i < p->h_prob[b].n_bricks; ++i) brick_prob[p->h_prob[b].brick_base + i] = b;
-  // device buffers (all host-side validation is done above)
-  HIP_TRY(hipGetDevice(&p->device));
-  DEV_ALLOC(p, p->d_prob, n_problems);
-  DEV_ALLOC(p, p->d_stack, n_stacks);
-  DEV_ALLOC(p, p->d_patch, n_patches);
-  DEV_ALLOC(p, p->d_sim_blocks, p->n_sim_blocks);
-  DEV_ALLOC(p, p->d_tiles, p->n_tiles);
-  p->tile_cap = p->n_tiles;
-  DEV_ALLOC(p, p->d_box_max, 4);
-  DEV_ALLOC(p, p->d_brick_prob, nbr);
-  DEV_ALLOC(p, p->d_plane_prob, plane_prob.size());
-  DEV_ALLOC(p, p->d_theta, 6 * (size_t)n_patches);
-  DEV_ALLOC(p, p->d_geod, n_patches);
-  DEV_ALLOC(p, p->d_geof, n_patches);
-  DEV_ALLOC(p, p->d_bb, 6 * (size_t)n_patches);
-  DEV_ALLOC(p, p->d_sbox, 18 * (size_t)n_patches);
-  DEV_ALLOC(p, p->d_invz, p->N);
-  DEV_ALLOC(p, p->d_mask, p->N);
-  DEV_ALLOC(p, p->d_active, n_patches);
-  DEV_ALLOC(p, p->d_bin_count, nbr);
-  DEV_ALLOC(p, p->d_bin_off, nbr + 1);
-  DEV_ALLOC(p, p->d_sub_count, 8 * (size_t)nbr);
-  DEV_ALLOC(p, p->d_sub_off, 8 * (size_t)nbr + 1);
-  // one guard entry (zero) before and after the N entries: the adjoint's
-  // wide loads may pair a patch's first or last entry with its neighbour
-  DEV_ALLOC(p, p->d_rq, p->N + 2);
-  launch_fill_f32((float *)p->d_rq, 0.f, 2 * (p->N + 2), nullptr);
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipStreamSynchronize(nullptr));
-  DEV_ALLOC(p, p->d_pstat, 10 * (size_t)n_patches);
-  DEV_ALLOC(p, p->d_pbar, n_patches);
-  DEV_ALLOC(p, p->d_pval, n_patches);
-  DEV_ALLOC(p, p->d_chunk_stats, 5 * (size_t)p->n_sim_blocks);
-  if (p->any_xt) DEV_ALLOC(p, p->d_xt, p->V);
-  DEV_ALLOC(p, p->d_total, 4);
-  DEV_ALLOC(p, p->d_status, 1);
-  HIP_TRY(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
-  HIP_TRY(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
-  HIP_TRY(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
-  HIP_TRY(hipMemset(p->d_status, 0, sizeof(unsigned)));
-  HIP_TRY(hipHostMalloc((void **)&p->h_total, sizeof(int) * 4, hipHostMallocDefault));
-  HIP_TRY(hipMemcpy(p->d_prob, p->h_prob, sizeof(ProbDev) * n_problems, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(p->d_stack, p->h_stack, sizeof(StackDev) * n_stacks, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(p->d_patch, p->h_patch, sizeof(PatchDev) * n_patches, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(p->d_sim_blocks, blocks.data(), sizeof(BlockWork) * blocks.size(), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(p->d_tiles, tiles.data(), sizeof(TileWork) * tiles.size(), hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(p->d_brick_prob, brick_prob.data(), sizeof(int) * nbr, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(p->d_plane_prob, plane_prob.data(), sizeof(int) * plane_prob.size(),
-                    hipMemcpyHostToDevice));
-  HIP_TRY(hipDeviceSynchronize());
+    for (int i = 0; i < p->h_prob[b].n_bricks; ++i) p->h_brick_prob[p->h_prob[b].brick_base + i] = b;
+  p->h_sim_blocks = (BlockWork *)malloc(sizeof(BlockWork) * std::max<size_t>(blocks.size(), 1));
+  std::copy(blocks.begin(), blocks.end(), p->h_sim_blocks);
+  // capacity of the adjoint's index: bounds over every motion, so that no
+  // build needs to read a count back or to grow a list
+  {
+    long long bins = 0, subs = 0;
+    for (int s = 0; s < n_patches; ++s) {
+      const PatchDev &q = p->h_patch[s];
+      const ProbDev &pr = p->h_prob[q.problem];
+      const long long b = pair_bound(pr, p->h_stack[q.stack], q, cutoff_k, BRICK, pr.n_bricks);
+      bins += b;
+      subs += std::min(8 * b, pair_bound(pr, p->h_stack[q.stack], q, cutoff_k, SUB, 8LL * pr.n_bricks));
+    }
+    p->bin_cap = std::min(bins, (long long)INDEX_CAP_MAX);
+    p->sub_cap = std::min(subs, (long long)INDEX_CAP_MAX);
+  }
+  p->device = -1;  // the device of the first workspace
   guard.release();
   *out = p;
+  return PVR_OK;
+  PVR_API_END();
+}
+
+// The plan's device state, in one fixed order: with a NULL base this only
+// measures the workspace (the same calls size and carve it).
+static size_t layout(pvr_plan *p, char *base, int flags) {
+  WsCursor c{base, 0};
+  const long long M = p->M, N = p->N, nb = p->n_bricks;
+  p->d_prob = ws_take<ProbDev>(c, p->P);
+  p->d_stack = ws_take<StackDev>(c, p->S);
+  p->d_patch = ws_take<PatchDev>(c, M);
+  p->d_sim_blocks = ws_take<BlockWork>(c, p->n_sim_blocks);
+  p->d_tile_off = ws_take<int>(c, M + 1);
+  p->d_box_max = ws_take<int>(c, 4);
+  p->d_brick_prob = ws_take<int>(c, nb);
+  p->d_plane_prob = ws_take<int>(c, p->n_planes + p->P);
+  p->d_theta = ws_take<double>(c, 6 * M);
+  p->d_geod = ws_take<GeoD>(c, M);
+  p->d_geof = ws_take<GeoF>(c, M);
+  p->d_bb = ws_take<int>(c, 6 * M);
+  p->d_sbox = ws_take<double>(c, 18 * M);
+  p->d_invz = ws_take<float>(c, N);
+  p->d_mask = ws_take<uint8_t>(c, N);
+  p->d_active = ws_take<uint8_t>(c, M);
+  p->d_bin_count = ws_take<int>(c, nb);
+  p->d_bin_off = ws_take<int>(c, nb + 1);
+  p->d_bin_patch = ws_take<int>(c, p->bin_cap);
+  p->d_sub_count = ws_take<int>(c, 8 * nb);
+  p->d_sub_off = ws_take<int>(c, 8 * nb + 1);
+  p->d_sub_patch = ws_take<int>(c, p->sub_cap);
+  // one guard entry (zero) before and after the N entries: the adjoint's
+  // wide loads may pair a patch's first or last entry with its neighbour
+  p->d_rq = ws_take<float2>(c, N + 2);
+  p->d_pstat = ws_take<double>(c, 10 * M);
+  p->d_pbar = ws_take<float>(c, M);
+  p->d_pval = ws_take<float>(c, M);
+  p->d_chunk_stats = ws_take<double>(c, 5LL * p->n_sim_blocks);
+  p->d_xt = p->any_xt ? ws_take<float>(c, p->V) : nullptr;
+  p->d_total = ws_take<int>(c, 4);
+  p->d_status = ws_take<unsigned>(c, 1);
+  p->d_invz64 = (flags & PVR_WS_F64) ? ws_take<double>(c, N) : nullptr;
+  p->d_rq64 = (flags & PVR_WS_F64) ? ws_take<double2>(c, N + 2) : nullptr;
+  return (c.off + 255) & ~(size_t)255;
+}
+
+extern "C" pvr_status pvr_plan_workspace_size(const pvr_plan *p, int32_t flags, size_t *bytes) {
+  PVR_API_BEGIN();
+  if (!p || !bytes) return fail(PVR_EINVAL, "pvr_plan_workspace_size: NULL argument");
+  if (flags & ~PVR_WS_F64) return fail(PVR_EINVAL, "pvr_plan_workspace_size: unknown flags 0x%x", flags);
+  pvr_plan q = *p;  // layout() writes pointers: measure on a copy
+  *bytes = layout(&q, nullptr, flags);
+  return PVR_OK;
+  PVR_API_END();
+}
+
+extern "C" pvr_status pvr_plan_attach(pvr_plan *p, void *workspace, size_t bytes, int32_t flags,
+                                      hipStream_t stream) {
+  PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_plan_attach", workspace, 256);
+  if (!p || !workspace) return fail(PVR_EINVAL, "pvr_plan_attach: NULL argument");
+  if (flags & ~PVR_WS_F64) return fail(PVR_EINVAL, "pvr_plan_attach: unknown flags 0x%x", flags);
+  {
+    pvr_plan q = *p;
+    const size_t need = layout(&q, nullptr, flags);
+    if (bytes < need)
+      return fail(PVR_ESHAPE, "pvr_plan_attach: workspace of %zu bytes, %zu needed", bytes, need);
+  }
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (p->device >= 0 && dev != p->device)
+    return fail(PVR_EINVAL, "pvr_plan_attach: device %d is current, the plan belongs to device %d",
+                dev, p->device);
+  if (p->attached) HIP_TRY(hipStreamSynchronize(stream));  // the old workspace may be in use
+  if (!p->side) {
+    HIP_TRY(hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+  }
+  p->device = dev;
+  layout(p, (char *)workspace, flags);
+  p->ws = workspace;
+  p->ws_bytes = bytes;
+  p->ws_flags = flags;
+  const int M = p->M;
+  HIP_TRY(hipMemcpyAsync(p->d_prob, p->h_prob, sizeof(ProbDev) * p->P, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(p->d_stack, p->h_stack, sizeof(StackDev) * p->S, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(p->d_patch, p->h_patch, sizeof(PatchDev) * M, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(p->d_sim_blocks, p->h_sim_blocks, sizeof(BlockWork) * p->n_sim_blocks,
+                         hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(p->d_tile_off, p->h_tile_off, sizeof(int) * (M + 1), hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(p->d_brick_prob, p->h_brick_prob, sizeof(int) * p->n_bricks,
+                         hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipMemcpyAsync(p->d_plane_prob, p->h_plane_prob, sizeof(int) * (p->n_planes + p->P),
+                         hipMemcpyHostToDevice, stream));
+  launch_fill_f32((float *)p->d_rq, 0.f, 2 * (p->N + 2), stream);
+  if (p->d_rq64) launch_fill_f64((double *)p->d_rq64, 0.0, 2 * (p->N + 2), stream);
+  launch_fill_i32((int *)p->d_status, 0, 1, stream);
+  launch_fill_i32(p->d_total, 0, 4, stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(stream));  // the uploads read pageable host tables of the plan
+  p->attached = true;
+  p->built = p->built64 = false;
+  p->index_valid = false;
+  p->stats_valid = false;
+  p->rq_fresh = false;
+  ++p->generation;
   return PVR_OK;
   PVR_API_END();
 }
@@ -499,8 +639,16 @@ extern "C" pvr_status pvr_plan_info(const pvr_plan *p, pvr_plan_sizes *out) {
   out->n_problems = p->P;
   out->n_stacks = p->S;
   out->n_bricks = p->n_bricks;
-  out->n_bin_pairs = p->n_sub_pairs;
-  out->device_bytes = p->device_bytes;
+  out->n_bin_pairs = 0;
+  if (p->attached && p->index_valid) {
+    int tot[4];
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(tot, p->d_total, sizeof tot, hipMemcpyDeviceToHost));
+    out->n_bin_pairs = tot[1];
+  }
+  out->device_bytes = p->attached ? (int64_t)p->ws_bytes : 0;
+  out->bin_capacity = p->bin_cap;
+  out->sub_capacity = p->sub_cap;
   return PVR_OK;
   PVR_API_END();
 }
@@ -514,31 +662,40 @@ extern "C" pvr_status pvr_plan_offsets(const pvr_plan *p, int64_t *sample_off, i
   PVR_API_END();
 }
 
-extern "C" const float *pvr_plan_inv_z(const pvr_plan *p) { return p ? p->d_invz : nullptr; }
+extern "C" const float *pvr_plan_inv_z(const pvr_plan *p) {
+  return p && p->attached ? p->d_invz : nullptr;
+}
 
 // Forward tiles: every patch cut into tile_w x tile_h rectangles (edge tiles
-// smaller), patch-major.
-static void make_tiles(const pvr_plan *p, std::vector<TileWork> &tiles) {
-  tiles.clear();
+// smaller), row of tiles after row of tiles; h_tile_off counts the tiles
+// before each patch (a workgroup finds its tile with tile_at).
+static pvr_status make_tiles(pvr_plan *p, int tile_w, int tile_h) {
+  long long t = 0;
   for (int s = 0; s < p->M; ++s) {
     const PatchDev &q = p->h_patch[s];
-    const int tw = std::min(q.w, p->tile_w), th = std::min(q.h, p->tile_h);
-    for (int v0 = 0; v0 < q.h; v0 += th)
-      for (int u0 = 0; u0 < q.w; u0 += tw)
-        tiles.push_back(TileWork{s, (short)u0, (short)v0, (short)std::min(tw, q.w - u0),
-                                 (short)std::min(th, q.h - v0)});
+    const int tw = std::min(q.w, tile_w), th = std::min(q.h, tile_h);
+    p->h_tile_off[s] = (int)t;
+    t += (long long)((q.w + tw - 1) / tw) * ((q.h + th - 1) / th);
+    if (t > 0x7fffffffLL)
+      return fail(PVR_ESHAPE, "forward tiles of %dx%d: more than 2^31 tiles", tile_w, tile_h);
   }
+  p->h_tile_off[p->M] = (int)t;
+  p->n_tiles = (int)t;
+  p->tile_w = tile_w;
+  p->tile_h = tile_h;
+  return PVR_OK;
 }
 
 static pvr_status update_lds_box(pvr_plan *p, hipStream_t stream) {
   const int T = 256;
   launch_fill_i32(p->d_box_max, 0, 1, stream);
   hipLaunchKernelGGL(k_tile_boxmax, dim3((p->n_tiles + T - 1) / T), dim3(T), 0, stream, p->d_prob,
-                     p->d_patch, p->d_tiles, p->n_tiles, p->d_geof, p->d_box_max);
+                     p->d_patch, p->d_tile_off, p->M, p->tile_w, p->tile_h, p->n_tiles, p->d_geof,
+                     p->d_box_max);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync(p->h_total + 1, p->d_box_max, sizeof(int), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(p->h_total + 2, p->d_box_max, sizeof(int), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
-  p->lds_box = std::min(p->h_total[1], LDS_BOX_MAX);
+  p->lds_box = std::min(p->h_total[2], LDS_BOX_MAX);
   return PVR_OK;
 }
 
@@ -573,6 +730,7 @@ extern "C" pvr_status pvr_plan_set_tiles(pvr_plan *p, int32_t tile_w, int32_t ti
                                          hipStream_t stream) {
   PVR_API_BEGIN();
   if (!p) return fail(PVR_EINVAL, "pvr_plan_set_tiles: plan is NULL");
+  if (!p->attached) return fail(PVR_EINVAL, "pvr_plan_set_tiles: no workspace attached");
   ++p->generation;
   if (tile_w == 0 && tile_h == 0) {
     p->use_tiles = false;
@@ -580,28 +738,24 @@ extern "C" pvr_status pvr_plan_set_tiles(pvr_plan *p, int32_t tile_w, int32_t ti
   }
   if (tile_w <= 0 || tile_h <= 0 || tile_w * tile_h > 256)
     return fail(PVR_EINVAL, "pvr_plan_set_tiles: need 0 < tile_w * tile_h <= 256 (or 0 x 0)");
-  HIP_TRY(hipStreamSynchronize(stream));
-  p->use_tiles = true;
-  p->tile_w = tile_w;
-  p->tile_h = tile_h;
-  std::vector<TileWork> tiles;
-  make_tiles(p, tiles);
-  if ((int)tiles.size() > p->tile_cap) {
-    HIP_TRY(hipFree(p->d_tiles));
-    p->d_tiles = nullptr;
-    DEV_ALLOC(p, p->d_tiles, tiles.size());
-    p->tile_cap = (int)tiles.size();
+  HIP_TRY(hipStreamSynchronize(stream));  // earlier launches may still read the tile table
+  const pvr_status st = make_tiles(p, tile_w, tile_h);
+  if (st != PVR_OK) {
+    p->use_tiles = false;
+    return st;
   }
-  p->n_tiles = (int)tiles.size();
-  HIP_TRY(hipMemcpy(p->d_tiles, tiles.data(), sizeof(TileWork) * tiles.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpyAsync(p->d_tile_off, p->h_tile_off, sizeof(int) * (p->M + 1),
+                         hipMemcpyHostToDevice, stream));
+  p->use_tiles = true;
   if (p->built) return update_lds_box(p, stream);
+  HIP_TRY(hipStreamSynchronize(stream));
   return PVR_OK;
   PVR_API_END();
 }
 
 // brick -> patch and sub-brick -> patch lists of the gather adjoint for the
-// geometry of the last build (synchronises the stream once per level to size
-// the lists).
+// geometry of the last build, into lists of the capacities bounded at plan
+// creation: no count is read back, nothing is synchronised.
 pvr_status pvr::plan_build_index(pvr_plan *p, hipStream_t stream) {
   const int T = 256;
   const int nb = p->n_bricks;
@@ -610,20 +764,8 @@ pvr_status pvr::plan_build_index(pvr_plan *p, hipStream_t stream) {
                      p->d_brick_prob, p->d_bb, p->d_sbox, nb, p->d_bin_count);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, stream, p->d_bin_count, nb, p->d_bin_off,
-                     p->d_total);
+                     p->d_total, p->bin_cap, p->d_status);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync(p->h_total, p->d_total, sizeof(int), hipMemcpyDeviceToHost, stream));
-  HIP_TRY(hipStreamSynchronize(stream));
-  const long long pairs = p->h_total[0];
-  if (pairs >= 0x7fffffffLL) return fail(PVR_ESHAPE, "pvr_plan_build: brick index exceeds 2^31 pairs");
-  if (pairs > p->bin_cap) {
-    if (p->d_bin_patch) { HIP_TRY(hipFree(p->d_bin_patch)); p->device_bytes -= p->bin_cap * 4; }
-    p->d_bin_patch = nullptr;
-    long long cap = pairs + pairs / 8 + 1024;
-    DEV_ALLOC(p, p->d_bin_patch, cap);
-    p->bin_cap = cap;
-  }
-  p->n_pairs = pairs;
   hipLaunchKernelGGL(k_bin_fill, dim3(nbw), dim3(BIN_THREADS), 0, stream, p->d_prob,
                      p->d_brick_prob, p->d_bb, p->d_sbox, nb, p->d_bin_off, p->d_bin_patch);
   HIP_TRY(hipGetLastError());
@@ -632,20 +774,8 @@ pvr_status pvr::plan_build_index(pvr_plan *p, hipStream_t stream) {
                      p->d_brick_prob, p->d_sbox, nsb, p->d_bin_off, p->d_bin_patch, p->d_sub_count);
   HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, stream, p->d_sub_count, nsb, p->d_sub_off,
-                     p->d_total);
+                     p->d_total + 1, p->sub_cap, p->d_status);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync(p->h_total, p->d_total, sizeof(int), hipMemcpyDeviceToHost, stream));
-  HIP_TRY(hipStreamSynchronize(stream));
-  const long long spairs = p->h_total[0];
-  if (spairs >= 0x7fffffffLL) return fail(PVR_ESHAPE, "pvr_plan_build: sub-brick index exceeds 2^31 pairs");
-  if (spairs > p->sub_cap) {
-    if (p->d_sub_patch) { HIP_TRY(hipFree(p->d_sub_patch)); p->device_bytes -= p->sub_cap * 4; }
-    p->d_sub_patch = nullptr;
-    long long cap = spairs + spairs / 8 + 1024;
-    DEV_ALLOC(p, p->d_sub_patch, cap);
-    p->sub_cap = cap;
-  }
-  p->n_sub_pairs = spairs;
   hipLaunchKernelGGL(k_sub_fill, dim3((nsb + T - 1) / T), dim3(T), 0, stream, p->d_prob,
                      p->d_brick_prob, p->d_sbox, nsb, p->d_bin_off, p->d_bin_patch, p->d_sub_off,
                      p->d_sub_patch);
@@ -673,8 +803,9 @@ static pvr_status plan_build_common(pvr_plan *p, const uint8_t *active, const ui
                      p->d_patch, p->d_theta, M, p->k, p->psf, p->d_geod, p->d_geof, p->d_bb,
                      p->d_sbox);
   HIP_TRY(hipGetLastError());
-  if (f64) {
-    if (!p->d_invz64) DEV_ALLOC(p, p->d_invz64, p->N);
+  // an FP64 build also writes FP64 normalisers when the workspace has room
+  // for them (PVR_WS_F64); the FP32 ones are written either way
+  if (f64 && p->d_invz64) {
     hipLaunchKernelGGL(k_normalisers<double>, dim3(p->n_sim_blocks), dim3(SIM_THREADS), 0, stream,
                        p->d_prob, p->d_patch, p->d_sim_blocks, p->d_geod, p->d_mask, p->d_active,
                        p->d_invz, p->d_invz64);
@@ -693,7 +824,7 @@ static pvr_status plan_build_common(pvr_plan *p, const uint8_t *active, const ui
   p->stats_valid = false;
   p->rq_fresh = false;
   p->built = true;
-  p->built64 = f64;
+  p->built64 = f64 && p->d_invz64;
   ++p->generation;
   return PVR_OK;
 }
@@ -703,6 +834,7 @@ extern "C" pvr_status pvr_plan_build(pvr_plan *p, const float *theta, const uint
   PVR_API_BEGIN();
   PVR_ALIGNED("pvr_plan_build", theta, 4);
   if (!p || !theta) return fail(PVR_EINVAL, "pvr_plan_build: NULL plan or theta");
+  if (!p->attached) return fail(PVR_EINVAL, "pvr_plan_build: no workspace attached (pvr_plan_attach)");
   const int n = 6 * p->M;
   hipLaunchKernelGGL(k_theta_to_f64, dim3((n + 255) / 256), dim3(256), 0, stream, theta, p->d_theta, n);
   HIP_TRY(hipGetLastError());
@@ -715,6 +847,7 @@ extern "C" pvr_status pvr_plan_build_f64(pvr_plan *p, const double *theta, const
   PVR_API_BEGIN();
   PVR_ALIGNED("pvr_plan_build_f64", theta, 8);
   if (!p || !theta) return fail(PVR_EINVAL, "pvr_plan_build_f64: NULL plan or theta");
+  if (!p->attached) return fail(PVR_EINVAL, "pvr_plan_build_f64: no workspace attached (pvr_plan_attach)");
   const int n = 6 * p->M;
   hipLaunchKernelGGL(k_copy_theta, dim3((n + 255) / 256), dim3(256), 0, stream, theta, p->d_theta, n);
   HIP_TRY(hipGetLastError());

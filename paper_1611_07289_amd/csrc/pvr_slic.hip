@@ -15,7 +15,6 @@
 #include "pvr_util.h"
 
 #include <algorithm>
-#include <vector>
 
 using namespace pvr;
 
@@ -442,49 +441,78 @@ extern "C" pvr_status pvr_slic_boxes(const int32_t *labels, int32_t n_img, int32
   PVR_API_END();
 }
 
+// Checks the host table of pvr_slic_pack and returns the largest box (pixels,
+// the kernel's LDS bytes).
+static pvr_status pack_check(const char *fn, int32_t n_img, int32_t h, int32_t w, int32_t M,
+                             const int32_t *table, int *most) {
+  *most = 0;
+  for (int s = 0; s < M; ++s) {
+    const int32_t *t = table + 6 * (size_t)s;
+    if (t[0] < 0 || t[0] >= n_img || t[4] <= 0 || t[5] <= 0 || t[2] < 0 || t[3] < 0 ||
+        t[2] > w - t[4] || t[3] > h - t[5])
+      return fail(PVR_ESHAPE, "%s: patch %d (image %d, box %d,%d %dx%d) leaves its image", fn, s,
+                  t[0], t[2], t[3], t[4], t[5]);
+    if ((long long)t[4] * t[5] > PACK_MAX_PIXELS)
+      return fail(PVR_ESHAPE, "%s: patch %d holds %lld pixels (at most %d)", fn, s,
+                  (long long)t[4] * t[5], PACK_MAX_PIXELS);
+    *most = std::max(*most, t[4] * t[5]);
+  }
+  return PVR_OK;
+}
+
+// Writes the M descriptors (with their sample offsets) into the device table
+// `dtab` through a host staging array on the stack, one synchronised copy per
+// PACK_STAGE descriptors, then launches the packing.  No memory is allocated.
+constexpr int PACK_STAGE = 1024;
+
+static pvr_status pack_launch(const float *img, const int32_t *labels, int32_t h, int32_t w,
+                              int32_t gamma, int32_t M, const int32_t *table, int most,
+                              PackDesc *dtab, float *y, uint8_t *mask, hipStream_t stream) {
+  PackDesc stage[PACK_STAGE];
+  long long off = 0;
+  for (int s0 = 0; s0 < M; s0 += PACK_STAGE) {
+    const int n = std::min(PACK_STAGE, M - s0);
+    for (int i = 0; i < n; ++i) {
+      const int32_t *t = table + 6 * (size_t)(s0 + i);
+      stage[i] = PackDesc{t[0], t[1], t[2], t[3], t[4], t[5], off};
+      off += (long long)t[4] * t[5];
+    }
+    HIP_TRY(hipMemcpyAsync(dtab + s0, stage, sizeof(PackDesc) * (size_t)n, hipMemcpyHostToDevice,
+                           stream));
+    HIP_TRY(hipStreamSynchronize(stream));  // the stage is reused / leaves scope
+  }
+  hipLaunchKernelGGL(k_slic_pack, dim3(M), dim3(SLIC_T), (size_t)most, stream, img, labels, h, w,
+                     gamma, (const PackDesc *)dtab, y, mask);
+  HIP_TRY(hipGetLastError());
+  return PVR_OK;
+}
+
+extern "C" size_t pvr_slic_pack_workspace(int32_t M) {
+  return M > 0 ? sizeof(PackDesc) * (size_t)M : 0;
+}
+
 extern "C" pvr_status pvr_slic_pack(const float *img, const int32_t *labels, int32_t n_img,
                                     int32_t h, int32_t w, int32_t gamma, int32_t M,
-                                    const int32_t *table, float *y, uint8_t *mask,
-                                    hipStream_t stream) {
+                                    const int32_t *table, void *workspace, size_t workspace_bytes,
+                                    float *y, uint8_t *mask, hipStream_t stream) {
   PVR_API_BEGIN();
   PVR_ALIGNED("pvr_slic_pack", img, 4);
   PVR_ALIGNED("pvr_slic_pack", labels, 4);
   PVR_ALIGNED("pvr_slic_pack", y, 4);
-  if (!img || !labels || !table || (M > 0 && (!y || !mask)))
+  PVR_ALIGNED("pvr_slic_pack", workspace, 16);
+  if (!img || !labels || !table || (M > 0 && (!y || !mask || !workspace)))
     return fail(PVR_EINVAL, "pvr_slic_pack: NULL argument");
   if (gamma < 0 || M < 0) return fail(PVR_EINVAL, "pvr_slic_pack: gamma < 0 or M < 0");
   pvr_status st = check_sizes("pvr_slic_pack", n_img, h, w, 0);
   if (st != PVR_OK) return st;
   if (M == 0) return PVR_OK;
-  std::vector<PackDesc> d(M);
-  long long off = 0;
+  if (workspace_bytes < pvr_slic_pack_workspace(M))
+    return fail(PVR_ESHAPE, "pvr_slic_pack: workspace of %zu bytes, %zu needed for %d patches",
+                workspace_bytes, pvr_slic_pack_workspace(M), M);
   int most = 0;
-  for (int s = 0; s < M; ++s) {
-    const int32_t *t = table + 6 * (size_t)s;
-    if (t[0] < 0 || t[0] >= n_img || t[4] <= 0 || t[5] <= 0 || t[2] < 0 || t[3] < 0 ||
-        t[2] > w - t[4] || t[3] > h - t[5])
-      return fail(PVR_ESHAPE, "pvr_slic_pack: patch %d (image %d, box %d,%d %dx%d) leaves its image",
-                  s, t[0], t[2], t[3], t[4], t[5]);
-    if ((long long)t[4] * t[5] > PACK_MAX_PIXELS)
-      return fail(PVR_ESHAPE, "pvr_slic_pack: patch %d holds %lld pixels (at most %d)", s,
-                  (long long)t[4] * t[5], PACK_MAX_PIXELS);
-    d[s] = PackDesc{t[0], t[1], t[2], t[3], t[4], t[5], off};
-    off += (long long)t[4] * t[5];
-    most = std::max(most, t[4] * t[5]);
-  }
-  PackDesc *dd = nullptr;
-  HIP_TRY(hipMalloc((void **)&dd, sizeof(PackDesc) * (size_t)M));
-  hipError_t e = hipMemcpyAsync(dd, d.data(), sizeof(PackDesc) * (size_t)M,
-                                hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_slic_pack, dim3(M), dim3(SLIC_T), (size_t)most, stream, img, labels, h,
-                       w, gamma, dd, y, mask);
-    e = hipGetLastError();
-  }
-  const hipError_t e2 = hipStreamSynchronize(stream);
-  (void)hipFree(dd);
-  HIP_TRY(e);
-  HIP_TRY(e2);
-  return PVR_OK;
+  st = pack_check("pvr_slic_pack", n_img, h, w, M, table, &most);
+  if (st != PVR_OK) return st;
+  return pack_launch(img, labels, h, w, gamma, M, table, most, (PackDesc *)workspace, y, mask,
+                     stream);
   PVR_API_END();
 }

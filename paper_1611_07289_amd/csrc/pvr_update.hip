@@ -79,6 +79,7 @@ extern "C" pvr_status pvr_sr_update(const pvr_plan *p, const float *X, const flo
   PVR_ALIGNED("pvr_sr_update", X_out, 4);
   if (!p || !X || !num || !den || !prm || !X_out) return fail(PVR_EINVAL, "pvr_sr_update: NULL argument");
   if (X_out == X) return fail(PVR_EINVAL, "pvr_sr_update: X_out must not alias X");
+  if (!p->attached) return fail(PVR_EINVAL, "pvr_sr_update: no workspace attached (pvr_plan_attach)");
   if (!(prm->delta > 0)) return fail(PVR_EINVAL, "pvr_sr_update: delta must be > 0");
   hipLaunchKernelGGL(k_sr_update, dim3((p->max_nx + 63) / 64, (p->max_ny + 3) / 4, p->n_planes),
                      dim3(256), 0, stream, p->d_prob, p->d_plane_prob, X, num, den, *prm, X_out,

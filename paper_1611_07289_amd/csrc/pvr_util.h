@@ -62,15 +62,17 @@ struct PlanGuard {
                        (int)(a));                                              \
   } while (0)
 
-#define DEV_ALLOC(plan, ptr, count)                                            \
-  do {                                                                         \
-    size_t n_ = (size_t)(count) * sizeof(*(ptr));                              \
-    if (n_ == 0) n_ = 16;                                                      \
-    hipError_t e_ = hipMalloc((void **)&(ptr), n_);                            \
-    if (e_ != hipSuccess) {                                                    \
-      (ptr) = nullptr;                                                         \
-      return pvr::fail(PVR_ENOMEM, "hipMalloc of %zu bytes failed: %s", n_,    \
-                       hipGetErrorString(e_));                                 \
-    }                                                                          \
-    (plan)->device_bytes += (long long)n_;                                     \
-  } while (0)
+// Places `count` elements of T at the next 256-byte boundary of a workspace
+// and advances the cursor.  With a NULL base it only measures: the same
+// sequence of calls sizes a workspace and then carves it.
+struct WsCursor {
+  char *base;
+  size_t off;
+};
+template <typename T>
+inline T *ws_take(WsCursor &c, long long count) {
+  c.off = (c.off + 255) & ~(size_t)255;
+  T *r = c.base ? reinterpret_cast<T *>(c.base + c.off) : nullptr;
+  c.off += (size_t)(count > 0 ? count : 1) * sizeof(T);
+  return r;
+}

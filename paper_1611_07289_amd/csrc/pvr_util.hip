@@ -42,15 +42,8 @@ void launch_fill_f64(double *dst, double v, long long n, hipStream_t s) { fill<d
 
 void plan_free(pvr_plan *p) {
   if (!p) return;
-  if (p->d_prob) (void)hipDeviceSynchronize();
-  void *dev[] = {p->d_prob, p->d_stack, p->d_patch, p->d_sim_blocks, p->d_tiles, p->d_box_max, p->d_brick_prob, p->d_plane_prob,
-                 p->d_theta, p->d_geod, p->d_geof, p->d_bb, p->d_sbox, p->d_invz, p->d_invz64,
-                 p->d_mask, p->d_active, p->d_bin_count, p->d_bin_off, p->d_bin_patch, p->d_sub_count, p->d_sub_off, p->d_sub_patch,
-                 p->d_rq, p->d_rq64, p->d_pstat, p->d_pbar, p->d_pval, p->d_chunk_stats, p->d_xt, p->d_total,
-                 p->d_status};
-  for (void *q : dev)
-    if (q) (void)hipFree(q);
-  if (p->h_total) (void)hipHostFree(p->h_total);
+  // the caller frees the workspace once this returns: let the device finish
+  if (p->attached) (void)hipDeviceSynchronize();
   if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
   if (p->ev_join) (void)hipEventDestroy(p->ev_join);
   if (p->side) (void)hipStreamDestroy(p->side);
@@ -66,6 +59,10 @@ void plan_free(pvr_plan *p) {
   free(p->h_patch);
   free(p->h_sample_off);
   free(p->h_vol_off);
+  free(p->h_sim_blocks);
+  free(p->h_brick_prob);
+  free(p->h_plane_prob);
+  free(p->h_tile_off);
   free(p);
 }
 

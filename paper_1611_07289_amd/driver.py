@@ -84,10 +84,15 @@ def reconstruct(plan, y, theta0, cycles: int = 3, n_sr: int = 10,
                 reg_params: Optional[pvr.RegParams] = None,
                 sr_params: Optional[pvr.SRParams] = None, register: bool = True,
                 init_fn=None, active_schedule=None, sample_mask=None, X0=None,
-                first_cycle: int = 0, on_cycle=None):
+                first_cycle: int = 0, on_cycle=None, fallback_tau: Optional[float] = None,
+                fallback_params: Optional[pvr.RegParams] = None):
     """Full reconstruction; theta0 is [M, 6] float32 on the device and is
     updated in place.  ``init_fn(plan, X, y, theta)``, when given, runs before
-    each registration (a learned initialiser).  ``active_schedule``, when
+    each registration (a learned initialiser) with the keyword arguments
+    active and mask of the cycle's build; with ``fallback_tau`` the patches
+    whose NCC after the registration stays below it are registered again
+    from their motion before init_fn, with ``fallback_params`` (default the
+    same parameters).  ``active_schedule``, when
     given, is a list of per-patch uint8 device masks used cycle by cycle (in
     turn): multi-scale patches (paper Sec. II, eq. Y_i), where cycle c
     registers and reconstructs from the patches of one scale only.
@@ -118,17 +123,28 @@ def reconstruct(plan, y, theta0, cycles: int = 3, n_sr: int = 10,
     plan.build(theta, active=active(first_cycle), mask=sample_mask)
     X = initial_volume(plan, y, buf) if X0 is None else X0.clone()
     t1 = tick(); timings["build"] += t1 - t
-    hist = {"ncc": [], "excluded": []}
+    hist = {"ncc": [], "excluded": [], "fallback": []}
     ymax = float(y.abs().max())
     rp = reg_params or pvr.RegParams.make(min_std=0.01 * ymax)
     for c in range(first_cycle, first_cycle + cycles):
         if register:
             if init_fn is not None:
                 t = tick()
-                init_fn(plan, X, y, theta)
+                theta_pre = theta.clone()
+                init_fn(plan, X, y, theta, active=active(c), mask=sample_mask)
                 timings["init_fn"] += tick() - t
             t = tick()
             plan.register(X, y, theta, buf.ncc, reg=active(c), params=rp)
+            if init_fn is not None and fallback_tau is not None:
+                # where the refined proposal scores below tau, the plain
+                # registration takes over from the motion before the proposal
+                flag = torch.empty(plan.M, dtype=torch.uint8, device=theta.device)
+                plan.motion_fallback(buf.ncc, fallback_tau, theta_pre, theta, flag)
+                if active(c) is not None:
+                    flag.mul_(active(c))
+                plan.register(X, y, theta, buf.ncc, reg=flag,
+                              params=fallback_params or rp)
+                hist["fallback"].append(int(flag.sum()))
             t1 = tick(); timings["register"] += t1 - t
             hist["ncc"].append(float(buf.ncc.mean()))
             t = tick()
@@ -213,38 +229,31 @@ def patch_radius(plan):
 
 
 def register_gradient(plan, X, y, theta, iters: int = 30, step0: float = 1.0,
-                      step_min: float = 0.01, min_std: float = 0.0):
+                      step_min: float = 0.01, min_std: float = 0.0, active=None, mask=None):
     """Joint gradient-based registration of all patches with the
     differentiable forward model: d NCC_s / d theta_s is the NCC derivative
     with respect to the simulated samples (pvr_ncc_grad) pulled back through
     pvr_simulate_grad_theta.  Each patch takes a normalised ascent step in the
-    radius-scaled variables, kept on strict NCC improvement (the step then
-    doubles, capped at step0) and halved otherwise.  Patches with std(y_s) <
-    min_std and patches whose step fell below step_min stay put.  theta
-    ([M, 6] float32 on the device) is updated in place; the plan is left
-    built at the final theta.  Returns the final per-patch NCC."""
+    radius-scaled variables (pvr_motion_step), kept on strict NCC improvement
+    (the step then doubles, capped at step0) and halved otherwise
+    (pvr_motion_accept).  Patches with std(y_s) < min_std and patches whose
+    step fell below step_min stay put (pvr_motion_init_step).  Every build
+    takes ``active`` and ``mask`` (uint8 device arrays, nullable) as
+    driver.reconstruct passes them.  theta ([M, 6] float32 on the device) is
+    updated in place; the plan is left built at the final theta.  Returns the
+    final per-patch NCC."""
     import torch
     dev = theta.device
-    sc = torch.tensor(np.repeat(patch_radius(plan)[:, None], 6, 1), dtype=torch.float32,
-                      device=dev)
-    sc[:, 3:] = 1.0
     ysim = torch.empty(plan.N, dtype=torch.float32, device=dev)
     g = torch.empty_like(ysim)
     ncc = torch.empty(plan.M, dtype=torch.float32, device=dev)
     ncc_t = torch.empty_like(ncc)
     G = torch.empty(plan.M, 6, dtype=torch.float32, device=dev)
-    delta = torch.full((plan.M,), float(step0), device=dev)
-    if min_std > 0:
-        off = torch.tensor(plan.sample_off, device=dev)
-        seg = torch.repeat_interleave(torch.arange(plan.M, device=dev), off[1:] - off[:-1])
-        cnt = torch.bincount(seg, minlength=plan.M).float()
-        m1 = torch.bincount(seg, weights=y.double(), minlength=plan.M) / cnt
-        m2 = torch.bincount(seg, weights=y.double() ** 2, minlength=plan.M) / cnt
-        sd = (m2 - m1 ** 2).clamp_min(0).sqrt().float()
-        delta = torch.where(sd >= min_std, delta, torch.zeros_like(delta))
+    trial = torch.empty_like(G)
+    delta = torch.empty(plan.M, dtype=torch.float32, device=dev)
 
     def evaluate(th, grad):
-        plan.build(th)
+        plan.build(th, active=active, mask=mask)
         plan.simulate(X, y_sim=ysim)
         if grad:
             plan.ncc_grad(y, ysim, g, ncc)
@@ -252,20 +261,16 @@ def register_gradient(plan, X, y, theta, iters: int = 30, step0: float = 1.0,
         else:
             plan.ncc_grad(y, ysim, None, ncc_t)
 
+    n_live = torch.zeros(1, dtype=torch.int32, device=dev)
     evaluate(theta, True)
+    plan.motion_init_step(y, step0, min_std, delta)
     for it in range(iters):
-        live = delta >= step_min
-        if not bool(live.any()):
-            break
-        Gq = G / sc
-        n = Gq.norm(dim=1, keepdim=True).clamp_min(1e-30)
-        step = torch.where(live[:, None], delta[:, None] * Gq / n, torch.zeros_like(Gq))
-        trial = theta + step / sc
+        plan.motion_step(theta, G, delta, step_min, trial)
         evaluate(trial, False)
-        acc = live & (ncc_t > ncc)
-        theta.copy_(torch.where(acc[:, None], trial, theta))
-        delta = torch.where(acc, torch.clamp(2 * delta, max=step0),
-                            torch.where(live, 0.5 * delta, delta))
+        n_live.zero_()
+        plan.motion_accept(trial, ncc_t, theta, ncc, delta, step0, step_min, n_live)
+        if it % 4 == 3 and int(n_live.item()) == 0:  # every patch has converged
+            break
         evaluate(theta, True)
-    plan.build(theta)
+    plan.build(theta, active=active, mask=mask)
     return ncc

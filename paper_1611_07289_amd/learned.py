@@ -193,34 +193,6 @@ class Net:
         return self.forward(B).view(B, 6)
 
 
-def target_maps(plan):
-    """Per-patch linear maps between motion offsets and network targets:
-    target = A offset with A = diag(rho F^T, F^T), F the patch's stack frame
-    (columns: in-plane u, in-plane v, slice normal) and rho the patch
-    half-diagonal.  In the patch's own frame the same image change means the
-    same target on every stack orientation, which the network can learn;
-    rho turns rotations into the displacement (mm) of the farthest pixel.
-    Returns (A, A^-1) as float32 arrays [M][6][6]."""
-    from .driver import patch_radius, patch_table
-    rho = patch_radius(plan)
-    frames = np.array([np.asarray(list(st.pix2world), float).reshape(3, 4)[:, :3] for st in plan._s])
-    frames /= np.linalg.norm(frames, axis=1, keepdims=True)
-    F = frames[patch_table(plan)[:, 0]]                     # [M][3][3]
-    Ft = np.swapaxes(F, 1, 2)
-    A = np.zeros((plan.M, 6, 6))
-    Ai = np.zeros((plan.M, 6, 6))
-    A[:, :3, :3] = rho[:, None, None] * Ft
-    A[:, 3:, 3:] = Ft
-    Ai[:, :3, :3] = F / rho[:, None, None]
-    Ai[:, 3:, 3:] = F
-    return A.astype(np.float32), Ai.astype(np.float32)
-
-
-def apply_maps(maps, v):
-    """maps [M][6][6] (device), v [M][6] -> [M][6]."""
-    return (maps @ v.unsqueeze(-1)).squeeze(-1)
-
-
 def make_pairs(plan, X, theta_ref, offsets, noise_sd: float, seed: int):
     """Observed patches at theta_ref (plus Gaussian noise) and patches
     simulated at theta_ref - offsets; returns (y_obs, y_sim) device tensors
@@ -247,7 +219,6 @@ def train(net: Net, plan, volumes: List, n_pairs: int, batch: int = 256, lr: flo
     import torch
     from . import synth
     dev = volumes[0].device
-    A = torch.from_numpy(target_maps(plan)[0]).to(dev)
     M = plan.M
     rounds = max(1, int(math.ceil(n_pairs / M)))
     hist = []
@@ -263,7 +234,7 @@ def train(net: Net, plan, volumes: List, n_pairs: int, batch: int = 256, lr: flo
         off = torch.from_numpy(synth.random_motion_batch(M, max_rot_deg, max_trans,
                                                          seed + 2 * r + 1).astype(np.float32)).to(dev)
         y_obs, y_sim = make_pairs(plan, X, ref, off, 0.01 * float(X.max()), seed + r)
-        target = apply_maps(A, off)
+        target = plan.motion_frame(off)  # the offset in each patch's own frame
         perm = torch.from_numpy(rng.permutation(M).astype(np.int32)).to(dev)
         torch.cuda.synchronize()
         t_data += time.perf_counter() - td
@@ -292,20 +263,14 @@ def train(net: Net, plan, volumes: List, n_pairs: int, batch: int = 256, lr: flo
 def init_fn_factory(net: Net, batch: int = 1024):
     """A driver init function: predicts every patch's correction from the
     current volume and keeps, per patch, whichever of the old and the
-    proposed motion has the higher NCC (the registration refines it next)."""
+    proposed motion has the higher NCC (the registration refines it next).
+    Every build takes the cycle's active set and sample mask."""
     import torch
 
-    maps = {}
-
-    def init_fn(plan, X, y, theta):
+    def init_fn(plan, X, y, theta, active=None, mask=None):
         dev = X.device
-        key = (id(plan), str(dev))
-        if key not in maps:
-            maps.clear()
-            maps[key] = torch.from_numpy(target_maps(plan)[1]).to(dev)
-        Ai = maps[key]
         ysim = torch.empty(plan.N, dtype=torch.float32, device=dev)
-        plan.build(theta)
+        plan.build(theta, active=active, mask=mask)
         plan.simulate(X, y_sim=ysim)
         n_old = torch.empty(plan.M, device=dev)
         plan.ncc_grad(y, ysim, None, n_old)
@@ -316,14 +281,13 @@ def init_fn_factory(net: Net, batch: int = 1024):
             bf = net.buffers(B)
             bf["ids"].copy_(ids_all[b0:b0 + B])
             delta[b0:b0 + B] = net.predict(plan, y, ysim, bf["ids"], B)
-        prop = theta + apply_maps(Ai, delta)
-        plan.build(prop)
+        # proposal = theta + the predicted offset taken back from the patch frame
+        prop = plan.motion_frame(delta, inverse=True, base=theta)
+        plan.build(prop, active=active, mask=mask)
         plan.simulate(X, y_sim=ysim)
         n_new = torch.empty(plan.M, device=dev)
         plan.ncc_grad(y, ysim, None, n_new)
-        take = n_new > n_old
-        theta.copy_(torch.where(take[:, None], prop, theta))
-        plan.build(theta)
-        return float(take.float().mean())
+        plan.motion_accept(prop, n_new, theta, n_old)  # keep the better of the two
+        plan.build(theta, active=active, mask=mask)
 
     return init_fn

@@ -16,6 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpvr.so")
 
+PVR_OK, PVR_EINVAL, PVR_ESHAPE, PVR_ENOMEM, PVR_EHIP, PVR_ENUMERIC, PVR_EUNSUPPORTED = range(7)
 PVR_KERNEL_SIMULATE = 0
 PVR_KERNEL_BACKPROJECT = 1
 PVR_EM_INIT = 1
@@ -26,6 +27,7 @@ PVR_REG_GRAD_FD = 0
 PVR_REG_GRAD_EXACT = 1
 PVR_PSF_GAUSSIAN = 0
 PVR_PSF_SINC = 1
+PVR_WS_F64 = 1
 
 _STATUS = {0: "PVR_OK", 1: "PVR_EINVAL", 2: "PVR_ESHAPE", 3: "PVR_ENOMEM",
            4: "PVR_EHIP", 5: "PVR_ENUMERIC", 6: "PVR_EUNSUPPORTED"}
@@ -57,7 +59,8 @@ class PlanSizes(ctypes.Structure):
     _fields_ = [("n_samples", ctypes.c_int64), ("n_voxels", ctypes.c_int64),
                 ("n_patches", ctypes.c_int32), ("n_problems", ctypes.c_int32),
                 ("n_stacks", ctypes.c_int32), ("n_bricks", ctypes.c_int32),
-                ("n_bin_pairs", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+                ("n_bin_pairs", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("bin_capacity", ctypes.c_int64), ("sub_capacity", ctypes.c_int64)]
 
 
 class EMState(ctypes.Structure):
@@ -91,6 +94,8 @@ class RegParams(ctypes.Structure):
 
 
 EXPORTS = ["pvr_last_error", "pvr_version", "pvr_plan_create", "pvr_plan_destroy",
+           "pvr_plan_workspace_size", "pvr_plan_attach", "pvr_motion_frame", "pvr_motion_step",
+           "pvr_motion_accept", "pvr_motion_init_step", "pvr_motion_fallback",
            "pvr_plan_info", "pvr_plan_offsets", "pvr_plan_build", "pvr_plan_build_f64",
            "pvr_plan_inv_z", "pvr_simulate", "pvr_simulate_f64", "pvr_backproject",
            "pvr_backproject_f64", "pvr_robust_weights", "pvr_sr_update",
@@ -101,7 +106,7 @@ EXPORTS = ["pvr_last_error", "pvr_version", "pvr_plan_create", "pvr_plan_destroy
            "pvr_cnn_wgrad_scratch", "pvr_cnn_conv_wgrad", "pvr_cnn_pack_pairs",
            "pvr_cnn_head_scratch", "pvr_cnn_head", "pvr_cnn_adam",
            "pvr_slic_centres", "pvr_slic_init", "pvr_slic_assign", "pvr_slic_update", "pvr_slic",
-           "pvr_slic_boxes", "pvr_slic_pack", "pvr_check", "pvr_sr_graph_create",
+           "pvr_slic_boxes", "pvr_slic_pack", "pvr_slic_pack_workspace", "pvr_check", "pvr_sr_graph_create",
            "pvr_sr_graph_launch", "pvr_sr_graph_destroy"]
 
 _lib = None
@@ -123,6 +128,14 @@ def load(path: str = LIB_PATH):
     L.pvr_plan_destroy.argtypes = [P]
     L.pvr_plan_destroy.restype = None
     L.pvr_plan_info.argtypes = [P, P]
+    L.pvr_plan_workspace_size.argtypes = [P, i32, P]
+    L.pvr_plan_attach.argtypes = [P, P, ctypes.c_size_t, i32, P]
+    f32_ = ctypes.c_float
+    L.pvr_motion_frame.argtypes = [P, P, i32, P, P, P]
+    L.pvr_motion_step.argtypes = [P, P, P, P, f32_, P, P]
+    L.pvr_motion_accept.argtypes = [P, P, P, P, P, P, f32_, f32_, P, P]
+    L.pvr_motion_init_step.argtypes = [P, P, f32_, ctypes.c_double, P, P]
+    L.pvr_motion_fallback.argtypes = [P, P, f32_, P, P, P, P]
     L.pvr_plan_offsets.argtypes = [P, P, P]
     L.pvr_plan_build.argtypes = [P, P, P, P, P]
     L.pvr_plan_build_f64.argtypes = [P, P, P, P, P]
@@ -161,7 +174,9 @@ def load(path: str = LIB_PATH):
     L.pvr_slic_update.argtypes = [P, i32, i32, i32, i32, P, f32, P, P]
     L.pvr_slic.argtypes = [P, i32, i32, i32, i32, f32, f32, i32, P, P, P, P]
     L.pvr_slic_boxes.argtypes = [P, i32, i32, i32, i32, P, i32, P, P]
-    L.pvr_slic_pack.argtypes = [P, P, i32, i32, i32, i32, i32, P, P, P, P]
+    L.pvr_slic_pack.argtypes = [P, P, i32, i32, i32, i32, i32, P, P, ctypes.c_size_t, P, P, P]
+    L.pvr_slic_pack_workspace.argtypes = [i32]
+    L.pvr_slic_pack_workspace.restype = ctypes.c_size_t
     L.pvr_check.argtypes = [P, P]
     L.pvr_sr_graph_create.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, i32, P, P]
     L.pvr_sr_graph_launch.argtypes = [P, P]
@@ -224,7 +239,9 @@ def make_descriptors(grids: Sequence, stacks_per_problem: Sequence[Sequence],
 class Plan:
     """A plan over one or more independent reconstructions."""
 
-    def __init__(self, grids, stacks_per_problem, patches_per_problem, cutoff_k: float = 3.0):
+    def __init__(self, grids, stacks_per_problem, patches_per_problem, cutoff_k: float = 3.0,
+                 f64: bool = False):
+        """f64: give the workspace room for the FP64 calls (PVR_WS_F64)."""
         L = load()
         self._g, self._s, self._p = make_descriptors(grids, stacks_per_problem,
                                                      patches_per_problem)
@@ -244,16 +261,33 @@ class Plan:
         _check(L.pvr_plan_offsets(self.h, so.ctypes.data, vo.ctypes.data))
         self.sample_off = so
         self.vol_off = vo
+        self.workspace = None
+        self.attach(f64)
+
+    def attach(self, f64: bool = False):
+        """Allocate the plan's device workspace with torch (the library
+        allocates no device memory) and hand it to the plan; the plan then
+        counts as unbuilt."""
+        import torch
+        L = load()
+        flags = PVR_WS_F64 if f64 else 0
+        n = ctypes.c_size_t()
+        _check(L.pvr_plan_workspace_size(self.h, flags, ctypes.byref(n)))
+        ws = torch.empty(max(int(n.value), 256), dtype=torch.uint8, device="cuda")
+        _check(L.pvr_plan_attach(self.h, ws.data_ptr(), ws.numel(), flags, _stream()))
+        self.workspace = ws  # held as long as the plan uses it
+        self.f64 = f64
 
     @classmethod
-    def from_problems(cls, problems, cutoff_k: float = 3.0):
+    def from_problems(cls, problems, cutoff_k: float = 3.0, f64: bool = False):
         return cls([p.grid for p in problems], [p.stacks for p in problems],
-                   [p.patches for p in problems], cutoff_k)
+                   [p.patches for p in problems], cutoff_k, f64)
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
-            load().pvr_plan_destroy(self.h)
+            load().pvr_plan_destroy(self.h)  # synchronises before the workspace goes
             self.h = None
+        self.workspace = None
 
     def __del__(self):
         try:
@@ -324,6 +358,33 @@ class Plan:
         prm = params or RegParams.make()
         _check(load().pvr_register_patches(self.h, _ptr(X), _ptr(y_obs), _ptr(theta), _ptr(ncc),
                                            _ptr(reg), ctypes.byref(prm), _stream()))
+
+    # -- per-patch motion bookkeeping (pvr_motion_*) ---------------------------------
+    def motion_frame(self, v, inverse=False, base=None, out=None):
+        """out = base + A v (or A^-1 v), A = diag(rho F^T, F^T) per patch."""
+        import torch
+        out = torch.empty_like(v) if out is None else out
+        _check(load().pvr_motion_frame(self.h, _ptr(v), 1 if inverse else 0, _ptr(base),
+                                       _ptr(out), _stream()))
+        return out
+
+    def motion_step(self, theta, grad_theta, delta, step_min, trial):
+        _check(load().pvr_motion_step(self.h, _ptr(theta), _ptr(grad_theta), _ptr(delta),
+                                      float(step_min), _ptr(trial), _stream()))
+
+    def motion_accept(self, cand, score_cand, theta, score, delta=None, step0=1.0,
+                      step_min=0.0, n_live=None):
+        _check(load().pvr_motion_accept(self.h, _ptr(cand), _ptr(score_cand), _ptr(theta),
+                                        _ptr(score), _ptr(delta), float(step0), float(step_min),
+                                        _ptr(n_live), _stream()))
+
+    def motion_init_step(self, y_obs, step0, min_std, delta):
+        _check(load().pvr_motion_init_step(self.h, _ptr(y_obs), float(step0), float(min_std),
+                                           _ptr(delta), _stream()))
+
+    def motion_fallback(self, score, tau, theta_ref, theta, flag):
+        _check(load().pvr_motion_fallback(self.h, _ptr(score), float(tau), _ptr(theta_ref),
+                                          _ptr(theta), _ptr(flag), _stream()))
 
     def grad_theta(self, X, grad_y, grad_theta):
         import torch

@@ -91,9 +91,12 @@ def pack(img, lab, gamma: int, table: np.ndarray):
     N = int((tab[:, 4].astype(np.int64) * tab[:, 5]).sum())
     y = torch.empty(max(N, 1), dtype=torch.float32, device=img.device)
     m = torch.empty(max(N, 1), dtype=torch.uint8, device=img.device)
-    pvr._check(pvr.load().pvr_slic_pack(img.data_ptr(), lab.data_ptr(), n, h, w, int(gamma),
-                                        tab.shape[0], tab.ctypes.data, y.data_ptr(),
-                                        m.data_ptr(), pvr._stream()))
+    L = pvr.load()
+    nbytes = int(L.pvr_slic_pack_workspace(tab.shape[0]))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=img.device)
+    pvr._check(L.pvr_slic_pack(img.data_ptr(), lab.data_ptr(), n, h, w, int(gamma),
+                               tab.shape[0], tab.ctypes.data, ws.data_ptr(), nbytes,
+                               y.data_ptr(), m.data_ptr(), pvr._stream()))
     return y[:N], m[:N]
 
 

@@ -70,7 +70,7 @@ def diff():
 def _grad(d, dtype):
     from paper_1611_07289_amd.autograd import simulate
     P = d["P"]
-    plan = pvr.Plan.from_problems([P])
+    plan = pvr.Plan.from_problems([P], f64=dtype == torch.float64)
     X = torch.tensor(np.asarray(P.x_true, np.float64).reshape(-1), dtype=dtype,
                      device="cuda", requires_grad=True)
     th = torch.tensor(d["th"], dtype=dtype, device="cuda", requires_grad=True)

@@ -121,11 +121,10 @@ def _heldout_rel_mse(net, plan, X):
     offsets, relative to the targets' mean square (1 = no better than
     predicting no correction)."""
     dev = X.device
-    A = torch.from_numpy(learned.target_maps(plan)[0]).to(dev)
     ref = torch.from_numpy(synth.random_motion(plan.M, 10, 5, 9001).astype(np.float32)).to(dev)
     off = torch.from_numpy(synth.random_motion(plan.M, 10, 5, 9002).astype(np.float32)).to(dev)
     y_obs, y_sim = learned.make_pairs(plan, X, ref, off, 0.01 * float(X.max()), 9003)
-    tgt = learned.apply_maps(A, off)
+    tgt = plan.motion_frame(off)
     B = 128
     se = torch.zeros(6, device=dev, dtype=torch.float64)
     ms = torch.zeros(6, device=dev, dtype=torch.float64)

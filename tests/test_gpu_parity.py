@@ -376,7 +376,7 @@ def test_exact_registration_gradient_matches_oracle():
 
 def test_f64_path_matches_oracle(tiny):
     P, ctx = tiny["P"], tiny["ctx"]
-    plan = pvr.Plan.from_problems([P])
+    plan = pvr.Plan.from_problems([P], f64=True)
     th = dev(P.theta_true, torch.float64)
     plan.build(th)
     X = dev(P.x_true.astype(np.float64))

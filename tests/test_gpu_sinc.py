@@ -91,7 +91,7 @@ def test_sinc_ten_sr_iterations_match_oracle(sinc):
 
 def test_sinc_f64_path_matches_oracle(sinc):
     P, ctx = sinc["P"], sinc["ctx"]
-    plan = pvr.Plan.from_problems([P])
+    plan = pvr.Plan.from_problems([P], f64=True)
     plan.set_psf(pvr.PVR_PSF_SINC)
     plan.build(dev(P.theta_true, torch.float64))
     ys = torch.empty(plan.N, dtype=torch.float64, device="cuda")

@@ -30,16 +30,30 @@ def test_invalid_arguments_rejected_on_host():
     assert L.pvr_slic_update(fake, 1, 8, 8, 4, None, 0.0, fake, None) == 1
     assert L.pvr_slic(fake, 1, 8, 8, 4, 1.0, 1.0, -1, fake, fake, fake, None) == 1
     assert L.pvr_slic_boxes(fake, 1, 8, 8, 4, fake, -1, fake, None) == 1
+    big = 1 << 20  # workspace bytes claimed by the fake pointer
     tab = np.array([[0, 0, 4, 4, 5, 4]], np.int32)  # x0 + w = 9 > 8
-    st = L.pvr_slic_pack(fake, fake, 1, 8, 8, 2, 1, tab.ctypes.data, fake, fake, None)
+    st = L.pvr_slic_pack(fake, fake, 1, 8, 8, 2, 1, tab.ctypes.data, fake, big, fake, fake, None)
     assert st == 2 and "leaves its image" in L.pvr_last_error().decode()
     tab = np.array([[1, 0, 0, 0, 4, 4]], np.int32)  # image 1 of 1
-    assert L.pvr_slic_pack(fake, fake, 1, 8, 8, 2, 1, tab.ctypes.data, fake, fake, None) == 2
+    assert L.pvr_slic_pack(fake, fake, 1, 8, 8, 2, 1, tab.ctypes.data, fake, big, fake, fake,
+                           None) == 2
     tab = np.array([[0, 0, 0, 0, 300, 300]], np.int32)  # 90 000 pixels
-    st = L.pvr_slic_pack(fake, fake, 1, 512, 512, 2, 1, tab.ctypes.data, fake, fake, None)
+    st = L.pvr_slic_pack(fake, fake, 1, 512, 512, 2, 1, tab.ctypes.data, fake, big, fake, fake,
+                         None)
     assert st == 2 and "at most 65536" in L.pvr_last_error().decode()
-    assert L.pvr_slic_pack(fake, fake, 1, 8, 8, -1, 1, tab.ctypes.data, fake, fake, None) == 1
-    assert L.pvr_slic_pack(fake, fake, 1, 8, 8, 1, 0, tab.ctypes.data, None, None, None) == 0
+    assert L.pvr_slic_pack(fake, fake, 1, 8, 8, -1, 1, tab.ctypes.data, fake, big, fake, fake,
+                           None) == 1
+    assert L.pvr_slic_pack(fake, fake, 1, 8, 8, 1, 0, tab.ctypes.data, None, 0, None, None,
+                           None) == 0
+    # the staged descriptor table needs its workspace
+    tab = np.array([[0, 0, 0, 0, 4, 4]] * 3, np.int32)
+    need = L.pvr_slic_pack_workspace(3)
+    assert need >= 3 * 28 and L.pvr_slic_pack_workspace(0) == 0
+    st = L.pvr_slic_pack(fake, fake, 1, 8, 8, 1, 3, tab.ctypes.data, fake, need - 1, fake, fake,
+                         None)
+    assert st == 2 and "workspace" in L.pvr_last_error().decode()
+    assert L.pvr_slic_pack(fake, fake, 1, 8, 8, 1, 3, tab.ctypes.data, None, need, fake, fake,
+                           None) == 1
 
 
 def test_pack_table_follows_the_oracle_patch_order():
