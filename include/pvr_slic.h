@@ -93,6 +93,22 @@ pvr_status pvr_slic_pack(const float *img, const int32_t *labels, int32_t n_img,
                          void *workspace, size_t workspace_bytes, float *y, uint8_t *mask,
                          hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * pvr_slic_pack without a workspace.  The descriptor table goes to a
+ * library-resident device array of PVR_SLIC_PACK_NOALLOC_MAX entries (2 MiB,
+ * held by every device the library runs on until the process ends); more
+ * patches give PVR_ESHAPE.  No device memory is allocated or freed.  Same
+ * arguments, output and errors as pvr_slic_pack otherwise; synchronises
+ * `stream` before returning, so calls made one after another may use any
+ * streams, but calls that overlap in time on one device (other threads)
+ * share the array and race. */
+#define PVR_SLIC_PACK_NOALLOC_MAX 65536
+pvr_status pvr_slic_pack_noalloc(const float *img, const int32_t *labels, int32_t n_img,
+                                 int32_t h, int32_t w, int32_t gamma, int32_t M,
+                                 const int32_t *table, float *y, uint8_t *mask,
+                                 hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

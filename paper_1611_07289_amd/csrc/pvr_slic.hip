@@ -15,6 +15,7 @@
 #include "pvr_util.h"
 
 #include <algorithm>
+#include <mutex>
 
 using namespace pvr;
 
@@ -257,19 +258,19 @@ extern "C" pvr_status pvr_slic_init(const float *img, int32_t n_img, int32_t h, 
 }
 
 extern "C" pvr_status pvr_slic_assign(const float *img, int32_t n_img, int32_t h, int32_t w,
-                                      int32_t a, const float *centres, uint64_t *scratch,
+                                      int32_t a, const float *centres, uint64_t *ws,
                                       int32_t *labels, hipStream_t stream) {
   PVR_API_BEGIN();
   PVR_ALIGNED("pvr_slic_assign", img, 4);
   PVR_ALIGNED("pvr_slic_assign", centres, 16);
-  PVR_ALIGNED("pvr_slic_assign", scratch, 8);
+  PVR_ALIGNED("pvr_slic_assign", ws, 8);
   PVR_ALIGNED("pvr_slic_assign", labels, 4);
-  if (!img || !centres || !scratch || !labels) return fail(PVR_EINVAL, "pvr_slic_assign: NULL argument");
+  if (!img || !centres || !ws || !labels) return fail(PVR_EINVAL, "pvr_slic_assign: NULL argument");
   if (a <= 0 || a > (1 << 20)) return fail(PVR_EINVAL, "pvr_slic_assign: a must be in [1, 2^20]");
   pvr_status st = check_sizes("pvr_slic_assign", n_img, h, w, a);
   if (st != PVR_OK) return st;
   const int kx = (w + a - 1) / a, ky = (h + a - 1) / a, K = kx * ky;
-  float *drift = (float *)scratch;  // n_img floats
+  float *drift = (float *)ws;  // n_img floats
   hipLaunchKernelGGL(k_slic_drift, dim3(n_img), dim3(SLIC_T), 0, stream, centres, h, w, a, kx, K,
                      drift);
   const long long tiles = (long long)((w + TILE_X - 1) / TILE_X) * ((h + TILE_Y - 1) / TILE_Y);
@@ -300,20 +301,20 @@ extern "C" pvr_status pvr_slic_update(const float *img, int32_t n_img, int32_t h
 }
 
 extern "C" pvr_status pvr_slic(const float *img, int32_t n_img, int32_t h, int32_t w, int32_t a,
-                               float t0, float t_min, int32_t iters, uint64_t *scratch,
+                               float t0, float t_min, int32_t iters, uint64_t *ws,
                                float *centres, int32_t *labels, hipStream_t stream) {
   PVR_API_BEGIN();
   PVR_ALIGNED("pvr_slic", img, 4);
   PVR_ALIGNED("pvr_slic", centres, 16);
-  PVR_ALIGNED("pvr_slic", scratch, 8);
+  PVR_ALIGNED("pvr_slic", ws, 8);
   PVR_ALIGNED("pvr_slic", labels, 4);
   if (iters < 0) return fail(PVR_EINVAL, "pvr_slic: iters < 0");
   pvr_status st = pvr_slic_init(img, n_img, h, w, a, t0, centres, stream);
   for (int it = 0; st == PVR_OK && it < iters; ++it) {
-    st = pvr_slic_assign(img, n_img, h, w, a, centres, scratch, labels, stream);
+    st = pvr_slic_assign(img, n_img, h, w, a, centres, ws, labels, stream);
     if (st == PVR_OK) st = pvr_slic_update(img, n_img, h, w, a, labels, t_min, centres, stream);
   }
-  if (st == PVR_OK) st = pvr_slic_assign(img, n_img, h, w, a, centres, scratch, labels, stream);
+  if (st == PVR_OK) st = pvr_slic_assign(img, n_img, h, w, a, centres, ws, labels, stream);
   return st;
   PVR_API_END();
 }
@@ -514,5 +515,67 @@ extern "C" pvr_status pvr_slic_pack(const float *img, const int32_t *labels, int
   if (st != PVR_OK) return st;
   return pack_launch(img, labels, h, w, gamma, M, table, most, (PackDesc *)workspace, y, mask,
                      stream);
+  PVR_API_END();
+}
+
+// ---------------------------------------------------------------------------
+// pvr_slic_pack_noalloc: the same packing for callers that cannot allocate
+// device memory.  The descriptor table lives in `scratch`, a file-scope
+// device array of PVR_SLIC_PACK_NOALLOC_MAX entries; every device holds its
+// own copy, whose address is looked up once per device.  In host code the
+// array's name is only a host-side stand-in: the kernels receive the looked
+// up device address.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) PackDesc scratch[PVR_SLIC_PACK_NOALLOC_MAX];
+
+namespace {
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+PackDesc *g_scratch_ptr[SCRATCH_DEVICES];  // device address of `scratch` per device
+}  // namespace
+
+static pvr_status scratch_on_current_device(PackDesc **out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SCRATCH_DEVICES)
+    return fail(PVR_EUNSUPPORTED, "pvr_slic_pack_noalloc: device %d beyond %d", dev, SCRATCH_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(PVR_EHIP, "pvr_slic_pack_noalloc: no device address for the table");
+    g_scratch_ptr[dev] = (PackDesc *)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return PVR_OK;
+}
+
+extern "C" pvr_status pvr_slic_pack_noalloc(const float *img, const int32_t *labels,
+                                            int32_t n_img, int32_t h, int32_t w, int32_t gamma,
+                                            int32_t M, const int32_t *table, float *y,
+                                            uint8_t *mask, hipStream_t stream) {
+  PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_slic_pack_noalloc", img, 4);
+  PVR_ALIGNED("pvr_slic_pack_noalloc", labels, 4);
+  PVR_ALIGNED("pvr_slic_pack_noalloc", y, 4);
+  if (!img || !labels || !table || (M > 0 && (!y || !mask)))
+    return fail(PVR_EINVAL, "pvr_slic_pack_noalloc: NULL argument");
+  if (gamma < 0 || M < 0) return fail(PVR_EINVAL, "pvr_slic_pack_noalloc: gamma < 0 or M < 0");
+  if (M > PVR_SLIC_PACK_NOALLOC_MAX)
+    return fail(PVR_ESHAPE, "pvr_slic_pack_noalloc: %d patches, at most %d", M,
+                PVR_SLIC_PACK_NOALLOC_MAX);
+  pvr_status st = check_sizes("pvr_slic_pack_noalloc", n_img, h, w, 0);
+  if (st != PVR_OK) return st;
+  if (M == 0) return PVR_OK;
+  int most = 0;
+  st = pack_check("pvr_slic_pack_noalloc", n_img, h, w, M, table, &most);
+  if (st != PVR_OK) return st;
+  PackDesc *tab = nullptr;
+  st = scratch_on_current_device(&tab);
+  if (st != PVR_OK) return st;
+  st = pack_launch(img, labels, h, w, gamma, M, table, most, tab, y, mask, stream);
+  if (st != PVR_OK) return st;
+  HIP_TRY(hipStreamSynchronize(stream));  // the device's table is free again on return
+  return PVR_OK;
   PVR_API_END();
 }

@@ -28,6 +28,7 @@ PVR_REG_GRAD_EXACT = 1
 PVR_PSF_GAUSSIAN = 0
 PVR_PSF_SINC = 1
 PVR_WS_F64 = 1
+PVR_SLIC_PACK_NOALLOC_MAX = 65536
 
 _STATUS = {0: "PVR_OK", 1: "PVR_EINVAL", 2: "PVR_ESHAPE", 3: "PVR_ENOMEM",
            4: "PVR_EHIP", 5: "PVR_ENUMERIC", 6: "PVR_EUNSUPPORTED"}
@@ -106,7 +107,8 @@ EXPORTS = ["pvr_last_error", "pvr_version", "pvr_plan_create", "pvr_plan_destroy
            "pvr_cnn_wgrad_scratch", "pvr_cnn_conv_wgrad", "pvr_cnn_pack_pairs",
            "pvr_cnn_head_scratch", "pvr_cnn_head", "pvr_cnn_adam",
            "pvr_slic_centres", "pvr_slic_init", "pvr_slic_assign", "pvr_slic_update", "pvr_slic",
-           "pvr_slic_boxes", "pvr_slic_pack", "pvr_slic_pack_workspace", "pvr_check", "pvr_sr_graph_create",
+           "pvr_slic_boxes", "pvr_slic_pack", "pvr_slic_pack_workspace", "pvr_slic_pack_noalloc",
+           "pvr_check", "pvr_sr_graph_create",
            "pvr_sr_graph_launch", "pvr_sr_graph_destroy"]
 
 _lib = None
@@ -175,6 +177,7 @@ def load(path: str = LIB_PATH):
     L.pvr_slic.argtypes = [P, i32, i32, i32, i32, f32, f32, i32, P, P, P, P]
     L.pvr_slic_boxes.argtypes = [P, i32, i32, i32, i32, P, i32, P, P]
     L.pvr_slic_pack.argtypes = [P, P, i32, i32, i32, i32, i32, P, P, ctypes.c_size_t, P, P, P]
+    L.pvr_slic_pack_noalloc.argtypes = [P, P, i32, i32, i32, i32, i32, P, P, P, P]
     L.pvr_slic_pack_workspace.argtypes = [i32]
     L.pvr_slic_pack_workspace.restype = ctypes.c_size_t
     L.pvr_check.argtypes = [P, P]

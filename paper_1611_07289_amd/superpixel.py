@@ -81,9 +81,11 @@ def boxes(lab, C, a: int, gamma: int):
     return B
 
 
-def pack(img, lab, gamma: int, table: np.ndarray):
+def pack(img, lab, gamma: int, table: np.ndarray, noalloc: bool = False):
     """(y float32 [N], mask uint8 [N]) of the patches table int32 [M][6] =
-    (image, label, x0, y0, w, h), patch after patch, row-major inside each."""
+    (image, label, x0, y0, w, h), patch after patch, row-major inside each.
+    noalloc: use pvr_slic_pack_noalloc (no workspace; at most
+    PVR_SLIC_PACK_NOALLOC_MAX patches)."""
     import torch
     img = _img(img)
     n, h, w = img.shape
@@ -92,6 +94,11 @@ def pack(img, lab, gamma: int, table: np.ndarray):
     y = torch.empty(max(N, 1), dtype=torch.float32, device=img.device)
     m = torch.empty(max(N, 1), dtype=torch.uint8, device=img.device)
     L = pvr.load()
+    if noalloc:
+        pvr._check(L.pvr_slic_pack_noalloc(img.data_ptr(), lab.data_ptr(), n, h, w, int(gamma),
+                                           tab.shape[0], tab.ctypes.data, y.data_ptr(),
+                                           m.data_ptr(), pvr._stream()))
+        return y[:N], m[:N]
     nbytes = int(L.pvr_slic_pack_workspace(tab.shape[0]))
     ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=img.device)
     pvr._check(L.pvr_slic_pack(img.data_ptr(), lab.data_ptr(), n, h, w, int(gamma),
