@@ -164,17 +164,15 @@ def hbm_equivalent(nnz, nnz_adj, n_valid, V, ms_step):
     return {"bytes_per_iteration": b, "floor_ms": floor_ms, "frac": floor_ms / ms_step}
 
 
-def cpu_baseline(P, n_patch_sample: int = 192):
-    """FP64 oracle on a bounded sample of the same workload: one SR
-    iteration restricted to n_patch_sample patches (simulate, EM, two
-    back-projections) plus the update of the full volume, extrapolated to all
-    patches.  Value in patch-samples/s."""
+def _oracle_sample(P, n_patch_sample: int, seed: int):
+    """Seconds of one FP64 SR iteration restricted to n_patch_sample patches
+    (simulate, EM, two back-projections) and of the full-volume update, and
+    the valid samples of the sample."""
     import oracle
-    from oracle import em as oem
     from oracle import recon
     from oracle.update import sr_update
     from paper_1611_07289_amd import synth
-    rng = np.random.default_rng(7)
+    rng = np.random.default_rng(seed)
     sel = np.sort(rng.choice(P.M, size=min(n_patch_sample, P.M), replace=False))
     tab = P.patches.table()[sel]
     sub = synth.Patches(*[tab[:, i].copy() for i in range(6)])
@@ -194,21 +192,45 @@ def cpu_baseline(P, n_patch_sample: int = 192):
     t1 = time.perf_counter()
     sr_update(X, num, den)
     t_volume = time.perf_counter() - t1
-    n_sub = int(val.sum())
-    frac = P.M / len(sel)
-    t_full = t_samples * frac + t_volume
-    n_valid_full = n_sub * frac
-    return {
-        "value": n_valid_full / t_full,
+    return len(sel), int(val.sum()), t_samples, t_volume
+
+
+def cpu_baseline(P, n_patch_sample: int = 1024, n_patch_single: int = 32):
+    """FP64 oracle on a bounded sample of the same workload: one SR
+    iteration restricted to n_patch_sample patches (simulate, EM, two
+    back-projections) plus the update of the full volume, extrapolated to all
+    patches, on all the host threads the oracle uses; and the same on one
+    thread over n_patch_single patches.  Value in patch-samples/s."""
+    import oracle
+    cores = oracle.num_threads()
+    n_sel, n_sub, t_s, t_v = _oracle_sample(P, n_patch_sample, 7)
+    frac = P.M / n_sel
+    t_full = t_s * frac + t_v
+    out = {
+        "value": n_sub * frac / t_full,
         "unit": "patch-samples/s",
-        "cores": oracle.num_threads(),
+        "cores": cores,
         "kind": "oracle",
-        "sample": (f"one FP64 SR iteration over {len(sel)} of {P.M} patches "
+        "sample": (f"one FP64 SR iteration over {n_sel} of {P.M} patches "
                    f"({n_sub} valid samples; simulate, EM, 2 back-projections: "
-                   f"{t_samples:.1f} s) plus the full-volume update ({t_volume:.1f} s), "
-                   f"sample part extrapolated x{frac:.1f}"),
-        "seconds_measured": t_samples + t_volume,
+                   f"{t_s:.1f} s) plus the full-volume update ({t_v:.1f} s) on {cores} "
+                   f"threads, sample part extrapolated x{frac:.1f}"),
+        "seconds_measured": t_s + t_v,
+        "full_iteration_s_estimate": t_full,
     }
+    oracle.set_num_threads(1)
+    try:
+        n1, s1, t1s, t1v = _oracle_sample(P, n_patch_single, 8)
+    finally:
+        oracle.set_num_threads(cores)
+    f1 = P.M / n1
+    out["single_core"] = {
+        "value": s1 * f1 / (t1s * f1 + t1v), "cores": 1,
+        "sample": (f"the same over {n1} patches ({s1} valid samples: {t1s:.1f} s) plus the "
+                   f"full-volume update ({t1v:.1f} s) on one thread, extrapolated x{f1:.1f}"),
+        "seconds_measured": t1s + t1v,
+    }
+    return out
 
 
 def main():
@@ -268,8 +290,7 @@ def main():
     plan.build(theta)
     torch.cuda.synchronize()
     t_build = time.perf_counter() - tb
-    info = plan.info()
-    log(f"[bench] build {t_build * 1e3:.1f} ms, brick/patch pairs {info.n_bin_pairs}")
+    log(f"[bench] build (geometry, normalisers) {t_build * 1e3:.1f} ms")
 
     # observations: the forward model at the true motion, then noise and
     # outlier patches drawn by the generator
@@ -301,7 +322,20 @@ def main():
     # initial volume X0 = A^T y / A^T 1 (the update with X = 0, lambda = 0)
     X = torch.zeros(plan.V, dtype=torch.float32, device=dev)
     Xn = torch.empty_like(X)
+    # (the first back-projection after the build also builds the adjoint's
+    # brick index: its extra time over a second, identical call is reported)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
     plan.backproject(y, None, None, num, den)
+    torch.cuda.synchronize()
+    t_bp_first = time.perf_counter() - tb
+    tb = time.perf_counter()
+    plan.backproject(y, None, None, num, den)
+    torch.cuda.synchronize()
+    t_index = max(t_bp_first - (time.perf_counter() - tb), 0.0)
+    info = plan.info()
+    log(f"[bench] adjoint index: {t_index * 1e3:.2f} ms, sub-brick/patch pairs {info.n_bin_pairs} "
+        f"(capacity {info.sub_capacity})")
     plan.sr_update(X, num, den, Xn, pvr.SRParams.make(lam=0.0, use_clamp=False))
     X, Xn = Xn, X
     prm = pvr.SRParams.make()
@@ -404,6 +438,9 @@ def main():
         "kernels_ms": per,
         "hot_kernels_ms": kern,
         "build_ms": t_build * 1e3,
+        "index_build_ms": t_index * 1e3,
+        "index_pairs": {"sub_brick_patch": int(info.n_bin_pairs),
+                        "capacity": int(info.sub_capacity)},
         "roofline": roofline,
         "hbm_equivalent": hbm_equivalent(nnz, nnz_adj, n_valid, plan.V, ms_step),  # same bytes per nonzero
         "em": {"sigma2": st[0].sigma2, "c": st[0].c, "excluded": st[0].n_excluded},
@@ -664,31 +701,98 @@ def plan_patch_begin(plan, probs, b):
     return int(sum(P.M for P in probs[:b]))
 
 
-def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10, learned_pairs=0, exact=True):
+# Algorithmic FP32 work of a registration evaluation per PSF nonzero of a
+# walked sample: plain NCC evaluation as the forward walk (16); exact
+# gradient: the forward walk plus the accumulation of the weight's nine
+# offset moments of e^-Q/2 (X - X_b) and of e^-Q/2 (8 more: the two products
+# em (X - X_b) and em wc, and six sums); per walked sample the NCC sums
+# (plain 10; exact 10 + the six derivatives from the moments and their
+# three sums each, 100).
+FLOP_PER_NNZ_REG = 16
+FLOP_PER_NNZ_REG_EXACT = 24
+FLOP_PER_SAMPLE_REG = 10
+FLOP_PER_SAMPLE_REG_EXACT = 100
+
+
+def register_roofline(stats, reg_ms, nnz_per_sample):
+    """Algorithmic FP32 rate of the registration kernel over a run: the
+    samples its NCC evaluations walked (counted by the kernel) times the work
+    per walked sample, over the summed duration of its launches."""
+    flop = (stats["samples"] * (nnz_per_sample * FLOP_PER_NNZ_REG + FLOP_PER_SAMPLE_REG)
+            + stats["samples_exact"] * (nnz_per_sample * FLOP_PER_NNZ_REG_EXACT
+                                        + FLOP_PER_SAMPLE_REG_EXACT))
+    ach = flop / max(reg_ms * 1e-3, 1e-12) / 1e12
+    return {"bound": "alu", "kernel": "k_register", "achieved": ach,
+            "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP32_VALU_PEAK_TFLOPS,
+            "kernel_ms": reg_ms, "work": stats, "nnz_per_sample": nnz_per_sample}
+
+
+def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10, learned_pairs=0, exact=True,
+             tight=(0.25, 5), fallback_tau=0.3):
     """Seconds and PSNR of a whole reconstruction from the motion-corrupted
-    start (zero motion): plain registration, and with learned_pairs > 0 also
-    the learned initialiser (trained first, on a phantom of another seed)."""
+    start (zero motion), each with its registration kernel's time, work and
+    roofline: plain registration with the full budget (step0 1, 40 trial
+    steps) and with a tight one (step0 and trial steps of `tight`,
+    "_tight"), the control of the learned runs; with learned_pairs > 0 the
+    learned initialiser (trained first, on a phantom of another seed) whose
+    prediction the tight budget refines, except where the patch's NCC after
+    the prediction stays below fallback_tau: there plain registration takes
+    over with the full budget from the motion before the prediction; and
+    (exact only) the
+    joint gradient-based registration through the differentiable forward
+    model (driver.register_gradient) in place of the per-patch one."""
     import torch
     from paper_1611_07289_amd import driver, learned, pvr, synth
     res = {}
     ymax = float(y.abs().max())
+    nnz_ps = nnz_estimate(probs, 1)
 
-    def run(key, rp, init_fn=None):
+    def run(key, rp, init_fn=None, register_fn=None):
         th0 = torch.zeros(plan.M, 6, dtype=torch.float32, device=dev)
+        plan.set_timing(True)
+        plan.kernel_time(pvr.PVR_KERNEL_REGISTER)
+        plan.reg_stats()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        X, th, hist = driver.reconstruct(plan, y, th0, cycles=cycles, n_sr=n_sr, reg_params=rp,
-                                         init_fn=init_fn)
+        X, th, hist = driver.reconstruct(
+            plan, y, th0, cycles=cycles, n_sr=n_sr, reg_params=rp, init_fn=init_fn,
+            fallback_tau=fallback_tau if init_fn is not None else None,
+            fallback_params=pvr.RegParams.make(min_std=0.01 * ymax, exact=rp.gradient == 1),
+            register_fn=register_fn)
         torch.cuda.synchronize()
-        res[key] = {"seconds": time.perf_counter() - t0, "psnr_db": driver.psnr(X, Xtrue, plan),
-                    "timings": hist["timings"], "mean_ncc": hist["ncc"]}
-        log(f"full PVR {key}: {res[key]['seconds']:.3f} s, PSNR {res[key]['psnr_db']:.2f} dB")
+        sec = time.perf_counter() - t0
+        reg_ms, n_reg = plan.kernel_time(pvr.PVR_KERNEL_REGISTER)
+        stats = plan.reg_stats()
+        plan.set_timing(False)
+        for kid in (pvr.PVR_KERNEL_SIMULATE, pvr.PVR_KERNEL_BACKPROJECT):
+            plan.kernel_time(kid)
+        res[key] = {"seconds": sec, "psnr_db": driver.psnr(X, Xtrue, plan),
+                    "timings": hist["timings"], "mean_ncc": hist["ncc"],
+                    "register_launches": n_reg}
+        if init_fn is not None:
+            res[key]["fallback_patches"] = hist["fallback"]
+        if register_fn is None:
+            res[key]["register_roofline"] = register_roofline(stats, reg_ms, nnz_ps)
+        log(f"full PVR {key}: {sec:.3f} s, PSNR {res[key]['psnr_db']:.2f} dB"
+            + (f", registration kernel {reg_ms:.1f} ms "
+               f"({res[key]['register_roofline']['frac']:.3f} of the FP32 ALU peak)"
+               if register_fn is None else "")
+            + (f", fallback {hist['fallback']}" if init_fn is not None else ""))
 
-    # plain registration: central-difference gradient (12 NCC evaluations per
-    # gradient), then the exact gradient (one evaluation)
-    run("plain", pvr.RegParams.make(min_std=0.01 * ymax))
+    full = dict(min_std=0.01 * ymax)
+    short = dict(step0=tight[0], max_iter=tight[1], min_std=0.01 * ymax)
+    # central-difference gradient (12 NCC evaluations per gradient), then the
+    # exact gradient (one evaluation)
+    run("plain", pvr.RegParams.make(**full))
+    run("plain_tight", pvr.RegParams.make(**short))
     if exact:
-        run("plain_exact", pvr.RegParams.make(min_std=0.01 * ymax, exact=True))
+        run("plain_exact", pvr.RegParams.make(**full, exact=True))
+        run("plain_tight_exact", pvr.RegParams.make(**short, exact=True))
+
+        def joint(pl, X, yy, th, ncc, act, mask):
+            ncc.copy_(driver.register_gradient(pl, X, yy, th, iters=30, min_std=0.01 * ymax,
+                                               active=act, mask=mask))
+        run("joint_gradient", pvr.RegParams.make(**full), register_fn=joint)
     if learned_pairs > 0 and exact:
         P = probs[0]
         Xtr = torch.from_numpy(synth.phantom_uterus(P.grid.nx, 7700, 7701).reshape(-1)).to(dev)
@@ -697,16 +801,23 @@ def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10, learned_pairs=0, exa
                            seed=7800, log=log)
         del Xtr
         init_fn = learned.init_fn_factory(net)
-        run("learned", pvr.RegParams.make(step0=0.5, min_std=0.01 * ymax, max_iter=20), init_fn)
-        run("learned_exact", pvr.RegParams.make(step0=0.5, min_std=0.01 * ymax, max_iter=20,
-                                                exact=True), init_fn)
+        run("learned", pvr.RegParams.make(**short), init_fn)
+        run("learned_exact", pvr.RegParams.make(**short, exact=True), init_fn)
         res["training"] = {"pairs": tr["pairs"], "seconds": tr["seconds"],
                            "data_seconds": tr["data_seconds"],
                            "loss_first_last": [tr["loss"][0][1], tr["loss"][-1][1]]
                            if tr["loss"] else None}
         for sfx in ("", "_exact"):
-            res["delta_psnr_db" + sfx] = res["learned" + sfx]["psnr_db"] - res["plain" + sfx]["psnr_db"]
-            res["speedup" + sfx] = res["plain" + sfx]["seconds"] / res["learned" + sfx]["seconds"]
+            lr_, pl_, pt_ = res["learned" + sfx], res["plain" + sfx], res["plain_tight" + sfx]
+            res["learned_vs_plain" + sfx] = {
+                "delta_psnr_db": lr_["psnr_db"] - pl_["psnr_db"],
+                "speedup": pl_["seconds"] / lr_["seconds"]}
+            res["learned_vs_plain_tight" + sfx] = {
+                "delta_psnr_db": lr_["psnr_db"] - pt_["psnr_db"],
+                "speedup": pt_["seconds"] / lr_["seconds"]}
+    res["budgets"] = {"full": {"step0": 1.0, "max_iter": 40},
+                      "tight": {"step0": tight[0], "max_iter": tight[1]}}
+    res["fallback_tau"] = fallback_tau
     res["cycles"] = cycles
     res["sr_iterations"] = n_sr
     res["paper_runtime_s"] = "2000-4000 (whole PVR, unspecified NVIDIA GPU machines; Sec. V)"

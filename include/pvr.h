@@ -301,6 +301,8 @@ pvr_status pvr_plan_set_tiles(pvr_plan *plan, int32_t tile_w, int32_t tile_h,
 /* Kernel timing, a profiling aid.  With on != 0 the plan records a HIP
  * event pair on the launch stream around every launch of the kernel named by
  * `kernel` (PVR_KERNEL_SIMULATE: the forward kernel of pvr_simulate;
+ * PVR_KERNEL_REGISTER: the registration of pvr_register_patches, both
+ * volume layouts and the volume copy between them;
  * PVR_KERNEL_BACKPROJECT: the gather kernel of pvr_backproject, without its
  * operand preparation), up to 256 launches per kernel between reads.
  * pvr_plan_kernel_time synchronises on the recorded events and returns the
@@ -309,9 +311,18 @@ pvr_status pvr_plan_set_tiles(pvr_plan *plan, int32_t tile_w, int32_t tile_h,
  * graph.  Enabling creates the events (host call); disabling keeps them. */
 #define PVR_KERNEL_SIMULATE 0
 #define PVR_KERNEL_BACKPROJECT 1
+#define PVR_KERNEL_REGISTER 2
 pvr_status pvr_plan_set_timing(pvr_plan *plan, int32_t on);
 pvr_status pvr_plan_kernel_time(pvr_plan *plan, int32_t kernel, double *total_ms,
                                 int32_t *launches);
+
+/* Work of the registrations since the previous read (a profiling aid, Sec.
+ * II "Patch to Volume Registration"): out[0] NCC evaluations and out[1]
+ * valid samples they walked (plain evaluations: the gradient by central
+ * differences and every trial step), out[2] and out[3] the same for
+ * evaluations with the exact gradient.  Synchronises `stream`, then starts
+ * a new count. */
+pvr_status pvr_plan_reg_stats(pvr_plan *plan, int64_t out[4], hipStream_t stream);
 
 /* (device) inverse normalisers 1/Z_j of the last build, [N] float
  * (0 for invalid samples).  The pointer stays valid until the next build. */
@@ -442,9 +453,12 @@ pvr_status pvr_ncc_grad(const pvr_plan *plan, const float *y_obs,
  *   (those the last build's mask keeps) have a population standard
  *   deviation >= min_std, else 0 (flat patches keep their motion).  Needs a
  *   built plan.
- * pvr_motion_fallback: where score_s < tau: theta_s = theta_ref_s and
- *   flag_s = 1, else flag_s = 0 (uint8 [M]) -- the patches to register
- *   again from their reference motion. */
+ * pvr_motion_fallback: the threshold is tau, or score_ref_s + tau when
+ *   score_ref is given (nullable); for the patches with active_s != 0
+ *   (active nullable = all) and score_s below their threshold: theta_s =
+ *   theta_ref_s and flag_s = 1 -- the patches a plain registration takes
+ *   over from their reference motion; every other patch gets flag_s = 0 and
+ *   keep_s = 1 if active (keep nullable; flag and keep uint8 [M]). */
 pvr_status pvr_motion_frame(const pvr_plan *plan, const float *in, int32_t inverse,
                             const float *base, float *out, hipStream_t stream);
 pvr_status pvr_motion_step(const pvr_plan *plan, const float *theta, const float *grad_theta,
@@ -455,7 +469,8 @@ pvr_status pvr_motion_accept(const pvr_plan *plan, const float *cand, const floa
 pvr_status pvr_motion_init_step(const pvr_plan *plan, const float *y_obs, float step0,
                                 double min_std, float *delta, hipStream_t stream);
 pvr_status pvr_motion_fallback(const pvr_plan *plan, const float *score, float tau,
-                               const float *theta_ref, float *theta, uint8_t *flag,
+                               const float *score_ref, const float *theta_ref, float *theta,
+                               const uint8_t *active, uint8_t *flag, uint8_t *keep,
                                hipStream_t stream);
 
 /* Numeric faults.  The SR update raises PVR_FAULT_VOLUME when a voxel of the

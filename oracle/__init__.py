@@ -76,6 +76,8 @@ def lib():
         L.ora_ncc_patch.restype = ctypes.c_double
         L.ora_ncc_patch.argtypes = [P, ctypes.c_int, P, P, P, P]
         L.ora_num_threads.restype = ctypes.c_int
+        L.ora_set_num_threads.argtypes = [ctypes.c_int]
+        L.ora_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -107,6 +109,11 @@ def sinc_taylor(R: float) -> float:
 
 def num_threads() -> int:
     return int(lib().ora_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the following oracle calls."""
+    lib().ora_set_num_threads(int(n))
 
 
 class Ctx:

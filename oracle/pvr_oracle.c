@@ -863,3 +863,12 @@ int ora_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Threads of the following calls (n >= 1); a timing aid. */
+void ora_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}

@@ -329,6 +329,10 @@ struct RegShared {
   double grad[6];
   double sc[6];
   double fval;      // result of the last evaluation
+  // work done, for the kernel's roofline: evaluations and samples walked
+  // (plain, exact gradient); written by lane 0 only
+  double walked[2];
+  int evals[2];
 };
 
 // NCC of the patch against its simulation at sh.th (valid samples only);
@@ -375,6 +379,10 @@ __device__ double reg_eval(RegShared &sh, const ProbDev &pr, const StackDev &st,
   }
   block_sum<6>(acc6, sh.red);
   const double cnt = acc6[0];
+  if (threadIdx.x == 0) {
+    sh.walked[0] += cnt;
+    sh.evals[0] += 1;
+  }
   if (!(cnt > 0)) return 0.0;
   const double my = acc6[1] / cnt, mh = acc6[3] / cnt;
   const double vy = acc6[2] / cnt - my * my, vh = acc6[4] / cnt - mh * mh;
@@ -461,6 +469,10 @@ __device__ double reg_eval_exact(RegShared &sh, const ProbDev &pr, const StackDe
 #pragma unroll
   for (int c = 0; c < 6; ++c) gth[c] = 0.0;
   const double cnt = acc[0];
+  if (threadIdx.x == 0) {
+    sh.walked[1] += cnt;
+    sh.evals[1] += 1;
+  }
   if (!(cnt > 0)) return 0.0;
   const double my = acc[1] / cnt, mh = acc[3] / cnt;
   const double vy = acc[2] / cnt - my * my, vh = acc[4] / cnt - mh * mh;
@@ -485,7 +497,7 @@ __device__ __forceinline__ void register_patch(
     const PatchDev *__restrict__ patches, const float *__restrict__ Xv,
     const float *__restrict__ y, const uint8_t *__restrict__ mask, float *__restrict__ theta,
     float *__restrict__ ncc_out, const uint8_t *__restrict__ reg, const pvr_reg_params &prm,
-    double k) {
+    double k, unsigned long long *__restrict__ stats) {
   const int s = blockIdx.x;
   const PatchDev pt = patches[s];
   const ProbDev pr = probs[pt.problem];
@@ -510,6 +522,8 @@ __device__ __forceinline__ void register_patch(
     sd = sqrt(fmax(sy[2] / sy[0] - m * m, 0.0));
   }
   if (threadIdx.x == 0) {
+    sh.walked[0] = sh.walked[1] = 0.0;
+    sh.evals[0] = sh.evals[1] = 0;
     const double su = st.spacing[0], sv = st.spacing[1];
     double rho = 0.5 * sqrt((pt.w - 1) * (pt.w - 1) * su * su + (pt.h - 1) * (pt.h - 1) * sv * sv);
     rho = rho < 1.0 ? 1.0 : rho;
@@ -580,6 +594,12 @@ __device__ __forceinline__ void register_patch(
     }
   }
   if (ncc_out && threadIdx.x == 0) ncc_out[s] = (float)f0;
+  if (threadIdx.x == 0) {
+    atomicAdd(&stats[0], (unsigned long long)sh.evals[0]);
+    atomicAdd(&stats[1], (unsigned long long)sh.walked[0]);
+    atomicAdd(&stats[2], (unsigned long long)sh.evals[1]);
+    atomicAdd(&stats[3], (unsigned long long)sh.walked[1]);
+  }
 }
 
 // The optimiser of register_patch for the patches of one volume layout (the
@@ -591,11 +611,12 @@ k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stack
            const PatchDev *__restrict__ patches, const float *__restrict__ Xv, int any_xt,
            const float *__restrict__ y, const uint8_t *__restrict__ mask,
            float *__restrict__ theta, float *__restrict__ ncc_out,
-           const uint8_t *__restrict__ reg, pvr_reg_params prm, double k) {
+           const uint8_t *__restrict__ reg, pvr_reg_params prm, double k,
+           unsigned long long *__restrict__ stats) {
   __shared__ RegShared sh;
   if ((any_xt && patches[blockIdx.x].layout == 1) != XT) return;
   register_patch<EXACT, XT, PSF>(sh, probs, stacks, patches, Xv, y, mask, theta, ncc_out, reg, prm,
-                                 k);
+                                 k, stats);
 }
 
 extern "C" pvr_status pvr_register_patches(const pvr_plan *p, const float *X, const float *y_obs,
@@ -617,13 +638,15 @@ extern "C" pvr_status pvr_register_patches(const pvr_plan *p, const float *X, co
     return fail(PVR_EUNSUPPORTED,
                 "pvr_register_patches: the exact gradient is implemented for the Gaussian PSF "
                 "(use PVR_REG_GRAD_FD with the sinc PSF)");
+  hipEvent_t *ev = timing_slot(p, PVR_KERNEL_REGISTER);
+  if (ev) HIP_TRY(hipEventRecord(ev[0], stream));
   const float *XT = volume_xt(p, X, stream);
   HIP_TRY(hipGetLastError());
   const int any = XT != nullptr;
 #define REG_LAUNCH(E, L, S, V)                                                                   \
   hipLaunchKernelGGL((k_register<E, L, S>), dim3(p->M), dim3(REG_THREADS), 0, stream, p->d_prob, \
                      p->d_stack, p->d_patch, V, any, y_obs, p->d_mask, theta, ncc, reg, *prm,     \
-                     p->k)
+                     p->k, p->d_reg_stats)
   if (sinc) {
     REG_LAUNCH(false, false, PVR_PSF_SINC, X);
     if (any) REG_LAUNCH(false, true, PVR_PSF_SINC, XT);
@@ -635,6 +658,22 @@ extern "C" pvr_status pvr_register_patches(const pvr_plan *p, const float *X, co
     if (any) REG_LAUNCH(false, true, PVR_PSF_GAUSSIAN, XT);
   }
 #undef REG_LAUNCH
+  HIP_TRY(hipGetLastError());
+  if (ev) HIP_TRY(hipEventRecord(ev[1], stream));
+  return PVR_OK;
+  PVR_API_END();
+}
+
+extern "C" pvr_status pvr_plan_reg_stats(pvr_plan *p, int64_t out[4], hipStream_t stream) {
+  PVR_API_BEGIN();
+  if (!p || !out) return fail(PVR_EINVAL, "pvr_plan_reg_stats: NULL argument");
+  for (int i = 0; i < 4; ++i) out[i] = 0;
+  if (!p->attached) return PVR_OK;
+  unsigned long long v[4];
+  HIP_TRY(hipMemcpyAsync(v, p->d_reg_stats, sizeof v, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  for (int i = 0; i < 4; ++i) out[i] = (int64_t)v[i];
+  launch_fill_i32((int *)p->d_reg_stats, 0, 8, stream);
   HIP_TRY(hipGetLastError());
   return PVR_OK;
   PVR_API_END();

@@ -558,7 +558,7 @@ __device__ __forceinline__ T block_sum(T v, T *lds) {
 // host-side plan object
 // ---------------------------------------------------------------------------
 namespace pvr {
-constexpr int TIMING_KERNELS = 2;
+constexpr int TIMING_KERNELS = 3;
 constexpr int TIMING_CAP = 256;  // event pairs per kernel between reads
 struct KernelTimer {
   hipEvent_t ev[TIMING_CAP][2];
@@ -647,5 +647,7 @@ struct pvr_plan {
   unsigned *d_status;        // [1] fault flags (PVR_FAULT_*), read by pvr_check
   long long generation;      // bumped whenever launches recorded earlier would go stale
   int *d_total;              // [4] index totals: brick pairs, sub-brick pairs
+  unsigned long long *d_reg_stats;  // [4] registration evaluations and samples walked
+                                    // (plain, then exact gradient) since the last read
   int h_total[4];            // host readback
 };

@@ -148,16 +148,20 @@ k_motion_init_step(const PatchDev *__restrict__ patches, const uint8_t *__restri
 
 __global__ void __launch_bounds__(MOT_T)
 k_motion_fallback(int M, const float *__restrict__ score, float tau,
-                  const float *__restrict__ theta_ref, float *__restrict__ theta,
-                  uint8_t *__restrict__ flag) {
+                  const float *__restrict__ score_ref, const float *__restrict__ theta_ref,
+                  float *__restrict__ theta, const uint8_t *__restrict__ active,
+                  uint8_t *__restrict__ flag, uint8_t *__restrict__ keep) {
   const int s = blockIdx.x * MOT_T + threadIdx.x;
   if (s >= M) return;
-  const bool back = score[s] < tau;
+  const bool act = active ? active[s] != 0 : true;
+  const float thr = score_ref ? score_ref[s] + tau : tau;
+  const bool back = act && score[s] < thr;
   if (back) {
 #pragma unroll
     for (int a = 0; a < 6; ++a) theta[6 * s + a] = theta_ref[6 * s + a];
   }
   flag[s] = back ? 1 : 0;
+  if (keep) keep[s] = act && !back ? 1 : 0;
 }
 
 inline unsigned lanes(int M) { return (unsigned)((M + MOT_T - 1) / MOT_T); }
@@ -232,16 +236,18 @@ extern "C" pvr_status pvr_motion_init_step(const pvr_plan *p, const float *y_obs
 }
 
 extern "C" pvr_status pvr_motion_fallback(const pvr_plan *p, const float *score, float tau,
-                                          const float *theta_ref, float *theta, uint8_t *flag,
-                                          hipStream_t stream) {
+                                          const float *score_ref, const float *theta_ref,
+                                          float *theta, const uint8_t *active, uint8_t *flag,
+                                          uint8_t *keep, hipStream_t stream) {
   PVR_API_BEGIN();
   PVR_ALIGNED("pvr_motion_fallback", score, 4);
+  PVR_ALIGNED("pvr_motion_fallback", score_ref, 4);
   PVR_ALIGNED("pvr_motion_fallback", theta_ref, 4);
   PVR_ALIGNED("pvr_motion_fallback", theta, 4);
   if (!p || !score || !theta_ref || !theta || !flag)
     return fail(PVR_EINVAL, "pvr_motion_fallback: NULL argument");
   hipLaunchKernelGGL(k_motion_fallback, dim3(lanes(p->M)), dim3(MOT_T), 0, stream, p->M, score,
-                     tau, theta_ref, theta, flag);
+                     tau, score_ref, theta_ref, theta, active, flag, keep);
   HIP_TRY(hipGetLastError());
   return PVR_OK;
   PVR_API_END();

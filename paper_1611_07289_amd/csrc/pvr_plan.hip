@@ -554,6 +554,7 @@ static size_t layout(pvr_plan *p, char *base, int flags) {
   p->d_chunk_stats = ws_take<double>(c, 5LL * p->n_sim_blocks);
   p->d_xt = p->any_xt ? ws_take<float>(c, p->V) : nullptr;
   p->d_total = ws_take<int>(c, 4);
+  p->d_reg_stats = ws_take<unsigned long long>(c, 4);
   p->d_status = ws_take<unsigned>(c, 1);
   p->d_invz64 = (flags & PVR_WS_F64) ? ws_take<double>(c, N) : nullptr;
   p->d_rq64 = (flags & PVR_WS_F64) ? ws_take<double2>(c, N + 2) : nullptr;
@@ -613,6 +614,7 @@ extern "C" pvr_status pvr_plan_attach(pvr_plan *p, void *workspace, size_t bytes
   if (p->d_rq64) launch_fill_f64((double *)p->d_rq64, 0.0, 2 * (p->N + 2), stream);
   launch_fill_i32((int *)p->d_status, 0, 1, stream);
   launch_fill_i32(p->d_total, 0, 4, stream);
+  launch_fill_i32((int *)p->d_reg_stats, 0, 8, stream);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(stream));  // the uploads read pageable host tables of the plan
   p->attached = true;

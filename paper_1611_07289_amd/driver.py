@@ -85,15 +85,22 @@ def reconstruct(plan, y, theta0, cycles: int = 3, n_sr: int = 10,
                 sr_params: Optional[pvr.SRParams] = None, register: bool = True,
                 init_fn=None, active_schedule=None, sample_mask=None, X0=None,
                 first_cycle: int = 0, on_cycle=None, fallback_tau: Optional[float] = None,
-                fallback_params: Optional[pvr.RegParams] = None):
+                fallback_params: Optional[pvr.RegParams] = None, register_fn=None,
+                fallback_relative: bool = False):
     """Full reconstruction; theta0 is [M, 6] float32 on the device and is
     updated in place.  ``init_fn(plan, X, y, theta)``, when given, runs before
     each registration (a learned initialiser) with the keyword arguments
-    active and mask of the cycle's build; with ``fallback_tau`` the patches
-    whose NCC after the registration stays below it are registered again
-    from their motion before init_fn, with ``fallback_params`` (default the
-    same parameters).  ``active_schedule``, when
-    given, is a list of per-patch uint8 device masks used cycle by cycle (in
+    active and mask of the cycle's build; it returns the per-patch NCC before
+    the prediction and at the motion it leaves (device tensors), or None.
+    With ``fallback_tau`` that NCC decides: patches where it is below tau
+    (below the NCC before the prediction plus tau with
+    ``fallback_relative``) are registered from their motion before the
+    prediction with ``fallback_params`` (default the same parameters), the
+    others refine the prediction with ``reg_params``.
+    ``register_fn(plan, X, y, theta, ncc, active,
+    mask)``, when given, replaces the per-patch registration
+    (pvr_register_patches), e.g. the joint gradient-based registration.
+    ``active_schedule``, when given, is a list of per-patch uint8 device masks used cycle by cycle (in
     turn): multi-scale patches (paper Sec. II, eq. Y_i), where cycle c
     registers and reconstructs from the patches of one scale only.
     ``sample_mask`` (uint8 [N] on the device), when given, applies at every
@@ -128,23 +135,32 @@ def reconstruct(plan, y, theta0, cycles: int = 3, n_sr: int = 10,
     rp = reg_params or pvr.RegParams.make(min_std=0.01 * ymax)
     for c in range(first_cycle, first_cycle + cycles):
         if register:
+            scores = None
             if init_fn is not None:
                 t = tick()
                 theta_pre = theta.clone()
-                init_fn(plan, X, y, theta, active=active(c), mask=sample_mask)
+                scores = init_fn(plan, X, y, theta, active=active(c), mask=sample_mask)
                 timings["init_fn"] += tick() - t
             t = tick()
-            plan.register(X, y, theta, buf.ncc, reg=active(c), params=rp)
-            if init_fn is not None and fallback_tau is not None:
-                # where the refined proposal scores below tau, the plain
-                # registration takes over from the motion before the proposal
+            if register_fn is not None:
+                register_fn(plan, X, y, theta, buf.ncc, active(c), sample_mask)
+            elif scores is not None and fallback_tau is not None:
+                # the NCC after the prediction decides: where it stays below
+                # the threshold (tau, or the NCC before the prediction plus
+                # tau with fallback_relative) the plain registration takes
+                # over from the motion before the prediction, elsewhere the
+                # registration refines the prediction
+                n_old, n_pred = scores
                 flag = torch.empty(plan.M, dtype=torch.uint8, device=theta.device)
-                plan.motion_fallback(buf.ncc, fallback_tau, theta_pre, theta, flag)
-                if active(c) is not None:
-                    flag.mul_(active(c))
-                plan.register(X, y, theta, buf.ncc, reg=flag,
-                              params=fallback_params or rp)
+                keep = torch.empty_like(flag)
+                plan.motion_fallback(n_pred, fallback_tau, theta_pre, theta, flag,
+                                     score_ref=n_old if fallback_relative else None,
+                                     active=active(c), keep=keep)
+                plan.register(X, y, theta, buf.ncc, reg=keep, params=rp)
+                plan.register(X, y, theta, buf.ncc, reg=flag, params=fallback_params or rp)
                 hist["fallback"].append(int(flag.sum()))
+            else:
+                plan.register(X, y, theta, buf.ncc, reg=active(c), params=rp)
             t1 = tick(); timings["register"] += t1 - t
             hist["ncc"].append(float(buf.ncc.mean()))
             t = tick()

@@ -264,7 +264,8 @@ def init_fn_factory(net: Net, batch: int = 1024):
     """A driver init function: predicts every patch's correction from the
     current volume and keeps, per patch, whichever of the old and the
     proposed motion has the higher NCC (the registration refines it next).
-    Every build takes the cycle's active set and sample mask."""
+    Every build takes the cycle's active set and sample mask.  Returns the
+    per-patch NCC before the prediction and at the motion kept."""
     import torch
 
     def init_fn(plan, X, y, theta, active=None, mask=None):
@@ -287,7 +288,9 @@ def init_fn_factory(net: Net, batch: int = 1024):
         plan.simulate(X, y_sim=ysim)
         n_new = torch.empty(plan.M, device=dev)
         plan.ncc_grad(y, ysim, None, n_new)
+        n_before = n_old.clone()
         plan.motion_accept(prop, n_new, theta, n_old)  # keep the better of the two
         plan.build(theta, active=active, mask=mask)
+        return n_before, n_old
 
     return init_fn

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libpvr.so")
 PVR_OK, PVR_EINVAL, PVR_ESHAPE, PVR_ENOMEM, PVR_EHIP, PVR_ENUMERIC, PVR_EUNSUPPORTED = range(7)
 PVR_KERNEL_SIMULATE = 0
 PVR_KERNEL_BACKPROJECT = 1
+PVR_KERNEL_REGISTER = 2
 PVR_EM_INIT = 1
 PVR_EM_FIX_W = 2
 PVR_EM_RESID_FRESH = 4
@@ -95,7 +96,8 @@ class RegParams(ctypes.Structure):
 
 
 EXPORTS = ["pvr_last_error", "pvr_version", "pvr_plan_create", "pvr_plan_destroy",
-           "pvr_plan_workspace_size", "pvr_plan_attach", "pvr_motion_frame", "pvr_motion_step",
+           "pvr_plan_workspace_size", "pvr_plan_attach", "pvr_plan_reg_stats",
+           "pvr_motion_frame", "pvr_motion_step",
            "pvr_motion_accept", "pvr_motion_init_step", "pvr_motion_fallback",
            "pvr_plan_info", "pvr_plan_offsets", "pvr_plan_build", "pvr_plan_build_f64",
            "pvr_plan_inv_z", "pvr_simulate", "pvr_simulate_f64", "pvr_backproject",
@@ -132,12 +134,13 @@ def load(path: str = LIB_PATH):
     L.pvr_plan_info.argtypes = [P, P]
     L.pvr_plan_workspace_size.argtypes = [P, i32, P]
     L.pvr_plan_attach.argtypes = [P, P, ctypes.c_size_t, i32, P]
+    L.pvr_plan_reg_stats.argtypes = [P, P, P]
     f32_ = ctypes.c_float
     L.pvr_motion_frame.argtypes = [P, P, i32, P, P, P]
     L.pvr_motion_step.argtypes = [P, P, P, P, f32_, P, P]
     L.pvr_motion_accept.argtypes = [P, P, P, P, P, P, f32_, f32_, P, P]
     L.pvr_motion_init_step.argtypes = [P, P, f32_, ctypes.c_double, P, P]
-    L.pvr_motion_fallback.argtypes = [P, P, f32_, P, P, P, P]
+    L.pvr_motion_fallback.argtypes = [P, P, f32_, P, P, P, P, P, P, P]
     L.pvr_plan_offsets.argtypes = [P, P, P]
     L.pvr_plan_build.argtypes = [P, P, P, P, P]
     L.pvr_plan_build_f64.argtypes = [P, P, P, P, P]
@@ -362,6 +365,14 @@ class Plan:
         _check(load().pvr_register_patches(self.h, _ptr(X), _ptr(y_obs), _ptr(theta), _ptr(ncc),
                                            _ptr(reg), ctypes.byref(prm), _stream()))
 
+    def reg_stats(self):
+        """Registration work since the previous read: dict of NCC evaluations
+        and valid samples walked, plain and with the exact gradient."""
+        v = (ctypes.c_int64 * 4)()
+        _check(load().pvr_plan_reg_stats(self.h, v, _stream()))
+        return {"evals": int(v[0]), "samples": int(v[1]), "evals_exact": int(v[2]),
+                "samples_exact": int(v[3])}
+
     # -- per-patch motion bookkeeping (pvr_motion_*) ---------------------------------
     def motion_frame(self, v, inverse=False, base=None, out=None):
         """out = base + A v (or A^-1 v), A = diag(rho F^T, F^T) per patch."""
@@ -385,9 +396,11 @@ class Plan:
         _check(load().pvr_motion_init_step(self.h, _ptr(y_obs), float(step0), float(min_std),
                                            _ptr(delta), _stream()))
 
-    def motion_fallback(self, score, tau, theta_ref, theta, flag):
-        _check(load().pvr_motion_fallback(self.h, _ptr(score), float(tau), _ptr(theta_ref),
-                                          _ptr(theta), _ptr(flag), _stream()))
+    def motion_fallback(self, score, tau, theta_ref, theta, flag, score_ref=None, active=None,
+                        keep=None):
+        _check(load().pvr_motion_fallback(self.h, _ptr(score), float(tau), _ptr(score_ref),
+                                          _ptr(theta_ref), _ptr(theta), _ptr(active), _ptr(flag),
+                                          _ptr(keep), _stream()))
 
     def grad_theta(self, X, grad_y, grad_theta):
         import torch

@@ -113,11 +113,23 @@ def test_flat_patches_and_fallback(case):
                    for s in range(P.M)])
     assert np.array_equal(host(delta), np.where(sd >= 1.0, 0.5, 0.0).astype(np.float32))
     score = rng.uniform(size=P.M).astype(np.float32)
+    score_ref = rng.uniform(size=P.M).astype(np.float32)
+    active = (rng.uniform(size=P.M) < 0.7).astype(np.uint8)
     th = rng.normal(size=(P.M, 6)).astype(np.float32)
     ref = rng.normal(size=(P.M, 6)).astype(np.float32)
-    tt = dev(th)
     flag = torch.empty(P.M, dtype=torch.uint8, device="cuda")
+    keep = torch.empty_like(flag)
+    # a fixed threshold over every patch
+    tt = dev(th)
     plan.motion_fallback(dev(score), 0.4, dev(ref), tt, flag)
     back = score < 0.4
     assert np.array_equal(host(flag), back.astype(np.uint8))
+    assert np.array_equal(host(tt), np.where(back[:, None], ref, th))
+    # a threshold relative to a reference score, over an active set
+    tt = dev(th)
+    plan.motion_fallback(dev(score), 0.05, dev(ref), tt, flag, score_ref=dev(score_ref),
+                         active=dev(active), keep=keep)
+    back = (active > 0) & (score < score_ref + np.float32(0.05))
+    assert np.array_equal(host(flag), back.astype(np.uint8))
+    assert np.array_equal(host(keep), ((active > 0) & ~back).astype(np.uint8))
     assert np.array_equal(host(tt), np.where(back[:, None], ref, th))
