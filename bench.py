@@ -249,6 +249,11 @@ def main():
                     help="learned workload: time inference only")
     ap.add_argument("--no-superpixel", action="store_true",
                     help="skip the superpixel-versus-square-patch reconstruction")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batched workload: skip the one-after-another comparison")
+    ap.add_argument("--fixed-launch", default=None,
+                    help="batched workload: launch shapes instead of the autotuner, "
+                         "'walk:G,BPG' or 'tiles:WxH,BPG'")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (for counter scaling)")
     args = ap.parse_args()
@@ -471,9 +476,12 @@ def main():
 
 
 def batched_bench(args, probs, dev):
-    """Batched form: all problems in one plan, autotuned forward tiles, two SR
-    iterations per HIP-graph replay; compared with the same problems run one
-    after another, each in its own plan, eagerly."""
+    """Batched form: all problems in one plan, launch shapes of the two PSF
+    kernels chosen by the autotuner (or given with --fixed-launch), two SR
+    iterations per HIP-graph replay; the roofline of the dominant kernel from
+    event pairs around eager iterations of the same plan; compared with the
+    same problems run one after another, each in its own plan, eagerly
+    (skipped with --no-sequential)."""
     import torch
     from paper_1611_07289_amd import autotune, pvr, synth
     from paper_1611_07289_amd.batch import GraphedSR
@@ -493,10 +501,23 @@ def batched_bench(args, probs, dev):
     y = torch.from_numpy(np.concatenate(parts)).to(dev)
     ones = torch.ones(plan.V, dtype=torch.float32, device=dev)
     plan.simulate(ones, y_sim=yc)
-    n_valid = int((yc > 0.5).sum().item())
+    valid = yc > 0.5
+    n_valid = int(valid.sum().item())
     X0 = Xt * 0.9
-    tiles, tile_ms = autotune.tune_tiles(plan, X0, y, cache=None)
-    log(f"[bench] batched: {plan.P} problems, N={plan.N} M={plan.M} V={plan.V}; tiles {tiles}")
+    if args.fixed_launch:
+        fwd, g = args.fixed_launch.split(",")
+        kind, val = fwd.split(":")
+        if kind == "walk":
+            plan.set_tiles(0, 0)
+            plan.set_granules(int(val), int(g))
+        else:
+            tw, th = (int(v) for v in val.split("x"))
+            plan.set_granules(1, int(g))
+            plan.set_tiles(tw, th)
+        tuned = {"fixed": args.fixed_launch}
+    else:
+        tuned = autotune.tune(plan, X0, y, cache=None)
+    log(f"[bench] batched: {plan.P} problems, N={plan.N} M={plan.M} V={plan.V}; launch {tuned}")
     gs = GraphedSR(plan, y, X0.clone())
     gs.start()
     gs.capture()
@@ -509,26 +530,32 @@ def batched_bench(args, probs, dev):
     el = time.perf_counter() - t0
     it = 2 * pairs
     value = n_valid * it / el
-    # the same problems one after another, eagerly, each in its own plan
-    seq_t = 0.0
-    for b, P in enumerate(probs):
-        pl = pvr.Plan.from_problems([P])
-        pl.build(torch.from_numpy(P.theta_true.astype(np.float32)).to(dev))
-        a = plan.sample_off[plan_patch_begin(plan, probs, b)]
-        z = plan.sample_off[plan_patch_begin(plan, probs, b + 1)]
-        yb = y[a:z].contiguous()
-        g1 = GraphedSR(pl, yb, torch.from_numpy(P.x_true.reshape(-1) * 0.9).to(dev))
-        g1.start()
-        g1._iter(g1.X, g1.Xn)
-        g1._iter(g1.Xn, g1.X)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(pairs):
-            g1._iter(g1.X, g1.Xn)
-            g1._iter(g1.Xn, g1.X)
-        torch.cuda.synchronize()
-        seq_t += time.perf_counter() - t1
-        pl.close()
+    # kernel durations: eager iterations of the same plan with the library's
+    # event pairs around the two PSF kernels
+    plan.set_timing(True)
+    for kid in (pvr.PVR_KERNEL_SIMULATE, pvr.PVR_KERNEL_BACKPROJECT):
+        plan.kernel_time(kid)
+    for k in range(4):
+        gs._iter(gs.X, gs.Xn) if k % 2 == 0 else gs._iter(gs.Xn, gs.X)
+    kern = {}
+    for name, kid in (("k_simulate", pvr.PVR_KERNEL_SIMULATE),
+                      ("k_backproject", pvr.PVR_KERNEL_BACKPROJECT)):
+        tot, n = plan.kernel_time(kid)
+        kern[name] = tot / max(n, 1)
+    plan.set_timing(False)
+    nnz = nnz_estimate(probs, n_valid)
+    counts = torch.from_numpy(np.diff(plan.sample_off)).to(dev)
+    n_kept = int((valid & torch.repeat_interleave(gs.W > 0, counts)).sum().item())
+    nnz_adj = nnz * n_kept / max(n_valid, 1)
+    dom = max(kern, key=kern.get)
+    fpn = FLOP_PER_NNZ_FWD if dom == "k_simulate" else FLOP_PER_NNZ_ADJ
+    nnz_dom = nnz if dom == "k_simulate" else nnz_adj
+    achieved = nnz_dom * fpn / (kern[dom] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved,
+                "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": None,
+                "kernel_ms": kern[dom], "nnz_per_launch": nnz_dom, "flop_per_nnz": fpn,
+                "valid_samples_kept": n_kept}
     out = {
         "metric": "SR-iteration patch-samples/s (batched, graph)",
         "value": value, "unit": "patch-samples/s", "n_gpus": 1, "steps": it,
@@ -538,10 +565,31 @@ def batched_bench(args, probs, dev):
                    "samples": plan.N, "valid_samples": n_valid, "voxels": plan.V,
                    "sizes": [P.grid.nx for P in probs],
                    "stacks": [len(P.stacks) for P in probs], "parallelism": "single GPU"},
-        "tiles": list(tiles), "tile_ms": tile_ms,
-        "sequential_ms_per_step": seq_t * 1e3 / it,
-        "speedup_vs_sequential": seq_t / el,
+        "launch": tuned, "hot_kernels_ms": kern, "roofline": roofline,
     }
+    if not args.no_sequential:
+        # the same problems one after another, eagerly, each in its own plan
+        seq_t = 0.0
+        for b, P in enumerate(probs):
+            pl = pvr.Plan.from_problems([P])
+            pl.build(torch.from_numpy(P.theta_true.astype(np.float32)).to(dev))
+            a = plan.sample_off[plan_patch_begin(plan, probs, b)]
+            z = plan.sample_off[plan_patch_begin(plan, probs, b + 1)]
+            yb = y[a:z].contiguous()
+            g1 = GraphedSR(pl, yb, torch.from_numpy(P.x_true.reshape(-1) * 0.9).to(dev))
+            g1.start()
+            g1._iter(g1.X, g1.Xn)
+            g1._iter(g1.Xn, g1.X)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(pairs):
+                g1._iter(g1.X, g1.Xn)
+                g1._iter(g1.Xn, g1.X)
+            torch.cuda.synchronize()
+            seq_t += time.perf_counter() - t1
+            pl.close()
+        out["sequential_ms_per_step"] = seq_t * 1e3 / it
+        out["speedup_vs_sequential"] = seq_t / el
     print(json.dumps(out), flush=True)
 
 

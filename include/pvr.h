@@ -298,6 +298,15 @@ pvr_status pvr_plan_set_psf(pvr_plan *plan, int32_t kind);
 pvr_status pvr_plan_set_tiles(pvr_plan *plan, int32_t tile_w, int32_t tile_h,
                               hipStream_t stream);
 
+/* Launch order of the two PSF kernels (a tuning knob, used by the
+ * autotuner): workgroups are dealt to the 8 XCDs round-robin, each XCD with
+ * its own L2; the work lists (forward chunks of 1024 samples, patch-major;
+ * adjoint bricks of 8^3 voxels, x fastest) are regrouped into granules of
+ * g consecutive items so that XCD x takes granules x, x + 8, ....  Defaults:
+ * forward 1, adjoint 64.  Results do not depend on the granules (every
+ * output keeps its summation order).  Both in [1, 4096].  (host) */
+pvr_status pvr_plan_set_granules(pvr_plan *plan, int32_t sim_granule, int32_t bp_granule);
+
 /* Kernel timing, a profiling aid.  With on != 0 the plan records a HIP
  * event pair on the launch stream around every launch of the kernel named by
  * `kernel` (PVR_KERNEL_SIMULATE: the forward kernel of pvr_simulate;
@@ -501,7 +510,8 @@ pvr_status pvr_check(pvr_plan *plan, hipStream_t stream);
  * params is read at capture.  Before capturing, the call prepares the
  * adjoint's brick index and synchronises `stream`; kernel timing must be off.
  * A graph records the plan as it is: after pvr_plan_build*, pvr_plan_set_psf,
- * pvr_plan_set_tiles or an index rebuild pvr_sr_graph_launch returns
+ * pvr_plan_set_tiles, pvr_plan_set_granules or an index rebuild
+ * pvr_sr_graph_launch returns
  * PVR_EINVAL (capture again).  Destroy graphs before their plan.  Launches
  * are asynchronous on `stream`. */
 typedef struct pvr_sr_graph pvr_sr_graph;

@@ -1,23 +1,29 @@
-"""Autotuner for the forward tile shape of a plan.
+"""Autotuner for the launch shapes of a plan's two PSF kernels.
 
-Every candidate tile shape (tile_w x tile_h pixels per workgroup with the
-tile's voxel box staged in LDS, or 0 x 0 for the global-memory walk) is
-applied with pvr_plan_set_tiles and the simulation is timed with HIP events; the
-fastest shape is kept and remembered in a JSON cache keyed by the workload
-signature (problem sizes, patch sizes, stack frames), so later plans of the
-same workload skip the search.
+Forward pass: the global-memory walk with its XCD granule (how many
+consecutive 1024-sample chunks one XCD takes at a time), or LDS-staged tiles
+of tile_w x tile_h pixels per workgroup.  Adjoint: the XCD granule of its
+brick list.  Every candidate is applied (pvr_plan_set_tiles,
+pvr_plan_set_granules) and its kernel timed with HIP events over a few
+repetitions (median); the fastest of each kernel is kept and remembered in a
+JSON cache keyed by the workload signature (problem sizes, patch sizes,
+stack frames), so later plans of the same workload skip the search.  The
+launch shapes change no result (every output keeps its summation order).
 """
 from __future__ import annotations
 
 import hashlib
 import json
 import os
-from typing import Dict, Optional, Tuple
+from typing import Dict, Optional
 
 import numpy as np
 
-# (0, 0) is the untiled global-memory walk
-CANDIDATES = [(0, 0), (16, 16), (32, 8), (8, 32), (64, 4), (16, 8), (8, 16), (8, 8)]
+# forward candidates: ("walk", granule) or ("tiles", tile_w, tile_h)
+FORWARD = [("walk", 1), ("walk", 2), ("walk", 4), ("walk", 16),
+           ("tiles", 16, 16), ("tiles", 32, 8), ("tiles", 8, 32), ("tiles", 64, 4)]
+# adjoint candidates: XCD granules of the brick list
+ADJOINT = [1, 4, 16, 64, 256]
 CACHE = os.environ.get("PVR_AUTOTUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "pvr_mi355x",
                                     "autotune.json"))
@@ -30,7 +36,7 @@ def signature(plan) -> str:
     h.update(bytes(plan._s))
     wh = np.asarray([(p.w, p.h) for p in plan._p], np.int32)
     h.update(np.unique(wh, axis=0).tobytes())
-    return h.hexdigest()[:16]
+    return "v2-" + h.hexdigest()[:16]
 
 
 def _load_cache(path: str) -> Dict:
@@ -52,34 +58,65 @@ def _save_cache(path: str, data: Dict) -> None:
         pass
 
 
-def tune_tiles(plan, X, y, reps: int = 3, cache: Optional[str] = CACHE,
-               candidates=CANDIDATES) -> Tuple[Tuple[int, int], Dict[str, float]]:
-    """Pick and apply the fastest forward tile shape for this plan (which must
-    be built).  Returns (shape, {shape: ms})."""
+def _name(c) -> str:
+    return f"walk/g{c[1]}" if c[0] == "walk" else f"tiles/{c[1]}x{c[2]}"
+
+
+def _apply(plan, fwd, bp_granule):
+    if fwd[0] == "walk":
+        plan.set_tiles(0, 0)
+        plan.set_granules(fwd[1], bp_granule)
+    else:
+        plan.set_granules(1, bp_granule)
+        plan.set_tiles(fwd[1], fwd[2])
+
+
+def _median_ms(fn, reps):
+    import torch
+    fn()  # warm
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    evs[0].record()
+    for r in range(reps):
+        fn()
+        evs[r + 1].record()
+    torch.cuda.synchronize()
+    return sorted(evs[r].elapsed_time(evs[r + 1]) for r in range(reps))[reps // 2]
+
+
+def tune(plan, X, y, reps: int = 3, cache: Optional[str] = CACHE, forward=FORWARD,
+         adjoint=ADJOINT) -> Dict:
+    """Pick and apply the fastest forward launch shape and adjoint granule
+    for this plan (which must be built).  Returns {"forward": name,
+    "adjoint_granule": g, "forward_ms": {...}, "adjoint_ms": {...}}."""
     import torch
     key = signature(plan)
     db = _load_cache(cache) if cache else {}
     if key in db:
-        tw, th = db[key]["best"]
-        plan.set_tiles(tw, th)
-        return (tw, th), db[key]["ms"]
-    e = torch.empty(plan.N, dtype=torch.float32, device=X.device)
-    times = {}
-    for tw, th in candidates:
-        plan.set_tiles(tw, th)
-        plan.simulate(X, y_obs=y, resid=e)  # warm
-        evs = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
-        evs[0].record()
-        for r in range(reps):
-            plan.simulate(X, y_obs=y, resid=e)
-            evs[r + 1].record()
-        torch.cuda.synchronize()
-        ms = sorted(evs[r].elapsed_time(evs[r + 1]) for r in range(reps))[reps // 2]
-        times[f"{tw}x{th}"] = ms
-    best = min(times, key=times.get)
-    tw, th = (int(v) for v in best.split("x"))
-    plan.set_tiles(tw, th)
+        r = db[key]
+        fwd = next(c for c in forward if _name(c) == r["forward"])
+        _apply(plan, fwd, r["adjoint_granule"])
+        return r
+    dev = X.device
+    e = torch.empty(plan.N, dtype=torch.float32, device=dev)
+    p = torch.ones(plan.N, dtype=torch.float32, device=dev)
+    W = torch.ones(plan.M, dtype=torch.float32, device=dev)
+    num = torch.empty(plan.V, dtype=torch.float32, device=dev)
+    den = torch.empty_like(num)
+    fwd_ms = {}
+    for c in forward:
+        _apply(plan, c, 64)
+        fwd_ms[_name(c)] = _median_ms(lambda: plan.simulate(X, y_obs=y, resid=e), reps)
+    best_f = min(fwd_ms, key=fwd_ms.get)
+    fwd = next(c for c in forward if _name(c) == best_f)
+    adj_ms = {}
+    for g in adjoint:
+        _apply(plan, fwd, g)
+        adj_ms[str(g)] = _median_ms(lambda: plan.backproject(e, p, W, num, den), reps)
+    best_g = int(min(adj_ms, key=adj_ms.get))
+    _apply(plan, fwd, best_g)
+    res = {"forward": best_f, "adjoint_granule": best_g, "forward_ms": fwd_ms,
+           "adjoint_ms": adj_ms}
     if cache:
-        db[key] = {"best": [tw, th], "ms": times}
+        db[key] = res
         _save_cache(cache, db)
-    return (tw, th), times
+    return res

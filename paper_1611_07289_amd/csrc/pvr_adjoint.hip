@@ -193,10 +193,10 @@ k_backproject(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ pa
               const typename GeoOf<T>::type *__restrict__ geo, const int *__restrict__ brick_prob,
               const int *__restrict__ sub_off, const int *__restrict__ sub_patch,
               const typename Vec2Of<T>::type *__restrict__ rq, const T *__restrict__ patch_w,
-              T *__restrict__ num, T *__restrict__ den, int n_bricks) {
+              T *__restrict__ num, T *__restrict__ den, int n_bricks, int granule) {
   using GEO = typename GeoOf<T>::type;
   using V2 = typename Vec2Of<T>::type;
-  const int bi = xcd_work(blockIdx.x, BP_XCD_GRANULE);
+  const int bi = xcd_work(blockIdx.x, granule);
   if (bi >= n_bricks) return;
   const ProbDev pr = probs[brick_prob[bi]];
   const int local = bi - pr.brick_base;
@@ -272,7 +272,7 @@ static pvr_status backproject_impl(const pvr_plan *p, const T *e, const T *pp, c
     HIP_TRY(hipGetLastError());
   }
   const void *geo = sizeof(T) == 4 ? (const void *)p->d_geof : (const void *)p->d_geod;
-  const dim3 grid(xcd_blocks(p->n_bricks, BP_XCD_GRANULE));
+  const dim3 grid(xcd_blocks(p->n_bricks, p->bp_granule));
   hipEvent_t *ev = timing_slot(p, PVR_KERNEL_BACKPROJECT);
   if (ev) HIP_TRY(hipEventRecord(ev[0], stream));
   const int hw = (p->max_hu <= 1 && p->max_hv <= 1) ? 1 : (p->max_hu <= 2 && p->max_hv <= 2) ? 2 : 0;
@@ -280,7 +280,7 @@ static pvr_status backproject_impl(const pvr_plan *p, const T *e, const T *pp, c
 #define BP_LAUNCH(D, H, SC)                                                                     \
   hipLaunchKernelGGL((k_backproject<T, D, H, SC>), grid, dim3(BP_THREADS), 0, stream, p->d_prob, \
                      p->d_patch, geot, p->d_brick_prob, p->d_sub_off, p->d_sub_patch, rq,         \
-                     patch_w, num, den, p->n_bricks)
+                     patch_w, num, den, p->n_bricks, p->bp_granule)
 #define BP_LAUNCH_HW(D, SC)            \
   if (hw == 1) BP_LAUNCH(D, 1, SC);    \
   else if (hw == 2) BP_LAUNCH(D, 2, SC); \

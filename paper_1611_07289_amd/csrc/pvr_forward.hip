@@ -25,8 +25,8 @@ k_simulate(const ProbDev *__restrict__ probs, const PatchDev *__restrict__ patch
            const BlockWork *__restrict__ work, const typename GeoOf<T>::type *__restrict__ geo,
            const T *__restrict__ invz, const T *__restrict__ X, const T *__restrict__ XT,
            const T *__restrict__ y_obs, T *__restrict__ y_sim, T *__restrict__ resid,
-           double *__restrict__ chunk_stats, int n_work) {
-  const int wi = xcd_work(blockIdx.x, SIM_XCD_GRANULE);
+           double *__restrict__ chunk_stats, int n_work, int granule) {
+  const int wi = xcd_work(blockIdx.x, granule);
   if (wi >= n_work) return;
   const BlockWork wk = work[wi];
   const PatchDev pt = patches[wk.patch];
@@ -121,9 +121,9 @@ k_simulate_tiles(const ProbDev *__restrict__ probs, const PatchDev *__restrict__
                  const int *__restrict__ tile_off, int M, int tile_w, int tile_h, int n_tiles,
                  const GeoF *__restrict__ geo, const float *__restrict__ invz,
                  const float *__restrict__ X, const float *__restrict__ y_obs,
-                 float *__restrict__ y_sim, float *__restrict__ resid, int lds_cap) {
+                 float *__restrict__ y_sim, float *__restrict__ resid, int lds_cap, int granule) {
   extern __shared__ float xs[];
-  const int t = xcd_work(blockIdx.x, SIM_XCD_GRANULE);
+  const int t = xcd_work(blockIdx.x, granule);
   if (t >= n_tiles) return;
   const TileWork tw = tile_at(tile_off, M, patches, tile_w, tile_h, t);
   const PatchDev pt = patches[tw.patch];
@@ -212,12 +212,12 @@ static pvr_status simulate_impl(const pvr_plan *p, const T *X, const T *y_obs, T
   if (sizeof(T) == 4 && p->use_tiles && p->lds_box > 0 && p->psf == PVR_PSF_GAUSSIAN) {
     hipEvent_t *ev = timing_slot(p, PVR_KERNEL_SIMULATE);
     if (ev) HIP_TRY(hipEventRecord(ev[0], stream));
-    hipLaunchKernelGGL(k_simulate_tiles, dim3(xcd_blocks(p->n_tiles, SIM_XCD_GRANULE)), dim3(SIM_THREADS),
+    hipLaunchKernelGGL(k_simulate_tiles, dim3(xcd_blocks(p->n_tiles, p->sim_granule)), dim3(SIM_THREADS),
                        (size_t)p->lds_box * sizeof(float), stream, p->d_prob, p->d_patch,
                        p->d_tile_off, p->M, p->tile_w, p->tile_h, p->n_tiles, p->d_geof,
                        (const float *)invz,
                        (const float *)X, (const float *)y_obs, (float *)y_sim, (float *)resid,
-                       p->lds_box);
+                       p->lds_box, p->sim_granule);
     HIP_TRY(hipGetLastError());
     if (ev) HIP_TRY(hipEventRecord(ev[1], stream));
     const_cast<pvr_plan *>(p)->stats_valid = false;
@@ -231,12 +231,12 @@ static pvr_status simulate_impl(const pvr_plan *p, const T *X, const T *y_obs, T
     XT = volume_xt(p, X, stream);
     HIP_TRY(hipGetLastError());
   }
-  hipLaunchKernelGGL(k_simulate<T>, dim3(xcd_blocks(p->n_sim_blocks, SIM_XCD_GRANULE)),
+  hipLaunchKernelGGL(k_simulate<T>, dim3(xcd_blocks(p->n_sim_blocks, p->sim_granule)),
                      dim3(SIM_THREADS), 0, stream, p->d_prob,
                      p->d_patch, p->d_sim_blocks,
                      (const typename GeoOf<T>::type *)(sizeof(T) == 4 ? (const void *)p->d_geof
                                                                       : (const void *)p->d_geod),
-                     invz, X, XT, y_obs, y_sim, resid, stats, p->n_sim_blocks);
+                     invz, X, XT, y_obs, y_sim, resid, stats, p->n_sim_blocks, p->sim_granule);
   HIP_TRY(hipGetLastError());
   if (ev) HIP_TRY(hipEventRecord(ev[1], stream));
   // the residual statistics describe these buffers until the next build

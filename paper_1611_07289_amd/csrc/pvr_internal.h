@@ -120,6 +120,8 @@ __device__ __forceinline__ int xcd_work(int b, int g) {
   const int i = b / N_XCD;
   return (i / g) * (N_XCD * g) + (b % N_XCD) * g + i % g;
 }
+// default granules (pvr_plan_set_granules changes them per plan; the launch
+// order changes, the results do not)
 constexpr int SIM_XCD_GRANULE = 1;   // forward chunks: plain round-robin measured fastest
 constexpr int BP_XCD_GRANULE = 64;   // adjoint bricks (z-slab pieces)
 
@@ -598,6 +600,7 @@ struct pvr_plan {
   pvr::BlockWork *d_sim_blocks;
   int *d_tile_off;           // [M+1]
   int n_tiles, tile_w, tile_h;
+  int sim_granule, bp_granule;  // XCD granules of the forward work and the adjoint bricks
   bool use_tiles;            // forward pass staged per tile in LDS (else global walk)
   bool timing;               // record event pairs around the hot kernels
   pvr::KernelTimer *timers;  // [TIMING_KERNELS] (created on first enable)

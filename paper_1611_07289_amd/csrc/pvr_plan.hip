@@ -473,6 +473,8 @@ extern "C" pvr_status pvr_plan_create(const pvr_grid *grids, int32_t n_problems,
   p->tile_w = TILE;
   p->tile_h = TILE;
   p->use_tiles = false;
+  p->sim_granule = SIM_XCD_GRANULE;
+  p->bp_granule = BP_XCD_GRANULE;
   p->h_tile_off = (int *)calloc(n_patches + 1, sizeof(int));
   {
     const pvr_status st = make_tiles(p, TILE, TILE);
@@ -751,6 +753,19 @@ extern "C" pvr_status pvr_plan_set_tiles(pvr_plan *p, int32_t tile_w, int32_t ti
   p->use_tiles = true;
   if (p->built) return update_lds_box(p, stream);
   HIP_TRY(hipStreamSynchronize(stream));
+  return PVR_OK;
+  PVR_API_END();
+}
+
+extern "C" pvr_status pvr_plan_set_granules(pvr_plan *p, int32_t sim_granule,
+                                            int32_t bp_granule) {
+  PVR_API_BEGIN();
+  if (!p) return fail(PVR_EINVAL, "pvr_plan_set_granules: plan is NULL");
+  if (sim_granule < 1 || sim_granule > 4096 || bp_granule < 1 || bp_granule > 4096)
+    return fail(PVR_EINVAL, "pvr_plan_set_granules: granules must lie in [1, 4096]");
+  p->sim_granule = sim_granule;
+  p->bp_granule = bp_granule;
+  ++p->generation;
   return PVR_OK;
   PVR_API_END();
 }

@@ -97,6 +97,7 @@ class RegParams(ctypes.Structure):
 
 EXPORTS = ["pvr_last_error", "pvr_version", "pvr_plan_create", "pvr_plan_destroy",
            "pvr_plan_workspace_size", "pvr_plan_attach", "pvr_plan_reg_stats",
+           "pvr_plan_set_granules",
            "pvr_motion_frame", "pvr_motion_step",
            "pvr_motion_accept", "pvr_motion_init_step", "pvr_motion_fallback",
            "pvr_plan_info", "pvr_plan_offsets", "pvr_plan_build", "pvr_plan_build_f64",
@@ -135,6 +136,7 @@ def load(path: str = LIB_PATH):
     L.pvr_plan_workspace_size.argtypes = [P, i32, P]
     L.pvr_plan_attach.argtypes = [P, P, ctypes.c_size_t, i32, P]
     L.pvr_plan_reg_stats.argtypes = [P, P, P]
+    L.pvr_plan_set_granules.argtypes = [P, i32, i32]
     f32_ = ctypes.c_float
     L.pvr_motion_frame.argtypes = [P, P, i32, P, P, P]
     L.pvr_motion_step.argtypes = [P, P, P, P, f32_, P, P]
@@ -364,6 +366,10 @@ class Plan:
         prm = params or RegParams.make()
         _check(load().pvr_register_patches(self.h, _ptr(X), _ptr(y_obs), _ptr(theta), _ptr(ncc),
                                            _ptr(reg), ctypes.byref(prm), _stream()))
+
+    def set_granules(self, sim: int, bp: int):
+        """XCD granules of the forward work list and the adjoint bricks."""
+        _check(load().pvr_plan_set_granules(self.h, int(sim), int(bp)))
 
     def reg_stats(self):
         """Registration work since the previous read: dict of NCC evaluations

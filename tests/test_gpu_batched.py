@@ -138,3 +138,46 @@ def test_graph_replays_equal_eager(batch):
         torch.cuda.synchronize()
         assert torch.equal(gs.X, snaps[k]), f"replay {k} differs from eager"
         del busy
+
+
+def test_launch_shapes_change_no_result(batch):
+    """The autotuner's knobs reorder workgroups only: every XCD granule of
+    the forward walk and of the adjoint gives bit-identical outputs; the
+    LDS-staged forward tiles agree with the walk within the per-sample bar;
+    the tuner applies its choice and reports every candidate's time."""
+    from paper_1611_07289_amd import autotune
+    probs, plan = batch["probs"], batch["plan"]
+    X = torch.from_numpy(np.concatenate([P.x_true.reshape(-1) for P in probs])).cuda()
+    r = torch.from_numpy(np.random.default_rng(3).normal(size=plan.N).astype(np.float32)).cuda()
+    p = torch.rand(plan.N, device="cuda")
+    W = torch.rand(plan.M, device="cuda")
+
+    def outputs():
+        ys = torch.empty(plan.N, dtype=torch.float32, device="cuda")
+        plan.simulate(X, y_sim=ys)
+        num = torch.empty(plan.V, dtype=torch.float32, device="cuda")
+        den = torch.empty_like(num)
+        plan.backproject(r, p, W, num, den)
+        torch.cuda.synchronize()
+        return ys.clone(), num.clone(), den.clone()
+
+    plan.set_tiles(0, 0)
+    plan.set_granules(1, 64)
+    ref = outputs()
+    for gs, gb in ((2, 1), (16, 4), (4, 256)):
+        plan.set_granules(gs, gb)
+        got = outputs()
+        assert all(torch.equal(a, b) for a, b in zip(got, ref)), (gs, gb)
+    plan.set_granules(1, 64)
+    plan.set_tiles(16, 16)
+    ys_t = outputs()[0]
+    scale = torch.clamp(ref[0].abs(), min=1e-3 * float(ref[0].abs().max()))
+    assert float(((ys_t - ref[0]).abs() / scale).max()) <= 1e-5
+    res = autotune.tune(plan, X, r, reps=2, cache=None)
+    assert set(res["forward_ms"]) == {autotune._name(c) for c in autotune.FORWARD}
+    assert set(res["adjoint_ms"]) == {str(g) for g in autotune.ADJOINT}
+    print(f"[gpu] autotune: forward {res['forward']}, adjoint granule {res['adjoint_granule']}")
+    got = outputs()
+    assert torch.equal(got[1], ref[1]) and torch.equal(got[2], ref[2])
+    plan.set_tiles(0, 0)
+    plan.set_granules(1, 64)
