@@ -249,6 +249,9 @@ def main():
                     help="learned workload: time inference only")
     ap.add_argument("--no-superpixel", action="store_true",
                     help="skip the superpixel-versus-square-patch reconstruction")
+    ap.add_argument("--full-pvr-runs", default=None,
+                    help="comma-separated subset of the whole-reconstruction runs (e.g. "
+                         "plain,plain_exact), a profiling aid")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batched workload: skip the one-after-another comparison")
     ap.add_argument("--fixed-launch", default=None,
@@ -452,7 +455,9 @@ def main():
     }
 
     if not args.no_full_pvr and args.workload == "uterus256":
-        out["full_pvr"] = full_pvr(plan, probs, y, Xtrue, dev, learned_pairs=args.learned_pairs)
+        out["full_pvr"] = full_pvr(plan, probs, y, Xtrue, dev, learned_pairs=args.learned_pairs,
+                                   only=args.full_pvr_runs.split(",") if args.full_pvr_runs
+                                   else None)
     if not args.no_full_pvr and args.workload == "sinc256":
         # the sinc PSF registers with the central-difference gradient only
         out["full_pvr"] = full_pvr(plan, probs, y, Xtrue, dev, exact=False)
@@ -776,7 +781,7 @@ def register_roofline(stats, reg_ms, nnz_per_sample):
 
 
 def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10, learned_pairs=0, exact=True,
-             tight=(0.25, 5), fallback_tau=0.3):
+             tight=(0.25, 5), fallback_tau=0.3, only=None):
     """Seconds and PSNR of a whole reconstruction from the motion-corrupted
     start (zero motion), each with its registration kernel's time, work and
     roofline: plain registration with the full budget (step0 1, 40 trial
@@ -788,7 +793,8 @@ def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10, learned_pairs=0, exa
     over with the full budget from the motion before the prediction; and
     (exact only) the
     joint gradient-based registration through the differentiable forward
-    model (driver.register_gradient) in place of the per-patch one."""
+    model (driver.register_gradient) in place of the per-patch one.  `only`,
+    when given, names the runs to make (a profiling aid)."""
     import torch
     from paper_1611_07289_amd import driver, learned, pvr, synth
     res = {}
@@ -796,6 +802,8 @@ def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10, learned_pairs=0, exa
     nnz_ps = nnz_estimate(probs, 1)
 
     def run(key, rp, init_fn=None, register_fn=None):
+        if only and key not in only:
+            return
         th0 = torch.zeros(plan.M, 6, dtype=torch.float32, device=dev)
         plan.set_timing(True)
         plan.kernel_time(pvr.PVR_KERNEL_REGISTER)
@@ -841,7 +849,7 @@ def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10, learned_pairs=0, exa
             ncc.copy_(driver.register_gradient(pl, X, yy, th, iters=30, min_std=0.01 * ymax,
                                                active=act, mask=mask))
         run("joint_gradient", pvr.RegParams.make(**full), register_fn=joint)
-    if learned_pairs > 0 and exact:
+    if learned_pairs > 0 and exact and (not only or any(k.startswith("learned") for k in only)):
         P = probs[0]
         Xtr = torch.from_numpy(synth.phantom_uterus(P.grid.nx, 7700, 7701).reshape(-1)).to(dev)
         net = learned.Net(seed=5005)
@@ -856,6 +864,8 @@ def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10, learned_pairs=0, exa
                            "loss_first_last": [tr["loss"][0][1], tr["loss"][-1][1]]
                            if tr["loss"] else None}
         for sfx in ("", "_exact"):
+            if any(k + sfx not in res for k in ("learned", "plain", "plain_tight")):
+                continue
             lr_, pl_, pt_ = res["learned" + sfx], res["plain" + sfx], res["plain_tight" + sfx]
             res["learned_vs_plain" + sfx] = {
                 "delta_psnr_db": lr_["psnr_db"] - pl_["psnr_db"],

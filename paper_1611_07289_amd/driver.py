@@ -132,7 +132,10 @@ def reconstruct(plan, y, theta0, cycles: int = 3, n_sr: int = 10,
     t1 = tick(); timings["build"] += t1 - t
     hist = {"ncc": [], "excluded": [], "fallback": []}
     ymax = float(y.abs().max())
-    rp = reg_params or pvr.RegParams.make(min_std=0.01 * ymax)
+    # default: the exact NCC gradient (the same registrations as central
+    # differences at a third of the time); the sinc PSF has only the latter
+    rp = reg_params or pvr.RegParams.make(
+        min_std=0.01 * ymax, exact=getattr(plan, "psf", pvr.PVR_PSF_GAUSSIAN) == pvr.PVR_PSF_GAUSSIAN)
     for c in range(first_cycle, first_cycle + cycles):
         if register:
             scores = None
