@@ -68,6 +68,12 @@ def test_register_recovers_known_motion(tex):
     assert np.median(dtr) < 0.03 and np.median(dtr) < 0.1 * np.median(dtr0)
     assert np.median(drot) < 0.35 and np.median(drot) < 0.3 * np.median(drot0)
     assert np.mean(ncc > 0.999) > 0.8
+    # fractions the plain ascent reaches on these 16-pixel patches (every
+    # patch is non-flat here): 0.48 within (0.25 deg, 0.05 voxel), 0.80 of
+    # translations within 0.05 voxel, 0.85 of rotations within 1 deg
+    assert np.mean((drot < 0.25) & (dtr < 0.05)) >= 0.46
+    assert np.mean(dtr < 0.05) >= 0.78
+    assert np.mean(drot < 1.0) >= 0.83
 
 
 def test_flat_patches_keep_parameters():
@@ -112,6 +118,11 @@ def test_register_with_exact_gradient_recovers_known_motion(tex):
     assert np.median(dtr) < 0.03
     assert np.median(drot) < 0.35
     assert np.mean(ncc > 0.999) > 0.8
+    # the exact gradient gets further than central differences: 0.61 within
+    # (0.25 deg, 0.05 voxel), 0.87 of translations, 0.91 of rotations within 1 deg
+    assert np.mean((drot < 0.25) & (dtr < 0.05)) >= 0.58
+    assert np.mean(dtr < 0.05) >= 0.85
+    assert np.mean(drot < 1.0) >= 0.89
     th_t, _ = ctx.register(X, y, P.theta_true, gradient="analytic")
     assert np.allclose(th_t, P.theta_true, atol=1e-6)
     with pytest.raises(ValueError):
