@@ -195,7 +195,7 @@ def _oracle_sample(P, n_patch_sample: int, seed: int):
     return len(sel), int(val.sum()), t_samples, t_volume
 
 
-def cpu_baseline(P, n_patch_sample: int = 1024, n_patch_single: int = 32):
+def cpu_baseline(P, n_patch_sample: int = 2048, n_patch_single: int = 48):
     """FP64 oracle on a bounded sample of the same workload: one SR
     iteration restricted to n_patch_sample patches (simulate, EM, two
     back-projections) plus the update of the full volume, extrapolated to all
