@@ -497,6 +497,29 @@ pvr_status pvr_motion_fallback(const pvr_plan *plan, const float *score, float t
                                returns PVR_ESHAPE) */
 pvr_status pvr_check(pvr_plan *plan, hipStream_t stream);
 
+/* Debug mode, for callers tracking down bad inputs (it costs a device scan
+ * and a stream synchronisation per checked array).  When on, the entry
+ * points below check their input arrays on the device before launching and
+ * synchronise `stream`; the first offending element gives PVR_EINVAL with
+ * the function, the array and the index in pvr_last_error():
+ *   pvr_plan_build[_f64]            theta [6M] finite
+ *   pvr_simulate[_f64]              X [V], y_obs [N] finite
+ *   pvr_backproject[_f64]           e [N], p [N] finite; patch_w [M] finite
+ *                                   and >= 0
+ *   pvr_robust_weights              resid [N], y_obs [N] finite
+ *   pvr_sr_update                   X, num, den [V] finite
+ *   pvr_register_patches            X [V], y_obs [N], theta [6M] finite
+ *   pvr_simulate_grad_theta[_f64]   X [V], grad_y [N] finite
+ * Null (optional) arrays are not checked, and no check runs while `stream`
+ * is being captured into a graph (the graph's launches are the ones of the
+ * calls made during the capture, checked or not).  The mode is process-wide
+ * (every plan, every thread); it starts on when the environment variable
+ * PVR_DEBUG is set to anything other than "" or "0" when first consulted, and
+ * pvr_set_debug switches it (on != 0) at any time.  Always PVR_OK. */
+pvr_status pvr_set_debug(int32_t on);
+/* 1 when the debug mode is on, else 0. */
+int32_t pvr_get_debug(void);
+
 /* Captured SR iterations (the batched form of Sec. III level II: every
  * problem of the plan in each launch).  Records `iters` SR iterations into a
  * HIP graph: iteration i simulates from the current volume (X for even i,

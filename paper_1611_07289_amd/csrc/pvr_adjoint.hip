@@ -311,6 +311,9 @@ extern "C" pvr_status pvr_backproject(const pvr_plan *p, const float *e, const f
   PVR_ALIGNED("pvr_backproject", den, 4);
   if (!p) return fail(PVR_EINVAL, "pvr_backproject: plan is NULL");
   if (!p->built) return fail(PVR_EINVAL, "pvr_backproject: plan has not been built");
+  PVR_TRY_STATUS(debug_finite(p, "pvr_backproject", "e", e, p->N, stream));
+  PVR_TRY_STATUS(debug_finite(p, "pvr_backproject", "p", pp, p->N, stream));
+  PVR_TRY_STATUS(debug_weights(p, "pvr_backproject", "patch_w", patch_w, p->M, stream));
   return backproject_impl<float>(p, e, pp, patch_w, num, den, p->d_invz, p->d_rq + 1, stream);
   PVR_API_END();
 }
@@ -328,6 +331,9 @@ extern "C" pvr_status pvr_backproject_f64(const pvr_plan *p, const double *e, co
   if (!p->built || !p->built64)
     return fail(PVR_EINVAL, "pvr_backproject_f64: plan needs pvr_plan_build_f64 on a workspace "
                             "attached with PVR_WS_F64");
+  PVR_TRY_STATUS(debug_finite(p, "pvr_backproject_f64", "e", e, p->N, stream));
+  PVR_TRY_STATUS(debug_finite(p, "pvr_backproject_f64", "p", pp, p->N, stream));
+  PVR_TRY_STATUS(debug_weights(p, "pvr_backproject_f64", "patch_w", patch_w, p->M, stream));
   return backproject_impl<double>(p, e, pp, patch_w, num, den, p->d_invz64, p->d_rq64 + 1, stream);
   PVR_API_END();
 }

@@ -457,6 +457,8 @@ extern "C" pvr_status pvr_robust_weights(pvr_plan *p, const float *resid, const 
   PVR_ALIGNED("pvr_robust_weights", patch_w, 4);
   if (!p || !resid || !y_obs || !em || !patch_w) return fail(PVR_EINVAL, "pvr_robust_weights: NULL argument");
   if (!p->built) return fail(PVR_EINVAL, "pvr_robust_weights: plan has not been built");
+  PVR_TRY_STATUS(debug_finite(p, "pvr_robust_weights", "resid", resid, p->N, stream));
+  PVR_TRY_STATUS(debug_finite(p, "pvr_robust_weights", "y_obs", y_obs, p->N, stream));
   const int init = (flags & PVR_EM_INIT) != 0;
   const int fix = (flags & PVR_EM_FIX_W) != 0;
   // p_bar is needed by the classification even when the caller does not want it

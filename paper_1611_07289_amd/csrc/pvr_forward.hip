@@ -257,6 +257,8 @@ extern "C" pvr_status pvr_simulate(const pvr_plan *p, const float *X, const floa
   PVR_ALIGNED("pvr_simulate", resid, 4);
   if (!p) return fail(PVR_EINVAL, "pvr_simulate: plan is NULL");
   if (!p->built) return fail(PVR_EINVAL, "pvr_simulate: plan has not been built");
+  PVR_TRY_STATUS(debug_finite(p, "pvr_simulate", "X", X, p->V, stream));
+  PVR_TRY_STATUS(debug_finite(p, "pvr_simulate", "y_obs", y_obs, p->N, stream));
   return simulate_impl<float>(p, X, y_obs, y_sim, resid, p->d_invz, stream);
   PVR_API_END();
 }
@@ -272,6 +274,8 @@ extern "C" pvr_status pvr_simulate_f64(const pvr_plan *p, const double *X, const
   if (!p->built || !p->built64)
     return fail(PVR_EINVAL, "pvr_simulate_f64: plan needs pvr_plan_build_f64 on a workspace "
                             "attached with PVR_WS_F64");
+  PVR_TRY_STATUS(debug_finite(p, "pvr_simulate_f64", "X", X, p->V, stream));
+  PVR_TRY_STATUS(debug_finite(p, "pvr_simulate_f64", "y_obs", y_obs, p->N, stream));
   return simulate_impl<double>(p, X, y_obs, y_sim, resid, p->d_invz64, stream);
   PVR_API_END();
 }
@@ -629,6 +633,9 @@ extern "C" pvr_status pvr_register_patches(const pvr_plan *p, const float *X, co
   PVR_ALIGNED("pvr_register_patches", ncc, 4);
   if (!p || !X || !y_obs || !theta || !prm) return fail(PVR_EINVAL, "pvr_register_patches: NULL argument");
   if (!p->built) return fail(PVR_EINVAL, "pvr_register_patches: plan has not been built");
+  PVR_TRY_STATUS(debug_finite(p, "pvr_register_patches", "X", X, p->V, stream));
+  PVR_TRY_STATUS(debug_finite(p, "pvr_register_patches", "y_obs", y_obs, p->N, stream));
+  PVR_TRY_STATUS(debug_finite(p, "pvr_register_patches", "theta", theta, 6LL * p->M, stream));
   if (prm->max_iter < 0 || !(prm->step0 > 0) || !(prm->step_min > 0) || !(prm->fd_h > 0))
     return fail(PVR_EINVAL, "pvr_register_patches: invalid optimiser parameters");
   if (prm->gradient != PVR_REG_GRAD_FD && prm->gradient != PVR_REG_GRAD_EXACT)

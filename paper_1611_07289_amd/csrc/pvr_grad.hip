@@ -102,6 +102,8 @@ extern "C" pvr_status pvr_simulate_grad_theta(const pvr_plan *p, const float *X,
   PVR_ALIGNED("pvr_simulate_grad_theta", grad_theta, 4);
   if (!p) return fail(PVR_EINVAL, "pvr_simulate_grad_theta: plan is NULL");
   if (!p->built) return fail(PVR_EINVAL, "pvr_simulate_grad_theta: plan has not been built");
+  PVR_TRY_STATUS(debug_finite(p, "pvr_simulate_grad_theta", "X", X, p->V, stream));
+  PVR_TRY_STATUS(debug_finite(p, "pvr_simulate_grad_theta", "grad_y", gy, p->N, stream));
   return grad_impl<float>(p, X, gy, grad_theta, p->d_invz, stream);
   PVR_API_END();
 }
@@ -117,6 +119,8 @@ extern "C" pvr_status pvr_simulate_grad_theta_f64(const pvr_plan *p, const doubl
   if (!p->built || !p->built64)
     return fail(PVR_EINVAL, "pvr_simulate_grad_theta_f64: plan needs pvr_plan_build_f64 on a "
                             "workspace attached with PVR_WS_F64");
+  PVR_TRY_STATUS(debug_finite(p, "pvr_simulate_grad_theta_f64", "X", X, p->V, stream));
+  PVR_TRY_STATUS(debug_finite(p, "pvr_simulate_grad_theta_f64", "grad_y", gy, p->N, stream));
   return grad_impl<double>(p, X, gy, grad_theta, p->d_invz64, stream);
   PVR_API_END();
 }

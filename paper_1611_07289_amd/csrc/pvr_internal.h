@@ -648,9 +648,27 @@ struct pvr_plan {
   hipStream_t side;
   hipEvent_t ev_fork, ev_join;
   unsigned *d_status;        // [1] fault flags (PVR_FAULT_*), read by pvr_check
+  unsigned long long *d_dbg; // [1] first offending index of a debug-mode input check
   long long generation;      // bumped whenever launches recorded earlier would go stale
   int *d_total;              // [4] index totals: brick pairs, sub-brick pairs
   unsigned long long *d_reg_stats;  // [4] registration evaluations and samples walked
                                     // (plain, then exact gradient) since the last read
   int h_total[4];            // host readback
 };
+
+// Debug mode (pvr_set_debug, or PVR_DEBUG in the environment): input checks
+// of the core entry points, run on the device before their launches.
+// debug_finite rejects a non-finite element of a[0, n); debug_weights also a
+// negative one.  Both are no-ops outside debug mode, for a null array and
+// while the stream is captured into a graph.
+namespace pvr {
+bool debug_on();
+pvr_status debug_finite(const pvr_plan *p, const char *fn, const char *what, const float *a,
+                        long long n, hipStream_t stream);
+pvr_status debug_finite(const pvr_plan *p, const char *fn, const char *what, const double *a,
+                        long long n, hipStream_t stream);
+pvr_status debug_weights(const pvr_plan *p, const char *fn, const char *what, const float *a,
+                         long long n, hipStream_t stream);
+pvr_status debug_weights(const pvr_plan *p, const char *fn, const char *what, const double *a,
+                         long long n, hipStream_t stream);
+}  // namespace pvr

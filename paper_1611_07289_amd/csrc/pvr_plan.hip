@@ -558,6 +558,7 @@ static size_t layout(pvr_plan *p, char *base, int flags) {
   p->d_total = ws_take<int>(c, 4);
   p->d_reg_stats = ws_take<unsigned long long>(c, 4);
   p->d_status = ws_take<unsigned>(c, 1);
+  p->d_dbg = ws_take<unsigned long long>(c, 1);
   p->d_invz64 = (flags & PVR_WS_F64) ? ws_take<double>(c, N) : nullptr;
   p->d_rq64 = (flags & PVR_WS_F64) ? ws_take<double2>(c, N + 2) : nullptr;
   return (c.off + 255) & ~(size_t)255;
@@ -852,6 +853,7 @@ extern "C" pvr_status pvr_plan_build(pvr_plan *p, const float *theta, const uint
   PVR_ALIGNED("pvr_plan_build", theta, 4);
   if (!p || !theta) return fail(PVR_EINVAL, "pvr_plan_build: NULL plan or theta");
   if (!p->attached) return fail(PVR_EINVAL, "pvr_plan_build: no workspace attached (pvr_plan_attach)");
+  PVR_TRY_STATUS(debug_finite(p, "pvr_plan_build", "theta", theta, 6LL * p->M, stream));
   const int n = 6 * p->M;
   hipLaunchKernelGGL(k_theta_to_f64, dim3((n + 255) / 256), dim3(256), 0, stream, theta, p->d_theta, n);
   HIP_TRY(hipGetLastError());
@@ -865,6 +867,7 @@ extern "C" pvr_status pvr_plan_build_f64(pvr_plan *p, const double *theta, const
   PVR_ALIGNED("pvr_plan_build_f64", theta, 8);
   if (!p || !theta) return fail(PVR_EINVAL, "pvr_plan_build_f64: NULL plan or theta");
   if (!p->attached) return fail(PVR_EINVAL, "pvr_plan_build_f64: no workspace attached (pvr_plan_attach)");
+  PVR_TRY_STATUS(debug_finite(p, "pvr_plan_build_f64", "theta", theta, 6LL * p->M, stream));
   const int n = 6 * p->M;
   hipLaunchKernelGGL(k_copy_theta, dim3((n + 255) / 256), dim3(256), 0, stream, theta, p->d_theta, n);
   HIP_TRY(hipGetLastError());

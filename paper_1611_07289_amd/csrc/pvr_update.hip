@@ -81,6 +81,9 @@ extern "C" pvr_status pvr_sr_update(const pvr_plan *p, const float *X, const flo
   if (X_out == X) return fail(PVR_EINVAL, "pvr_sr_update: X_out must not alias X");
   if (!p->attached) return fail(PVR_EINVAL, "pvr_sr_update: no workspace attached (pvr_plan_attach)");
   if (!(prm->delta > 0)) return fail(PVR_EINVAL, "pvr_sr_update: delta must be > 0");
+  PVR_TRY_STATUS(debug_finite(p, "pvr_sr_update", "X", X, p->V, stream));
+  PVR_TRY_STATUS(debug_finite(p, "pvr_sr_update", "num", num, p->V, stream));
+  PVR_TRY_STATUS(debug_finite(p, "pvr_sr_update", "den", den, p->V, stream));
   hipLaunchKernelGGL(k_sr_update, dim3((p->max_nx + 63) / 64, (p->max_ny + 3) / 4, p->n_planes),
                      dim3(256), 0, stream, p->d_prob, p->d_plane_prob, X, num, den, *prm, X_out,
                      p->d_status);

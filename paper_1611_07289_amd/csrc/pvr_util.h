@@ -45,6 +45,13 @@ struct PlanGuard {
     return pvr::fail(PVR_EINVAL, "internal error");                            \
   }
 
+// Return a non-OK status of a library call from the enclosing entry point.
+#define PVR_TRY_STATUS(expr)                                                   \
+  do {                                                                         \
+    const pvr_status st_try_ = (expr);                                         \
+    if (st_try_ != PVR_OK) return st_try_;                                     \
+  } while (0)
+
 #define HIP_TRY(expr)                                                          \
   do {                                                                         \
     hipError_t e_ = (expr);                                                    \

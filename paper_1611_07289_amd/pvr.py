@@ -111,7 +111,7 @@ EXPORTS = ["pvr_last_error", "pvr_version", "pvr_plan_create", "pvr_plan_destroy
            "pvr_cnn_head_scratch", "pvr_cnn_head", "pvr_cnn_adam",
            "pvr_slic_centres", "pvr_slic_init", "pvr_slic_assign", "pvr_slic_update", "pvr_slic",
            "pvr_slic_boxes", "pvr_slic_pack", "pvr_slic_pack_workspace", "pvr_slic_pack_noalloc",
-           "pvr_check", "pvr_sr_graph_create",
+           "pvr_check", "pvr_set_debug", "pvr_get_debug", "pvr_sr_graph_create",
            "pvr_sr_graph_launch", "pvr_sr_graph_destroy"]
 
 _lib = None
@@ -186,6 +186,9 @@ def load(path: str = LIB_PATH):
     L.pvr_slic_pack_workspace.argtypes = [i32]
     L.pvr_slic_pack_workspace.restype = ctypes.c_size_t
     L.pvr_check.argtypes = [P, P]
+    L.pvr_set_debug.argtypes = [i32]
+    L.pvr_get_debug.argtypes = []
+    L.pvr_get_debug.restype = i32
     L.pvr_sr_graph_create.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, i32, P, P]
     L.pvr_sr_graph_launch.argtypes = [P, P]
     L.pvr_sr_graph_destroy.argtypes = [P]
@@ -197,6 +200,17 @@ def load(path: str = LIB_PATH):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
+
+
+def set_debug(on: bool = True):
+    """Switch the library's debug mode (pvr_set_debug): the core calls then
+    check their input arrays on the device and reject the first non-finite
+    value (or negative patch weight) with PvrError(PVR_EINVAL)."""
+    _check(load().pvr_set_debug(1 if on else 0))
+
+
+def get_debug() -> bool:
+    return bool(load().pvr_get_debug())
 
 
 def _check(st: int):

@@ -20,7 +20,7 @@ def _declared():
         if not h.endswith(".h"):
             continue
         txt = open(os.path.join(ROOT, "include", h)).read()
-        names |= set(re.findall(r"^(?:pvr_status|const char|const float|void|int64_t|size_t)[\s*]+"
+        names |= set(re.findall(r"^(?:pvr_status|const char|const float|void|int64_t|int32_t|size_t)[\s*]+"
                                 r"(pvr_[a-z0-9_]+)\s*\(", txt, re.M))
     return sorted(names)
 
