@@ -31,19 +31,37 @@ k_bp_prep(const PatchDev *__restrict__ patches, const BlockWork *__restrict__ wo
   const PatchDev pt = patches[wk.patch];
   const int n = pt.w * pt.h;
   const int l1 = min(n, wk.l0 + SIM_CHUNK);
-  for (int l = wk.l0 + threadIdx.x; l < l1; l += SIM_THREADS) {
-    const long long j = pt.off + l;
-    const T iz = invz[j];
+  // one sample (invalid samples, 1/Z = 0, get 0)
+  auto one = [&](long long j, T iz, T pj, T ej) {
     typename Vec2Of<T>::type o;
     if (iz > (T)0) {
-      const T q = (p ? p[j] : (T)1) * iz;
-      o.x = q * e[j];
+      const T q = pj * iz;
+      o.x = q * ej;
       o.y = q;
     } else {
       o.x = 0;
       o.y = 0;
     }
     rq[j] = o;
+  };
+  // four samples per thread in flight: their reads are independent (e and p
+  // are defined for every sample)
+  int l = wk.l0 + threadIdx.x;
+  for (; l + 3 * SIM_THREADS < l1; l += 4 * SIM_THREADS) {
+    T iz[4], pj[4], ej[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long long j = pt.off + l + u * SIM_THREADS;
+      iz[u] = invz[j];
+      pj[u] = p ? p[j] : (T)1;
+      ej[u] = e[j];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) one(pt.off + l + u * SIM_THREADS, iz[u], pj[u], ej[u]);
+  }
+  for (; l < l1; l += SIM_THREADS) {
+    const long long j = pt.off + l;
+    one(j, invz[j], p ? p[j] : (T)1, e[j]);
   }
 }
 

@@ -168,11 +168,10 @@ k_em_estep(const PatchDev *__restrict__ patches, const float *__restrict__ invz,
   (void)sigma2;
   const int n = pt.w * pt.h;
   double ns = 0, sp2 = 0, sp = 0, spe2 = 0;
-  for (int l = threadIdx.x; l < n; l += EM_T) {
-    const long long j = pt.off + l;
+  // one sample: the posterior and the sums (invalid samples, 1/Z = 0, get 0)
+  auto one = [&](long long j, float iz, float ev) {
     float pj = 0.f;
-    if (invz[j] > 0.f) {
-      const float ev = e[j];
+    if (iz > 0.f) {
       const float Gc = cG0 * expf(-ev * ev * inv2s2);
       const float dd = Gc + mo;
       pj = dd > 0.f ? Gc / dd : 0.f;
@@ -182,6 +181,25 @@ k_em_estep(const PatchDev *__restrict__ patches, const float *__restrict__ invz,
       spe2 += (double)pj * ev * ev;
     }
     if (p_out) p_out[j] = pj;
+  };
+  // four samples per thread in flight (the loop is latency-bound), taken in
+  // the same order as one at a time; e is read for invalid samples too (it
+  // is defined for every sample)
+  int l = threadIdx.x;
+  for (; l + 3 * EM_T < n; l += 4 * EM_T) {
+    float iz[4], ev[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long long j = pt.off + l + u * EM_T;
+      iz[u] = invz[j];
+      ev[u] = e[j];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) one(pt.off + l + u * EM_T, iz[u], ev[u]);
+  }
+  for (; l < n; l += EM_T) {
+    const long long j = pt.off + l;
+    one(j, invz[j], e[j]);
   }
   double red[4] = {ns, sp2, sp, spe2};
   bsumk<EM_T, 4>(red, lds);
@@ -277,15 +295,37 @@ k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
   const int pb = pr.patch_begin, np = pr.patch_end - pr.patch_begin;
   float *V = use_lds ? sval : gval + pb;
   double n = 0, s_all = 0, q_all = 0;
-  for (int q = t; q < np; q += EMP_T) {
-    const int s = pb + q;
-    float v = -1.f;
-    if (pstat[PSTAT * s + 5] > 0 && active[s] != 0) v = pbar[s];
+  // the patches taking part (valid samples, active) and their potentials;
+  // the three reads of a patch are independent and four patches per thread
+  // are in flight, taken in the same order as one at a time
+  auto take = [&](int q, double ns, uint8_t act, float pv) {
+    const float v = (ns > 0 && act != 0) ? pv : -1.f;
     V[q] = v;
     if (v >= 0.f) {
       n += 1.0;
       s_all += (double)v;
       q_all += (double)v * (double)v;
+    }
+  };
+  {
+    int q = t;
+    for (; q + 3 * EMP_T < np; q += 4 * EMP_T) {
+      double ns[4];
+      uint8_t act[4];
+      float pv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int s = pb + q + u * EMP_T;
+        ns[u] = pstat[PSTAT * s + 5];
+        act[u] = active[s];
+        pv[u] = pbar[s];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) take(q + u * EMP_T, ns[u], act[u], pv[u]);
+    }
+    for (; q < np; q += EMP_T) {
+      const int s = pb + q;
+      take(q, pstat[PSTAT * s + 5], active[s], pbar[s]);
     }
   }
   {
@@ -407,12 +447,14 @@ k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
   const Mix mfin = make_mix(mu0, sd0, mu1, sd1, w1);
   // patch weights, then the M-step sums over the problem's patches
   double swpe2 = 0, swp = 0, sw = 0, nex = 0;
-  for (int q = t; q < np; q += EMP_T) {
+  // one patch: its weight (given, or from the fitted mixture) and its terms
+  // of the M-step sums, from its partials o = (N_s, sum p, sum p e^2)
+  auto weigh = [&](int q, double o5, double o7, double o8, float wgiven) {
     const int s = pb + q;
     double W;
     const bool u = V[q] >= 0.f;
     if (fix_w) {
-      W = patch_w[s];
+      W = wgiven;
     } else {
       double pi = 0;
       if (u) {
@@ -423,11 +465,34 @@ k_em_patches(const ProbDev *__restrict__ probs, const float *__restrict__ pbar,
       patch_w[s] = (float)W;
       W = (double)(float)W;
     }
-    const double *o = pstat + PSTAT * s;
-    swpe2 += W * o[8];
-    swp += W * o[7];
-    sw += W * o[5];
+    swpe2 += W * o8;
+    swp += W * o7;
+    sw += W * o5;
     nex += (u && W == 0) ? 1.0 : 0.0;
+  };
+  // four patches' partials per thread in flight, in the order of one at a time
+  {
+    int q = t;
+    for (; q + 3 * EMP_T < np; q += 4 * EMP_T) {
+      double o5[4], o7[4], o8[4];
+      float wg[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int s = pb + q + u * EMP_T;
+        const double *o = pstat + PSTAT * s;
+        o5[u] = o[5];
+        o7[u] = o[7];
+        o8[u] = o[8];
+        wg[u] = fix_w ? patch_w[s] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) weigh(q + u * EMP_T, o5[u], o7[u], o8[u], wg[u]);
+    }
+    for (; q < np; q += EMP_T) {
+      const int s = pb + q;
+      const double *o = pstat + PSTAT * s;
+      weigh(q, o[5], o[7], o[8], fix_w ? patch_w[s] : 0.f);
+    }
   }
   double red4b[4] = {swpe2, swp, sw, nex};
   bsumk<EMP_T, 4>(red4b, lds);
