@@ -129,11 +129,38 @@ k_em_problem(const ProbDev *__restrict__ probs, const double *__restrict__ pstat
     se2 += o[3];
     cnt += o[4];
   }
-  mn = bmin<EMP_T>(mn, lds);
-  mx = bmax<EMP_T>(mx, lds);
-  ym = bmax<EMP_T>(ym, lds);
-  se2 = bsum<EMP_T>(se2, lds);
-  cnt = bsum<EMP_T>(cnt, lds);
+  // the five reductions at once: a butterfly inside every wave, then thread 0
+  // combines the wave results in wave order (the order of breduce / bsumk)
+  {
+    constexpr int NW = EMP_T / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      mn = fmin(mn, __shfl_xor(mn, o, 64));
+      mx = fmax(mx, __shfl_xor(mx, o, 64));
+      ym = fmax(ym, __shfl_xor(ym, o, 64));
+      se2 += __shfl_xor(se2, o, 64);
+      cnt += __shfl_xor(cnt, o, 64);
+    }
+    if (lane == 0) {
+      lds[0 * NW + wave] = mn;
+      lds[1 * NW + wave] = mx;
+      lds[2 * NW + wave] = ym;
+      lds[3 * NW + wave] = se2;
+      lds[4 * NW + wave] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      mn = lds[0]; mx = lds[NW]; ym = lds[2 * NW]; se2 = lds[3 * NW]; cnt = lds[4 * NW];
+      for (int w = 1; w < NW; ++w) {
+        mn = fmin(mn, lds[w]);
+        mx = fmax(mx, lds[NW + w]);
+        ym = fmax(ym, lds[2 * NW + w]);
+        se2 += lds[3 * NW + w];
+        cnt += lds[4 * NW + w];
+      }
+    }
+  }
   if (threadIdx.x == 0) {
     // min / max skip NaN residuals, their squares' sum does not
     if (!isfinite(se2) || !isfinite(mx - mn) || !isfinite(ym)) atomicOr(status, PVR_FAULT_RESIDUAL);
