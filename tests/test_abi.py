@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -121,3 +122,19 @@ def test_destroy_null_is_noop_and_null_plan_calls_fail():
     assert L.pvr_sr_graph_launch(None, None) == 1
     L.pvr_sr_graph_destroy(None)
     assert "NULL" in L.pvr_last_error().decode()
+
+
+@pytest.mark.parametrize("env,expect", [(None, 0), ("0", 0), ("", 0), ("1", 1), ("yes", 1)])
+def test_debug_mode_starts_from_the_environment(env, expect):
+    """PVR_DEBUG decides the initial debug mode (read on first use, in a fresh
+    process); pvr_set_debug switches it afterwards.  No device call."""
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1611_07289_amd import pvr\n"
+            "a = pvr.get_debug(); pvr.set_debug(not a); b = pvr.get_debug()\n"
+            "print(int(a), int(b))\n") % ROOT
+    envd = {k: v for k, v in os.environ.items() if k != "PVR_DEBUG"}
+    if env is not None:
+        envd["PVR_DEBUG"] = env
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=envd,
+                         check=True, timeout=120).stdout.split()
+    assert out == [str(expect), str(1 - expect)]
