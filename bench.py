@@ -121,6 +121,9 @@ def make_workload(name: str):
     from paper_1611_07289_amd import synth
     if name in ("uterus256", "sinc256"):
         return [synth.full_problem()]
+    if name == "uterus384":
+        # the same construction at 384^3 (4 stacks of 384 x 384 x 90)
+        return [synth.full_problem(n=384, slices=90)]
     if name == "tiny32":
         return [synth.tiny_problem()]
     if name == "batched":
@@ -439,7 +442,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "problems": plan.P, "patches": plan.M,
                    "samples": plan.N, "valid_samples": n_valid, "voxels": plan.V,
-                   "patch": "64x64 stride 32" if args.workload == "uterus256" else "mixed",
+                   "patch": ("64x64 stride 32" if args.workload in ("uterus256", "uterus384")
+                             else "mixed"),
                    "psf_fwhm_mm": [1, 1, 4], "psf": "sinc" if sinc else "gaussian",
                    "plan_device_bytes": int(plan.info().device_bytes),
                    "parallelism": "single GPU"},
