@@ -608,9 +608,14 @@ __device__ __forceinline__ void register_patch(
 
 // The optimiser of register_patch for the patches of one volume layout (the
 // others return at once): one launch per layout keeps the register use of a
-// single optimiser.
+// single optimiser.  The central-difference optimiser with the Gaussian PSF
+// is held to 128 registers (4 waves per SIMD): its few spills cost less than
+// the waves gained (1.16 -> 1.09 s for the registration passes of a 256^3
+// four-stack reconstruction); the exact-gradient and sinc variants keep their
+// allocation (at 128 registers they spill heavily and run slower; an
+// explicit two-wave minimum changed their code and cost the exact one 12 %).
 template <bool EXACT, bool XT, int PSF>
-__global__ void __launch_bounds__(REG_THREADS)
+__global__ void __launch_bounds__(REG_THREADS, (!EXACT && PSF == PVR_PSF_GAUSSIAN) ? 4 : 1)
 k_register(const ProbDev *__restrict__ probs, const StackDev *__restrict__ stacks,
            const PatchDev *__restrict__ patches, const float *__restrict__ Xv, int any_xt,
            const float *__restrict__ y, const uint8_t *__restrict__ mask,

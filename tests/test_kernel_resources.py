@@ -18,7 +18,7 @@ FLOORS = {
         "_Z10k_simulateIfE": 7,
         "_Z10k_registerILb1ELb0ELi0E": 2,   # exact gradient, x-fastest volume
         "_Z10k_registerILb1ELb1ELi0E": 2,   # exact gradient, y-fastest copy
-        "_Z10k_registerILb0ELb0ELi0E": 3,   # central differences
+        "_Z10k_registerILb0ELb0ELi0E": 4,   # central differences (held to 128 VGPRs)
         "_Z10k_registerILb0ELb0ELi1E": 2,   # central differences, sinc PSF
     },
     "pvr_adjoint.hip": {
