@@ -403,7 +403,10 @@ pvr_status pvr_sr_update(const pvr_plan *plan, const float *X,
  * trial steps.  Patches with std(y_s) < min_std keep theta.
  * theta [M][6] in/out; ncc [M] out (nullable); reg [M] (nullable = all):
  * only patches with reg != 0 move; params (host); sample_mask of the last
- * build applies.  With max_iter = 0 it only evaluates NCC at theta. */
+ * build applies.  With max_iter = 0 it only evaluates NCC at theta.  The
+ * patches whose rows run closer to voxel y than to x are registered on the
+ * plan's second stream, concurrently with the others; `stream` waits for
+ * them before any later work. */
 pvr_status pvr_register_patches(const pvr_plan *plan, const float *X,
                                 const float *y_obs, float *theta, float *ncc,
                                 const uint8_t *reg,
