@@ -273,9 +273,9 @@ pvr_status pvr_plan_build_f64(pvr_plan *plan, const double *theta,
  *     profile through-plane.  In the moved patch frame (offsets d_u, d_v, d_n
  *     in mm) the weight is s(d_u / w_u) s(d_v / w_v) (exp(-d_n^2 / 2 sigma_n^2)
  *     - exp(-k^2 / 2)) on |d_u| < w_u, |d_v| < w_v, |d_n| <= k sigma_n, where
- *     s(t) = sin(pi t) / (pi t) is summed as its Taylor series in (pi t)^2
- *     (terms through (pi t)^16 in FP32, remainder below 1.1e-8; through
- *     (pi t)^22 in FP64), w = the in-plane FWHMs (the sinc's first zero;
+ *     s(t) = sin(pi t) / (pi t) is a polynomial in (pi t)^2 (in FP32 its
+ *     degree-6 Chebyshev interpolant on |t| <= 1, within 1e-9 of s; in FP64
+ *     the Taylor series through (pi t)^22), w = the in-plane FWHMs (the sinc's first zero;
  *     main lobe only) and sigma_n the slice profile's deviation from the
  *     through-plane FWHM.  Normalised over in-volume voxels like the Gaussian.
  *     Registration runs with the central-difference gradient only: the

@@ -388,21 +388,22 @@ __device__ __forceinline__ T psf_walk_fwd(const GEO &g, const ProbDev &p, const 
   return acc;
 }
 
-// s(t) = sin(pi t) / (pi t) by its Taylor series in y = (pi t)^2,
-// sum_m (-1)^m y^m / (2m + 1)!, in Horner form: terms through y^8 in FP32
-// (for |t| <= 1 the first omitted term, pi^18 / 19!, is below 1.1e-8) and
-// through y^11 in FP64 (pi^24 / 25! < 6e-14).
+// s(t) = sin(pi t) / (pi t) for |t| <= 1 as a polynomial in y = (pi t)^2.
+// FP32: degree 6, the Chebyshev interpolant of s on y in [0, pi^2] (nodes
+// at the zeros of T_7 mapped onto the interval) in monomial form; it differs
+// from s by less than 1e-9, far below the FP32 rounding of the Horner
+// evaluation (about 1.5e-7 at worst over |t| <= 1).  FP64: the Taylor series
+// sum_m (-1)^m y^m / (2m + 1)! through y^11 (the first omitted term,
+// pi^24 / 25!, is below 6e-14).
 template <typename T> __device__ __forceinline__ T sinc_poly(T t);
 template <> __device__ __forceinline__ float sinc_poly<float>(float t) {
   const float y = (3.14159265358979f * t) * (3.14159265358979f * t);
-  float s = 2.8114572543455208e-15f;              //  1 / 17!
-  s = fmaf(s, y, -7.6471637318198164e-13f);       // -1 / 15!
-  s = fmaf(s, y, 1.6059043836821613e-10f);        //  1 / 13!
-  s = fmaf(s, y, -2.5052108385441720e-08f);       // -1 / 11!
-  s = fmaf(s, y, 2.7557319223985893e-06f);        //  1 / 9!
-  s = fmaf(s, y, -1.9841269841269841e-04f);       // -1 / 7!
-  s = fmaf(s, y, 8.3333333333333333e-03f);        //  1 / 5!
-  s = fmaf(s, y, -1.6666666666666667e-01f);       // -1 / 3!
+  float s = 1.3611596572093987e-10f;
+  s = fmaf(s, y, -2.4728366909698707e-08f);
+  s = fmaf(s, y, 2.7535800199984806e-06f);
+  s = fmaf(s, y, -1.9840530876535922e-04f);
+  s = fmaf(s, y, 8.3333216607570648e-03f);
+  s = fmaf(s, y, -1.6666665673255920e-01f);
   return fmaf(s, y, 1.0f);
 }
 template <> __device__ __forceinline__ double sinc_poly<double>(double t) {
@@ -450,6 +451,12 @@ __device__ __forceinline__ T psf_walk_sinc(const GEO &g, const ProbDev &p, const
     Lc[i] = (T)g.L[3 * i + ic];
   }
   const T Bd[3] = {(T)1, (T)1, (T)g.kcut};
+  // the slab bounds along the inner axis scale by 1 / Lc: one division per
+  // axis and sample instead of two per axis and row (the bounds are widened
+  // below, so a last-place difference never drops a voxel of the support)
+  T iLc[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) iLc[i] = fabs(Lc[i]) > (T)1e-20 ? (T)1 / Lc[i] : (T)0;
   const T cut = (T)g.cut, kap = (T)KAPPA;
   const T ea = (T)g.ext[ia], eb = (T)g.ext[ib];
   const int lo_a = max((int)ceil(f_a - ea), -b_a);
@@ -470,7 +477,7 @@ __device__ __forceinline__ T psf_walk_sinc(const GEO &g, const ProbDev &p, const
       for (int i = 0; i < 3; ++i) {
         r[i] = La[i] * wa + Lb[i] * wb;
         if (fabs(Lc[i]) > (T)1e-20) {
-          const T t1 = (-Bd[i] - r[i]) / Lc[i], t2 = (Bd[i] - r[i]) / Lc[i];
+          const T t1 = (-Bd[i] - r[i]) * iLc[i], t2 = (Bd[i] - r[i]) * iLc[i];
           lo = fmax(lo, fmin(t1, t2));
           hi = fmin(hi, fmax(t1, t2));
         } else if (fabs(r[i]) > Bd[i]) {
