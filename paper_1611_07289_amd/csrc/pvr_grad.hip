@@ -5,8 +5,11 @@
 //   d y_hat_j / d theta = sum_i (X_i - y_hat_j) d g_hat_ji / d theta / Z_j,
 // with d g_hat / d theta as derived in pvr_grad.h.
 //
-// One workgroup per patch; two walks per sample (y_hat, then the derivative
-// sums); FP64 accumulation of the six per-patch sums.
+// One workgroup per patch; FP64 accumulation of the six per-patch sums.  In
+// FP32 one walk per sample gathers the nine offset moments of pvr_grad.h
+// (the exact registration's walk, grouped loads through a buffer resource)
+// and forms the six derivatives once per sample; in FP64 two walks (y_hat,
+// then the derivative evaluated at every voxel) keep the direct form.
 #include <math.h>
 
 #include "pvr_geometry.h"
@@ -33,6 +36,10 @@ k_grad_theta(const ProbDev *__restrict__ probs, const StackDev *__restrict__ sta
   GradConst gc;
   make_grad_const(pr, st, pt, theta + 6 * s, gc);
   const T *Xp = X + pr.vol_off;
+  GradMom gm;
+  if constexpr (sizeof(T) == 4) make_grad_mom(gc, g.perm, gm);
+  const unsigned nbytes = (unsigned)(pr.nx * pr.ny * pr.nz) * (unsigned)sizeof(T);
+  const __amdgpu_buffer_rsrc_t xr = raw_buffer(Xp, nbytes);
   double sum6[6] = {0, 0, 0, 0, 0, 0};
   const int n = pt.w * pt.h;
   for (int l = threadIdx.x; l < n; l += GR_THREADS) {
@@ -45,9 +52,6 @@ k_grad_theta(const ProbDev *__restrict__ probs, const StackDev *__restrict__ sta
     int b[3];
     T f[3];
     sample_centre(g, pr, u, v, pt.slice, b, f);
-    T z = 0, acc = 0;
-    psf_walk<T, typename GeoOf<T>::type, true>(g, pr, b, f, Xp, z, acc);
-    const T yh = acc * iz;
     // q = x_world - (c + t), x_world = Vl x_vox + o
     double xv[3], q[3];
 #pragma unroll
@@ -60,7 +64,25 @@ k_grad_theta(const ProbDev *__restrict__ probs, const StackDev *__restrict__ sta
              gc.v2w_o[r] - gc.ct[r];
     const T qt[3] = {(T)q[0], (T)q[1], (T)q[2]};
     T a6[6] = {0, 0, 0, 0, 0, 0};
-    grad_walk<T>(g, pr, gc, b, f, qt, Xp, yh, a6);
+    if constexpr (sizeof(T) == 4) {
+      // moments of w_i = e^{-Q_i/2} (X_i - y_hat) from those relative to the
+      // centre voxel's value X_b: y_hat - X_b = sum g_hat (X - X_b) / Z
+      float xb, a, z, mx[9], me[9];
+      if (g.perm[2] == 0)
+        psf_walk_grad<1, false>(g, pr, b, f, xr, nbytes, xb, a, z, mx, me);
+      else
+        psf_walk_grad<2, false>(g, pr, b, f, xr, nbytes, xb, a, z, mx, me);
+      const float dl = a * iz;
+      float m[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) m[c] = fma(-dl, me[c], mx[c]);
+      grad_from_moments(gm, m, qt, a6);
+    } else {
+      T z = 0, acc = 0;
+      psf_walk<T, typename GeoOf<T>::type, true>(g, pr, b, f, Xp, z, acc);
+      const T yh = acc * iz;
+      grad_walk<T>(g, pr, gc, b, f, qt, Xp, yh, a6);
+    }
 #pragma unroll
     for (int k = 0; k < 6; ++k) sum6[k] += (double)gj * (double)(a6[k] * iz);
   }

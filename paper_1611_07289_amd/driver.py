@@ -267,29 +267,36 @@ def register_gradient(plan, X, y, theta, iters: int = 30, step0: float = 1.0,
     g = torch.empty_like(ysim)
     ncc = torch.empty(plan.M, dtype=torch.float32, device=dev)
     ncc_t = torch.empty_like(ncc)
+    ncc_c = torch.empty_like(ncc)
     G = torch.empty(plan.M, 6, dtype=torch.float32, device=dev)
+    G_t = torch.empty_like(G)
     trial = torch.empty_like(G)
     delta = torch.empty(plan.M, dtype=torch.float32, device=dev)
 
-    def evaluate(th, grad):
+    def evaluate(th, score, grad):
         plan.build(th, active=active, mask=mask)
         plan.simulate(X, y_sim=ysim)
-        if grad:
-            plan.ncc_grad(y, ysim, g, ncc)
-            plan.grad_theta(X, g, G)
-        else:
-            plan.ncc_grad(y, ysim, None, ncc_t)
+        plan.ncc_grad(y, ysim, g, score)
+        plan.grad_theta(X, g, grad)
 
+    # NCC and gradient at every trial: an accepted trial becomes the patch's
+    # motion with the NCC and gradient just computed there, a rejected one
+    # leaves the motion, NCC and gradient as they were, so the motion is
+    # never evaluated twice
     n_live = torch.zeros(1, dtype=torch.int32, device=dev)
-    evaluate(theta, True)
+    evaluate(theta, ncc, G)
     plan.motion_init_step(y, step0, min_std, delta)
     for it in range(iters):
         plan.motion_step(theta, G, delta, step_min, trial)
-        evaluate(trial, False)
+        evaluate(trial, ncc_t, G_t)
+        # the gradient follows the motion: the same strict-improvement test
+        # (on a copy of the scores, which the motion's acceptance updates);
+        # a patch below step_min did not move, so its trial cannot improve
+        ncc_c.copy_(ncc)
+        plan.motion_accept(G_t, ncc_t, G, ncc_c)
         n_live.zero_()
         plan.motion_accept(trial, ncc_t, theta, ncc, delta, step0, step_min, n_live)
         if it % 4 == 3 and int(n_live.item()) == 0:  # every patch has converged
             break
-        evaluate(theta, True)
     plan.build(theta, active=active, mask=mask)
     return ncc
