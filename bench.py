@@ -252,6 +252,10 @@ def main():
                     help="learned workload: time inference only")
     ap.add_argument("--no-superpixel", action="store_true",
                     help="skip the superpixel-versus-square-patch reconstruction")
+    ap.add_argument("--learned-seeds", default="5005:7800",
+                    help="comma-separated NET:TRAIN seed pairs of the learned initialiser; "
+                         "the first gives the learned runs, every pair is reported under "
+                         "full_pvr.learned_seeds (the spread of the learned result)")
     ap.add_argument("--full-pvr-runs", default=None,
                     help="comma-separated subset of the whole-reconstruction runs (e.g. "
                          "plain,plain_exact), a profiling aid")
@@ -459,7 +463,9 @@ def main():
     }
 
     if not args.no_full_pvr and args.workload == "uterus256":
+        seeds = [tuple(int(v) for v in kv.split(":")) for kv in args.learned_seeds.split(",")]
         out["full_pvr"] = full_pvr(plan, probs, y, Xtrue, dev, learned_pairs=args.learned_pairs,
+                                   learned_seeds=seeds,
                                    only=args.full_pvr_runs.split(",") if args.full_pvr_runs
                                    else None)
     if not args.no_full_pvr and args.workload == "sinc256":
@@ -785,7 +791,7 @@ def register_roofline(stats, reg_ms, nnz_per_sample):
 
 
 def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10, learned_pairs=0, exact=True,
-             tight=(0.25, 5), fallback_tau=0.3, only=None):
+             tight=(0.25, 5), fallback_tau=0.3, only=None, learned_seeds=((5005, 7800),)):
     """Seconds and PSNR of a whole reconstruction from the motion-corrupted
     start (zero motion), each with its registration kernel's time, work and
     roofline: plain registration with the full budget (step0 1, 40 trial
@@ -798,7 +804,9 @@ def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10, learned_pairs=0, exa
     (exact only) the
     joint gradient-based registration through the differentiable forward
     model (driver.register_gradient) in place of the per-patch one.  `only`,
-    when given, names the runs to make (a profiling aid)."""
+    when given, names the runs to make (a profiling aid).  Every (network,
+    training) seed pair of `learned_seeds` trains its own network; the first
+    gives the "learned" runs, and all are listed under "learned_seeds"."""
     import torch
     from paper_1611_07289_amd import driver, learned, pvr, synth
     res = {}
@@ -806,7 +814,7 @@ def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10, learned_pairs=0, exa
     nnz_ps = nnz_estimate(probs, 1)
 
     def run(key, rp, init_fn=None, register_fn=None):
-        if only and key not in only:
+        if only and key.split("@")[0] not in only:
             return
         th0 = torch.zeros(plan.M, 6, dtype=torch.float32, device=dev)
         plan.set_timing(True)
@@ -856,17 +864,27 @@ def full_pvr(plan, probs, y, Xtrue, dev, cycles=3, n_sr=10, learned_pairs=0, exa
     if learned_pairs > 0 and exact and (not only or any(k.startswith("learned") for k in only)):
         P = probs[0]
         Xtr = torch.from_numpy(synth.phantom_uterus(P.grid.nx, 7700, 7701).reshape(-1)).to(dev)
-        net = learned.Net(seed=5005)
-        tr = learned.train(net, plan, [Xtr], n_pairs=learned_pairs, batch=256, lr=1e-3,
-                           seed=7800, log=log)
+        res["learned_seeds"] = []
+        for i, (net_seed, train_seed) in enumerate(learned_seeds):
+            net = learned.Net(seed=net_seed)
+            tr = learned.train(net, plan, [Xtr], n_pairs=learned_pairs, batch=256, lr=1e-3,
+                               seed=train_seed, log=log)
+            init_fn = learned.init_fn_factory(net)
+            sfx = "" if i == 0 else f"@{net_seed}"
+            run("learned" + sfx, pvr.RegParams.make(**short), init_fn)
+            run("learned_exact" + sfx, pvr.RegParams.make(**short, exact=True), init_fn)
+            if i == 0:
+                res["training"] = {"pairs": tr["pairs"], "seconds": tr["seconds"],
+                                   "data_seconds": tr["data_seconds"],
+                                   "loss_first_last": [tr["loss"][0][1], tr["loss"][-1][1]]
+                                   if tr["loss"] else None}
+            entry = {"net_seed": net_seed, "train_seed": train_seed}
+            for k in ("learned", "learned_exact"):
+                if k + sfx in res:
+                    r = res[k + sfx] if i == 0 else res.pop(k + sfx)
+                    entry[k] = {"seconds": r["seconds"], "psnr_db": r["psnr_db"]}
+            res["learned_seeds"].append(entry)
         del Xtr
-        init_fn = learned.init_fn_factory(net)
-        run("learned", pvr.RegParams.make(**short), init_fn)
-        run("learned_exact", pvr.RegParams.make(**short, exact=True), init_fn)
-        res["training"] = {"pairs": tr["pairs"], "seconds": tr["seconds"],
-                           "data_seconds": tr["data_seconds"],
-                           "loss_first_last": [tr["loss"][0][1], tr["loss"][-1][1]]
-                           if tr["loss"] else None}
         for sfx in ("", "_exact"):
             if any(k + sfx not in res for k in ("learned", "plain", "plain_tight")):
                 continue

@@ -192,6 +192,16 @@ __device__ __forceinline__ bool sample_centre(const GEO &g, const ProbDev &p,
   return in;
 }
 
+// Square root for the row bounds of the walks: in FP32 the hardware square
+// root (about one ulp) widened by a relative 1e-6, so a row never loses a
+// voxel of the support (a voxel the wider range adds lies outside it, where
+// the clamped weight 2^-Q - 2^-K2 is 0); in FP64 the IEEE square root.
+template <typename T> __device__ __forceinline__ T fast_sqrt(T x);
+template <> __device__ __forceinline__ float fast_sqrt<float>(float x) {
+  return __builtin_amdgcn_sqrtf(x) * 1.000001f;
+}
+template <> __device__ __forceinline__ double fast_sqrt<double>(double x) { return sqrt(x); }
+
 // Walk the PSF support of one sample (nearest voxel b, offset f) over the
 // voxels inside the grid and return sum g_hat and sum g_hat * X.  Rows along
 // the inner axis c are enumerated exactly from the quadratic form: for the
@@ -223,7 +233,7 @@ __device__ __forceinline__ void psf_walk_s(const GEO &g, const int clo[3], const
     const T rem = K2 - wa * wa * iAaa;
     if (rem < (T)0) continue;
     const T wbc = nSab * wa;
-    const T rb = sqrt(rem * iSbb);
+    const T rb = fast_sqrt<T>(rem * iSbb);
     const int lo_b = max((int)ceil(f_b + wbc - rb), cl_b);
     const int hi_b = min((int)floor(f_b + wbc + rb), ch_b);
     const T qa = Saa * wa * wa;
@@ -234,7 +244,7 @@ __device__ __forceinline__ void psf_walk_s(const GEO &g, const int clo[3], const
       const T rem2 = K2 - q1;
       if (rem2 < (T)0) continue;
       const T wcc = -(Aca * wa + Acb * wb) * iAcc;
-      const T rc = sqrt(rem2 * iAcc);
+      const T rc = fast_sqrt<T>(rem2 * iAcc);
       const int lo_c = max((int)ceil(f_c + wcc - rc), cl_c);
       const int hi_c = min((int)floor(f_c + wcc + rc), ch_c);
       T d = ((T)lo_c - f_c) - wcc;
@@ -308,11 +318,6 @@ __device__ __forceinline__ void load_group(__amdgpu_buffer_rsrc_t r, unsigned of
   for (int k = 0; k < 4; ++k) x[k] = load_vox<T>(r, off + (unsigned)k * step);
 }
 
-template <typename T> __device__ __forceinline__ T fast_sqrt(T x);
-template <> __device__ __forceinline__ float fast_sqrt<float>(float x) {
-  return __builtin_amdgcn_sqrtf(x) * 1.000001f;
-}
-template <> __device__ __forceinline__ double fast_sqrt<double>(double x) { return sqrt(x); }
 // max(x, 0) for x in [-1, 1] (the output clamp of the producing instruction)
 template <typename T> __device__ __forceinline__ T clamp01(T x);
 template <> __device__ __forceinline__ float clamp01<float>(float x) {
