@@ -630,6 +630,8 @@ struct pvr_plan {
   uint8_t *d_mask;           // [N]
   uint8_t *d_active;         // [M]
   int *d_bb;                 // [M][6] brick range per patch
+  int *d_gbox;               // [ceil(M / 64)][6] union of the ranges of 64 consecutive patches
+  long long *d_scan;         // block sums of the index scans
   double *d_sbox;            // [M][18] voxel->pixel map and pixel support box
   int *d_bin_count;          // [n_bricks]
   int *d_bin_off;            // [n_bricks + 1]

@@ -1,5 +1,6 @@
 // Plan creation and the motion-dependent build: per-patch geometry, per-sample
 // PSF normalisers and the brick -> patch index of the gather adjoint.
+#include <limits.h>
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -187,57 +188,142 @@ __device__ __forceinline__ void sub_box(const ProbDev &pr, int sbi, double lo[3]
   for (int a = 0; a < 3; ++a) hi[a] = lo[a] + SUB - 1;
 }
 
-__global__ void k_sub_count(const ProbDev *__restrict__ probs, const int *__restrict__ brick_prob,
-                            const double *__restrict__ sbox, int nsb, const int *__restrict__ off,
-                            const int *__restrict__ list, int *__restrict__ count) {
-  const int sbi = blockIdx.x * blockDim.x + threadIdx.x;
-  if (sbi >= nsb) return;
-  const ProbDev pr = probs[brick_prob[sbi >> 3]];
-  double lo[3], hi[3];
-  sub_box(pr, sbi, lo, hi);
-  int c = 0;
-  for (int q = off[sbi >> 3]; q < off[(sbi >> 3) + 1]; ++q)
-    c += box_meets_patch(sbox + 18 * list[q], lo, hi) ? 1 : 0;
-  count[sbi] = c;
+// One wavefront per brick: the lanes take 64 entries of the brick's list at
+// a time and test each entry's patch against the 8 sub-bricks; per
+// sub-brick a ballot counts the hits (k_sub_count) or places them in list
+// order, which is ascending patch order (k_sub_fill).
+__device__ __forceinline__ unsigned sub_mask(const ProbDev &pr, int bi,
+                                             const double *__restrict__ sb) {
+  unsigned m = 0;
+#pragma unroll
+  for (int w = 0; w < 8; ++w) {
+    double lo[3], hi[3];
+    sub_box(pr, bi * 8 + w, lo, hi);
+    m |= box_meets_patch(sb, lo, hi) ? 1u << w : 0u;
+  }
+  return m;
 }
 
-__global__ void k_sub_fill(const ProbDev *__restrict__ probs, const int *__restrict__ brick_prob,
-                           const double *__restrict__ sbox, int nsb, const int *__restrict__ off,
-                           const int *__restrict__ list, const int *__restrict__ soff,
-                           int *__restrict__ slist) {
-  const int sbi = blockIdx.x * blockDim.x + threadIdx.x;
-  if (sbi >= nsb) return;
-  const ProbDev pr = probs[brick_prob[sbi >> 3]];
-  double lo[3], hi[3];
-  sub_box(pr, sbi, lo, hi);
-  int c = soff[sbi];
-  const int end = soff[sbi + 1];  // clamped to the capacity
-  for (int q = off[sbi >> 3]; q < off[(sbi >> 3) + 1] && c < end; ++q) {
-    const int s = list[q];
-    if (box_meets_patch(sbox + 18 * s, lo, hi)) slist[c++] = s;
+__global__ void __launch_bounds__(256)
+k_sub_count(const ProbDev *__restrict__ probs, const int *__restrict__ brick_prob,
+            const double *__restrict__ sbox, int nb, const int *__restrict__ off,
+            const int *__restrict__ list, int *__restrict__ count) {
+  const int lane = threadIdx.x & 63;
+  const int bi = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (bi >= nb) return;  // uniform over the wavefront
+  const ProbDev pr = probs[brick_prob[bi]];
+  int c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int q0 = off[bi]; q0 < off[bi + 1]; q0 += 64) {
+    const int q = q0 + lane;
+    const unsigned m = q < off[bi + 1] ? sub_mask(pr, bi, sbox + 18 * list[q]) : 0u;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) c[w] += __popcll(__ballot((m >> w) & 1u));
+  }
+  if (lane < 8) {
+    int v = c[0];
+#pragma unroll
+    for (int w = 1; w < 8; ++w) v = lane == w ? c[w] : v;
+    count[bi * 8 + lane] = v;
   }
 }
 
-// One wavefront per brick: the lanes test 64 consecutive patches of the
-// brick's problem at a time.  The count is a wave sum; the fill writes the
-// meeting patches in ascending patch order (ballot prefix counts), the order
-// that fixes the adjoint's summation order.
+__global__ void __launch_bounds__(256)
+k_sub_fill(const ProbDev *__restrict__ probs, const int *__restrict__ brick_prob,
+           const double *__restrict__ sbox, int nb, const int *__restrict__ off,
+           const int *__restrict__ list, const int *__restrict__ soff,
+           int *__restrict__ slist) {
+  const int lane = threadIdx.x & 63;
+  const int bi = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (bi >= nb) return;  // uniform over the wavefront
+  const ProbDev pr = probs[brick_prob[bi]];
+  const unsigned long long below = (1ull << lane) - 1ull;
+  int c[8], end[8];
+#pragma unroll
+  for (int w = 0; w < 8; ++w) {
+    c[w] = soff[bi * 8 + w];
+    end[w] = soff[bi * 8 + w + 1];  // clamped to the capacity
+  }
+  for (int q0 = off[bi]; q0 < off[bi + 1]; q0 += 64) {
+    const int q = q0 + lane;
+    const int sp = q < off[bi + 1] ? list[q] : 0;
+    const unsigned m = q < off[bi + 1] ? sub_mask(pr, bi, sbox + 18 * sp) : 0u;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+      const bool h = (m >> w) & 1u;
+      const unsigned long long bal = __ballot(h);
+      const int pos = c[w] + __popcll(bal & below);
+      if (h && pos < end[w]) slist[pos] = sp;
+      c[w] += __popcll(bal);
+    }
+  }
+}
+
+// Union of the brick ranges of 64 consecutive patches (group G holds the
+// patches 64 G .. 64 G + 63 of the whole table): a brick outside it meets
+// none of them.  Empty ranges (low end above the high end) only widen it.
+constexpr int PGROUP = 64;
+__global__ void __launch_bounds__(256)
+k_group_box(const int *__restrict__ bb, int M, int *__restrict__ gbox) {
+  const int lane = threadIdx.x & 63;
+  const int G = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (G * PGROUP >= M) return;  // uniform over the wavefront
+  const int s = G * PGROUP + lane;
+  const bool ok = s < M;
+  int v[6];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    v[r] = ok ? bb[6 * s + r] : INT_MAX;
+    v[3 + r] = ok ? bb[6 * s + 3 + r] : INT_MIN;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      v[r] = min(v[r], __shfl_xor(v[r], o, 64));
+      v[3 + r] = max(v[3 + r], __shfl_xor(v[3 + r], o, 64));
+    }
+  if (lane < 6) gbox[6 * G + lane] = v[lane];
+}
+
+__device__ __forceinline__ bool brick_in_group(const int *__restrict__ gb, int bx, int by, int bz) {
+  return bx >= gb[0] && bx <= gb[3] && by >= gb[1] && by <= gb[4] && bz >= gb[2] && bz <= gb[5];
+}
+
+// One wavefront per brick: over the groups that hold the brick's problem's
+// patches, the lanes first test 64 group ranges at once, then the 64
+// patches of each group whose range union holds the brick.  The count is a
+// wave sum; the fill writes the meeting patches in ascending patch order
+// (ballot prefix counts), the order that fixes the adjoint's summation
+// order.
 constexpr int BIN_THREADS = 256;
 
 __global__ void __launch_bounds__(BIN_THREADS)
 k_bin_count(const ProbDev *__restrict__ probs, const int *__restrict__ brick_prob,
-            const int *__restrict__ bb, const double *__restrict__ sbox, int nb,
-            int *__restrict__ count) {
+            const int *__restrict__ bb, const int *__restrict__ gbox,
+            const double *__restrict__ sbox, int nb, int *__restrict__ count) {
   const int lane = threadIdx.x & 63;
-  const int bi = blockIdx.x * (BIN_THREADS / 64) + (threadIdx.x >> 6);
+  const int bi = __builtin_amdgcn_readfirstlane(blockIdx.x * (BIN_THREADS / 64) + (threadIdx.x >> 6));
   if (bi >= nb) return;  // uniform over the wavefront
   const ProbDev pr = probs[brick_prob[bi]];
   const int local = bi - pr.brick_base;
   const int bx = local % pr.nbx, by = (local / pr.nbx) % pr.nby, bz = local / (pr.nbx * pr.nby);
   int c = 0;
-  for (int s0 = pr.patch_begin; s0 < pr.patch_end; s0 += 64) {
-    const int s = s0 + lane;
-    if (s < pr.patch_end && brick_meets_patch(bb + 6 * s, sbox + 18 * s, bx, by, bz)) ++c;
+  if (pr.patch_end > pr.patch_begin) {
+    const int g1 = (pr.patch_end - 1) / PGROUP;
+    for (int G0 = pr.patch_begin / PGROUP; G0 <= g1; G0 += 64) {
+      // the lanes test 64 groups at once; the groups that hold the brick
+      // are then taken in ascending order
+      const int Gl = G0 + lane;
+      unsigned long long hit = __ballot(Gl <= g1 && brick_in_group(gbox + 6 * Gl, bx, by, bz));
+      while (hit) {
+        const int G = G0 + __builtin_ctzll(hit);
+        hit &= hit - 1;
+        const int s = G * PGROUP + lane;
+        if (s >= pr.patch_begin && s < pr.patch_end &&
+            brick_meets_patch(bb + 6 * s, sbox + 18 * s, bx, by, bz))
+          ++c;
+      }
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
@@ -246,10 +332,11 @@ k_bin_count(const ProbDev *__restrict__ probs, const int *__restrict__ brick_pro
 
 __global__ void __launch_bounds__(BIN_THREADS)
 k_bin_fill(const ProbDev *__restrict__ probs, const int *__restrict__ brick_prob,
-           const int *__restrict__ bb, const double *__restrict__ sbox, int nb,
-           const int *__restrict__ off, int *__restrict__ list) {
+           const int *__restrict__ bb, const int *__restrict__ gbox,
+           const double *__restrict__ sbox, int nb, const int *__restrict__ off,
+           int *__restrict__ list) {
   const int lane = threadIdx.x & 63;
-  const int bi = blockIdx.x * (BIN_THREADS / 64) + (threadIdx.x >> 6);
+  const int bi = __builtin_amdgcn_readfirstlane(blockIdx.x * (BIN_THREADS / 64) + (threadIdx.x >> 6));
   if (bi >= nb) return;  // uniform over the wavefront
   const ProbDev pr = probs[brick_prob[bi]];
   const int local = bi - pr.brick_base;
@@ -257,13 +344,23 @@ k_bin_fill(const ProbDev *__restrict__ probs, const int *__restrict__ brick_prob
   const unsigned long long below = (1ull << lane) - 1ull;
   int c = off[bi];
   const int end = off[bi + 1];  // the list's end, clamped to its capacity
-  for (int s0 = pr.patch_begin; s0 < pr.patch_end; s0 += 64) {
-    const int s = s0 + lane;
-    const bool m = s < pr.patch_end && brick_meets_patch(bb + 6 * s, sbox + 18 * s, bx, by, bz);
-    const unsigned long long bal = __ballot(m);
-    const int pos = c + __popcll(bal & below);
-    if (m && pos < end) list[pos] = s;
-    c += __popcll(bal);
+  if (pr.patch_end > pr.patch_begin) {
+    const int g1 = (pr.patch_end - 1) / PGROUP;
+    for (int G0 = pr.patch_begin / PGROUP; G0 <= g1; G0 += 64) {
+      const int Gl = G0 + lane;
+      unsigned long long hit = __ballot(Gl <= g1 && brick_in_group(gbox + 6 * Gl, bx, by, bz));
+      while (hit) {
+        const int G = G0 + __builtin_ctzll(hit);
+        hit &= hit - 1;
+        const int s = G * PGROUP + lane;
+        const bool m = s >= pr.patch_begin && s < pr.patch_end &&
+                       brick_meets_patch(bb + 6 * s, sbox + 18 * s, bx, by, bz);
+        const unsigned long long bal = __ballot(m);
+        const int pos = c + __popcll(bal & below);
+        if (m && pos < end) list[pos] = s;
+        c += __popcll(bal);
+      }
+    }
   }
 }
 
@@ -280,38 +377,103 @@ __global__ void k_tile_boxmax(const ProbDev *__restrict__ probs, const PatchDev 
   atomicMax(out, c);
 }
 
-// Exclusive scan of count[0..n) into off[0..n], off[n] = total, by one
-// workgroup of 1024 threads (each owns a contiguous run).  The offsets are
-// clamped to the list's capacity `cap`; a total beyond it (which the host
-// bound on the pairs rules out) raises PVR_FAULT_INDEX, and the lists then
-// keep only what fits.
-__global__ void __launch_bounds__(1024) k_scan(const int *__restrict__ count, int n,
-                                               int *__restrict__ off, int *__restrict__ total,
-                                               long long cap, unsigned *__restrict__ status) {
-  __shared__ long long lds[1024];
+// Exclusive scan of count[0..n) into off[0..n], off[n] = total, in three
+// passes: block sums over chunks of SCAN_CHUNK counts (each thread four
+// consecutive ones), one workgroup scanning the block sums (tiles of
+// SCAN_T with a carry) and writing the total, then every block scanning its
+// chunk from its base.  The offsets are clamped to the list's capacity
+// `cap`; a total beyond it (which the host bound on the pairs rules out)
+// raises PVR_FAULT_INDEX, and the lists then keep only what fits.
+constexpr int SCAN_T = 1024, SCAN_PER = 4, SCAN_CHUNK = SCAN_T * SCAN_PER;
+
+static int scan_blocks(long long n) { return (int)((n + SCAN_CHUNK - 1) / SCAN_CHUNK); }
+
+// inclusive scan of one value per thread across the workgroup (Hillis-Steele)
+__device__ __forceinline__ long long block_incl_scan(long long v, long long *lds) {
   const int tid = threadIdx.x;
-  const int per = (n + 1023) / 1024;
-  const int a = min(n, tid * per), b = min(n, a + per);
-  long long s = 0;
-  for (int i = a; i < b; ++i) s += count[i];
-  lds[tid] = s;
+  lds[tid] = v;
   __syncthreads();
-  for (int d = 1; d < 1024; d <<= 1) {
-    long long v = tid >= d ? lds[tid - d] : 0;
+  for (int d = 1; d < SCAN_T; d <<= 1) {
+    const long long u = tid >= d ? lds[tid - d] : 0;
     __syncthreads();
-    lds[tid] += v;
+    lds[tid] += u;
     __syncthreads();
   }
-  long long run = lds[tid] - s;
-  for (int i = a; i < b; ++i) {
-    off[i] = (int)min(run, cap);
-    run += count[i];
+  return lds[tid];
+}
+
+__global__ void __launch_bounds__(SCAN_T)
+k_scan_sums(const int *__restrict__ count, int n, long long *__restrict__ bsum) {
+  __shared__ long long lds[SCAN_T / 64];
+  const int base = blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_PER;
+  long long v = 0;
+#pragma unroll
+  for (int q = 0; q < SCAN_PER; ++q)
+    if (base + q < n) v += count[base + q];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long t = 0;
+    for (int w = 0; w < SCAN_T / 64; ++w) t += lds[w];
+    bsum[blockIdx.x] = t;
   }
-  if (tid == 1023) {
-    off[n] = (int)min(lds[1023], cap);
-    total[0] = (int)min(lds[1023], cap);
-    if (lds[1023] > cap) atomicOr(status, PVR_FAULT_INDEX);
+}
+
+__global__ void __launch_bounds__(SCAN_T)
+k_scan_top(long long *__restrict__ bsum, int nblk, int n, int *__restrict__ off,
+           int *__restrict__ total, long long cap, unsigned *__restrict__ status) {
+  __shared__ long long lds[SCAN_T];
+  long long carry = 0;
+  for (int t0 = 0; t0 < nblk; t0 += SCAN_T) {
+    const int i = t0 + threadIdx.x;
+    const long long v = i < nblk ? bsum[i] : 0;
+    const long long incl = block_incl_scan(v, lds);
+    if (i < nblk) bsum[i] = carry + incl - v;  // the block's base
+    carry += lds[SCAN_T - 1];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) {
+    off[n] = (int)min(carry, cap);
+    total[0] = (int)min(carry, cap);
+    if (carry > cap) atomicOr(status, PVR_FAULT_INDEX);
+  }
+}
+
+__global__ void __launch_bounds__(SCAN_T)
+k_scan_apply(const int *__restrict__ count, int n, const long long *__restrict__ bbase,
+             int *__restrict__ off, long long cap) {
+  __shared__ long long lds[SCAN_T];
+  const int base = blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_PER;
+  int c[SCAN_PER];
+  long long v = 0;
+#pragma unroll
+  for (int q = 0; q < SCAN_PER; ++q) {
+    c[q] = base + q < n ? count[base + q] : 0;
+    v += c[q];
+  }
+  long long run = bbase[blockIdx.x] + block_incl_scan(v, lds) - v;
+#pragma unroll
+  for (int q = 0; q < SCAN_PER; ++q)
+    if (base + q < n) {
+      off[base + q] = (int)min(run, cap);
+      run += c[q];
+    }
+}
+
+static pvr_status launch_scan(const int *count, int n, long long *scratch, int *off, int *total,
+                              long long cap, unsigned *status, hipStream_t stream) {
+  const int nblk = scan_blocks(n);
+  hipLaunchKernelGGL(k_scan_sums, dim3(nblk), dim3(SCAN_T), 0, stream, count, n, scratch);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_T), 0, stream, scratch, nblk, n, off, total,
+                     cap, status);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_scan_apply, dim3(nblk), dim3(SCAN_T), 0, stream, count, n,
+                     (const long long *)scratch, off, cap);
+  HIP_TRY(hipGetLastError());
+  return PVR_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -537,6 +699,8 @@ static size_t layout(pvr_plan *p, char *base, int flags) {
   p->d_geod = ws_take<GeoD>(c, M);
   p->d_geof = ws_take<GeoF>(c, M);
   p->d_bb = ws_take<int>(c, 6 * M);
+  p->d_gbox = ws_take<int>(c, 6 * ((M + 63) / 64));
+  p->d_scan = ws_take<long long>(c, (8 * nb + 4095) / 4096 + 1);
   p->d_sbox = ws_take<double>(c, 18 * M);
   p->d_invz = ws_take<float>(c, N);
   p->d_mask = ws_take<uint8_t>(c, N);
@@ -775,27 +939,28 @@ extern "C" pvr_status pvr_plan_set_granules(pvr_plan *p, int32_t sim_granule,
 // geometry of the last build, into lists of the capacities bounded at plan
 // creation: no count is read back, nothing is synchronised.
 pvr_status pvr::plan_build_index(pvr_plan *p, hipStream_t stream) {
-  const int T = 256;
   const int nb = p->n_bricks;
   const int nbw = (nb + BIN_THREADS / 64 - 1) / (BIN_THREADS / 64);
+  hipLaunchKernelGGL(k_group_box, dim3((p->M + 255) / 256), dim3(256), 0, stream, p->d_bb, p->M,
+                     p->d_gbox);
+  HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(k_bin_count, dim3(nbw), dim3(BIN_THREADS), 0, stream, p->d_prob,
-                     p->d_brick_prob, p->d_bb, p->d_sbox, nb, p->d_bin_count);
+                     p->d_brick_prob, p->d_bb, p->d_gbox, p->d_sbox, nb, p->d_bin_count);
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, stream, p->d_bin_count, nb, p->d_bin_off,
-                     p->d_total, p->bin_cap, p->d_status);
-  HIP_TRY(hipGetLastError());
+  PVR_TRY_STATUS(launch_scan(p->d_bin_count, nb, p->d_scan, p->d_bin_off, p->d_total, p->bin_cap,
+                             p->d_status, stream));
   hipLaunchKernelGGL(k_bin_fill, dim3(nbw), dim3(BIN_THREADS), 0, stream, p->d_prob,
-                     p->d_brick_prob, p->d_bb, p->d_sbox, nb, p->d_bin_off, p->d_bin_patch);
+                     p->d_brick_prob, p->d_bb, p->d_gbox, p->d_sbox, nb, p->d_bin_off,
+                     p->d_bin_patch);
   HIP_TRY(hipGetLastError());
   const int nsb = nb * 8;
-  hipLaunchKernelGGL(k_sub_count, dim3((nsb + T - 1) / T), dim3(T), 0, stream, p->d_prob,
-                     p->d_brick_prob, p->d_sbox, nsb, p->d_bin_off, p->d_bin_patch, p->d_sub_count);
+  hipLaunchKernelGGL(k_sub_count, dim3((nb + 3) / 4), dim3(256), 0, stream, p->d_prob,
+                     p->d_brick_prob, p->d_sbox, nb, p->d_bin_off, p->d_bin_patch, p->d_sub_count);
   HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, stream, p->d_sub_count, nsb, p->d_sub_off,
-                     p->d_total + 1, p->sub_cap, p->d_status);
-  HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(k_sub_fill, dim3((nsb + T - 1) / T), dim3(T), 0, stream, p->d_prob,
-                     p->d_brick_prob, p->d_sbox, nsb, p->d_bin_off, p->d_bin_patch, p->d_sub_off,
+  PVR_TRY_STATUS(launch_scan(p->d_sub_count, nsb, p->d_scan, p->d_sub_off, p->d_total + 1,
+                             p->sub_cap, p->d_status, stream));
+  hipLaunchKernelGGL(k_sub_fill, dim3((nb + 3) / 4), dim3(256), 0, stream, p->d_prob,
+                     p->d_brick_prob, p->d_sbox, nb, p->d_bin_off, p->d_bin_patch, p->d_sub_off,
                      p->d_sub_patch);
   HIP_TRY(hipGetLastError());
   p->index_valid = true;
