@@ -264,8 +264,11 @@ def init_fn_factory(net: Net, batch: int = 1024):
     """A driver init function: predicts every patch's correction from the
     current volume and keeps, per patch, whichever of the old and the
     proposed motion has the higher NCC (the registration refines it next).
-    Every build takes the cycle's active set and sample mask.  Returns the
-    per-patch NCC before the prediction and at the motion kept."""
+    Every build takes the cycle's active set and sample mask; the plan is
+    left built at the proposal (the registration that follows computes each
+    patch's geometry itself and needs only the build's mask and active set,
+    and the driver rebuilds after it).  Returns the per-patch NCC before the
+    prediction and at the motion kept."""
     import torch
 
     def init_fn(plan, X, y, theta, active=None, mask=None):
@@ -290,7 +293,6 @@ def init_fn_factory(net: Net, batch: int = 1024):
         plan.ncc_grad(y, ysim, None, n_new)
         n_before = n_old.clone()
         plan.motion_accept(prop, n_new, theta, n_old)  # keep the better of the two
-        plan.build(theta, active=active, mask=mask)
         return n_before, n_old
 
     return init_fn
