@@ -23,7 +23,7 @@ import numpy as np
 FORWARD = [("walk", 1), ("walk", 2), ("walk", 4), ("walk", 16),
            ("tiles", 16, 16), ("tiles", 32, 8), ("tiles", 8, 32), ("tiles", 64, 4)]
 # adjoint candidates: XCD granules of the brick list
-ADJOINT = [1, 4, 16, 64, 256]
+ADJOINT = [1, 4, 16, 32, 64, 256]
 CACHE = os.environ.get("PVR_AUTOTUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "pvr_mi355x",
                                     "autotune.json"))
