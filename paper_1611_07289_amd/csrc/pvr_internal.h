@@ -122,7 +122,7 @@ __device__ __forceinline__ int xcd_work(int b, int g) {
 }
 // default granules (pvr_plan_set_granules changes them per plan; the launch
 // order changes, the results do not)
-constexpr int SIM_XCD_GRANULE = 1;   // forward chunks: plain round-robin measured fastest
+constexpr int SIM_XCD_GRANULE = 4;   // forward chunks (4 of 1024 samples, one 64x64 patch)
 constexpr int BP_XCD_GRANULE = 32;   // adjoint bricks (a row of a 256^3 grid's bricks)
 
 constexpr int TILE = 16;            // forward tile edge (pixels)
