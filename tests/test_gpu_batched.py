@@ -164,7 +164,7 @@ def test_launch_shapes_change_no_result(batch):
     plan.set_tiles(0, 0)
     plan.set_granules(1, 64)
     ref = outputs()
-    for gs, gb in ((2, 1), (16, 4), (4, 256)):
+    for gs, gb in ((2, 1), (16, 4), (4, 32), (4, 256), (8, 1024)):
         plan.set_granules(gs, gb)
         got = outputs()
         assert all(torch.equal(a, b) for a, b in zip(got, ref)), (gs, gb)
