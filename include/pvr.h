@@ -470,7 +470,11 @@ pvr_status pvr_ncc_grad(const pvr_plan *plan, const float *y_obs,
  *   (active nullable = all) and score_s below their threshold: theta_s =
  *   theta_ref_s and flag_s = 1 -- the patches a plain registration takes
  *   over from their reference motion; every other patch gets flag_s = 0 and
- *   keep_s = 1 if active (keep nullable; flag and keep uint8 [M]). */
+ *   keep_s = 1 if active (keep nullable; flag and keep uint8 [M]).
+ * pvr_motion_live: live_s = 1 where delta_s >= step_min and active_s != 0
+ *   (active nullable = all), else 0 (live uint8 [M]): the patches whose
+ *   optimiser still moves, the active set of a build that evaluates only
+ *   them. */
 pvr_status pvr_motion_frame(const pvr_plan *plan, const float *in, int32_t inverse,
                             const float *base, float *out, hipStream_t stream);
 pvr_status pvr_motion_step(const pvr_plan *plan, const float *theta, const float *grad_theta,
@@ -484,6 +488,8 @@ pvr_status pvr_motion_fallback(const pvr_plan *plan, const float *score, float t
                                const float *score_ref, const float *theta_ref, float *theta,
                                const uint8_t *active, uint8_t *flag, uint8_t *keep,
                                hipStream_t stream);
+pvr_status pvr_motion_live(const pvr_plan *plan, const float *delta, float step_min,
+                           const uint8_t *active, uint8_t *live, hipStream_t stream);
 
 /* Numeric faults.  The SR update raises PVR_FAULT_VOLUME when a voxel of the
  * new volume is not finite before the clamp (which would otherwise hide a

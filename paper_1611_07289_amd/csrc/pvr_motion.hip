@@ -164,6 +164,15 @@ k_motion_fallback(int M, const float *__restrict__ score, float tau,
   if (keep) keep[s] = act && !back ? 1 : 0;
 }
 
+__global__ void __launch_bounds__(MOT_T)
+k_motion_live(int M, const float *__restrict__ delta, float step_min,
+              const uint8_t *__restrict__ active, uint8_t *__restrict__ live) {
+  const int s = blockIdx.x * MOT_T + threadIdx.x;
+  if (s >= M) return;
+  const bool act = active ? active[s] != 0 : true;
+  live[s] = act && delta[s] >= step_min ? 1 : 0;
+}
+
 inline unsigned lanes(int M) { return (unsigned)((M + MOT_T - 1) / MOT_T); }
 
 }  // namespace
@@ -248,6 +257,18 @@ extern "C" pvr_status pvr_motion_fallback(const pvr_plan *p, const float *score,
     return fail(PVR_EINVAL, "pvr_motion_fallback: NULL argument");
   hipLaunchKernelGGL(k_motion_fallback, dim3(lanes(p->M)), dim3(MOT_T), 0, stream, p->M, score,
                      tau, score_ref, theta_ref, theta, active, flag, keep);
+  HIP_TRY(hipGetLastError());
+  return PVR_OK;
+  PVR_API_END();
+}
+
+extern "C" pvr_status pvr_motion_live(const pvr_plan *p, const float *delta, float step_min,
+                                      const uint8_t *active, uint8_t *live, hipStream_t stream) {
+  PVR_API_BEGIN();
+  PVR_ALIGNED("pvr_motion_live", delta, 4);
+  if (!p || !delta || !live) return fail(PVR_EINVAL, "pvr_motion_live: NULL argument");
+  hipLaunchKernelGGL(k_motion_live, dim3(lanes(p->M)), dim3(MOT_T), 0, stream, p->M, delta,
+                     step_min, active, live);
   HIP_TRY(hipGetLastError());
   return PVR_OK;
   PVR_API_END();

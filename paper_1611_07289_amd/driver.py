@@ -272,9 +272,10 @@ def register_gradient(plan, X, y, theta, iters: int = 30, step0: float = 1.0,
     G_t = torch.empty_like(G)
     trial = torch.empty_like(G)
     delta = torch.empty(plan.M, dtype=torch.float32, device=dev)
+    live = torch.empty(plan.M, dtype=torch.uint8, device=dev)
 
-    def evaluate(th, score, grad):
-        plan.build(th, active=active, mask=mask)
+    def evaluate(th, score, grad, act):
+        plan.build(th, active=act, mask=mask)
         plan.simulate(X, y_sim=ysim)
         plan.ncc_grad(y, ysim, g, score)
         plan.grad_theta(X, g, grad)
@@ -282,20 +283,25 @@ def register_gradient(plan, X, y, theta, iters: int = 30, step0: float = 1.0,
     # NCC and gradient at every trial: an accepted trial becomes the patch's
     # motion with the NCC and gradient just computed there, a rejected one
     # leaves the motion, NCC and gradient as they were, so the motion is
-    # never evaluated twice
+    # never evaluated twice.  Only the patches whose step is still at least
+    # step_min are evaluated (pvr_motion_live); the others could not move
+    # anyway, and their NCC and motion stay as they are.
     n_live = torch.zeros(1, dtype=torch.int32, device=dev)
-    evaluate(theta, ncc, G)
+    evaluate(theta, ncc, G, active)
     plan.motion_init_step(y, step0, min_std, delta)
+    plan.motion_live(delta, step_min, live, active)
     for it in range(iters):
         plan.motion_step(theta, G, delta, step_min, trial)
-        evaluate(trial, ncc_t, G_t)
+        evaluate(trial, ncc_t, G_t, live)
         # the gradient follows the motion: the same strict-improvement test
         # (on a copy of the scores, which the motion's acceptance updates);
-        # a patch below step_min did not move, so its trial cannot improve
+        # a patch not evaluated may pass it (its trial score reads 0), but its
+        # gradient is never used again, as its step stays below step_min
         ncc_c.copy_(ncc)
         plan.motion_accept(G_t, ncc_t, G, ncc_c)
         n_live.zero_()
         plan.motion_accept(trial, ncc_t, theta, ncc, delta, step0, step_min, n_live)
+        plan.motion_live(delta, step_min, live, active)
         if it % 4 == 3 and int(n_live.item()) == 0:  # every patch has converged
             break
     plan.build(theta, active=active, mask=mask)

@@ -99,7 +99,7 @@ EXPORTS = ["pvr_last_error", "pvr_version", "pvr_plan_create", "pvr_plan_destroy
            "pvr_plan_workspace_size", "pvr_plan_attach", "pvr_plan_reg_stats",
            "pvr_plan_set_granules",
            "pvr_motion_frame", "pvr_motion_step",
-           "pvr_motion_accept", "pvr_motion_init_step", "pvr_motion_fallback",
+           "pvr_motion_accept", "pvr_motion_init_step", "pvr_motion_fallback", "pvr_motion_live",
            "pvr_plan_info", "pvr_plan_offsets", "pvr_plan_build", "pvr_plan_build_f64",
            "pvr_plan_inv_z", "pvr_simulate", "pvr_simulate_f64", "pvr_backproject",
            "pvr_backproject_f64", "pvr_robust_weights", "pvr_sr_update",
@@ -143,6 +143,7 @@ def load(path: str = LIB_PATH):
     L.pvr_motion_accept.argtypes = [P, P, P, P, P, P, f32_, f32_, P, P]
     L.pvr_motion_init_step.argtypes = [P, P, f32_, ctypes.c_double, P, P]
     L.pvr_motion_fallback.argtypes = [P, P, f32_, P, P, P, P, P, P, P]
+    L.pvr_motion_live.argtypes = [P, P, f32_, P, P, P]
     L.pvr_plan_offsets.argtypes = [P, P, P]
     L.pvr_plan_build.argtypes = [P, P, P, P, P]
     L.pvr_plan_build_f64.argtypes = [P, P, P, P, P]
@@ -415,6 +416,10 @@ class Plan:
     def motion_init_step(self, y_obs, step0, min_std, delta):
         _check(load().pvr_motion_init_step(self.h, _ptr(y_obs), float(step0), float(min_std),
                                            _ptr(delta), _stream()))
+
+    def motion_live(self, delta, step_min, live, active=None):
+        _check(load().pvr_motion_live(self.h, _ptr(delta), float(step_min), _ptr(active),
+                                      _ptr(live), _stream()))
 
     def motion_fallback(self, score, tau, theta_ref, theta, flag, score_ref=None, active=None,
                         keep=None):

@@ -2,8 +2,8 @@
 statements of their rules on the 32^3 workload's 216 patches (three
 orthogonal stacks) plus an oblique stack: the patch-frame map
 A = diag(rho F^T, F^T) and its inverse, the normalised ascent trial, the
-accept / halve rule with its live count, the flat-patch test and the
-fallback selection."""
+accept / halve rule with its live count, the live set, the flat-patch test
+and the fallback selection."""
 import math
 
 import numpy as np
@@ -93,6 +93,13 @@ def test_step_accept_and_live_count(case):
     plan.motion_accept(trial, dev(score_c), tt, ss)
     sel = score_c > score
     assert np.array_equal(host(tt), np.where(sel[:, None], host(trial), th))
+    # the live set: step at least step_min, within an active set (or all)
+    live = torch.empty(P.M, dtype=torch.uint8, device="cuda")
+    plan.motion_live(dev(delta), step_min, live)
+    assert np.array_equal(host(live), (delta >= step_min).astype(np.uint8))
+    active = (rng.uniform(size=P.M) < 0.6).astype(np.uint8)
+    plan.motion_live(dev(delta), step_min, live, dev(active))
+    assert np.array_equal(host(live), ((delta >= step_min) & (active > 0)).astype(np.uint8))
 
 
 def test_flat_patches_and_fallback(case):
